@@ -1,0 +1,133 @@
+/*
+ * g5 -- breadth-first search over an undirected Kronecker graph stored as CSR,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the pipeline of the paper "Graph500 from OCaml-Multicore
+ * Perspective" (algorithm "Basic Outline of Graph500"): Kernel 1 constructs a
+ * graph from the generated edge list (Section 2.2, CSR format), Kernel 2
+ * computes the parent array and BFS tree from a root (Section 2.3), and the
+ * metric is taken over 64 start vertices (Section 4.3).
+ *
+ * Conventions shared by every call
+ *   - Device pointers are HIP device memory of the current device; host
+ *     pointers are ordinary host memory.  Each argument below says which.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *     Every call returns after its work on `stream` has completed.
+ *   - Status codes are negative on failure (g5_status).  On failure no output
+ *     contents are promised; g5_last_error() describes the failure.
+ *   - Vertex ids are 0 .. n-1 with n <= 2^31 - 1.  Levels and parents use -1
+ *     for "not reached"; parent[root] = root.
+ *   - Calls on the same g5_csr from several host threads are allowed; each
+ *     BFS call takes a private workspace from a pool owned by the g5_csr.
+ */
+#ifndef G5_H
+#define G5_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct g5_csr g5_csr; /* opaque, device-resident, owned by the library */
+
+typedef enum {
+  G5_OK = 0,
+  G5_EINVAL = -1,  /* bad argument: NULL pointer, id or root outside [0, n), k outside [1, 64] */
+  G5_ENOMEM = -2,  /* a device or pinned-host allocation failed */
+  G5_EDEVICE = -3, /* a HIP runtime error */
+  G5_ERANGE = -4   /* a result does not fit its type (batched level > 126, nnz >= 2^32) */
+} g5_status;
+
+/* Kernel 1 (Section 2.2): builds the undirected CSR of an edge list.
+ *   edges       device, int64 [m][2] tuples (start, end), borrowed for the call.
+ *   m           number of tuples (>= 0).
+ *   n_vertices  number of vertices n (1 .. 2^31-1); every id must lie in [0, n).
+ *   out         host, receives the new graph; *out = NULL on any error.
+ * Each non-loop tuple (u, v) gives both u->v and v->u (the graph is
+ * undirected, Section 2); self-loops and repeated edges are dropped (they may
+ * be ignored by the kernels, Section 2.1).  Row v lists v's distinct
+ * neighbours in ascending order; row_ptr has n+1 entries, an empty row repeats
+ * the previous index and row_ptr[n] = nnz (the CSR description of Section 2.2).
+ * Errors: G5_EINVAL (id outside [0, n), m < 0, n out of range, NULL pointer),
+ * G5_ERANGE (nnz >= 2^32), G5_ENOMEM, G5_EDEVICE. */
+g5_status g5_build_csr(const int64_t *edges, int64_t m, int64_t n_vertices, void *stream,
+                       g5_csr **out);
+
+/* Sizes and borrowed device pointers of a graph built by g5_build_csr:
+ * row_ptr int64 [n+1], col_idx int32 [nnz].  Any output pointer may be NULL.
+ * The pointers stay valid until g5_csr_free. */
+g5_status g5_csr_info(const g5_csr *g, int64_t *n, int64_t *nnz, const int64_t **row_ptr,
+                      const int32_t **col_idx);
+
+/* Copies the CSR arrays into caller buffers (device or host memory):
+ * row_ptr int64 [n+1], col_idx int32 [nnz]; either may be NULL. */
+g5_status g5_csr_copy(const g5_csr *g, int64_t *row_ptr, int32_t *col_idx, void *stream);
+
+/* Frees a graph and every workspace it owns.  NULL-safe. */
+void g5_csr_free(g5_csr *g);
+
+/* Kernel 2 (Section 2.3): breadth-first search from `root`.
+ *   parent, level  device, int32 [n], written in full (caller-owned).
+ * level[v] is the hop distance from root to v, or -1 if v is not in root's
+ * component.  parent[root] = root; for another reached v, parent[v] is a
+ * neighbour of v at level[v] - 1 (which one is not specified); -1 if
+ * unreached.  The traversal is level-synchronous (Section 2.3.2) and
+ * direction-optimising (top-down steps on small frontiers, bottom-up steps on
+ * large ones).  A root of degree 0 is valid: only the root is reached.
+ * Errors: G5_EINVAL (root outside [0, n), NULL pointer), G5_ENOMEM,
+ * G5_EDEVICE. */
+g5_status g5_bfs(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level, void *stream);
+
+/* Direction policy of one traversal. */
+typedef enum {
+  G5_DIR_AUTO = 0,     /* direction-optimising switch on alpha / beta */
+  G5_DIR_TOPDOWN = 1,  /* every level top-down */
+  G5_DIR_BOTTOMUP = 2  /* every level after the root's bottom-up */
+} g5_direction;
+
+/* Tuning knobs of g5_bfs_ex.  Zero fields take the library defaults. */
+typedef struct {
+  int32_t direction; /* g5_direction */
+  double alpha;      /* top-down -> bottom-up when m_f > m_u / alpha (default 14) */
+  double beta;       /* bottom-up -> top-down when n_f < n / beta, shrinking (default 24) */
+  int32_t bu_lane_scan; /* neighbours a lane tests before its row goes wave-wide (1..16, default 4) */
+  int32_t reserved[7];
+} g5_bfs_params;
+
+#define G5_MAX_STAT_LEVELS 64
+
+/* Per-traversal statistics of g5_bfs_ex (host memory, filled on success). */
+typedef struct {
+  int32_t nlevels;                        /* levels processed, root level included */
+  int32_t dir[G5_MAX_STAT_LEVELS];        /* 1 top-down, 2 bottom-up, per level */
+  int64_t frontier[G5_MAX_STAT_LEVELS];   /* vertices in the frontier each level expands */
+  int64_t reached;                        /* vertices with level >= 0 */
+  int64_t reserved[8];
+} g5_bfs_stats;
+
+/* g5_bfs with explicit parameters (NULL = defaults) and optional statistics
+ * (NULL = none).  Same results and errors as g5_bfs. */
+g5_status g5_bfs_ex(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
+                    void *stream, const g5_bfs_params *params, g5_bfs_stats *stats);
+
+/* Batched BFS from k roots in one persistent launch (64-bit root masks per
+ * vertex: bit b of a vertex's mask stands for roots[b]).
+ *   roots    host, int64 [k], each in [0, n); duplicates allowed.
+ *   k        1 .. 64.
+ *   parents  device, int32 [k][n] (row b for roots[b]), or NULL to skip parents.
+ *   levels   device, int8 [k][n].
+ * Row b equals what g5_bfs(g, roots[b]) produces for levels (as int8), and a
+ * valid parent array for parents.  Errors: G5_EINVAL, G5_ERANGE (some level
+ * exceeds 126; fall back to g5_bfs), G5_ENOMEM, G5_EDEVICE. */
+g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
+                       int8_t *levels, void *stream);
+
+/* Message for the last non-OK status returned on the calling host thread. */
+const char *g5_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

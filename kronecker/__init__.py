@@ -49,6 +49,7 @@ def _load_host():
 def _load_dev():
     global _dev
     if _dev is None:
+        import torch  # noqa: F401  (bind to torch's HIP runtime; see the g5 binding)
         path = os.path.join(HERE, "libkron_dev.so")
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: run __graft_entry__.build() first")

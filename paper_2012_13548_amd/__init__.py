@@ -1,0 +1,192 @@
+"""g5: breadth-first search over Kronecker graphs on one MI355X (gfx950).
+
+Thin ctypes binding of ``libg5.so`` (C-ABI declared in ``include/g5.h``).  Every
+step of graph construction and traversal runs in the library's HIP kernels;
+this module only marshals arguments.  PyTorch supplies device memory and the
+current stream.  The library must be built (``__graft_entry__.build()``); the
+import fails if it is missing.
+
+* :func:`build_csr` -- Kernel 1 of the paper (Section 2.2): undirected CSR.
+* :func:`bfs` -- Kernel 2 (Section 2.3): parent and level arrays from a root.
+* :func:`bfs_batch` -- up to 64 roots in one launch.
+"""
+import ctypes
+import os
+
+__all__ = ["G5Error", "Csr", "build_csr", "bfs", "bfs_batch", "LIB_PATH", "lib",
+           "DIR_AUTO", "DIR_TOPDOWN", "DIR_BOTTOMUP", "CLAIM_OR", "CLAIM_CAS"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libg5.so")
+
+G5_OK, G5_EINVAL, G5_ENOMEM, G5_EDEVICE, G5_ERANGE = 0, -1, -2, -3, -4
+STATUS = {G5_EINVAL: "G5_EINVAL", G5_ENOMEM: "G5_ENOMEM", G5_EDEVICE: "G5_EDEVICE",
+          G5_ERANGE: "G5_ERANGE"}
+DIR_AUTO, DIR_TOPDOWN, DIR_BOTTOMUP = 0, 1, 2
+CLAIM_OR, CLAIM_CAS = 0, 1
+MAX_STAT_LEVELS = 64
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(there is no fallback implementation)")
+
+# torch ships its own libamdhip64.so.7.  Loading it first makes libg5 bind to
+# that same HIP runtime, so torch's device memory and streams are valid in the
+# library; loading libg5 first would start a second runtime in the process.
+import torch  # noqa: E402,F401
+
+lib = ctypes.CDLL(LIB_PATH)
+
+
+class BfsParams(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("bu_lane_scan", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class BfsStats(ctypes.Structure):
+    _fields_ = [("nlevels", ctypes.c_int32), ("dir", ctypes.c_int32 * MAX_STAT_LEVELS),
+                ("frontier", ctypes.c_int64 * MAX_STAT_LEVELS), ("reached", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 8)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_PP = ctypes.POINTER(ctypes.c_void_p)
+lib.g5_build_csr.argtypes = [_P, _I64, _I64, _P, _PP]
+lib.g5_build_csr.restype = ctypes.c_int
+lib.g5_csr_info.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _PP, _PP]
+lib.g5_csr_info.restype = ctypes.c_int
+lib.g5_csr_copy.argtypes = [_P, _P, _P, _P]
+lib.g5_csr_copy.restype = ctypes.c_int
+lib.g5_csr_free.argtypes = [_P]
+lib.g5_csr_free.restype = None
+lib.g5_bfs.argtypes = [_P, _I64, _P, _P, _P]
+lib.g5_bfs.restype = ctypes.c_int
+lib.g5_bfs_ex.argtypes = [_P, _I64, _P, _P, _P, ctypes.POINTER(BfsParams),
+                          ctypes.POINTER(BfsStats)]
+lib.g5_bfs_ex.restype = ctypes.c_int
+lib.g5_bfs_batch.argtypes = [_P, ctypes.POINTER(_I64), ctypes.c_int32, _P, _P, _P]
+lib.g5_bfs_batch.restype = ctypes.c_int
+lib.g5_last_error.argtypes = []
+lib.g5_last_error.restype = ctypes.c_char_p
+
+
+class G5Error(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = (lib.g5_last_error() or b"").decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+def _check(status, where):
+    if status != G5_OK:
+        raise G5Error(status, where)
+
+
+def _stream(device):
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Csr:
+    """A graph built by :func:`build_csr` (device-resident, owned by libg5)."""
+
+    def __init__(self, handle, device):
+        self._h = ctypes.c_void_p(handle)
+        self.device = device
+        n, nnz = _I64(), _I64()
+        _check(lib.g5_csr_info(self._h, ctypes.byref(n), ctypes.byref(nnz), None, None),
+               "g5_csr_info")
+        self.n, self.nnz = n.value, nnz.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def arrays(self):
+        """Copies of (row_ptr int64[n+1], col_idx int32[nnz]) as device tensors."""
+        import torch
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        _check(lib.g5_csr_copy(self._h, rp.data_ptr(), ci.data_ptr(), _stream(self.device)),
+               "g5_csr_copy")
+        return rp, ci[:self.nnz]
+
+    def free(self):
+        if self._h and self._h.value:
+            lib.g5_csr_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_csr(edges, n):
+    """Kernel 1: CSR of a device int64 [m, 2] tuple tensor over n vertices."""
+    import torch
+    if edges.dtype != torch.int64 or edges.dim() != 2 or edges.shape[1] != 2:
+        raise ValueError("edges must be an int64 tensor of shape [m, 2]")
+    if not edges.is_cuda:
+        raise ValueError("edges must be a device tensor")
+    edges = edges.contiguous()
+    out = ctypes.c_void_p()
+    ptr = edges.data_ptr() if edges.shape[0] else None
+    _check(lib.g5_build_csr(ptr, edges.shape[0], int(n), _stream(edges.device),
+                            ctypes.byref(out)), "g5_build_csr")
+    return Csr(out.value, edges.device)
+
+
+def _params(direction, alpha, beta, lane_scan, claim):
+    p = BfsParams()
+    p.direction = direction
+    p.alpha = alpha or 0.0
+    p.beta = beta or 0.0
+    p.bu_lane_scan = lane_scan or 0
+    p.reserved[0] = claim
+    return p
+
+
+def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta=None,
+        lane_scan=None, claim=CLAIM_OR, stats=False):
+    """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
+
+    With ``stats=True`` also returns a dict with the per-level directions and
+    frontier sizes.
+    """
+    import torch
+    if parent is None:
+        parent = torch.empty(csr.n, dtype=torch.int32, device=csr.device)
+    if level is None:
+        level = torch.empty(csr.n, dtype=torch.int32, device=csr.device)
+    for t in (parent, level):
+        if t.dtype != torch.int32 or t.numel() < csr.n or not t.is_contiguous():
+            raise ValueError("parent and level must be contiguous int32 tensors of length n")
+    p = _params(direction, alpha, beta, lane_scan, claim)
+    st = BfsStats()
+    _check(lib.g5_bfs_ex(csr.handle, int(root), parent.data_ptr(), level.data_ptr(),
+                         _stream(csr.device), ctypes.byref(p), ctypes.byref(st)), "g5_bfs")
+    if not stats:
+        return parent, level
+    nl = min(st.nlevels, MAX_STAT_LEVELS)
+    info = {"nlevels": st.nlevels, "dir": list(st.dir[:nl]),
+            "frontier": list(st.frontier[:nl]), "reached": st.reached}
+    return parent, level, info
+
+
+def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None):
+    """Batched BFS from up to 64 roots: (parents int32 [k, n] or None, levels int8 [k, n])."""
+    import torch
+    k = len(roots)
+    arr = (_I64 * max(k, 1))(*[int(r) for r in roots])
+    if levels is None:
+        levels = torch.empty((k, csr.n), dtype=torch.int8, device=csr.device)
+    if parents and parent_out is None:
+        parent_out = torch.empty((k, csr.n), dtype=torch.int32, device=csr.device)
+    pp = parent_out.data_ptr() if parents else None
+    _check(lib.g5_bfs_batch(csr.handle, arr, k, pp, levels.data_ptr(), _stream(csr.device)),
+           "g5_bfs_batch")
+    return (parent_out if parents else None), levels

@@ -1,0 +1,129 @@
+// C-ABI entry points of libg5 (declared in include/g5.h): argument checks,
+// error state and dispatch to the device implementations.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "g5_internal.h"
+
+namespace g5 {
+namespace {
+thread_local std::string t_err;
+}
+void set_error(const std::string &msg) { t_err = msg; }
+}  // namespace g5
+
+using g5::set_error;
+
+extern "C" {
+
+const char *g5_last_error(void) { return g5::t_err.c_str(); }
+
+g5_status g5_build_csr(const int64_t *edges, int64_t m, int64_t n_vertices, void *stream,
+                       g5_csr **out) {
+  if (!out) {
+    set_error("g5_build_csr: out is NULL");
+    return G5_EINVAL;
+  }
+  *out = nullptr;
+  try {
+    return g5::build_csr_impl(edges, m, n_vertices, (hipStream_t)stream, out);
+  } catch (const std::bad_alloc &) {
+    set_error("g5_build_csr: host allocation failed");
+    return G5_ENOMEM;
+  }
+}
+
+g5_status g5_csr_info(const g5_csr *g, int64_t *n, int64_t *nnz, const int64_t **row_ptr,
+                      const int32_t **col_idx) {
+  if (!g) {
+    set_error("g5_csr_info: graph is NULL");
+    return G5_EINVAL;
+  }
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  if (row_ptr) *row_ptr = g->row_ptr;
+  if (col_idx) *col_idx = g->col_idx;
+  return G5_OK;
+}
+
+g5_status g5_csr_copy(const g5_csr *g, int64_t *row_ptr, int32_t *col_idx, void *stream) {
+  if (!g) {
+    set_error("g5_csr_copy: graph is NULL");
+    return G5_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (row_ptr)
+    G5_HIP(hipMemcpyAsync(row_ptr, g->row_ptr, (g->n + 1) * sizeof(int64_t), hipMemcpyDefault, s));
+  if (col_idx && g->nnz)
+    G5_HIP(hipMemcpyAsync(col_idx, g->col_idx, g->nnz * sizeof(int32_t), hipMemcpyDefault, s));
+  G5_HIP(hipStreamSynchronize(s));
+  return G5_OK;
+}
+
+void g5_csr_free(g5_csr *g) {
+  if (!g) return;
+  for (auto *w : g->bfs_pool) delete w;
+  for (auto *w : g->batch_pool) delete w;
+  if (g->row_ptr) (void)hipFree(g->row_ptr);
+  if (g->col_idx) (void)hipFree(g->col_idx);
+  if (g->iso) (void)hipFree(g->iso);
+  delete g;
+}
+
+g5_status g5_bfs_ex(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
+                    void *stream, const g5_bfs_params *params, g5_bfs_stats *stats) {
+  if (!g || !parent || !level) {
+    set_error("g5_bfs: graph, parent and level must be non-NULL");
+    return G5_EINVAL;
+  }
+  if (root < 0 || root >= g->n) {
+    set_error("g5_bfs: root " + std::to_string(root) + " outside [0, " + std::to_string(g->n) +
+              ")");
+    return G5_EINVAL;
+  }
+  g5_bfs_params p;
+  std::memset(&p, 0, sizeof(p));
+  if (params) p = *params;
+  if (p.direction < 0 || p.direction > 2) {
+    set_error("g5_bfs: direction must be 0, 1 or 2");
+    return G5_EINVAL;
+  }
+  try {
+    return g5::bfs_impl(g, root, parent, level, (hipStream_t)stream, p, stats);
+  } catch (const std::bad_alloc &) {
+    set_error("g5_bfs: host allocation failed");
+    return G5_ENOMEM;
+  }
+}
+
+g5_status g5_bfs(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level, void *stream) {
+  return g5_bfs_ex(g, root, parent, level, stream, nullptr, nullptr);
+}
+
+g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
+                       int8_t *levels, void *stream) {
+  if (!g || !roots || !levels) {
+    set_error("g5_bfs_batch: graph, roots and levels must be non-NULL");
+    return G5_EINVAL;
+  }
+  if (k < 1 || k > 64) {
+    set_error("g5_bfs_batch: k must be in [1, 64]");
+    return G5_EINVAL;
+  }
+  for (int i = 0; i < k; ++i)
+    if (roots[i] < 0 || roots[i] >= g->n) {
+      set_error("g5_bfs_batch: root " + std::to_string(roots[i]) + " outside [0, n)");
+      return G5_EINVAL;
+    }
+  try {
+    return g5::bfs_batch_impl(g, roots, k, parents, levels, (hipStream_t)stream);
+  } catch (const std::bad_alloc &) {
+    set_error("g5_bfs_batch: host allocation failed");
+    return G5_ENOMEM;
+  }
+}
+
+}  // extern "C"

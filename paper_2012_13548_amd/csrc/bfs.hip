@@ -1,0 +1,600 @@
+// Kernel 2 of the paper (Section 2.3): level-synchronous breadth-first search
+// from one root, direction-optimising.
+//
+// Level synchronisation (Section 2.3.2): every level is a separate set of
+// kernel launches, so a level's claims finish before the next level reads
+// them; a vertex takes the level of the first level that reaches it.  The
+// paper's parallel BFS processes a level in two phases (gather the level's
+// neighbours, then update); the top-down step here does the same with one
+// edge per lane after a prefix sum of frontier degrees.
+//
+//   top-down  (paper's parallel BFS): frontier queue Q -> degree prefix sum ->
+//             every edge of Q gets one lane (each block owns 1024 consecutive
+//             edges, so hubs are split across blocks and small rows are packed
+//             together) -> claim the neighbour with an atomic on the visited
+//             bitmap (or a compare-and-swap on parent) -> compact winners into
+//             Q' by ballot + LDS prefix + one global atomic per block.
+//   bottom-up (Beamer, Asanovic, Patterson, SC'12): one lane per unvisited
+//             vertex (a wavefront covers one 64-bit visited word); scan the
+//             row until a neighbour in the frontier bitmap is found; the ballot
+//             of finders is the next-frontier word, written without atomics.
+//   switch    top-down -> bottom-up when m_f > m_u / alpha; back when
+//             n_f < n / beta and the frontier shrinks.
+#include <algorithm>
+
+#include "g5_internal.h"
+
+namespace g5 {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kDegItems = 4;
+constexpr int kDegTile = kBlock * kDegItems;  // frontier entries per degree block
+constexpr int kTdItems = 4;
+constexpr int kTdTile = kBlock * kTdItems;    // edges per top-down block
+constexpr int kScanBlock = 1024;
+
+// Device counters of one traversal (uint64 slots of BfsWork::ctr).
+enum Ctr : int {
+  C_QLEN0 = 0,  // length of queue 0
+  C_QLEN1 = 1,  // length of queue 1
+  C_MF = 2,     // degree sum of the scanned frontier queue
+  C_NNEW = 3,   // vertices found by a bottom-up step
+  C_MNEW = 4,   // their degree sum
+  C_RDEG = 5,   // degree of the root
+  C_ERR = 6,    // nonzero if a kernel met an impossible state
+  C_NCTR = 8
+};
+
+__global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ parent, int64_t n,
+                           uint64_t *__restrict__ vis, const uint64_t *__restrict__ iso,
+                           int64_t words, bool vec) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t n4 = vec ? n / 4 : 0;
+  int4 m1 = make_int4(-1, -1, -1, -1);
+  for (int64_t i = t; i < n4; i += stride) {
+    reinterpret_cast<int4 *>(level)[i] = m1;
+    reinterpret_cast<int4 *>(parent)[i] = m1;
+  }
+  for (int64_t i = n4 * 4 + t; i < n; i += stride) {
+    level[i] = -1;
+    parent[i] = -1;
+  }
+  for (int64_t i = t; i < words; i += stride) vis[i] = iso[i];
+}
+
+__global__ void k_bfs_seed(int64_t root, int32_t *level, int32_t *parent, uint64_t *vis,
+                           int32_t *q0, unsigned long long *ctr, const int64_t *rp) {
+  level[root] = 0;
+  parent[root] = (int32_t)root;
+  vis[root >> 6] |= 1ull << (root & 63);
+  q0[0] = (int32_t)root;
+  ctr[C_QLEN0] = 1;
+  ctr[C_QLEN1] = 0;
+  ctr[C_RDEG] = (unsigned long long)(rp[root + 1] - rp[root]);
+}
+
+__global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
+}
+
+// Degrees of Q[b*1024 .. +1024): block-local exclusive prefix into qoff,
+// block total into bsum[b].
+__global__ __launch_bounds__(kBlock) void k_td_deg(const int32_t *__restrict__ q, int64_t qlen,
+                                                   const int64_t *__restrict__ rp,
+                                                   uint32_t *__restrict__ qoff,
+                                                   uint32_t *__restrict__ bsum) {
+  __shared__ uint32_t s[kBlock / kWave];
+  int64_t b = (int64_t)blockIdx.x * kDegTile + (int64_t)threadIdx.x * kDegItems;
+  uint32_t d[kDegItems];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < kDegItems; ++j) {
+    int64_t i = b + j;
+    d[j] = 0;
+    if (i < qlen) {
+      int32_t u = q[i];
+      d[j] = (uint32_t)(rp[u + 1] - rp[u]);
+    }
+    sum += d[j];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan<kBlock, uint32_t>(sum, s, tot);
+#pragma unroll
+  for (int j = 0; j < kDegItems; ++j) {
+    int64_t i = b + j;
+    if (i < qlen) qoff[i] = run;
+    run += d[j];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// In-place exclusive scan of bsum[0..len) (single block); total -> *out.
+__global__ __launch_bounds__(kScanBlock) void k_scan_bsum(uint32_t *__restrict__ bsum,
+                                                          int64_t len,
+                                                          unsigned long long *__restrict__ out) {
+  __shared__ uint32_t s[kScanBlock / kWave];
+  int64_t per = (len + kScanBlock - 1) / kScanBlock;
+  int64_t b = per * threadIdx.x, e = std::min<int64_t>(b + per, len);
+  uint32_t sum = 0;
+  for (int64_t i = b; i < e; ++i) sum += bsum[i];
+  uint32_t tot;
+  uint32_t run = block_excl_scan<kScanBlock, uint32_t>(sum, s, tot);
+  for (int64_t i = b; i < e; ++i) {
+    uint32_t x = bsum[i];
+    bsum[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) *out = tot;
+}
+
+// qoff[i] += bsum[i / 1024]; qoff[qlen] = total.
+__global__ void k_td_fix(uint32_t *__restrict__ qoff, int64_t qlen,
+                         const uint32_t *__restrict__ bsum,
+                         const unsigned long long *__restrict__ total) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= qlen; i += stride)
+    qoff[i] = (i == qlen) ? (uint32_t)*total : qoff[i] + bsum[i / kDegTile];
+}
+
+// Largest i in [0, len) with off[i] <= e (off non-decreasing, off[0] = 0 <= e):
+// a 256-way search, one probe per thread per round.
+__device__ int64_t block_search(const uint32_t *__restrict__ off, int64_t len, uint32_t e) {
+  int64_t lo = 0, hi = len;
+  while (true) {
+    int64_t span = hi - lo;
+    if (span <= kBlock) {
+      int64_t p = lo + threadIdx.x;
+      int c = __syncthreads_count(p < hi && off[p] <= e);
+      return lo + c - 1;
+    }
+    int64_t p = lo + (span * (int64_t)threadIdx.x) / kBlock;
+    int c = __syncthreads_count(off[p] <= e);
+    int64_t nlo = lo + (span * (int64_t)(c - 1)) / kBlock;
+    int64_t nhi = (c < kBlock) ? lo + (span * (int64_t)c) / kBlock : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+}
+
+enum Claim : int { CLAIM_OR = 0, CLAIM_CAS = 1 };
+
+template <int CLAIM>
+__global__ __launch_bounds__(kBlock) void k_td_expand(
+    const int32_t *__restrict__ q, int64_t qlen, const uint32_t *__restrict__ qoff,
+    uint32_t total, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    uint64_t *vis, int32_t *parent, int32_t *__restrict__ level, int32_t *__restrict__ qn,
+    unsigned long long *__restrict__ qn_len, int32_t next_level,
+    unsigned long long *__restrict__ err) {
+  __shared__ uint32_t s_off[kTdTile + 1];
+  __shared__ int32_t s_src[kTdTile];
+  __shared__ int64_t s_base[kTdTile];
+  __shared__ int32_t s_out[kTdTile];
+  __shared__ uint32_t s_cnt;
+  __shared__ unsigned long long s_gbase;
+  const uint32_t e0 = blockIdx.x * (uint32_t)kTdTile;
+  if (e0 >= total) return;
+  const uint32_t e1 = (uint32_t)std::min<uint64_t>((uint64_t)e0 + kTdTile, total);
+  const int64_t i0 = block_search(qoff, qlen, e0);
+  const int64_t i1 = block_search(qoff, qlen, e1 - 1);
+  const int S = (int)(i1 - i0 + 1);
+  if (S > kTdTile) {  // only degree-0 vertices could do this, and none are queued
+    if (threadIdx.x == 0) atomicOr(err, 1ull);
+    return;
+  }
+  for (int k = threadIdx.x; k < S; k += kBlock) {
+    uint32_t o = qoff[i0 + k];
+    int32_t u = q[i0 + k];
+    s_off[k] = o;
+    s_src[k] = u;
+    s_base[k] = rp[u] - (int64_t)o;
+  }
+  if (threadIdx.x == 0) {
+    s_off[S] = qoff[i1 + 1];
+    s_cnt = 0;
+  }
+  __syncthreads();
+  const int lane = __lane_id();
+  const uint64_t lt = lanemask_lt();
+  int klo = 0;
+#pragma unroll
+  for (int j = 0; j < kTdItems; ++j) {
+    uint32_t e = e0 + j * kBlock + threadIdx.x;
+    bool won = false;
+    int32_t v = 0;
+    if (e < e1) {
+      int lo = klo, hi = S;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= e)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      klo = lo;
+      v = ci[s_base[lo] + (int64_t)e];
+      int32_t u = s_src[lo];
+      uint64_t bit = 1ull << (v & 63);
+      uint64_t *wp = vis + (v >> 6);
+      if (!(*wp & bit)) {
+        if (CLAIM == CLAIM_OR) {
+          won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
+          if (won) parent[v] = u;
+        } else {
+          won = atomicCAS(parent + v, -1, u) == -1;
+          if (won) atomicOr((unsigned long long *)wp, (unsigned long long)bit);
+        }
+        if (won) level[v] = next_level;
+      }
+    }
+    uint64_t bal = __ballot(won);
+    if (bal) {
+      uint32_t wbase = 0;
+      if (lane == 0) wbase = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
+      wbase = __shfl(wbase, 0, kWave);
+      if (won) s_out[wbase + __popcll(bal & lt)] = v;
+    }
+  }
+  __syncthreads();
+  const uint32_t cnt = s_cnt;
+  if (cnt == 0) return;
+  if (threadIdx.x == 0) s_gbase = atomicAdd(qn_len, (unsigned long long)cnt);
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) qn[s_gbase + k] = s_out[k];
+}
+
+// Frontier queue -> frontier bitmap (bitmap cleared beforehand).
+__global__ void k_q2front(const int32_t *__restrict__ q, int64_t qlen, uint64_t *front) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qlen; i += stride) {
+    int32_t v = q[i];
+    atomicOr((unsigned long long *)(front + (v >> 6)), 1ull << (v & 63));
+  }
+}
+
+// Bottom-up step.  Wavefront per 64-bit word w of the visited bitmap; lane l
+// owns vertex 64w+l.  A lane first tests LANE_SCAN neighbours itself (loads
+// issued together); rows still unresolved are then scanned by the whole
+// wavefront, 64 neighbours per step, one row at a time.
+template <int LANE_SCAN>
+__global__ __launch_bounds__(kBlock) void k_bu_step(
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, uint64_t *__restrict__ vis,
+    const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
+    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
+    int32_t next_level, unsigned long long *__restrict__ ctr) {
+  __shared__ uint64_t s[kBlock / kWave];
+  const int lane = __lane_id();
+  const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
+  uint64_t nnew = 0, mnew = 0;
+  for (int64_t w = gw; w < words; w += nw) {
+    const uint64_t vw = vis[w];
+    if (vw == ~0ull) {
+      if (lane == 0) next[w] = 0;
+      continue;
+    }
+    const int64_t v = w * kWave + lane;
+    const bool pending = !((vw >> lane) & 1);  // padding lanes past n are pre-set in iso
+    int64_t b = 0, e = 0, k = 0;
+    bool found = false;
+    int32_t par = -1;
+    if (pending) {
+      b = rp[v];
+      e = rp[v + 1];
+      k = b;
+      int32_t u[LANE_SCAN];
+      uint64_t fw[LANE_SCAN];
+#pragma unroll
+      for (int t = 0; t < LANE_SCAN; ++t) u[t] = (k + t < e) ? ci[k + t] : -1;
+#pragma unroll
+      for (int t = 0; t < LANE_SCAN; ++t) fw[t] = (u[t] >= 0) ? front[u[t] >> 6] : 0;
+#pragma unroll
+      for (int t = 0; t < LANE_SCAN; ++t) {
+        if (!found && u[t] >= 0 && ((fw[t] >> (u[t] & 63)) & 1)) {
+          found = true;
+          par = u[t];
+        }
+      }
+      k = std::min<int64_t>(k + LANE_SCAN, e);
+    }
+    uint64_t rem = __ballot(pending && !found && k < e);
+    while (rem) {
+      const int L = __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1;
+      const int64_t kb = __shfl(k, L, kWave), ke = __shfl(e, L, kWave);
+      int32_t got = -1;
+      for (int64_t c = kb; c < ke; c += kWave) {
+        int64_t kk = c + lane;
+        bool hit = false;
+        int32_t u = -1;
+        if (kk < ke) {
+          u = ci[kk];
+          hit = (front[u >> 6] >> (u & 63)) & 1;
+        }
+        uint64_t hm = __ballot(hit);
+        if (hm) {
+          got = __shfl(u, __ffsll((unsigned long long)hm) - 1, kWave);
+          break;
+        }
+      }
+      if (lane == L && got >= 0) {
+        found = true;
+        par = got;
+      }
+    }
+    const uint64_t fm = __ballot(found);
+    if (found) {
+      parent[v] = par;
+      level[v] = next_level;
+      mnew += (uint64_t)(e - b);
+    }
+    if (lane == 0) {
+      next[w] = fm;
+      if (fm) vis[w] = vw | fm;
+      nnew += (uint64_t)__popcll(fm);
+    }
+  }
+  uint64_t tn = block_sum<kBlock, uint64_t>(nnew, s);
+  uint64_t tm = block_sum<kBlock, uint64_t>(mnew, s);
+  if (threadIdx.x == 0) {
+    if (tn) atomicAdd(ctr + C_NNEW, (unsigned long long)tn);
+    if (tm) atomicAdd(ctr + C_MNEW, (unsigned long long)tm);
+  }
+}
+
+// Bitmap -> queue in vertex order: block b owns words [b*chunk, (b+1)*chunk).
+__global__ __launch_bounds__(kBlock) void k_front_count(const uint64_t *__restrict__ bm,
+                                                        int64_t words, int64_t chunk,
+                                                        uint32_t *__restrict__ bsum) {
+  __shared__ uint32_t s[kBlock / kWave];
+  int64_t b = (int64_t)blockIdx.x * chunk, e = std::min<int64_t>(b + chunk, words);
+  uint32_t c = 0;
+  for (int64_t w = b + threadIdx.x; w < e; w += kBlock) c += (uint32_t)__popcll(bm[w]);
+  uint32_t tot = block_sum<kBlock, uint32_t>(c, s);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_front_write(const uint64_t *__restrict__ bm,
+                                                        int64_t words, int64_t chunk,
+                                                        const uint32_t *__restrict__ boff,
+                                                        int32_t *__restrict__ q) {
+  __shared__ uint32_t s[kBlock / kWave];
+  int64_t b = (int64_t)blockIdx.x * chunk, e = std::min<int64_t>(b + chunk, words);
+  uint32_t base = boff[blockIdx.x];
+  for (int64_t w0 = b; w0 < e; w0 += kBlock) {
+    int64_t w = w0 + threadIdx.x;
+    uint64_t x = (w < e) ? bm[w] : 0;
+    uint32_t tot;
+    uint32_t pos = base + block_excl_scan<kBlock, uint32_t>((uint32_t)__popcll(x), s, tot);
+    while (x) {
+      int bit = __ffsll((unsigned long long)x) - 1;
+      x &= x - 1;
+      q[pos++] = (int32_t)(w * kWave + bit);
+    }
+    base += tot;
+  }
+}
+
+int grid_for(int64_t items, int per_block, int cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+g5_status alloc_work(const g5_csr *g, BfsWork **out) {
+  BfsWork *w = new BfsWork();
+  w->n = g->n;
+  w->words = g->words;
+  int64_t n = g->n, W = g->words;
+  int64_t nb = (n + kDegTile - 1) / kDegTile + 1;
+  int64_t nbf = (int64_t)g->num_cu * 8 + 1;
+  hipError_t e = hipSuccess;
+  auto A = [&](void **p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  A((void **)&w->vis, W * 8);
+  A((void **)&w->front, W * 8);
+  A((void **)&w->next, W * 8);
+  A((void **)&w->q[0], n * 4);
+  A((void **)&w->q[1], n * 4);
+  A((void **)&w->qoff, (n + 1) * 4);
+  A((void **)&w->bsum, std::max(nb, nbf) * 4);
+  A((void **)&w->ctr, C_NCTR * 8);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&w->host_ctr, C_NCTR * 8, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_error(std::string("g5_bfs workspace: ") + hipGetErrorString(e));
+    delete w;
+    return e == hipErrorOutOfMemory ? G5_ENOMEM : G5_EDEVICE;
+  }
+  *out = w;
+  return G5_OK;
+}
+
+struct WorkLease {
+  const g5_csr *g;
+  BfsWork *w = nullptr;
+  ~WorkLease() {
+    if (w) {
+      std::lock_guard<std::mutex> lk(g->mu);
+      g->bfs_pool.push_back(w);
+    }
+  }
+};
+
+}  // namespace
+
+BfsWork::~BfsWork() {
+  if (vis) (void)hipFree(vis);
+  if (front) (void)hipFree(front);
+  if (next) (void)hipFree(next);
+  if (q[0]) (void)hipFree(q[0]);
+  if (q[1]) (void)hipFree(q[1]);
+  if (qoff) (void)hipFree(qoff);
+  if (bsum) (void)hipFree(bsum);
+  if (ctr) (void)hipFree(ctr);
+  if (host_ctr) (void)hipHostFree(host_ctr);
+}
+
+g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
+                   hipStream_t s, const g5_bfs_params &p, g5_bfs_stats *stats) {
+  WorkLease lease{g};
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->bfs_pool.empty()) {
+      lease.w = g->bfs_pool.back();
+      g->bfs_pool.pop_back();
+    }
+  }
+  if (!lease.w) {
+    g5_status st = alloc_work(g, &lease.w);
+    if (st != G5_OK) return st;
+  }
+  BfsWork &w = *lease.w;
+  const int64_t n = g->n, W = g->words;
+  const int ncu = g->num_cu;
+  const double alpha = p.alpha > 0 ? p.alpha : 14.0;
+  const double beta = p.beta > 0 ? p.beta : 24.0;
+  const int lane_scan = p.bu_lane_scan > 0 ? p.bu_lane_scan : 4;
+  unsigned long long *ctr = (unsigned long long *)w.ctr;
+  uint64_t *hc = w.host_ctr;
+  const int bu_grid = ncu * 8;
+
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, w.ctr, (int64_t)C_NCTR);
+  hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
+                     dim3(kBlock), 0, s, level, parent, n, w.vis, g->iso, W,
+                     (((uintptr_t)level | (uintptr_t)parent) & 15) == 0);
+  hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, root, level, parent, w.vis, w.q[0], ctr,
+                     g->row_ptr);
+  G5_LAUNCH_CHECK();
+
+  int cur = 0;              // queue holding the current frontier (top-down)
+  int64_t qlen = 1;
+  bool q_deg_counted = true;  // degree of the root is excluded from m_u below
+  bool first = true;
+  int dir = 1;              // 1 top-down, 2 bottom-up
+  int64_t m_u = -1;         // edges (directed entries) of unvisited vertices
+  int64_t nf_prev = 0;
+  int32_t lvl = 0;
+  int64_t reached = 1;
+  uint64_t *front = w.front, *next = w.next;
+  if (stats) *stats = g5_bfs_stats{};
+
+  auto record = [&](int d, int64_t nf) {
+    if (stats) {
+      if (lvl < G5_MAX_STAT_LEVELS) {
+        stats->dir[lvl] = d;
+        stats->frontier[lvl] = nf;
+      }
+      stats->nlevels = lvl + 1;
+    }
+  };
+
+  while (true) {
+    if (dir == 1) {
+      if (qlen == 0) break;
+      // degree prefix sum of the frontier queue
+      const int64_t nb = (qlen + kDegTile - 1) / kDegTile;
+      hipLaunchKernelGGL(k_td_deg, dim3(nb), dim3(kBlock), 0, s, w.q[cur], qlen, g->row_ptr,
+                         w.qoff, w.bsum);
+      hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, s, w.bsum, nb, ctr + C_MF);
+      hipLaunchKernelGGL(k_td_fix, dim3(grid_for(qlen + 1, kBlock, ncu * 16)), dim3(kBlock), 0,
+                         s, w.qoff, qlen, w.bsum, (const unsigned long long *)(ctr + C_MF));
+      G5_LAUNCH_CHECK();
+      G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
+      G5_HIP(hipStreamSynchronize(s));
+      const int64_t mf = (int64_t)hc[C_MF];
+      if (first) {
+        m_u = g->nnz - (int64_t)hc[C_RDEG];
+        first = false;
+      } else if (!q_deg_counted) {
+        m_u -= mf;
+      }
+      q_deg_counted = false;
+      bool to_bu = (p.direction == G5_DIR_BOTTOMUP) ||
+                   (p.direction == G5_DIR_AUTO && (double)mf > (double)m_u / alpha);
+      if (to_bu) {
+        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0, s,
+                           front, W);
+        hipLaunchKernelGGL(k_q2front, dim3(grid_for(qlen, kBlock, ncu * 16)), dim3(kBlock), 0, s,
+                           w.q[cur], qlen, front);
+        G5_LAUNCH_CHECK();
+        dir = 2;
+        nf_prev = qlen;
+        continue;  // this level runs bottom-up
+      }
+      record(1, qlen);
+      const int nxt = cur ^ 1;
+      G5_HIP(hipMemsetAsync(ctr + nxt, 0, 8, s));
+      if (mf > 0) {
+        const int64_t tb = (mf + kTdTile - 1) / kTdTile;
+        if (p.reserved[0] == CLAIM_CAS)
+          hipLaunchKernelGGL(k_td_expand<CLAIM_CAS>, dim3(tb), dim3(kBlock), 0, s, w.q[cur], qlen,
+                             w.qoff, (uint32_t)mf, g->row_ptr, g->col_idx, w.vis, parent, level,
+                             w.q[nxt], ctr + nxt, lvl + 1, ctr + C_ERR);
+        else
+          hipLaunchKernelGGL(k_td_expand<CLAIM_OR>, dim3(tb), dim3(kBlock), 0, s, w.q[cur], qlen,
+                             w.qoff, (uint32_t)mf, g->row_ptr, g->col_idx, w.vis, parent, level,
+                             w.q[nxt], ctr + nxt, lvl + 1, ctr + C_ERR);
+        G5_LAUNCH_CHECK();
+      }
+      G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
+      G5_HIP(hipStreamSynchronize(s));
+      if (hc[C_ERR]) {
+        set_error("g5_bfs: top-down tile met more frontier rows than edges");
+        return G5_EDEVICE;
+      }
+      cur = nxt;
+      qlen = (int64_t)hc[nxt];
+      reached += qlen;
+      ++lvl;
+    } else {
+      record(2, nf_prev);
+      G5_HIP(hipMemsetAsync(ctr + C_NNEW, 0, 16, s));
+#define G5_BU(K)                                                                           \
+  hipLaunchKernelGGL(k_bu_step<K>, dim3(bu_grid), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, \
+                     w.vis, front, next, parent, level, n, W, lvl + 1, ctr)
+      switch (lane_scan) {
+        case 1: G5_BU(1); break;
+        case 2: G5_BU(2); break;
+        case 8: G5_BU(8); break;
+        case 16: G5_BU(16); break;
+        default: G5_BU(4); break;
+      }
+#undef G5_BU
+      G5_LAUNCH_CHECK();
+      G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
+      G5_HIP(hipStreamSynchronize(s));
+      const int64_t nnew = (int64_t)hc[C_NNEW];
+      m_u -= (int64_t)hc[C_MNEW];
+      reached += nnew;
+      ++lvl;
+      if (nnew == 0) break;
+      bool to_td = p.direction == G5_DIR_TOPDOWN ||
+                   (p.direction == G5_DIR_AUTO && (double)nnew < (double)n / beta &&
+                    nnew < nf_prev);
+      nf_prev = nnew;
+      std::swap(front, next);  // `front` now holds the new frontier
+      if (to_td) {
+        const int64_t chunk = (W + bu_grid - 1) / bu_grid;
+        const int fb = (int)((W + chunk - 1) / chunk);
+        hipLaunchKernelGGL(k_front_count, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum);
+        hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, s, w.bsum, (int64_t)fb,
+                           ctr + cur);
+        hipLaunchKernelGGL(k_front_write, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum,
+                           w.q[cur]);
+        G5_LAUNCH_CHECK();
+        qlen = nnew;
+        q_deg_counted = true;
+        dir = 1;
+      }
+    }
+  }
+  if (stats) stats->reached = reached;
+  G5_HIP(hipStreamSynchronize(s));
+  return G5_OK;
+}
+
+}  // namespace g5

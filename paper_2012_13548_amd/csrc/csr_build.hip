@@ -1,0 +1,376 @@
+// Kernel 1 of the paper (Section 2.2, CSR format; parallel CSR by a parallel
+// sort is the direction named in Section 4.2): build the undirected CSR of a
+// tuple list on the device.
+//
+//   pack      each non-loop tuple (u, v) -> keys (u << sb | v) and (v << sb | u);
+//             self-loops and out-of-range ids -> SENT (sorts last)
+//   sort      LSD radix sort of the 2*sb-bit keys, 8-bit digits, stable ranking
+//             by wavefront match (8 ballots per digit) and LDS counters
+//   compact   keep the first of each run of equal keys -> col_idx; the source of
+//             each kept key opens rows (prev_source, source] -> row_ptr, so an
+//             empty row repeats the next index; rows after the last key get nnz
+//   iso       bitmap of degree-0 vertices (used by the traversal to skip them)
+#include <algorithm>
+
+#include "g5_internal.h"
+
+namespace g5 {
+namespace {
+
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortBlock * kSortItems;  // 2048 keys
+constexpr int kWaveKeys = kWave * kSortItems;       // 512 keys per wavefront
+constexpr int kRadix = 256;
+constexpr int kMaxSortBlocks = 2048;
+constexpr int kScanBlock = 1024;
+constexpr int kCompactBlock = 256;
+constexpr int kCompactItems = 16;
+constexpr int kCompactTile = kCompactBlock * kCompactItems;  // 4096 keys
+
+__global__ __launch_bounds__(256) void k_pack(const int64_t *__restrict__ edges, int64_t m,
+                                              int64_t n, int sb, uint64_t sent,
+                                              uint64_t *__restrict__ keys,
+                                              uint32_t *__restrict__ err) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    longlong2 t = reinterpret_cast<const longlong2 *>(edges)[i];
+    uint64_t k0 = sent, k1 = sent;
+    if (t.x < 0 || t.x >= n || t.y < 0 || t.y >= n) {
+      bad = true;
+    } else if (t.x != t.y) {
+      k0 = ((uint64_t)t.x << sb) | (uint64_t)t.y;
+      k1 = ((uint64_t)t.y << sb) | (uint64_t)t.x;
+    }
+    ulonglong2 o;
+    o.x = k0;
+    o.y = k1;
+    reinterpret_cast<ulonglong2 *>(keys)[i] = o;
+  }
+  if (__ballot(bad) != 0 && __lane_id() == 0) atomicOr(err, 1u);
+}
+
+// Per-block digit histogram of the block's contiguous run of tiles.
+__global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(
+    const uint64_t *__restrict__ keys, uint64_t nkeys, int shift, int64_t tiles_per_block,
+    int nblocks, uint32_t *__restrict__ counts) {
+  __shared__ uint32_t hist[4][kRadix];
+  const int w = threadIdx.x / kWave;
+  for (int i = threadIdx.x; i < 4 * kRadix; i += kSortBlock) (&hist[0][0])[i] = 0;
+  __syncthreads();
+  uint64_t beg = (uint64_t)blockIdx.x * tiles_per_block * kSortTile;
+  uint64_t end = beg + (uint64_t)tiles_per_block * kSortTile;
+  if (end > nkeys) end = nkeys;
+  uint64_t i = beg + threadIdx.x;
+  for (; i + 3 * kSortBlock < end; i += 4 * kSortBlock) {
+    uint64_t a = keys[i], b = keys[i + kSortBlock], c = keys[i + 2 * kSortBlock],
+             d = keys[i + 3 * kSortBlock];
+    atomicAdd(&hist[w][(a >> shift) & 0xFF], 1u);
+    atomicAdd(&hist[w][(b >> shift) & 0xFF], 1u);
+    atomicAdd(&hist[w][(c >> shift) & 0xFF], 1u);
+    atomicAdd(&hist[w][(d >> shift) & 0xFF], 1u);
+  }
+  for (; i < end; i += kSortBlock) atomicAdd(&hist[w][(keys[i] >> shift) & 0xFF], 1u);
+  __syncthreads();
+  int d = threadIdx.x;  // kSortBlock == kRadix
+  counts[(int64_t)d * nblocks + blockIdx.x] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+}
+
+// Exclusive scan of a uint32 array into uint64 (single block); *total = sum.
+__global__ __launch_bounds__(kScanBlock) void k_scan_u32(const uint32_t *__restrict__ in,
+                                                        uint64_t *__restrict__ out,
+                                                        int64_t len,
+                                                        uint64_t *__restrict__ total) {
+  __shared__ uint64_t s[kScanBlock / kWave];
+  int64_t per = (len + kScanBlock - 1) / kScanBlock;
+  int64_t b = per * threadIdx.x, e = std::min<int64_t>(b + per, len);
+  uint64_t sum = 0;
+  for (int64_t i = b; i < e; ++i) sum += in[i];
+  uint64_t tot;
+  uint64_t run = block_excl_scan<kScanBlock, uint64_t>(sum, s, tot);
+  for (int64_t i = b; i < e; ++i) {
+    uint64_t x = in[i];
+    out[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
+// Stable scatter of one 8-bit digit.  Wavefront w of a tile owns keys
+// [w*512, (w+1)*512) in 8 steps of 64; a key's rank inside its wavefront is
+// the count of equal digits in earlier steps (LDS counter) plus earlier lanes
+// of its step (match mask from 8 ballots).
+__global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
+    const uint64_t *__restrict__ kin, uint64_t *__restrict__ kout, uint64_t nkeys, int shift,
+    int64_t tiles_per_block, int nblocks, const uint64_t *__restrict__ offs) {
+  __shared__ uint64_t base[kRadix];
+  __shared__ uint32_t wh[4][kRadix];
+  __shared__ uint32_t ttot[kRadix];
+  const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
+  base[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+  const uint64_t lt = lanemask_lt();
+  int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+  for (int64_t t = t0; t < t0 + tiles_per_block; ++t) {
+    uint64_t tbase = (uint64_t)t * kSortTile;
+    if (tbase >= nkeys) break;
+    for (int d = lane; d < kRadix; d += kWave) wh[w][d] = 0;
+    uint64_t key[kSortItems];
+    uint32_t rank[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      uint64_t idx = tbase + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
+      bool valid = idx < nkeys;
+      uint64_t k = valid ? kin[idx] : 0;
+      uint32_t d = (uint32_t)(k >> shift) & 0xFF;
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        uint64_t bal = __ballot((d >> b) & 1);
+        peers &= ((d >> b) & 1) ? bal : ~bal;
+      }
+      int leader = peers ? (__ffsll((unsigned long long)peers) - 1) : 0;
+      uint32_t old = 0;
+      if (valid && lane == leader) old = atomicAdd(&wh[w][d], (uint32_t)__popcll(peers));
+      old = __shfl(old, leader, kWave);
+      rank[j] = old + (uint32_t)__popcll(peers & lt);
+      key[j] = k;
+    }
+    __syncthreads();
+    {
+      uint32_t s = 0;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        uint32_t c = wh[ww][tid];
+        wh[ww][tid] = s;
+        s += c;
+      }
+      ttot[tid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      uint64_t idx = tbase + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
+      if (idx < nkeys) {
+        uint32_t d = (uint32_t)(key[j] >> shift) & 0xFF;
+        uint64_t pos = base[d] + wh[w][d] + rank[j];
+        if (pos < nkeys) kout[pos] = key[j];
+      }
+    }
+    __syncthreads();
+    base[tid] += ttot[tid];
+    __syncthreads();
+  }
+}
+
+__global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
+
+__device__ __forceinline__ bool is_head(const uint64_t *keys, uint64_t i, uint64_t sent) {
+  uint64_t k = keys[i];
+  return k != sent && (i == 0 || keys[i - 1] != k);
+}
+
+// Distinct keys per compaction tile (thread t owns 16 consecutive keys).
+__global__ __launch_bounds__(kCompactBlock) void k_heads_count(const uint64_t *__restrict__ keys,
+                                                               uint64_t nkeys, uint64_t sent,
+                                                               uint32_t *__restrict__ bsum) {
+  __shared__ uint32_t s[kCompactBlock / kWave];
+  uint64_t b = (uint64_t)blockIdx.x * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
+  uint32_t c = 0;
+  for (int j = 0; j < kCompactItems; ++j) {
+    uint64_t i = b + j;
+    if (i < nkeys && is_head(keys, i, sent)) ++c;
+  }
+  uint32_t tot = block_sum<kCompactBlock, uint32_t>(c, s);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kCompactBlock) void k_compact(
+    const uint64_t *__restrict__ keys, uint64_t nkeys, uint64_t sent, int sb, int64_t n,
+    const uint64_t *__restrict__ boff, int32_t *__restrict__ col_idx,
+    int64_t *__restrict__ row_ptr) {
+  __shared__ uint32_t s[kCompactBlock / kWave];
+  uint64_t b = (uint64_t)blockIdx.x * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
+  uint32_t c = 0;
+  for (int j = 0; j < kCompactItems; ++j) {
+    uint64_t i = b + j;
+    if (i < nkeys && is_head(keys, i, sent)) ++c;
+  }
+  uint32_t tot;
+  uint64_t pos = boff[blockIdx.x] + block_excl_scan<kCompactBlock, uint32_t>(c, s, tot);
+  const uint64_t vmask = (1ull << sb) - 1;
+  for (int j = 0; j < kCompactItems; ++j) {
+    uint64_t i = b + j;
+    if (i >= nkeys) break;
+    uint64_t k = keys[i];
+    uint64_t prev = i ? keys[i - 1] : sent;
+    int64_t up = i ? (int64_t)(prev >> sb) : -1;
+    if (k != sent) {
+      if (i == 0 || prev != k) {
+        col_idx[pos] = (int32_t)(k & vmask);
+        int64_t u = std::min<int64_t>((int64_t)(k >> sb), n - 1);
+        for (int64_t r = up + 1; r <= u; ++r) row_ptr[r] = (int64_t)pos;
+        ++pos;
+      }
+    } else if (i == 0 || prev != sent) {
+      // first sentinel: rows after the last stored key are empty
+      for (int64_t r = up + 1; r <= n; ++r) row_ptr[r] = (int64_t)pos;
+    }
+  }
+}
+
+// iso[w] bit l = vertex 64w+l has degree 0 (or lies past n).
+__global__ __launch_bounds__(256) void k_iso(const int64_t *__restrict__ rp, int64_t n,
+                                             int64_t words, uint64_t *__restrict__ iso,
+                                             unsigned long long *__restrict__ nonisolated) {
+  __shared__ uint64_t s[4];
+  int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  uint64_t cnt = 0;
+  for (int64_t w = gw; w < words; w += nw) {
+    int64_t v = w * kWave + __lane_id();
+    bool d0 = v >= n || rp[v + 1] == rp[v];
+    uint64_t mk = __ballot(d0);
+    if (__lane_id() == 0) {
+      iso[w] = mk;
+      cnt += (uint64_t)__popcll(~mk);
+    }
+  }
+  uint64_t tot = block_sum<256, uint64_t>(cnt, s);
+  if (threadIdx.x == 0 && tot) atomicAdd(nonisolated, (unsigned long long)tot);
+}
+
+int grid_cap(int64_t items, int per_block, int cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t s,
+                         g5_csr **out) {
+  *out = nullptr;
+  if (m < 0 || n < 1 || n > 2147483647LL || (m > 0 && !edges)) {
+    set_error("g5_build_csr: need m >= 0, 1 <= n <= 2^31-1 and a non-NULL edge list");
+    return G5_EINVAL;
+  }
+  int dev = 0, ncu = 256;
+  G5_HIP(hipGetDevice(&dev));
+  G5_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+
+  int sb = 1;
+  while ((1ll << sb) < n) ++sb;
+  const int key_bits = 2 * sb;
+  const uint64_t sent = (key_bits >= 64) ? ~0ull : ((1ull << key_bits) - 1);
+  const uint64_t nkeys = 2ull * (uint64_t)m;
+
+  DevBuf ka, kb, counts, offs, misc;
+  G5_HIP(hipMalloc(&ka.p, (nkeys + 1) * sizeof(uint64_t)));
+  G5_HIP(hipMalloc(&kb.p, (nkeys + 1) * sizeof(uint64_t)));
+  G5_HIP(hipMalloc(&misc.p, 64));
+  uint32_t *err = (uint32_t *)misc.p;
+  uint64_t *nnz_dev = (uint64_t *)((char *)misc.p + 8);
+  unsigned long long *noniso_dev = (unsigned long long *)((char *)misc.p + 16);
+  G5_HIP(hipMemsetAsync(misc.p, 0, 64, s));
+  uint64_t *keys = (uint64_t *)ka.p, *alt = (uint64_t *)kb.p;
+
+  if (m > 0) {
+    hipLaunchKernelGGL(k_pack, dim3(grid_cap(m, 256, ncu * 64)), dim3(256), 0, s, edges, m, n,
+                       sb, sent, keys, err);
+    G5_LAUNCH_CHECK();
+    // radix sort
+    int64_t tiles = (int64_t)((nkeys + kSortTile - 1) / kSortTile);
+    int64_t tpb = (tiles + kMaxSortBlocks - 1) / kMaxSortBlocks;
+    int nb = (int)((tiles + tpb - 1) / tpb);
+    G5_HIP(hipMalloc(&counts.p, (size_t)kRadix * nb * sizeof(uint32_t)));
+    G5_HIP(hipMalloc(&offs.p, (size_t)kRadix * nb * sizeof(uint64_t)));
+    for (int shift = 0; shift < key_bits; shift += 8) {
+      hipLaunchKernelGGL(k_radix_upsweep, dim3(nb), dim3(kSortBlock), 0, s, keys, nkeys, shift,
+                         tpb, nb, (uint32_t *)counts.p);
+      hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(kScanBlock), 0, s,
+                         (const uint32_t *)counts.p, (uint64_t *)offs.p,
+                         (int64_t)kRadix * nb, (uint64_t *)nullptr);
+      hipLaunchKernelGGL(k_radix_downsweep, dim3(nb), dim3(kSortBlock), 0, s, keys, alt, nkeys,
+                         shift, tpb, nb, (const uint64_t *)offs.p);
+      G5_LAUNCH_CHECK();
+      std::swap(keys, alt);
+    }
+  }
+  // keys[nkeys] = SENT guarantees a first sentinel for the tail rows
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, keys + nkeys, sent);
+  const uint64_t ntot = nkeys + 1;
+  int64_t cblocks = (int64_t)((ntot + kCompactTile - 1) / kCompactTile);
+  DevBuf cb, cbo;
+  G5_HIP(hipMalloc(&cb.p, cblocks * sizeof(uint32_t)));
+  G5_HIP(hipMalloc(&cbo.p, cblocks * sizeof(uint64_t)));
+  hipLaunchKernelGGL(k_heads_count, dim3(cblocks), dim3(kCompactBlock), 0, s, keys, ntot, sent,
+                     (uint32_t *)cb.p);
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(kScanBlock), 0, s, (const uint32_t *)cb.p,
+                     (uint64_t *)cbo.p, cblocks, nnz_dev);
+  G5_LAUNCH_CHECK();
+  uint64_t hv[2] = {0, 0};
+  uint32_t herr = 0;
+  G5_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
+  G5_HIP(hipMemcpyAsync(hv, nnz_dev, 8, hipMemcpyDeviceToHost, s));
+  G5_HIP(hipStreamSynchronize(s));
+  if (herr) {
+    set_error("g5_build_csr: an edge names a vertex outside [0, n)");
+    return G5_EINVAL;
+  }
+  const uint64_t nnz = hv[0];
+  if (nnz >= (1ull << 32)) {
+    set_error("g5_build_csr: nnz >= 2^32 is not supported");
+    return G5_ERANGE;
+  }
+  // the sort buffer that is not the result is no longer needed
+  if (alt == (uint64_t *)ka.p) {
+    G5_HIP(hipFree(ka.p));
+    ka.p = nullptr;
+  } else {
+    G5_HIP(hipFree(kb.p));
+    kb.p = nullptr;
+  }
+
+  g5_csr *g = new g5_csr();
+  g->n = n;
+  g->nnz = (int64_t)nnz;
+  g->sb = sb;
+  g->device = dev;
+  g->num_cu = ncu;
+  g->words = (n + 63) / 64;
+  auto fail = [&](hipError_t e, const char *what) {
+    set_error(std::string("g5_build_csr: ") + what + ": " + hipGetErrorString(e));
+    g5_csr_free(g);
+    return e == hipErrorOutOfMemory ? G5_ENOMEM : G5_EDEVICE;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&g->row_ptr, (n + 1) * sizeof(int64_t))) != hipSuccess)
+    return fail(e, "row_ptr");
+  if ((e = hipMalloc(&g->col_idx, std::max<uint64_t>(nnz, 1) * sizeof(int32_t))) != hipSuccess)
+    return fail(e, "col_idx");
+  if ((e = hipMalloc(&g->iso, g->words * sizeof(uint64_t))) != hipSuccess)
+    return fail(e, "iso");
+  hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(kCompactBlock), 0, s, keys, ntot, sent, sb,
+                     n, (const uint64_t *)cbo.p, g->col_idx, g->row_ptr);
+  hipLaunchKernelGGL(k_iso, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+                     n, g->words, g->iso, noniso_dev);
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+  unsigned long long noniso = 0;
+  if ((e = hipMemcpyAsync(&noniso, noniso_dev, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+  g->nonisolated = (int64_t)noniso;
+  *out = g;
+  return G5_OK;
+}
+
+}  // namespace g5

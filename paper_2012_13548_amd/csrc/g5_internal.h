@@ -1,0 +1,145 @@
+// Internal declarations of the g5 library: the graph object, error state and
+// wave-level device helpers for gfx950 (64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "g5.h"
+
+namespace g5 {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+
+#define G5_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      ::g5::set_error(std::string(#call) + ": " + hipGetErrorString(e_));             \
+      return e_ == hipErrorOutOfMemory ? G5_ENOMEM : G5_EDEVICE;                      \
+    }                                                                                 \
+  } while (0)
+
+#define G5_LAUNCH_CHECK()                                                             \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess) {                                                           \
+      ::g5::set_error(std::string("kernel launch: ") + hipGetErrorString(e_));       \
+      return G5_EDEVICE;                                                              \
+    }                                                                                 \
+  } while (0)
+
+// ---------------------------------------------------------------- workspaces
+// Device state of one single-root traversal; reused across calls.
+struct BfsWork {
+  int64_t n = 0, words = 0;
+  uint64_t *vis = nullptr;    // visited bitmap (isolated vertices pre-set)
+  uint64_t *front = nullptr;  // frontier bitmap (bottom-up input)
+  uint64_t *next = nullptr;   // next-frontier bitmap (bottom-up output)
+  int32_t *q[2] = {nullptr, nullptr};  // frontier queues
+  uint32_t *qoff = nullptr;   // per-frontier-vertex edge offsets (top-down)
+  uint32_t *bsum = nullptr;   // per-block partial sums
+  uint64_t *ctr = nullptr;    // device counters (see BfsCounters in bfs.hip)
+  uint64_t *host_ctr = nullptr;  // pinned mirror of ctr
+  ~BfsWork();
+};
+
+// Device state of one batched traversal.
+struct BatchWork {
+  int64_t n = 0;
+  uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
+  uint32_t *sync = nullptr;   // grid barrier and counters
+  uint64_t *host_ctr = nullptr;
+  ~BatchWork();
+};
+
+}  // namespace g5
+
+struct g5_csr {
+  int64_t n = 0, nnz = 0, words = 0;
+  int sb = 1;                  // bits of a vertex id in a sort key
+  int device = 0;
+  int num_cu = 256;
+  int64_t nonisolated = 0;     // vertices of degree >= 1
+  int64_t *row_ptr = nullptr;  // device [n+1]
+  int32_t *col_idx = nullptr;  // device [nnz]
+  uint64_t *iso = nullptr;     // device [words]: bit set = degree 0 (or padding)
+  mutable std::mutex mu;
+  mutable std::vector<g5::BfsWork *> bfs_pool;
+  mutable std::vector<g5::BatchWork *> batch_pool;
+};
+
+namespace g5 {
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  int l = __lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T t = __shfl_up(v, d, kWave);
+    if (l >= d) v += t;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Exclusive prefix sum over a block of NT threads; `s` is LDS scratch of
+// NT/64 entries.  Returns the exclusive prefix; `total` gets the block sum.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T *s, T &total) {
+  constexpr int NW = NT / kWave;
+  int l = __lane_id();
+  int w = threadIdx.x / kWave;
+  T v = wave_incl_scan(x);
+  if (l == kWave - 1) s[w] = v;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    T t = s[i];
+    if (i < w) base += t;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return base + v - x;
+}
+
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T x, T *s) {
+  T tot;
+  block_excl_scan<NT, T>(x, s, tot);
+  return tot;
+}
+
+// ---------------------------------------------------------------- host entry points
+g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t s,
+                         g5_csr **out);
+g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
+                   hipStream_t s, const g5_bfs_params &p, g5_bfs_stats *stats);
+g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *parents,
+                         int8_t *levels, hipStream_t s);
+
+}  // namespace g5

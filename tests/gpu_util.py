@@ -1,0 +1,45 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C-ABI binding
+and compare with the oracle on the same seeded inputs."""
+import numpy as np
+
+import oracle as O
+
+
+def device():
+    import torch
+    return torch.device("cuda:0")
+
+
+def to_dev(edges):
+    import torch
+    e = np.ascontiguousarray(edges, dtype=np.int64).reshape(-1, 2)
+    return torch.from_numpy(e).to(device())
+
+
+class Case:
+    """One graph on both sides: device CSR (HIP) and oracle CSR + labels."""
+
+    def __init__(self, edges, n):
+        import paper_2012_13548_amd as g5
+        self.edges = np.ascontiguousarray(edges, dtype=np.int64).reshape(-1, 2)
+        self.n = n
+        self.csr = g5.build_csr(to_dev(self.edges), n)
+        self.ocsr = O.build_csr(self.edges, n)
+        self.label = O.components(self.edges, n)
+
+    def check_csr(self):
+        rp, ci = self.csr.arrays()
+        assert np.array_equal(rp.cpu().numpy(), self.ocsr.row_ptr)
+        assert np.array_equal(ci.cpu().numpy(), self.ocsr.col_idx)
+
+    def check_root(self, root, **kw):
+        import paper_2012_13548_amd as g5
+        parent, level = g5.bfs(self.csr, root, **kw)
+        parent, level = parent.cpu().numpy(), level.cpu().numpy()
+        _, olevel = O.bfs(self.ocsr, root)
+        bad = np.flatnonzero(level != olevel)
+        assert bad.size == 0, (f"root {root} {kw}: {bad.size} levels differ, first at "
+                               f"{bad[:5]}: gpu {level[bad[:5]]} oracle {olevel[bad[:5]]}")
+        rule = O.validate(self.ocsr, root, parent, level, self.label)
+        assert rule == 0, f"root {root} {kw}: parent array invalid ({O.RULES[rule]})"
+        return parent, level

@@ -1,0 +1,169 @@
+"""Kernel 2 on the GPU: g5_bfs levels bit-exact against the oracle, parents
+valid by the oracle's validator, for every direction policy and claim mode."""
+import numpy as np
+import pytest
+
+import kronecker as K
+import paper_2012_13548_amd as g5
+from tests import golden
+from tests import graphs as G
+from tests.gpu_util import Case
+
+pytestmark = pytest.mark.gpu
+
+MODES = [dict(direction=g5.DIR_AUTO), dict(direction=g5.DIR_TOPDOWN),
+         dict(direction=g5.DIR_BOTTOMUP), dict(direction=g5.DIR_AUTO, claim=g5.CLAIM_CAS),
+         dict(direction=g5.DIR_AUTO, alpha=1e6, beta=1e6),
+         dict(direction=g5.DIR_AUTO, alpha=1e-3, beta=2.0)]
+MODE_IDS = ["auto", "td", "bu", "auto-cas", "auto-eager", "auto-late"]
+
+
+@pytest.fixture(params=range(len(MODES)), ids=MODE_IDS)
+def mode(request):
+    return MODES[request.param]
+
+
+def structured():
+    out = {}
+    out["path"] = G.path(300)
+    out["star"] = G.star(5000)
+    out["grid"] = G.grid(37, 41)
+    out["cycle"] = G.cycle(257)
+    out["complete"] = G.complete(40)
+    out["tree"] = G.binary_tree(10)
+    e, n, _ = G.disjoint_union(G.path(70), G.cycle(9), G.star(130))
+    out["union"] = (e, n + 5)
+    return out
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return {k: Case(*v) for k, v in structured().items()}
+
+
+@pytest.mark.parametrize("name", list(structured().keys()))
+def test_structured(cases, name, mode):
+    c = cases[name]
+    rng = np.random.default_rng(len(name))
+    for r in [0, c.n - 1] + list(rng.integers(0, c.n, 3)):
+        c.check_root(int(r), **mode)
+
+
+@pytest.mark.parametrize("name", ["fail1.txt", "two_components.txt"])
+def test_golden(name, mode):
+    g = golden.load(name)
+    c = Case(g["edges"], g["n"])
+    parent, level = c.check_root(g["root"], **mode)
+    for v, l in g["level"].items():
+        assert level[v] == l
+    for v, ch in g["parent_choices"].items():
+        assert parent[v] in ch
+
+
+def test_isolated_root(mode):
+    c = Case(np.array([[1, 2], [2, 3]]), 70)
+    parent, level = c.check_root(0, **mode)
+    assert (level >= 0).sum() == 1 and parent[0] == 0
+    c.check_root(69, **mode)
+
+
+@pytest.mark.parametrize("leaves", [100_000, 1_000_000])
+def test_hub_star(leaves):
+    # one row split over ~1000 top-down blocks
+    e, n = G.star(leaves)
+    c = Case(e, n)
+    for m in (dict(direction=g5.DIR_TOPDOWN), dict(direction=g5.DIR_AUTO),
+              dict(direction=g5.DIR_BOTTOMUP)):
+        c.check_root(0, **m)
+        c.check_root(leaves // 2, **m)
+
+
+def test_long_path():
+    # 10,000 levels; relabelled so consecutive levels are far apart in memory
+    e, n, perm = G.long_path_relabelled(10_000, 3)
+    c = Case(e, n)
+    for m in (dict(direction=g5.DIR_AUTO), dict(direction=g5.DIR_TOPDOWN)):
+        c.check_root(int(perm[0]), **m)
+        c.check_root(int(perm[n // 2]), **m)
+
+
+@pytest.fixture(scope="module")
+def kron10():
+    scale = 10
+    e = K.edges_host(scale)
+    c = Case(e, 1 << scale)
+    roots = K.select_roots(K.nonisolated_host(e, 1 << scale), 8, K.root_seed(scale))
+    return c, roots
+
+
+def test_kronecker_scale10_all_roots(kron10, mode):
+    c, roots = kron10
+    for r in roots:
+        c.check_root(r, **mode)
+
+
+@pytest.mark.parametrize("lane_scan", [1, 2, 4, 8, 16])
+def test_lane_scan_variants(kron10, lane_scan):
+    c, roots = kron10
+    for r in roots[:3]:
+        c.check_root(r, lane_scan=lane_scan)
+
+
+@pytest.fixture(scope="module")
+def kron16():
+    scale = 16
+    e = K.edges_host(scale)
+    c = Case(e, 1 << scale)
+    roots = K.select_roots(K.nonisolated_host(e, 1 << scale), 8, K.root_seed(scale))
+    return c, roots
+
+
+def test_kronecker_scale16(kron16, mode):
+    c, roots = kron16
+    for r in roots:
+        c.check_root(r, **mode)
+
+
+def test_kronecker_scale20_64_roots():
+    scale = 20
+    n = 1 << scale
+    e = K.edges_host(scale)
+    c = Case(e, n)
+    roots = K.select_roots(K.nonisolated_host(e, n), 64, K.root_seed(scale))
+    dirs = set()
+    for r in roots:
+        c.check_root(r)
+        _, _, st = g5.bfs(c.csr, r, stats=True)
+        dirs |= set(st["dir"])
+    assert dirs == {1, 2}, "direction-optimising run never switched"
+    for r in roots[:4]:
+        c.check_root(r, direction=g5.DIR_TOPDOWN)
+        c.check_root(r, direction=g5.DIR_BOTTOMUP)
+
+
+def test_repeat_stable(kron10):
+    c, roots = kron10
+    first = None
+    for _ in range(10):
+        _, level = g5.bfs(c.csr, roots[0])
+        level = level.cpu().numpy()
+        if first is None:
+            first = level
+        assert np.array_equal(level, first)
+
+
+def test_bad_root(kron10):
+    c, _ = kron10
+    for r in (-1, c.n, 1 << 40):
+        with pytest.raises(g5.G5Error) as ei:
+            g5.bfs(c.csr, r)
+        assert ei.value.status == g5.G5_EINVAL
+
+
+def test_unaligned_outputs(kron10):
+    import torch
+    c, roots = kron10
+    buf = torch.empty(2 * c.n + 2, dtype=torch.int32, device="cuda:0")
+    parent, level = g5.bfs(c.csr, roots[1], parent=buf[1:c.n + 1], level=buf[c.n + 1:2 * c.n + 1])
+    _, ref = g5.bfs(c.csr, roots[1])
+    assert torch.equal(level, ref)
