@@ -40,8 +40,11 @@ static int cmp_i32(const void *a, const void *b) {
 int64_t orc_build_csr(const int64_t *edges, int64_t m, int64_t n, int64_t *rp,
                       int32_t *ci) {
   if (n < 1 || n > 2147483647LL || m < 0) return -2;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
   for (int64_t i = 0; i < 2 * m; ++i)
-    if (edges[i] < 0 || edges[i] >= n) return -1;
+    if (edges[i] < 0 || edges[i] >= n) bad = 1;
+  if (bad) return -1;
   /* degree counts of both directions, self-loops skipped */
   int64_t *cnt = (int64_t *)calloc((size_t)n, sizeof(int64_t));
   int64_t *cur = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
@@ -50,22 +53,32 @@ int64_t orc_build_csr(const int64_t *edges, int64_t m, int64_t n, int64_t *rp,
     free(cur);
     return -3;
   }
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < m; ++i) {
     int64_t u = edges[2 * i], v = edges[2 * i + 1];
     if (u == v) continue;
+#pragma omp atomic
     cnt[u]++;
+#pragma omp atomic
     cnt[v]++;
   }
   /* exclusive prefix sum: start of each (not yet deduplicated) row */
   cur[0] = 0;
   for (int64_t v = 0; v < n; ++v) cur[v + 1] = cur[v] + cnt[v];
   memcpy(rp, cur, (size_t)(n + 1) * sizeof(int64_t));
-  /* scatter both directions */
+  /* scatter both directions (the order inside a row does not matter: rows
+   * are sorted next) */
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < m; ++i) {
     int64_t u = edges[2 * i], v = edges[2 * i + 1];
     if (u == v) continue;
-    ci[cur[u]++] = (int32_t)v;
-    ci[cur[v]++] = (int32_t)u;
+    int64_t pu, pv;
+#pragma omp atomic capture
+    pu = cur[u]++;
+#pragma omp atomic capture
+    pv = cur[v]++;
+    ci[pu] = (int32_t)v;
+    ci[pv] = (int32_t)u;
   }
   /* sort each row and count its distinct entries (rows are independent) */
 #pragma omp parallel for schedule(dynamic, 4096)
