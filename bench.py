@@ -1,0 +1,334 @@
+#!/usr/bin/env python3
+"""Benchmark: harmonic-mean GTEPS of single-root BFS on a scale-26, edge-factor-16
+Kronecker graph over 64 roots, on one MI355X.
+
+One step = one breadth-first search from each of the 64 roots (g5_bfs through
+the C-ABI).  Inputs are generated straight into HBM (seeded Kronecker
+generator, initiator 0.57/0.19/0.19/0.05, random relabel) and the CSR is built
+by g5_build_csr before timing; the CSR build is timed separately.
+
+Per root r: t_r = device time of g5_bfs (events on the launch stream around
+the call), m_r = distinct undirected edges of r's component, TEPS_r = m_r/t_r.
+value = harmonic mean of TEPS over every (step, root) sample (Section 4.3 of
+the paper names TEPS over 64 start vertices as the Graph500 metric).
+
+Printed JSON line (stdout): the contract fields plus
+  roofline      the dominant step kernel's algorithmic GB/s vs the 8 TB/s peak
+  cpu_baseline  the CPU oracle (single-threaded queue BFS) timed on this host
+                on a bounded sample (some roots of the same graph)
+  batch         64 roots in one batched launch vs 64 sequential runs (scale 22)
+Progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "harmonic-mean GTEPS, scale-26 ef16, 64 roots; batched vs single-root; HBM GB/s"
+T0 = time.time()
+
+
+def log(msg):
+    sys.stderr.write(f"[bench {time.time() - T0:7.1f}s] {msg}\n")
+    sys.stderr.flush()
+
+
+def hmean(xs):
+    return len(xs) / sum(1.0 / x for x in xs)
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+BFS_SOURCES = ["paper_2012_13548_amd/csrc/bfs.hip", "paper_2012_13548_amd/csrc/g5_internal.h"]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get(f"{kernel}@{workload}")
+    if not rec or rec.get("source_hash") != source_hash(BFS_SOURCES):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_gpu(args):
+    import torch
+    import kronecker as K
+    import paper_2012_13548_amd as g5
+
+    dev = torch.device("cuda:0")
+    scale, n = args.scale, 1 << args.scale
+    # load every kernel once on a small graph
+    small = g5.build_csr(K.edges_device(10, device=dev), 1 << 10)
+    g5.bfs(small, 0)
+    del small
+
+    log(f"generating scale-{scale} ef{args.edgefactor} tuples on the device")
+    edges = K.edges_device(scale, args.edgefactor, device=dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    csr = g5.build_csr(edges, n)
+    e1.record()
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    log(f"g5_build_csr: nnz {csr.nnz} in {build_ms:.1f} ms")
+    mask = K.nonisolated_device(edges, n).cpu().numpy()
+    roots = K.select_roots(mask, args.roots, K.root_seed(scale))
+    del edges, mask
+    torch.cuda.empty_cache()
+
+    rp, _ = csr.arrays()
+    deg = (rp[1:] - rp[:-1])
+    del rp
+    parent = torch.empty(n, dtype=torch.int32, device=dev)
+    level = torch.empty(n, dtype=torch.int32, device=dev)
+
+    # untimed accounting pass: traversed edges m_r and algorithmic bytes per step
+    m_r, acct = [], []
+    for r in roots:
+        _, _, st = g5.bfs(csr, r, parent, level, count_bytes=True)
+        m_r.append(int(deg[level >= 0].sum().item()) // 2)
+        acct.append(st)
+    del deg
+    log(f"accounting done: m_r of root 0 = {m_r[0]}, levels {acct[0]['nlevels']}, "
+        f"dirs {acct[0]['dir']}")
+
+    for _ in range(args.warmup):
+        for r in roots:
+            g5.bfs(csr, r, parent, level)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} step(s) done")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in roots]
+    samples, step_time = [], {1: 0.0, 2: 0.0}
+    step_bytes, step_launches = {1: 0, 2: 0}, {1: 0, 2: 0}
+    per_level = None
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for step in range(args.steps):
+        stats = []
+        for i, r in enumerate(roots):
+            ev[i][0].record()
+            _, _, st = g5.bfs(csr, r, parent, level, time_steps=True)
+            ev[i][1].record()
+            stats.append(st)
+        torch.cuda.synchronize()
+        for i, r in enumerate(roots):
+            t = ev[i][0].elapsed_time(ev[i][1]) / 1e3
+            samples.append(m_r[i] / t)
+            st, ac = stats[i], acct[i]
+            for lv in range(min(st["nlevels"], len(st["dir"]))):
+                d = st["dir"][lv]
+                step_time[d] += st["step_ms"][lv]
+                step_launches[d] += 1
+                if lv < len(ac["bytes"]) and ac["dir"][lv] == d:
+                    step_bytes[d] += ac["bytes"][lv]
+        if per_level is None:
+            per_level = [{"level": lv, "dir": "TD" if stats[0]["dir"][lv] == 1 else "BU",
+                          "frontier": stats[0]["frontier"][lv],
+                          "discovered": stats[0]["discovered"][lv],
+                          "alg_bytes": acct[0]["bytes"][lv],
+                          "ms": round(stats[0]["step_ms"][lv], 4)}
+                         for lv in range(min(stats[0]["nlevels"], len(stats[0]["dir"])))]
+        log(f"step {step + 1}/{args.steps}: hmean so far {hmean(samples) / 1e9:.2f} GTEPS")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    dom = max(step_time, key=lambda d: step_time[d])
+    name = {1: "td_step", 2: "k_bu_step"}[dom]
+    achieved = step_bytes[dom] / (step_time[dom] / 1e3) / 1e9 if step_time[dom] else 0.0
+    traffic = measured_traffic(name, f"s{scale}")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": name,
+                "launches": step_launches[dom],
+                "avg_launch_ms": round(step_time[dom] / max(step_launches[dom], 1), 4),
+                "alg_bytes_per_launch": int(step_bytes[dom] / max(step_launches[dom], 1))}
+    other = 3 - dom
+    if step_time[other]:
+        roofline["other_step"] = {
+            "kernel": {1: "td_step", 2: "k_bu_step"}[other],
+            "achieved": round(step_bytes[other] / (step_time[other] / 1e3) / 1e9, 1),
+            "time_share": round(step_time[other] / (step_time[1] + step_time[2]), 3)}
+    gpu = {"value": hmean(samples) / 1e9, "ms_per_step": wall * 1e3 / args.steps,
+           "build_ms": build_ms, "nnz": csr.nnz, "roots": roots, "m_r": m_r,
+           "roofline": roofline, "per_level_root0": per_level}
+    return gpu, csr, parent, level
+
+
+def run_batch(args):
+    """64 roots at scale 22: one batched launch vs 64 sequential single-root runs."""
+    import torch
+    import kronecker as K
+    import paper_2012_13548_amd as g5
+    dev = torch.device("cuda:0")
+    scale, n = args.batch_scale, 1 << args.batch_scale
+    edges = K.edges_device(scale, args.edgefactor, device=dev)
+    csr = g5.build_csr(edges, n)
+    mask = K.nonisolated_device(edges, n).cpu().numpy()
+    roots = K.select_roots(mask, 64, K.root_seed(scale))
+    del edges
+    rp, _ = csr.arrays()
+    deg = rp[1:] - rp[:-1]
+    parent = torch.empty(n, dtype=torch.int32, device=dev)
+    level = torch.empty(n, dtype=torch.int32, device=dev)
+    m_r = []
+    for r in roots:
+        g5.bfs(csr, r, parent, level)
+        m_r.append(int(deg[level >= 0].sum().item()) // 2)
+    parents = torch.empty((64, n), dtype=torch.int32, device=dev)
+    levels = torch.empty((64, n), dtype=torch.int8, device=dev)
+    try:
+        g5.bfs_batch(csr, roots, levels=levels, parent_out=parents)
+    except g5.G5Error as e:
+        log(f"batched BFS unavailable: {e}")
+        return None
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    seq, bat = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        e0.record()
+        for r in roots:
+            g5.bfs(csr, r, parent, level)
+        e1.record()
+        torch.cuda.synchronize()
+        seq.append(e0.elapsed_time(e1) / 1e3)
+        e0.record()
+        g5.bfs_batch(csr, roots, levels=levels, parent_out=parents)
+        e1.record()
+        torch.cuda.synchronize()
+        bat.append(e0.elapsed_time(e1) / 1e3)
+    total = sum(m_r)
+    t_seq, t_bat = min(seq), min(bat)
+    return {"scale": scale, "roots": 64, "with_parents": True,
+            "sequential_gteps": round(total / t_seq / 1e9, 3),
+            "batched_gteps": round(total / t_bat / 1e9, 3),
+            "ratio": round(t_seq / t_bat, 3), "sequential_ms": round(t_seq * 1e3, 3),
+            "batched_ms": round(t_bat * 1e3, 3)}
+
+
+def run_cpu(args, gpu_levels):
+    """Oracle timed on the host cores: queue BFS from the first roots of the same
+    graph, on the oracle's own CSR built from the host generator."""
+    import numpy as np
+    import kronecker as K
+    import oracle as O
+    scale, n = args.scale, 1 << args.scale
+    log("cpu baseline: host generator")
+    edges = K.edges_host(scale, args.edgefactor)
+    log("cpu baseline: oracle CSR")
+    ocsr = O.build_csr(edges, n)
+    del edges
+    roots = gpu_levels["roots"][:args.cpu_roots]
+    teps, secs, equal = [], [], True
+    for i, r in enumerate(roots):
+        _, lev, dt = O.bfs_timed(ocsr, r)
+        mr = O.teps_edges(ocsr, lev)
+        teps.append(mr / dt)
+        secs.append(dt)
+        if i == 0 and gpu_levels.get("level0") is not None:
+            equal = bool(np.array_equal(lev, gpu_levels["level0"]))
+        log(f"cpu baseline: root {r}: {dt:.2f} s, {mr / dt / 1e6:.1f} MTEPS")
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(hmean(teps) / 1e9, 5), "unit": "GTEPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"single-threaded oracle queue BFS from {len(roots)} of the 64 roots of "
+                      f"the same scale-{scale} graph ({sum(secs):.1f} s of BFS; oracle's own CSR "
+                      f"from the host generator, build untimed)",
+            "host_cpu": cpu_model, "host_threads": os.cpu_count(),
+            "levels_equal_gpu": equal}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=26)
+    ap.add_argument("--edgefactor", type=int, default=16)
+    ap.add_argument("--roots", type=int, default=64)
+    ap.add_argument("--batch-scale", type=int, default=22)
+    ap.add_argument("--cpu-roots", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the many-root workload shards by roots with no communication: run one "
+              "process per GPU instead)", file=sys.stderr)
+        sys.exit(2)
+
+    gpu, csr, parent, level = run_gpu(args)
+    import torch
+    import paper_2012_13548_amd as g5
+    g5.bfs(csr, gpu["roots"][0], parent, level)
+    level0 = level.cpu().numpy()
+    del csr, parent, level
+    torch.cuda.empty_cache()
+    batch = None if args.no_batch else run_batch(args)
+    if batch:
+        log(f"batch: ratio {batch['ratio']} ({batch['batched_gteps']} vs "
+            f"{batch['sequential_gteps']} GTEPS)")
+    cpu = None
+    if not args.no_cpu:
+        cpu = run_cpu(args, {"roots": gpu["roots"], "level0": level0})
+
+    out = {
+        "metric": METRIC,
+        "value": round(gpu["value"], 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(gpu["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"kronecker-scale{args.scale}-ef{args.edgefactor}-"
+                               f"{args.roots}roots-single-root-bfs",
+                   "scale": args.scale, "edgefactor": args.edgefactor,
+                   "vertices": 1 << args.scale, "tuples": args.edgefactor << args.scale,
+                   "nnz": gpu["nnz"], "roots": args.roots,
+                   "generator": "seeded Kronecker (0.57,0.19,0.19,0.05), relabelled, "
+                                "graph seed 1000+scale, root seed 2000+scale"},
+        "roofline": gpu["roofline"],
+        "cpu_baseline": cpu,
+        "csr_build_ms": round(gpu["build_ms"], 2),
+        "batch": batch,
+        "per_level_root0": gpu["per_level_root0"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

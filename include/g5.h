@@ -88,21 +88,45 @@ typedef enum {
 
 /* Tuning knobs of g5_bfs_ex.  Zero fields take the library defaults. */
 typedef struct {
-  int32_t direction; /* g5_direction */
-  double alpha;      /* top-down -> bottom-up when m_f > m_u / alpha (default 14) */
-  double beta;       /* bottom-up -> top-down when n_f < n / beta, shrinking (default 24) */
-  int32_t bu_lane_scan; /* neighbours a lane tests before its row goes wave-wide (1..16, default 4) */
-  int32_t reserved[7];
+  int32_t direction;    /* g5_direction */
+  double alpha;         /* top-down -> bottom-up when m_f > m_u / alpha (default 14) */
+  double beta;          /* bottom-up -> top-down when n_f < n / beta, shrinking (default 24) */
+  int32_t bu_lane_scan; /* neighbours a lane tests before its row goes wave-wide: 1, 2, 4, 8
+                           or 16 (default 4) */
+  int32_t claim;        /* top-down claim: 0 atomic OR on the visited bitmap (default),
+                           1 compare-and-swap of parent from -1 */
+  int32_t flags;        /* G5_FLAG_* */
+  int32_t reserved[5];
 } g5_bfs_params;
+
+/* Time each level's step with HIP events on `stream` (step_ms in the stats). */
+#define G5_FLAG_TIME_STEPS 1
+/* Count the algorithmic bytes and edges of each level (slower kernels; use in
+ * an untimed run).  Bytes per level:
+ *   top-down   20 per frontier vertex (queue entry + two row offsets)
+ *              + 4 per frontier edge + 12 per discovered vertex (level, parent,
+ *              queue entry);
+ *   bottom-up  8 per unvisited non-isolated vertex (its row offset)
+ *              + 4 per neighbour examined up to the first frontier hit
+ *              + n/4 (visited words read, next-frontier words written)
+ *              + 8 per discovered vertex (level, parent).
+ * Frontier-bitmap probes (one per examined neighbour) are reported apart. */
+#define G5_FLAG_COUNT_BYTES 2
 
 #define G5_MAX_STAT_LEVELS 64
 
-/* Per-traversal statistics of g5_bfs_ex (host memory, filled on success). */
+/* Per-traversal statistics of g5_bfs_ex (host memory, filled on success); the
+ * per-level arrays cover the first G5_MAX_STAT_LEVELS levels. */
 typedef struct {
-  int32_t nlevels;                        /* levels processed, root level included */
-  int32_t dir[G5_MAX_STAT_LEVELS];        /* 1 top-down, 2 bottom-up, per level */
-  int64_t frontier[G5_MAX_STAT_LEVELS];   /* vertices in the frontier each level expands */
-  int64_t reached;                        /* vertices with level >= 0 */
+  int32_t nlevels;                          /* levels processed, root level included */
+  int32_t dir[G5_MAX_STAT_LEVELS];          /* 1 top-down, 2 bottom-up */
+  int64_t frontier[G5_MAX_STAT_LEVELS];     /* vertices in the frontier the level expands */
+  int64_t discovered[G5_MAX_STAT_LEVELS];   /* vertices the level discovers */
+  int64_t edges[G5_MAX_STAT_LEVELS];        /* top-down: frontier degree sum; bottom-up:
+                                               neighbours examined (COUNT_BYTES only) */
+  int64_t bytes[G5_MAX_STAT_LEVELS];        /* algorithmic bytes (COUNT_BYTES only) */
+  double step_ms[G5_MAX_STAT_LEVELS];       /* device time of the step (TIME_STEPS only) */
+  int64_t reached;                          /* vertices with level >= 0 */
   int64_t reserved[8];
 } g5_bfs_stats;
 

@@ -38,15 +38,24 @@ import torch  # noqa: E402,F401
 lib = ctypes.CDLL(LIB_PATH)
 
 
+FLAG_TIME_STEPS, FLAG_COUNT_BYTES = 1, 2
+
+
 class BfsParams(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("bu_lane_scan", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("claim", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+_L = MAX_STAT_LEVELS
 
 
 class BfsStats(ctypes.Structure):
-    _fields_ = [("nlevels", ctypes.c_int32), ("dir", ctypes.c_int32 * MAX_STAT_LEVELS),
-                ("frontier", ctypes.c_int64 * MAX_STAT_LEVELS), ("reached", ctypes.c_int64),
+    _fields_ = [("nlevels", ctypes.c_int32), ("dir", ctypes.c_int32 * _L),
+                ("frontier", ctypes.c_int64 * _L), ("discovered", ctypes.c_int64 * _L),
+                ("edges", ctypes.c_int64 * _L), ("bytes", ctypes.c_int64 * _L),
+                ("step_ms", ctypes.c_double * _L), ("reached", ctypes.c_int64),
                 ("reserved", ctypes.c_int64 * 8)]
 
 
@@ -140,22 +149,24 @@ def build_csr(edges, n):
     return Csr(out.value, edges.device)
 
 
-def _params(direction, alpha, beta, lane_scan, claim):
+def _params(direction, alpha, beta, lane_scan, claim, flags):
     p = BfsParams()
     p.direction = direction
     p.alpha = alpha or 0.0
     p.beta = beta or 0.0
     p.bu_lane_scan = lane_scan or 0
-    p.reserved[0] = claim
+    p.claim = claim
+    p.flags = flags
     return p
 
 
 def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta=None,
-        lane_scan=None, claim=CLAIM_OR, stats=False):
+        lane_scan=None, claim=CLAIM_OR, stats=False, time_steps=False, count_bytes=False):
     """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
 
-    With ``stats=True`` also returns a dict with the per-level directions and
-    frontier sizes.
+    With ``stats=True`` also returns a dict of per-level directions, frontier
+    sizes and discoveries; ``time_steps`` adds each step's device time (HIP
+    events on the current stream) and ``count_bytes`` its algorithmic bytes.
     """
     import torch
     if parent is None:
@@ -165,15 +176,19 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
     for t in (parent, level):
         if t.dtype != torch.int32 or t.numel() < csr.n or not t.is_contiguous():
             raise ValueError("parent and level must be contiguous int32 tensors of length n")
-    p = _params(direction, alpha, beta, lane_scan, claim)
+    flags = (FLAG_TIME_STEPS if time_steps else 0) | (FLAG_COUNT_BYTES if count_bytes else 0)
+    p = _params(direction, alpha, beta, lane_scan, claim, flags)
+    want = stats or flags
     st = BfsStats()
     _check(lib.g5_bfs_ex(csr.handle, int(root), parent.data_ptr(), level.data_ptr(),
-                         _stream(csr.device), ctypes.byref(p), ctypes.byref(st)), "g5_bfs")
-    if not stats:
+                         _stream(csr.device), ctypes.byref(p),
+                         ctypes.byref(st) if want else None), "g5_bfs")
+    if not want:
         return parent, level
     nl = min(st.nlevels, MAX_STAT_LEVELS)
-    info = {"nlevels": st.nlevels, "dir": list(st.dir[:nl]),
-            "frontier": list(st.frontier[:nl]), "reached": st.reached}
+    info = {"nlevels": st.nlevels, "reached": st.reached}
+    for k in ("dir", "frontier", "discovered", "edges", "bytes", "step_ms"):
+        info[k] = list(getattr(st, k)[:nl])
     return parent, level, info
 
 

@@ -87,8 +87,11 @@ g5_status g5_bfs_ex(const g5_csr *g, int64_t root, int32_t *parent, int32_t *lev
   g5_bfs_params p;
   std::memset(&p, 0, sizeof(p));
   if (params) p = *params;
-  if (p.direction < 0 || p.direction > 2) {
-    set_error("g5_bfs: direction must be 0, 1 or 2");
+  if (p.direction < 0 || p.direction > 2 || p.claim < 0 || p.claim > 1 || p.bu_lane_scan < 0 ||
+      p.bu_lane_scan > 16 || (p.bu_lane_scan & (p.bu_lane_scan - 1)) != 0 || p.alpha < 0 ||
+      p.beta < 0) {
+    set_error("g5_bfs: direction must be 0..2, claim 0..1, bu_lane_scan 0 or a power of two "
+              "up to 16, alpha and beta >= 0");
     return G5_EINVAL;
   }
   try {

@@ -43,7 +43,9 @@ enum Ctr : int {
   C_MNEW = 4,   // their degree sum
   C_RDEG = 5,   // degree of the root
   C_ERR = 6,    // nonzero if a kernel met an impossible state
-  C_NCTR = 8
+  C_SCAN = 7,   // neighbours examined by a bottom-up step (byte counting only)
+  C_UNVIS = 8,  // unvisited non-isolated vertices it scanned (byte counting only)
+  C_NCTR = 16
 };
 
 __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ parent, int64_t n,
@@ -257,8 +259,10 @@ __global__ void k_q2front(const int32_t *__restrict__ q, int64_t qlen, uint64_t 
 // Bottom-up step.  Wavefront per 64-bit word w of the visited bitmap; lane l
 // owns vertex 64w+l.  A lane first tests LANE_SCAN neighbours itself (loads
 // issued together); rows still unresolved are then scanned by the whole
-// wavefront, 64 neighbours per step, one row at a time.
-template <int LANE_SCAN>
+// wavefront, 64 neighbours per step, one row at a time.  With ACCT the kernel
+// also counts the neighbours examined up to the first frontier hit and the
+// vertices scanned (algorithmic-byte accounting).
+template <int LANE_SCAN, bool ACCT>
 __global__ __launch_bounds__(kBlock) void k_bu_step(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
   const int lane = __lane_id();
   const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
-  uint64_t nnew = 0, mnew = 0;
+  uint64_t nnew = 0, mnew = 0, nscan = 0, nunvis = 0;
   for (int64_t w = gw; w < words; w += nw) {
     const uint64_t vw = vis[w];
     if (vw == ~0ull) {
@@ -295,9 +299,14 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
         if (!found && u[t] >= 0 && ((fw[t] >> (u[t] & 63)) & 1)) {
           found = true;
           par = u[t];
+          if (ACCT) nscan += (uint64_t)(t + 1);
         }
       }
       k = std::min<int64_t>(k + LANE_SCAN, e);
+      if (ACCT) {
+        nunvis += 1;
+        if (!found) nscan += (uint64_t)(k - b);
+      }
     }
     uint64_t rem = __ballot(pending && !found && k < e);
     while (rem) {
@@ -305,6 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
       rem &= rem - 1;
       const int64_t kb = __shfl(k, L, kWave), ke = __shfl(e, L, kWave);
       int32_t got = -1;
+      int64_t seen = ke - kb;
       for (int64_t c = kb; c < ke; c += kWave) {
         int64_t kk = c + lane;
         bool hit = false;
@@ -315,13 +325,18 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
         }
         uint64_t hm = __ballot(hit);
         if (hm) {
-          got = __shfl(u, __ffsll((unsigned long long)hm) - 1, kWave);
+          const int hl = __ffsll((unsigned long long)hm) - 1;
+          got = __shfl(u, hl, kWave);
+          seen = c - kb + hl + 1;
           break;
         }
       }
-      if (lane == L && got >= 0) {
-        found = true;
-        par = got;
+      if (lane == L) {
+        if (got >= 0) {
+          found = true;
+          par = got;
+        }
+        if (ACCT) nscan += (uint64_t)seen;
       }
     }
     const uint64_t fm = __ballot(found);
@@ -341,6 +356,14 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
   if (threadIdx.x == 0) {
     if (tn) atomicAdd(ctr + C_NNEW, (unsigned long long)tn);
     if (tm) atomicAdd(ctr + C_MNEW, (unsigned long long)tm);
+  }
+  if (ACCT) {
+    uint64_t ts = block_sum<kBlock, uint64_t>(nscan, s);
+    uint64_t tu = block_sum<kBlock, uint64_t>(nunvis, s);
+    if (threadIdx.x == 0) {
+      atomicAdd(ctr + C_SCAN, (unsigned long long)ts);
+      atomicAdd(ctr + C_UNVIS, (unsigned long long)tu);
+    }
   }
 }
 
@@ -436,6 +459,8 @@ BfsWork::~BfsWork() {
   if (bsum) (void)hipFree(bsum);
   if (ctr) (void)hipFree(ctr);
   if (host_ctr) (void)hipHostFree(host_ctr);
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
@@ -458,9 +483,14 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const double alpha = p.alpha > 0 ? p.alpha : 14.0;
   const double beta = p.beta > 0 ? p.beta : 24.0;
   const int lane_scan = p.bu_lane_scan > 0 ? p.bu_lane_scan : 4;
+  const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
+  const bool acct = stats && (p.flags & G5_FLAG_COUNT_BYTES);
   unsigned long long *ctr = (unsigned long long *)w.ctr;
   uint64_t *hc = w.host_ctr;
   const int bu_grid = ncu * 8;
+  if (timed && !w.ev[0]) {
+    for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
+  }
 
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, w.ctr, (int64_t)C_NCTR);
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
@@ -470,26 +500,24 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                      g->row_ptr);
   G5_LAUNCH_CHECK();
 
-  int cur = 0;              // queue holding the current frontier (top-down)
+  int cur = 0;                // queue holding the current frontier (top-down)
   int64_t qlen = 1;
-  bool q_deg_counted = true;  // degree of the root is excluded from m_u below
+  bool q_deg_counted = true;  // the frontier's degrees are already out of m_u
   bool first = true;
-  int dir = 1;              // 1 top-down, 2 bottom-up
-  int64_t m_u = -1;         // edges (directed entries) of unvisited vertices
+  int dir = 1;                // 1 top-down, 2 bottom-up
+  int64_t m_u = -1;           // directed entries of unvisited vertices
   int64_t nf_prev = 0;
   int32_t lvl = 0;
   int64_t reached = 1;
+  double deg_ms = 0;          // top-down degree scan time of the current level
   uint64_t *front = w.front, *next = w.next;
   if (stats) *stats = g5_bfs_stats{};
-
-  auto record = [&](int d, int64_t nf) {
-    if (stats) {
-      if (lvl < G5_MAX_STAT_LEVELS) {
-        stats->dir[lvl] = d;
-        stats->frontier[lvl] = nf;
-      }
-      stats->nlevels = lvl + 1;
-    }
+  auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
+  auto elapsed = [&](int a, int b, double *ms) -> g5_status {
+    float f = 0;
+    G5_HIP(hipEventElapsedTime(&f, w.ev[a], w.ev[b]));
+    *ms = f;
+    return G5_OK;
   };
 
   while (true) {
@@ -497,14 +525,20 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       if (qlen == 0) break;
       // degree prefix sum of the frontier queue
       const int64_t nb = (qlen + kDegTile - 1) / kDegTile;
+      if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
       hipLaunchKernelGGL(k_td_deg, dim3(nb), dim3(kBlock), 0, s, w.q[cur], qlen, g->row_ptr,
                          w.qoff, w.bsum);
       hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, s, w.bsum, nb, ctr + C_MF);
       hipLaunchKernelGGL(k_td_fix, dim3(grid_for(qlen + 1, kBlock, ncu * 16)), dim3(kBlock), 0,
                          s, w.qoff, qlen, w.bsum, (const unsigned long long *)(ctr + C_MF));
       G5_LAUNCH_CHECK();
+      if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
       G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
       G5_HIP(hipStreamSynchronize(s));
+      if (timed) {
+        g5_status st = elapsed(0, 1, &deg_ms);
+        if (st != G5_OK) return st;
+      }
       const int64_t mf = (int64_t)hc[C_MF];
       if (first) {
         m_u = g->nnz - (int64_t)hc[C_RDEG];
@@ -525,12 +559,12 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         nf_prev = qlen;
         continue;  // this level runs bottom-up
       }
-      record(1, qlen);
       const int nxt = cur ^ 1;
       G5_HIP(hipMemsetAsync(ctr + nxt, 0, 8, s));
+      if (timed) G5_HIP(hipEventRecord(w.ev[2], s));
       if (mf > 0) {
         const int64_t tb = (mf + kTdTile - 1) / kTdTile;
-        if (p.reserved[0] == CLAIM_CAS)
+        if (p.claim == CLAIM_CAS)
           hipLaunchKernelGGL(k_td_expand<CLAIM_CAS>, dim3(tb), dim3(kBlock), 0, s, w.q[cur], qlen,
                              w.qoff, (uint32_t)mf, g->row_ptr, g->col_idx, w.vis, parent, level,
                              w.q[nxt], ctr + nxt, lvl + 1, ctr + C_ERR);
@@ -540,34 +574,74 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                              w.q[nxt], ctr + nxt, lvl + 1, ctr + C_ERR);
         G5_LAUNCH_CHECK();
       }
+      if (timed) G5_HIP(hipEventRecord(w.ev[3], s));
       G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
       G5_HIP(hipStreamSynchronize(s));
       if (hc[C_ERR]) {
         set_error("g5_bfs: top-down tile met more frontier rows than edges");
         return G5_EDEVICE;
       }
+      const int64_t found = (int64_t)hc[nxt];
+      if (slot() >= 0) {
+        int i = slot();
+        stats->dir[i] = 1;
+        stats->frontier[i] = qlen;
+        stats->discovered[i] = found;
+        stats->edges[i] = mf;
+        if (acct) stats->bytes[i] = 20 * qlen + 4 * mf + 12 * found;
+        if (timed) {
+          double ms = 0;
+          g5_status st = elapsed(2, 3, &ms);
+          if (st != G5_OK) return st;
+          stats->step_ms[i] = deg_ms + ms;
+        }
+      }
       cur = nxt;
-      qlen = (int64_t)hc[nxt];
+      qlen = found;
       reached += qlen;
       ++lvl;
     } else {
-      record(2, nf_prev);
       G5_HIP(hipMemsetAsync(ctr + C_NNEW, 0, 16, s));
-#define G5_BU(K)                                                                           \
-  hipLaunchKernelGGL(k_bu_step<K>, dim3(bu_grid), dim3(kBlock), 0, s, g->row_ptr, g->col_idx, \
-                     w.vis, front, next, parent, level, n, W, lvl + 1, ctr)
-      switch (lane_scan) {
-        case 1: G5_BU(1); break;
-        case 2: G5_BU(2); break;
-        case 8: G5_BU(8); break;
-        case 16: G5_BU(16); break;
-        default: G5_BU(4); break;
+      if (acct) G5_HIP(hipMemsetAsync(ctr + C_SCAN, 0, 16, s));
+      if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
+#define G5_BU(K, A)                                                                        \
+  hipLaunchKernelGGL((k_bu_step<K, A>), dim3(bu_grid), dim3(kBlock), 0, s, g->row_ptr,     \
+                     g->col_idx, w.vis, front, next, parent, level, n, W, lvl + 1, ctr)
+#define G5_BU_K(A)               \
+  switch (lane_scan) {           \
+    case 1: G5_BU(1, A); break;  \
+    case 2: G5_BU(2, A); break;  \
+    case 8: G5_BU(8, A); break;  \
+    case 16: G5_BU(16, A); break; \
+    default: G5_BU(4, A); break; \
+  }
+      if (acct) {
+        G5_BU_K(true);
+      } else {
+        G5_BU_K(false);
       }
+#undef G5_BU_K
 #undef G5_BU
       G5_LAUNCH_CHECK();
+      if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
       G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
       G5_HIP(hipStreamSynchronize(s));
       const int64_t nnew = (int64_t)hc[C_NNEW];
+      if (slot() >= 0) {
+        int i = slot();
+        stats->dir[i] = 2;
+        stats->frontier[i] = nf_prev;
+        stats->discovered[i] = nnew;
+        if (acct) {
+          stats->edges[i] = (int64_t)hc[C_SCAN];
+          stats->bytes[i] = 8 * (int64_t)hc[C_UNVIS] + 4 * (int64_t)hc[C_SCAN] + 16 * W +
+                            8 * nnew;
+        }
+        if (timed) {
+          g5_status st = elapsed(0, 1, &stats->step_ms[i]);
+          if (st != G5_OK) return st;
+        }
+      }
       m_u -= (int64_t)hc[C_MNEW];
       reached += nnew;
       ++lvl;
@@ -592,7 +666,10 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       }
     }
   }
-  if (stats) stats->reached = reached;
+  if (stats) {
+    stats->nlevels = lvl;
+    stats->reached = reached;
+  }
   G5_HIP(hipStreamSynchronize(s));
   return G5_OK;
 }

@@ -48,6 +48,7 @@ struct BfsWork {
   uint32_t *bsum = nullptr;   // per-block partial sums
   uint64_t *ctr = nullptr;    // device counters (see BfsCounters in bfs.hip)
   uint64_t *host_ctr = nullptr;  // pinned mirror of ctr
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // step timing
   ~BfsWork();
 };
 
