@@ -36,7 +36,7 @@ typedef enum {
   G5_EINVAL = -1,  /* bad argument: NULL pointer, id or root outside [0, n), k outside [1, 64] */
   G5_ENOMEM = -2,  /* a device or pinned-host allocation failed */
   G5_EDEVICE = -3, /* a HIP runtime error */
-  G5_ERANGE = -4   /* a result does not fit its type (batched level > 126, nnz >= 2^32) */
+  G5_ERANGE = -4   /* a result does not fit its type (batched level > 127, nnz >= 2^32) */
 } g5_status;
 
 /* Kernel 1 (Section 2.2): builds the undirected CSR of an edge list.
@@ -135,17 +135,46 @@ typedef struct {
 g5_status g5_bfs_ex(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
                     void *stream, const g5_bfs_params *params, g5_bfs_stats *stats);
 
-/* Batched BFS from k roots in one persistent launch (64-bit root masks per
- * vertex: bit b of a vertex's mask stands for roots[b]).
+/* Batched BFS from k roots in one persistent launch (multi-source BFS: each
+ * vertex carries a 64-bit mask whose bit b stands for roots[b]; one pass over
+ * the graph per level serves every root; levels stay synchronous through a
+ * grid-wide barrier, Section 2.3.2).
  *   roots    host, int64 [k], each in [0, n); duplicates allowed.
  *   k        1 .. 64.
  *   parents  device, int32 [k][n] (row b for roots[b]), or NULL to skip parents.
  *   levels   device, int8 [k][n].
- * Row b equals what g5_bfs(g, roots[b]) produces for levels (as int8), and a
- * valid parent array for parents.  Errors: G5_EINVAL, G5_ERANGE (some level
- * exceeds 126; fall back to g5_bfs), G5_ENOMEM, G5_EDEVICE. */
+ * Row b of levels equals the level array of g5_bfs(g, roots[b]) as int8, and
+ * row b of parents is a valid parent array for roots[b].  Errors: G5_EINVAL,
+ * G5_ERANGE (some vertex lies deeper than 127, the int8 maximum; fall back to
+ * g5_bfs), G5_ENOMEM, G5_EDEVICE. */
 g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
                        int8_t *levels, void *stream);
+
+/* Knobs of g5_bfs_batch_ex.  Zero fields take the defaults. */
+typedef struct {
+  int32_t direction; /* g5_direction applied to every level of the batch */
+  double alpha;      /* top-down while m_f <= m_u / alpha (default 14), where m_f is the degree
+                        sum of vertices with a nonzero frontier mask and m_u the degree sum of
+                        vertices not yet reached by every root */
+  int32_t flags;     /* G5_FLAG_TIME_STEPS: time the persistent launch */
+  int32_t reserved[5];
+} g5_batch_params;
+
+/* Statistics of g5_bfs_batch_ex (host memory). */
+typedef struct {
+  int32_t nlevels;                         /* levels processed */
+  int32_t dir[G5_MAX_STAT_LEVELS];         /* 1 top-down, 2 bottom-up */
+  int64_t frontier[G5_MAX_STAT_LEVELS];    /* vertices with a nonzero frontier mask */
+  double launch_ms;                        /* device time of the persistent launch (TIME_STEPS) */
+  int32_t grid_blocks;                     /* workgroups of the persistent launch */
+  int32_t reserved[7];
+} g5_batch_stats;
+
+/* g5_bfs_batch with explicit parameters (NULL = defaults) and statistics
+ * (NULL = none). */
+g5_status g5_bfs_batch_ex(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
+                          int8_t *levels, void *stream, const g5_batch_params *params,
+                          g5_batch_stats *stats);
 
 /* Message for the last non-OK status returned on the calling host thread. */
 const char *g5_last_error(void);

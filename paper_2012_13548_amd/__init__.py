@@ -59,6 +59,17 @@ class BfsStats(ctypes.Structure):
                 ("reserved", ctypes.c_int64 * 8)]
 
 
+class BatchParams(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("nlevels", ctypes.c_int32), ("dir", ctypes.c_int32 * _L),
+                ("frontier", ctypes.c_int64 * _L), ("launch_ms", ctypes.c_double),
+                ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _PP = ctypes.POINTER(ctypes.c_void_p)
@@ -77,6 +88,9 @@ lib.g5_bfs_ex.argtypes = [_P, _I64, _P, _P, _P, ctypes.POINTER(BfsParams),
 lib.g5_bfs_ex.restype = ctypes.c_int
 lib.g5_bfs_batch.argtypes = [_P, ctypes.POINTER(_I64), ctypes.c_int32, _P, _P, _P]
 lib.g5_bfs_batch.restype = ctypes.c_int
+lib.g5_bfs_batch_ex.argtypes = [_P, ctypes.POINTER(_I64), ctypes.c_int32, _P, _P, _P,
+                                ctypes.POINTER(BatchParams), ctypes.POINTER(BatchStats)]
+lib.g5_bfs_batch_ex.restype = ctypes.c_int
 lib.g5_last_error.argtypes = []
 lib.g5_last_error.restype = ctypes.c_char_p
 
@@ -192,8 +206,13 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
     return parent, level, info
 
 
-def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None):
-    """Batched BFS from up to 64 roots: (parents int32 [k, n] or None, levels int8 [k, n])."""
+def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=DIR_AUTO,
+              alpha=None, stats=False, time_launch=False):
+    """Batched BFS from 1..64 roots in one persistent launch.
+
+    Returns (parents int32 [k, n] or None, levels int8 [k, n]) and, with
+    ``stats=True``, a dict of per-level directions and frontier sizes.
+    """
     import torch
     k = len(roots)
     arr = (_I64 * max(k, 1))(*[int(r) for r in roots])
@@ -201,7 +220,23 @@ def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None):
         levels = torch.empty((k, csr.n), dtype=torch.int8, device=csr.device)
     if parents and parent_out is None:
         parent_out = torch.empty((k, csr.n), dtype=torch.int32, device=csr.device)
+    for t, dt in ((levels, torch.int8), (parent_out if parents else None, torch.int32)):
+        if t is not None and (t.dtype != dt or t.numel() < k * csr.n or not t.is_contiguous()):
+            raise ValueError("levels must be contiguous int8 [k, n] and parents int32 [k, n]")
     pp = parent_out.data_ptr() if parents else None
-    _check(lib.g5_bfs_batch(csr.handle, arr, k, pp, levels.data_ptr(), _stream(csr.device)),
+    p = BatchParams()
+    p.direction = direction
+    p.alpha = alpha or 0.0
+    p.flags = FLAG_TIME_STEPS if time_launch else 0
+    st = BatchStats()
+    want = stats or time_launch
+    _check(lib.g5_bfs_batch_ex(csr.handle, arr, k, pp, levels.data_ptr(), _stream(csr.device),
+                               ctypes.byref(p), ctypes.byref(st) if want else None),
            "g5_bfs_batch")
-    return (parent_out if parents else None), levels
+    out = (parent_out if parents else None), levels
+    if not want:
+        return out
+    nl = min(st.nlevels, MAX_STAT_LEVELS)
+    info = {"nlevels": st.nlevels, "dir": list(st.dir[:nl]), "frontier": list(st.frontier[:nl]),
+            "launch_ms": st.launch_ms, "grid_blocks": st.grid_blocks}
+    return out + (info,)

@@ -70,6 +70,8 @@ void g5_csr_free(g5_csr *g) {
   if (g->row_ptr) (void)hipFree(g->row_ptr);
   if (g->col_idx) (void)hipFree(g->col_idx);
   if (g->iso) (void)hipFree(g->iso);
+  if (g->hub_list) (void)hipFree(g->hub_list);
+  if (g->hub_off) (void)hipFree(g->hub_off);
   delete g;
 }
 
@@ -106,8 +108,9 @@ g5_status g5_bfs(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
   return g5_bfs_ex(g, root, parent, level, stream, nullptr, nullptr);
 }
 
-g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
-                       int8_t *levels, void *stream) {
+g5_status g5_bfs_batch_ex(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
+                          int8_t *levels, void *stream, const g5_batch_params *params,
+                          g5_batch_stats *stats) {
   if (!g || !roots || !levels) {
     set_error("g5_bfs_batch: graph, roots and levels must be non-NULL");
     return G5_EINVAL;
@@ -121,12 +124,24 @@ g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t
       set_error("g5_bfs_batch: root " + std::to_string(roots[i]) + " outside [0, n)");
       return G5_EINVAL;
     }
+  g5_batch_params p;
+  std::memset(&p, 0, sizeof(p));
+  if (params) p = *params;
+  if (p.direction < 0 || p.direction > 2 || p.alpha < 0) {
+    set_error("g5_bfs_batch: direction must be 0..2 and alpha >= 0");
+    return G5_EINVAL;
+  }
   try {
-    return g5::bfs_batch_impl(g, roots, k, parents, levels, (hipStream_t)stream);
+    return g5::bfs_batch_impl(g, roots, k, parents, levels, (hipStream_t)stream, p, stats);
   } catch (const std::bad_alloc &) {
     set_error("g5_bfs_batch: host allocation failed");
     return G5_ENOMEM;
   }
+}
+
+g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
+                       int8_t *levels, void *stream) {
+  return g5_bfs_batch_ex(g, roots, k, parents, levels, stream, nullptr, nullptr);
 }
 
 }  // extern "C"

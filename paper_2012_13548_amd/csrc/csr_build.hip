@@ -10,6 +10,8 @@
 //             each kept key opens rows (prev_source, source] -> row_ptr, so an
 //             empty row repeats the next index; rows after the last key get nnz
 //   iso       bitmap of degree-0 vertices (used by the traversal to skip them)
+//   hubs      list of rows longer than kHubDeg and their kHubChunk-edge pieces
+//             (the batched traversal splits these rows across wavefronts)
 #include <algorithm>
 
 #include "g5_internal.h"
@@ -240,6 +242,22 @@ __global__ __launch_bounds__(256) void k_iso(const int64_t *__restrict__ rp, int
   if (threadIdx.x == 0 && tot) atomicAdd(nonisolated, (unsigned long long)tot);
 }
 
+__global__ void k_find_hubs(const int64_t *__restrict__ rp, int64_t n,
+                            int32_t *__restrict__ list, unsigned long long *__restrict__ count) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    if (rp[v + 1] - rp[v] > kHubDeg) list[atomicAdd(count, 1ull)] = (int32_t)v;
+}
+
+__global__ void k_hub_chunks(const int64_t *__restrict__ rp, const int32_t *__restrict__ list,
+                             int64_t h, uint64_t *__restrict__ chunks) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < h) {
+    int32_t v = list[i];
+    chunks[i] = (uint64_t)((rp[v + 1] - rp[v] + kHubChunk - 1) / kHubChunk);
+  }
+}
+
 int grid_cap(int64_t items, int per_block, int cap) {
   int64_t g = (items + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -369,6 +387,36 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
     return fail(e, "copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   g->nonisolated = (int64_t)noniso;
+
+  // hub list (order does not matter) and its chunk prefix
+  const int64_t max_hubs = (int64_t)(nnz / kHubDeg) + 1;
+  if ((e = hipMalloc(&g->hub_list, max_hubs * sizeof(int32_t))) != hipSuccess)
+    return fail(e, "hub list");
+  if ((e = hipMemsetAsync(noniso_dev, 0, 8, s)) != hipSuccess) return fail(e, "memset");
+  hipLaunchKernelGGL(k_find_hubs, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+                     n, g->hub_list, noniso_dev);
+  unsigned long long nh = 0;
+  if ((e = hipMemcpyAsync(&nh, noniso_dev, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+  g->num_hubs = (int64_t)nh;
+  std::vector<uint64_t> off(nh + 1, 0);
+  if ((e = hipMalloc(&g->hub_off, (nh + 1) * sizeof(uint64_t))) != hipSuccess)
+    return fail(e, "hub offsets");
+  if (nh) {
+    hipLaunchKernelGGL(k_hub_chunks, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s,
+                       g->row_ptr, g->hub_list, (int64_t)nh, g->hub_off);
+    if ((e = hipMemcpyAsync(off.data() + 1, g->hub_off, nh * 8, hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return fail(e, "copy");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+    for (size_t i = 1; i <= nh; ++i) off[i] += off[i - 1];
+  }
+  g->hub_chunks = (int64_t)off[nh];
+  if ((e = hipMemcpyAsync(g->hub_off, off.data(), (nh + 1) * 8, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   *out = g;
   return G5_OK;
 }

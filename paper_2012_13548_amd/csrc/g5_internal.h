@@ -14,6 +14,10 @@
 namespace g5 {
 
 constexpr int kWave = 64;
+// Rows longer than kHubDeg ("hubs") are listed by Kernel 1 and split into
+// kHubChunk-edge work items by the batched traversal.
+constexpr int kHubDeg = 4096;
+constexpr int kHubChunk = 1024;
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);
@@ -55,9 +59,12 @@ struct BfsWork {
 // Device state of one batched traversal.
 struct BatchWork {
   int64_t n = 0;
-  uint64_t *seen = nullptr, *front = nullptr, *next = nullptr;
-  uint32_t *sync = nullptr;   // grid barrier and counters
-  uint64_t *host_ctr = nullptr;
+  uint64_t *seen = nullptr;            // per-vertex mask of roots that reached it
+  uint64_t *buf[3] = {nullptr, nullptr, nullptr};  // frontier masks, rotated per level
+  void *ctl = nullptr;                 // level counters (MsCtl in msbfs.hip)
+  void *host_ctl = nullptr;            // pinned mirror
+  int64_t *roots = nullptr;            // device copy of the roots
+  hipEvent_t ev[2] = {nullptr, nullptr};
   ~BatchWork();
 };
 
@@ -72,6 +79,10 @@ struct g5_csr {
   int64_t *row_ptr = nullptr;  // device [n+1]
   int32_t *col_idx = nullptr;  // device [nnz]
   uint64_t *iso = nullptr;     // device [words]: bit set = degree 0 (or padding)
+  int64_t num_hubs = 0;        // vertices with degree > kHubDeg
+  int64_t hub_chunks = 0;      // their rows in kHubChunk-edge pieces
+  int32_t *hub_list = nullptr; // device [num_hubs]
+  uint64_t *hub_off = nullptr; // device [num_hubs+1]: first chunk of each hub
   mutable std::mutex mu;
   mutable std::vector<g5::BfsWork *> bfs_pool;
   mutable std::vector<g5::BatchWork *> batch_pool;
@@ -141,6 +152,7 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
 g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
                    hipStream_t s, const g5_bfs_params &p, g5_bfs_stats *stats);
 g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *parents,
-                         int8_t *levels, hipStream_t s);
+                         int8_t *levels, hipStream_t s, const g5_batch_params &p,
+                         g5_batch_stats *stats);
 
 }  // namespace g5

@@ -1,17 +1,558 @@
-// Batched multi-source BFS (placeholder until the persistent kernel lands).
+// Batched breadth-first search from up to 64 roots in one persistent launch.
+//
+// Each vertex carries 64-bit masks (bit b = roots[b]): seen (roots that have
+// reached it) and frontier (roots whose level-l frontier contains it), as in
+// multi-source BFS (Then et al., "The More the Merrier", VLDB 2014).  One pass
+// over the graph per level serves every root.  Levels stay synchronous
+// (Section 2.3.2 of the paper): a grid-wide barrier separates levels inside a
+// cooperative launch.
+//
+//   top-down  for u with frontier[u] != 0 and each neighbour v:
+//             new = frontier[u] & ~seen[v]; the atomic OR of new into next[v]
+//             returns the bits this edge won, and each won bit b gives
+//             level[b][v] = l+1, parent[b][v] = u
+//   bottom-up for v with seen[v] != all: OR frontier[u] & missing over its row
+//             (stop early once every missing bit is found); the first
+//             neighbour providing bit b is parent[b][v]
+//   hubs      rows longer than kHubDeg are split into kHubChunk-edge pieces
+//             spread over all wavefronts (list built by Kernel 1)
+//
+// Frontier masks rotate through three buffers: at level l buffer l%3 is read,
+// (l+1)%3 receives the next frontier and (l+2)%3 (the previous frontier) is
+// cleared for level l+1.  Level counters rotate the same way.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
 #include "g5_internal.h"
 
+namespace cg = cooperative_groups;
+
 namespace g5 {
-BatchWork::~BatchWork() {
-  if (seen) (void)hipFree(seen);
-  if (front) (void)hipFree(front);
-  if (next) (void)hipFree(next);
-  if (sync) (void)hipFree(sync);
-  if (host_ctr) (void)hipHostFree(host_ctr);
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kLaneRow = 32;  // rows up to this length are scanned by one lane
+constexpr int kStatLevels = G5_MAX_STAT_LEVELS;
+
+struct Slot {
+  unsigned long long nf;   // vertices with a nonzero frontier mask
+  unsigned long long mf;   // their degree sum
+  unsigned long long dec;  // degree sum of vertices that became fully seen
+  unsigned long long pad;
+};
+
+struct MsCtl {
+  Slot slot[3];
+  unsigned long long mu0;  // degree sum of vertices not yet seen by every root
+  unsigned long long err;
+  unsigned long long nlevels;
+  unsigned long long pad;
+  int64_t frontier[kStatLevels];
+  int32_t dir[kStatLevels];
+};
+
+struct MsArgs {
+  const int64_t *rp;
+  const int32_t *ci;
+  int64_t n;
+  uint64_t full;
+  uint64_t *seen;
+  uint64_t *buf0, *buf1, *buf2;
+  int8_t *levels;
+  int32_t *parents;
+  const int32_t *hub_list;
+  const uint64_t *hub_off;
+  int64_t num_hubs;
+  int64_t hub_chunks;
+  MsCtl *ctl;
+  double alpha;
+  int direction;
+  int max_level;
+};
+
+__device__ __forceinline__ unsigned long long ld_agent(unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-g5_status bfs_batch_impl(const g5_csr *, const int64_t *, int, int32_t *, int8_t *, hipStream_t) {
-  set_error("g5_bfs_batch: not available in this build");
-  return G5_EINVAL;
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) x |= __shfl_xor(x, d, kWave);
+  return x;
 }
+
+// Hub owning work item c: largest i with hub_off[i] <= c.
+__device__ __forceinline__ int64_t hub_of(const MsArgs &a, uint64_t c) {
+  int64_t lo = 0, hi = a.num_hubs;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a.hub_off[mid] <= c)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+struct Acc {
+  uint64_t nf = 0, mf = 0, dec = 0;
+};
+
+// Records the bits `won` of vertex v (already OR-ed into next[v], which held
+// `old`): seen, levels, parents and the frontier counters.
+template <bool PAR>
+__device__ __forceinline__ void commit_atomic(const MsArgs &a, int64_t v, uint64_t won,
+                                              uint64_t old, int32_t par, int8_t lvl,
+                                              Acc &acc) {
+  uint64_t ps = atomicOr((unsigned long long *)&a.seen[v], (unsigned long long)won);
+  int64_t d = -1;
+  if (old == 0) {
+    d = a.rp[v + 1] - a.rp[v];
+    acc.nf += 1;
+    acc.mf += (uint64_t)d;
+  }
+  if ((ps | won) == a.full && ps != a.full) {
+    if (d < 0) d = a.rp[v + 1] - a.rp[v];
+    acc.dec += (uint64_t)d;
+  }
+  while (won) {
+    const int b = __ffsll((unsigned long long)won) - 1;
+    won &= won - 1;
+    a.levels[(int64_t)b * a.n + v] = lvl;
+    if (PAR) a.parents[(int64_t)b * a.n + v] = par;
+  }
+}
+
+template <bool PAR>
+__device__ __forceinline__ void td_edge(const MsArgs &a, uint64_t *next, int32_t u, uint64_t fu,
+                                        int32_t v, int8_t lvl, Acc &acc) {
+  const uint64_t nw = fu & ~a.seen[v];
+  if (!nw) return;
+  const uint64_t old = atomicOr((unsigned long long *)&next[v], (unsigned long long)nw);
+  const uint64_t won = nw & ~old;
+  if (won) commit_atomic<PAR>(a, v, won, old, u, lvl, acc);
+}
+
+template <bool PAR>
+__device__ void td_phase(const MsArgs &a, const uint64_t *front, uint64_t *next, int8_t lvl,
+                         int64_t gw, int64_t nw, Acc &acc) {
+  const int lane = __lane_id();
+  const int64_t W = (a.n + kWave - 1) / kWave;
+  for (int64_t w = gw; w < W; w += nw) {
+    const int64_t u = w * kWave + lane;
+    const uint64_t f = (u < a.n) ? front[u] : 0;
+    if (__ballot(f != 0) == 0) continue;
+    int64_t b = 0, e = 0;
+    if (f) {
+      b = a.rp[u];
+      e = a.rp[u + 1];
+    }
+    const int64_t d = e - b;
+    if (f && d <= kLaneRow)
+      for (int64_t k = b; k < e; ++k) td_edge<PAR>(a, next, (int32_t)u, f, a.ci[k], lvl, acc);
+    uint64_t rem = __ballot(f && d > kLaneRow && d <= kHubDeg);
+    while (rem) {
+      const int L = __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1;
+      const int64_t kb = __shfl(b, L, kWave), ke = __shfl(e, L, kWave);
+      const uint64_t fL = __shfl(f, L, kWave);
+      const int32_t uL = (int32_t)(w * kWave + L);
+      for (int64_t k = kb + lane; k < ke; k += kWave) td_edge<PAR>(a, next, uL, fL, a.ci[k], lvl, acc);
+    }
+  }
+  for (int64_t c = gw; c < a.hub_chunks; c += nw) {
+    const int64_t i = hub_of(a, (uint64_t)c);
+    const int32_t h = a.hub_list[i];
+    const uint64_t fh = front[h];
+    if (!fh) continue;
+    const int64_t kb = a.rp[h] + (int64_t)((uint64_t)c - a.hub_off[i]) * kHubChunk;
+    const int64_t ke = std::min<int64_t>(kb + kHubChunk, a.rp[h + 1]);
+    for (int64_t k = kb + lane; k < ke; k += kWave) td_edge<PAR>(a, next, h, fh, a.ci[k], lvl, acc);
+  }
+}
+
+// Parents of the bits `found` of vertex v from one 64-edge step: lane with the
+// lowest index providing bit b (its neighbour u) is parent[b][v].
+template <bool PAR>
+__device__ __forceinline__ void step_parents(const MsArgs &a, int64_t v, uint64_t found,
+                                             uint64_t g, int32_t u) {
+  if (!PAR) return;
+  const int lane = __lane_id();
+  while (found) {
+    const int b = __ffsll((unsigned long long)found) - 1;
+    found &= found - 1;
+    const int pl = __ffsll((unsigned long long)__ballot((g >> b) & 1)) - 1;
+    const int32_t pu = __shfl(u, pl, kWave);
+    if (lane == 0) a.parents[(int64_t)b * a.n + v] = pu;
+  }
+}
+
+template <bool PAR>
+__device__ void bu_phase(const MsArgs &a, const uint64_t *front, uint64_t *next, int8_t lvl,
+                         int64_t gw, int64_t nw, Acc &acc) {
+  const int lane = __lane_id();
+  const int64_t W = (a.n + kWave - 1) / kWave;
+  for (int64_t w = gw; w < W; w += nw) {
+    const int64_t v = w * kWave + lane;
+    const uint64_t s = (v < a.n) ? a.seen[v] : a.full;
+    int64_t b = 0, e = 0;
+    if (s != a.full) {
+      b = a.rp[v];
+      e = a.rp[v + 1];
+    }
+    const int64_t d = e - b;
+    const bool act = s != a.full && d > 0 && d <= kHubDeg;  // hubs: chunk loop below
+    if (__ballot(act) == 0) continue;
+    const uint64_t missing = a.full & ~s;
+    uint64_t got = 0;
+    if (act && d <= kLaneRow) {
+      for (int64_t k = b; k < e; ++k) {
+        const int32_t u = a.ci[k];
+        const uint64_t g = front[u] & missing & ~got;
+        if (g) {
+          got |= g;
+          if (PAR) {
+            uint64_t x = g;
+            while (x) {
+              const int bb = __ffsll((unsigned long long)x) - 1;
+              x &= x - 1;
+              a.parents[(int64_t)bb * a.n + v] = u;
+            }
+          }
+          if (got == missing) break;
+        }
+      }
+    }
+    uint64_t rem = __ballot(act && d > kLaneRow);
+    while (rem) {
+      const int L = __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1;
+      const int64_t kb = __shfl(b, L, kWave), ke = __shfl(e, L, kWave);
+      const uint64_t mL = __shfl(missing, L, kWave);
+      const int64_t vL = w * kWave + L;
+      uint64_t gotL = 0;
+      for (int64_t c = kb; c < ke; c += kWave) {
+        const int64_t k = c + lane;
+        int32_t u = -1;
+        uint64_t g = 0;
+        if (k < ke) {
+          u = a.ci[k];
+          g = front[u] & mL;
+        }
+        const uint64_t fresh = wave_or(g) & ~gotL;
+        if (fresh) {
+          step_parents<PAR>(a, vL, fresh, g, u);
+          gotL |= fresh;
+          if (gotL == mL) break;
+        }
+      }
+      if (lane == L) got = gotL;
+    }
+    if (got) {
+      next[v] = got;
+      a.seen[v] = s | got;
+      acc.nf += 1;
+      acc.mf += (uint64_t)d;
+      if ((s | got) == a.full) acc.dec += (uint64_t)d;
+    }
+    uint64_t any = wave_or(got);
+    while (any) {  // one coalesced byte row per root
+      const int bb = __ffsll((unsigned long long)any) - 1;
+      any &= any - 1;
+      if ((got >> bb) & 1) a.levels[(int64_t)bb * a.n + v] = lvl;
+    }
+  }
+  for (int64_t c = gw; c < a.hub_chunks; c += nw) {
+    const int64_t i = hub_of(a, (uint64_t)c);
+    const int32_t h = a.hub_list[i];
+    const uint64_t sh = a.seen[h];
+    if (sh == a.full) continue;
+    const uint64_t mh = a.full & ~sh;
+    const int64_t kb = a.rp[h] + (int64_t)((uint64_t)c - a.hub_off[i]) * kHubChunk;
+    const int64_t ke = std::min<int64_t>(kb + kHubChunk, a.rp[h + 1]);
+    uint64_t gotc = 0;
+    for (int64_t cc = kb; cc < ke; cc += kWave) {
+      const int64_t k = cc + lane;
+      int32_t u = -1;
+      uint64_t g = 0;
+      if (k < ke) {
+        u = a.ci[k];
+        g = front[u] & mh;
+      }
+      const uint64_t fresh = wave_or(g) & ~gotc;
+      if (!fresh) continue;
+      gotc |= fresh;
+      uint64_t old = 0;
+      if (lane == 0) old = atomicOr((unsigned long long *)&next[h], (unsigned long long)fresh);
+      old = __shfl(old, 0, kWave);
+      const uint64_t won = fresh & ~old;
+      if (won) {
+        step_parents<PAR>(a, h, won, g, u);
+        if (lane == 0) commit_atomic<false>(a, h, won, old, -1, lvl, acc);
+      }
+      if (gotc == mh) break;
+    }
+  }
+}
+
+template <bool PAR>
+__global__ __launch_bounds__(kBlock) void k_msbfs(MsArgs a) {
+  cg::grid_group grid = cg::this_grid();
+  if (!grid.is_valid()) return;  // only a cooperative launch may run this kernel
+  __shared__ uint64_t s_red[kBlock / kWave];
+  MsCtl *ctl = a.ctl;
+  const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gthreads = (int64_t)gridDim.x * kBlock;
+  const int64_t gw = gtid / kWave, nw = gthreads / kWave;
+
+  {  // counters of the root frontier
+    uint64_t nf = 0, mf = 0, mu = 0;
+    for (int64_t v = gtid; v < a.n; v += gthreads) {
+      const uint64_t f = a.buf0[v], s = a.seen[v];
+      const int64_t d = a.rp[v + 1] - a.rp[v];
+      if (f) {
+        nf += 1;
+        mf += (uint64_t)d;
+      }
+      if (s != a.full) mu += (uint64_t)d;
+    }
+    nf = block_sum<kBlock, uint64_t>(nf, s_red);
+    mf = block_sum<kBlock, uint64_t>(mf, s_red);
+    mu = block_sum<kBlock, uint64_t>(mu, s_red);
+    if (threadIdx.x == 0) {
+      atomicAdd(&ctl->slot[0].nf, (unsigned long long)nf);
+      atomicAdd(&ctl->slot[0].mf, (unsigned long long)mf);
+      atomicAdd(&ctl->mu0, (unsigned long long)mu);
+    }
+  }
+  grid.sync();
+  uint64_t mu = ld_agent(&ctl->mu0);
+  uint64_t *bufs[3] = {a.buf0, a.buf1, a.buf2};
+  for (int l = 0;; ++l) {
+    Slot *cur = &ctl->slot[l % 3], *nxt = &ctl->slot[(l + 1) % 3], *old = &ctl->slot[(l + 2) % 3];
+    const uint64_t nf = ld_agent(&cur->nf), mf = ld_agent(&cur->mf);
+    if (nf == 0) break;
+    const bool td = a.direction == G5_DIR_TOPDOWN ||
+                    (a.direction == G5_DIR_AUTO && (double)mf <= (double)mu / a.alpha);
+    if (gtid == 0) {
+      atomicExch(&old->nf, 0ull);
+      atomicExch(&old->mf, 0ull);
+      atomicExch(&old->dec, 0ull);
+      ctl->nlevels = (unsigned long long)(l + 1);
+      if (l < kStatLevels) {
+        ctl->dir[l] = td ? 1 : 2;
+        ctl->frontier[l] = (int64_t)nf;
+      }
+    }
+    const uint64_t *front = bufs[l % 3];
+    uint64_t *next = bufs[(l + 1) % 3];
+    uint64_t *clr = bufs[(l + 2) % 3];
+    for (int64_t v = gtid; v < a.n; v += gthreads) clr[v] = 0;
+    Acc acc;
+    if (td)
+      td_phase<PAR>(a, front, next, (int8_t)(l + 1), gw, nw, acc);
+    else
+      bu_phase<PAR>(a, front, next, (int8_t)(l + 1), gw, nw, acc);
+    const uint64_t tnf = block_sum<kBlock, uint64_t>(acc.nf, s_red);
+    const uint64_t tmf = block_sum<kBlock, uint64_t>(acc.mf, s_red);
+    const uint64_t tdec = block_sum<kBlock, uint64_t>(acc.dec, s_red);
+    if (threadIdx.x == 0) {
+      if (tnf) atomicAdd(&nxt->nf, (unsigned long long)tnf);
+      if (tmf) atomicAdd(&nxt->mf, (unsigned long long)tmf);
+      if (tdec) atomicAdd(&nxt->dec, (unsigned long long)tdec);
+    }
+    grid.sync();
+    mu -= ld_agent(&nxt->dec);
+    if (l + 1 > a.max_level && ld_agent(&nxt->nf) != 0) {
+      // a vertex lies deeper than int8 can hold (its level byte wrapped)
+      if (gtid == 0) atomicExch(&ctl->err, 1ull);
+      break;
+    }
+  }
+}
+
+__global__ void k_fill_i8(int8_t *__restrict__ p, int64_t len, bool vec) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t n16 = vec ? len / 16 : 0;
+  int4 m1 = make_int4(-1, -1, -1, -1);
+  for (int64_t i = t; i < n16; i += stride) reinterpret_cast<int4 *>(p)[i] = m1;
+  for (int64_t i = n16 * 16 + t; i < len; i += stride) p[i] = -1;
+}
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t len, bool vec) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t n4 = vec ? len / 4 : 0;
+  int4 m1 = make_int4(-1, -1, -1, -1);
+  for (int64_t i = t; i < n4; i += stride) reinterpret_cast<int4 *>(p)[i] = m1;
+  for (int64_t i = n4 * 4 + t; i < len; i += stride) p[i] = -1;
+}
+
+__global__ void k_zero_words(uint64_t *__restrict__ p, int64_t len) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
+}
+
+__global__ void k_ms_seed(const int64_t *__restrict__ roots, int k, int64_t n, uint64_t *seen,
+                          uint64_t *front, int8_t *levels, int32_t *parents) {
+  int b = threadIdx.x;
+  if (b >= k) return;
+  int64_t v = roots[b];
+  atomicOr((unsigned long long *)&seen[v], 1ull << b);
+  atomicOr((unsigned long long *)&front[v], 1ull << b);
+  levels[(int64_t)b * n + v] = 0;
+  if (parents) parents[(int64_t)b * n + v] = (int32_t)v;
+}
+
+int grid_for(int64_t items, int per_block, int cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+BatchWork::~BatchWork() {
+  if (seen) (void)hipFree(seen);
+  for (auto *b : buf)
+    if (b) (void)hipFree(b);
+  if (ctl) (void)hipFree(ctl);
+  if (host_ctl) (void)hipHostFree(host_ctl);
+  if (roots) (void)hipFree(roots);
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+namespace {
+g5_status alloc_batch(const g5_csr *g, BatchWork **out) {
+  BatchWork *w = new BatchWork();
+  w->n = g->n;
+  hipError_t e = hipSuccess;
+  auto A = [&](void **p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  A((void **)&w->seen, g->n * 8);
+  for (auto &b : w->buf) A((void **)&b, g->n * 8);
+  A(&w->ctl, sizeof(MsCtl));
+  A((void **)&w->roots, 64 * sizeof(int64_t));
+  if (e == hipSuccess) e = hipHostMalloc(&w->host_ctl, sizeof(MsCtl), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_error(std::string("g5_bfs_batch workspace: ") + hipGetErrorString(e));
+    delete w;
+    return e == hipErrorOutOfMemory ? G5_ENOMEM : G5_EDEVICE;
+  }
+  *out = w;
+  return G5_OK;
+}
+
+struct BatchLease {
+  const g5_csr *g;
+  BatchWork *w = nullptr;
+  ~BatchLease() {
+    if (w) {
+      std::lock_guard<std::mutex> lk(g->mu);
+      g->batch_pool.push_back(w);
+    }
+  }
+};
+}  // namespace
+
+g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *parents,
+                         int8_t *levels, hipStream_t s, const g5_batch_params &p,
+                         g5_batch_stats *stats) {
+  BatchLease lease{g};
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->batch_pool.empty()) {
+      lease.w = g->batch_pool.back();
+      g->batch_pool.pop_back();
+    }
+  }
+  if (!lease.w) {
+    g5_status st = alloc_batch(g, &lease.w);
+    if (st != G5_OK) return st;
+  }
+  BatchWork &w = *lease.w;
+  const int64_t n = g->n;
+  const int ncu = g->num_cu;
+  const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
+  if (timed && !w.ev[0]) {
+    for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
+  }
+
+  G5_HIP(hipMemcpyAsync(w.roots, roots, k * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  const int fg = ncu * 16;
+  hipLaunchKernelGGL(k_fill_i8, dim3(grid_for((int64_t)k * n / 16, 256, fg)), dim3(256), 0, s,
+                     levels, (int64_t)k * n, ((uintptr_t)levels & 15) == 0);
+  if (parents)
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)k * n / 4, 256, fg)), dim3(256), 0, s,
+                       parents, (int64_t)k * n, ((uintptr_t)parents & 15) == 0);
+  hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, w.seen, n);
+  for (auto *b : w.buf)
+    hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, b, n);
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (uint64_t *)w.ctl,
+                     (int64_t)(sizeof(MsCtl) / 8));
+  hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, w.roots, k, n, w.seen, w.buf[0], levels,
+                     parents);
+  G5_LAUNCH_CHECK();
+
+  MsArgs a;
+  a.rp = g->row_ptr;
+  a.ci = g->col_idx;
+  a.n = n;
+  a.full = (k == 64) ? ~0ull : ((1ull << k) - 1);
+  a.seen = w.seen;
+  a.buf0 = w.buf[0];
+  a.buf1 = w.buf[1];
+  a.buf2 = w.buf[2];
+  a.levels = levels;
+  a.parents = parents;
+  a.hub_list = g->hub_list;
+  a.hub_off = g->hub_off;
+  a.num_hubs = g->num_hubs;
+  a.hub_chunks = g->hub_chunks;
+  a.ctl = (MsCtl *)w.ctl;
+  a.alpha = p.alpha > 0 ? p.alpha : 14.0;
+  a.direction = p.direction;
+  a.max_level = 127;
+
+  const void *fn = parents ? reinterpret_cast<const void *>(&k_msbfs<true>)
+                           : reinterpret_cast<const void *>(&k_msbfs<false>);
+  int per_cu = 0;
+  G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0));
+  if (per_cu < 1) {
+    set_error("g5_bfs_batch: the persistent kernel does not fit on a compute unit");
+    return G5_EDEVICE;
+  }
+  const int blocks = ncu * std::min(per_cu, 8);
+  void *args[] = {&a};
+  if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
+  G5_HIP(hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kBlock), args, 0, s));
+  if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
+  G5_HIP(hipMemcpyAsync(w.host_ctl, w.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
+  G5_HIP(hipStreamSynchronize(s));
+  const MsCtl *hc = (const MsCtl *)w.host_ctl;
+  if (stats) {
+    *stats = g5_batch_stats{};
+    stats->nlevels = (int32_t)hc->nlevels;
+    for (int i = 0; i < std::min<int>((int)hc->nlevels, kStatLevels); ++i) {
+      stats->dir[i] = hc->dir[i];
+      stats->frontier[i] = hc->frontier[i];
+    }
+    stats->grid_blocks = blocks;
+    if (timed) {
+      float ms = 0;
+      G5_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));
+      stats->launch_ms = ms;
+    }
+  }
+  if (hc->err) {
+    set_error("g5_bfs_batch: a level exceeds 127 (int8 levels); use g5_bfs for this root set");
+    return G5_ERANGE;
+  }
+  return G5_OK;
+}
+
 }  // namespace g5

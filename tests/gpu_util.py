@@ -43,3 +43,22 @@ class Case:
         rule = O.validate(self.ocsr, root, parent, level, self.label)
         assert rule == 0, f"root {root} {kw}: parent array invalid ({O.RULES[rule]})"
         return parent, level
+
+
+def check_batch(case, roots, **kw):
+    """g5_bfs_batch rows vs the oracle: levels bit-exact (int8), parents valid."""
+    import paper_2012_13548_amd as g5
+    want_par = kw.pop("parents", True)
+    res = g5.bfs_batch(case.csr, roots, parents=want_par, stats=True, **kw)
+    parents, levels, info = res
+    levels = levels.cpu().numpy()
+    parents = parents.cpu().numpy() if parents is not None else None
+    for b, r in enumerate(roots):
+        _, olevel = O.bfs(case.ocsr, r)
+        bad = np.flatnonzero(levels[b].astype(np.int32) != olevel)
+        assert bad.size == 0, (f"batch row {b} root {r} {kw}: {bad.size} levels differ, first "
+                               f"{bad[:5]}: gpu {levels[b][bad[:5]]} oracle {olevel[bad[:5]]}")
+        if parents is not None:
+            rule = O.validate(case.ocsr, r, parents[b], olevel, case.label)
+            assert rule == 0, f"batch row {b} root {r} {kw}: parents invalid ({O.RULES[rule]})"
+    return parents, levels, info
