@@ -86,17 +86,20 @@ typedef enum {
   G5_DIR_BOTTOMUP = 2  /* every level after the root's bottom-up */
 } g5_direction;
 
-/* Tuning knobs of g5_bfs_ex.  Zero fields take the library defaults. */
+/* Tuning knobs of g5_bfs_ex.  Zero fields take the defaults that g5_build_csr
+ * picked for the graph from the autotuned table compiled into the library
+ * (the entry tuned at the scale nearest to log2 n). */
 typedef struct {
   int32_t direction;    /* g5_direction */
-  double alpha;         /* top-down -> bottom-up when m_f > m_u / alpha (default 14) */
-  double beta;          /* bottom-up -> top-down when n_f < n / beta, shrinking (default 24) */
+  double alpha;         /* top-down -> bottom-up when m_f > m_u / alpha */
+  double beta;          /* bottom-up -> top-down when n_f < n / beta and shrinking */
   int32_t bu_lane_scan; /* neighbours a lane tests before its row goes wave-wide: 1, 2, 4, 8
-                           or 16 (default 4) */
+                           or 16 */
   int32_t claim;        /* top-down claim: 0 atomic OR on the visited bitmap (default),
                            1 compare-and-swap of parent from -1 */
   int32_t flags;        /* G5_FLAG_* */
-  int32_t reserved[5];
+  int32_t bu_blocks_per_cu; /* bottom-up grid: workgroups per compute unit (1..32) */
+  int32_t reserved[4];
 } g5_bfs_params;
 
 /* Time each level's step with HIP events on `stream` (step_ms in the stats). */
@@ -106,12 +109,20 @@ typedef struct {
  *   top-down   20 per frontier vertex (queue entry + two row offsets)
  *              + 4 per frontier edge + 12 per discovered vertex (level, parent,
  *              queue entry);
- *   bottom-up  8 per unvisited non-isolated vertex (its row offset)
- *              + 4 per neighbour examined up to the first frontier hit
- *              + n/4 (visited words read, next-frontier words written)
+ *   bottom-up  8 per unvisited non-isolated vertex (its row offset; 12 with the
+ *              neighbour hint) + 4 per row entry read up to the first frontier
+ *              hit + n/4 (visited words read, next-frontier words written)
  *              + 8 per discovered vertex (level, parent).
- * Frontier-bitmap probes (one per examined neighbour) are reported apart. */
+ * Frontier-bitmap probes (one per examined neighbour) are not counted. */
 #define G5_FLAG_COUNT_BYTES 2
+/* Do not test each vertex's highest-degree neighbour (built by g5_build_csr)
+ * before its row in bottom-up steps. */
+#define G5_FLAG_NO_HINT 4
+/* g5_bfs_batch_ex: one plain launch per level instead of one cooperative
+ * persistent launch (same results).  A persistent launch waits at grid-wide
+ * barriers for all of its workgroups, so it should own the device; stepped
+ * batches can overlap other work on other streams. */
+#define G5_FLAG_STEPPED 8
 
 #define G5_MAX_STAT_LEVELS 64
 
@@ -127,7 +138,9 @@ typedef struct {
   int64_t bytes[G5_MAX_STAT_LEVELS];        /* algorithmic bytes (COUNT_BYTES only) */
   double step_ms[G5_MAX_STAT_LEVELS];       /* device time of the step (TIME_STEPS only) */
   int64_t reached;                          /* vertices with level >= 0 */
-  int64_t reserved[8];
+  double alpha, beta;                       /* switch thresholds used */
+  int32_t bu_lane_scan, bu_blocks_per_cu;   /* bottom-up shape used */
+  int64_t reserved[6];
 } g5_bfs_stats;
 
 /* g5_bfs with explicit parameters (NULL = defaults) and optional statistics
@@ -153,11 +166,12 @@ g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t
 /* Knobs of g5_bfs_batch_ex.  Zero fields take the defaults. */
 typedef struct {
   int32_t direction; /* g5_direction applied to every level of the batch */
-  double alpha;      /* top-down while m_f <= m_u / alpha (default 14), where m_f is the degree
+  double alpha;      /* top-down while m_f <= m_u / alpha (tuned default), where m_f is the degree
                         sum of vertices with a nonzero frontier mask and m_u the degree sum of
                         vertices not yet reached by every root */
-  int32_t flags;     /* G5_FLAG_TIME_STEPS: time the persistent launch */
-  int32_t reserved[5];
+  int32_t flags;     /* G5_FLAG_TIME_STEPS: time the launch(es); G5_FLAG_STEPPED */
+  int32_t blocks_per_cu; /* persistent grid: workgroups per compute unit (capped by occupancy) */
+  int32_t reserved[4];
 } g5_batch_params;
 
 /* Statistics of g5_bfs_batch_ex (host memory). */
@@ -167,7 +181,9 @@ typedef struct {
   int64_t frontier[G5_MAX_STAT_LEVELS];    /* vertices with a nonzero frontier mask */
   double launch_ms;                        /* device time of the persistent launch (TIME_STEPS) */
   int32_t grid_blocks;                     /* workgroups of the persistent launch */
-  int32_t reserved[7];
+  int32_t pad;
+  double alpha;                            /* switch threshold used */
+  int32_t reserved[6];
 } g5_batch_stats;
 
 /* g5_bfs_batch with explicit parameters (NULL = defaults) and statistics

@@ -38,14 +38,14 @@ import torch  # noqa: E402,F401
 lib = ctypes.CDLL(LIB_PATH)
 
 
-FLAG_TIME_STEPS, FLAG_COUNT_BYTES = 1, 2
+FLAG_TIME_STEPS, FLAG_COUNT_BYTES, FLAG_NO_HINT, FLAG_STEPPED = 1, 2, 4, 8
 
 
 class BfsParams(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("bu_lane_scan", ctypes.c_int32),
                 ("claim", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("bu_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 _L = MAX_STAT_LEVELS
@@ -56,18 +56,22 @@ class BfsStats(ctypes.Structure):
                 ("frontier", ctypes.c_int64 * _L), ("discovered", ctypes.c_int64 * _L),
                 ("edges", ctypes.c_int64 * _L), ("bytes", ctypes.c_int64 * _L),
                 ("step_ms", ctypes.c_double * _L), ("reached", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 8)]
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("bu_lane_scan", ctypes.c_int32), ("bu_blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 6)]
 
 
 class BatchParams(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("alpha", ctypes.c_double),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("flags", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("nlevels", ctypes.c_int32), ("dir", ctypes.c_int32 * _L),
                 ("frontier", ctypes.c_int64 * _L), ("launch_ms", ctypes.c_double),
-                ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("grid_blocks", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("reserved", ctypes.c_int32 * 6)]
 
 
 _P = ctypes.c_void_p
@@ -163,8 +167,9 @@ def build_csr(edges, n):
     return Csr(out.value, edges.device)
 
 
-def _params(direction, alpha, beta, lane_scan, claim, flags):
+def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None):
     p = BfsParams()
+    p.bu_blocks_per_cu = blocks_per_cu or 0
     p.direction = direction
     p.alpha = alpha or 0.0
     p.beta = beta or 0.0
@@ -175,7 +180,8 @@ def _params(direction, alpha, beta, lane_scan, claim, flags):
 
 
 def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta=None,
-        lane_scan=None, claim=CLAIM_OR, stats=False, time_steps=False, count_bytes=False):
+        lane_scan=None, claim=CLAIM_OR, hint=True, blocks_per_cu=None, stats=False,
+        time_steps=False, count_bytes=False):
     """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
 
     With ``stats=True`` also returns a dict of per-level directions, frontier
@@ -190,8 +196,9 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
     for t in (parent, level):
         if t.dtype != torch.int32 or t.numel() < csr.n or not t.is_contiguous():
             raise ValueError("parent and level must be contiguous int32 tensors of length n")
-    flags = (FLAG_TIME_STEPS if time_steps else 0) | (FLAG_COUNT_BYTES if count_bytes else 0)
-    p = _params(direction, alpha, beta, lane_scan, claim, flags)
+    flags = ((FLAG_TIME_STEPS if time_steps else 0) | (FLAG_COUNT_BYTES if count_bytes else 0)
+             | (0 if hint else FLAG_NO_HINT))
+    p = _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu)
     want = stats or flags
     st = BfsStats()
     _check(lib.g5_bfs_ex(csr.handle, int(root), parent.data_ptr(), level.data_ptr(),
@@ -200,15 +207,17 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
     if not want:
         return parent, level
     nl = min(st.nlevels, MAX_STAT_LEVELS)
-    info = {"nlevels": st.nlevels, "reached": st.reached}
+    info = {"nlevels": st.nlevels, "reached": st.reached, "alpha": st.alpha, "beta": st.beta,
+            "lane_scan": st.bu_lane_scan, "blocks_per_cu": st.bu_blocks_per_cu}
     for k in ("dir", "frontier", "discovered", "edges", "bytes", "step_ms"):
         info[k] = list(getattr(st, k)[:nl])
     return parent, level, info
 
 
 def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=DIR_AUTO,
-              alpha=None, stats=False, time_launch=False):
-    """Batched BFS from 1..64 roots in one persistent launch.
+              alpha=None, blocks_per_cu=None, stepped=False, stats=False, time_launch=False):
+    """Batched BFS from 1..64 roots in one persistent launch (``stepped=True``:
+    one plain launch per level, which may overlap other streams' work).
 
     Returns (parents int32 [k, n] or None, levels int8 [k, n]) and, with
     ``stats=True``, a dict of per-level directions and frontier sizes.
@@ -227,7 +236,8 @@ def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=
     p = BatchParams()
     p.direction = direction
     p.alpha = alpha or 0.0
-    p.flags = FLAG_TIME_STEPS if time_launch else 0
+    p.flags = (FLAG_TIME_STEPS if time_launch else 0) | (FLAG_STEPPED if stepped else 0)
+    p.blocks_per_cu = blocks_per_cu or 0
     st = BatchStats()
     want = stats or time_launch
     _check(lib.g5_bfs_batch_ex(csr.handle, arr, k, pp, levels.data_ptr(), _stream(csr.device),
@@ -238,5 +248,5 @@ def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=
         return out
     nl = min(st.nlevels, MAX_STAT_LEVELS)
     info = {"nlevels": st.nlevels, "dir": list(st.dir[:nl]), "frontier": list(st.frontier[:nl]),
-            "launch_ms": st.launch_ms, "grid_blocks": st.grid_blocks}
+            "launch_ms": st.launch_ms, "grid_blocks": st.grid_blocks, "alpha": st.alpha}
     return out + (info,)

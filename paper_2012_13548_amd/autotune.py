@@ -1,0 +1,152 @@
+"""Autotuner for the traversal's thresholds and launch shapes.
+
+For each Kronecker scale, a coordinate search over
+  single root: alpha, beta (direction switch), bottom-up lane-scan width and
+               bottom-up workgroups per compute unit; objective = harmonic-mean
+               TEPS over sample roots (m_r / device time per call);
+  batch:       alpha and persistent-grid workgroups per compute unit;
+               objective = device time of one 64-root launch with parents.
+Writes ``tuning.json`` (every trial) and ``tuned_table.inc`` (the defaults table
+compiled into libg5; g5_build_csr picks the entry nearest to log2 n).
+
+    python -m paper_2012_13548_amd.autotune --scales 20 22 26 --out DIR
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ALPHA = [6, 10, 14, 20, 28, 40, 56, 80, 112, 160]
+BETA = [6, 12, 24, 48, 96, 192]
+LANE = [1, 2, 4, 8, 16]
+BPC = [4, 8, 16, 32]
+B_ALPHA = [2, 4, 8, 14, 28, 56, 112]
+B_BPC = [2, 4, 8]
+
+
+def log(msg):
+    sys.stderr.write(f"[autotune] {msg}\n")
+    sys.stderr.flush()
+
+
+def tune_scale(scale, nroots, rounds):
+    import torch
+    import kronecker as K
+    import paper_2012_13548_amd as g5
+
+    n = 1 << scale
+    dev = torch.device("cuda:0")
+    e = K.edges_device(scale, device=dev)
+    csr = g5.build_csr(e, n)
+    roots = K.select_roots(K.nonisolated_device(e, n).cpu().numpy(), max(nroots, 64),
+                           K.root_seed(scale) + 7)  # tuning roots differ from benchmark roots
+    del e
+    torch.cuda.empty_cache()
+    rp, _ = csr.arrays()
+    deg = rp[1:] - rp[:-1]
+    del rp
+    parent = torch.empty(n, dtype=torch.int32, device=dev)
+    level = torch.empty(n, dtype=torch.int32, device=dev)
+    sample = roots[:nroots]
+    m_r = []
+    for r in sample:
+        g5.bfs(csr, r, parent, level)
+        m_r.append(int(deg[level >= 0].sum().item()) // 2)
+    del deg
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def single(cfg):
+        inv = 0.0
+        for r, m in zip(sample, m_r):
+            e0.record()
+            g5.bfs(csr, r, parent, level, alpha=cfg["alpha"], beta=cfg["beta"],
+                   lane_scan=cfg["lane_scan"], blocks_per_cu=cfg["bu_blocks_per_cu"])
+            e1.record()
+            torch.cuda.synchronize()
+            inv += (e0.elapsed_time(e1) / 1e3) / m
+        return len(sample) / inv
+
+    trials = []
+
+    def search(cfg, space, score, higher=True):
+        best = score(cfg)
+        trials.append({**cfg, "score": best})
+        for _ in range(rounds):
+            for knob, values in space.items():
+                for v in values:
+                    if v == cfg[knob]:
+                        continue
+                    c = {**cfg, knob: v}
+                    s = score(c)
+                    trials.append({**c, "score": s})
+                    if (s > best) if higher else (s < best):
+                        best, cfg = s, c
+                log(f"scale {scale} {knob} -> {cfg[knob]} ({best:.4g})")
+        return cfg, best
+
+    t0 = time.time()
+    single(dict(alpha=14, beta=24, lane_scan=4, bu_blocks_per_cu=8))  # warm
+    cfg, best = search(dict(alpha=14, beta=24, lane_scan=4, bu_blocks_per_cu=8),
+                       {"alpha": ALPHA, "beta": BETA, "lane_scan": LANE, "bu_blocks_per_cu": BPC},
+                       single)
+    out = {"scale": scale, **cfg, "hmean_gteps": round(best / 1e9, 3), "roots": len(sample)}
+
+    k = 64
+    levels = torch.empty((k, n), dtype=torch.int8, device=dev)
+    parents = torch.empty((k, n), dtype=torch.int32, device=dev)
+    broots = roots[:k]
+
+    def batch(c):
+        ts = []
+        for _ in range(2):
+            _, _, st = g5.bfs_batch(csr, broots, levels=levels, parent_out=parents,
+                                    alpha=c["batch_alpha"], blocks_per_cu=c["batch_blocks_per_cu"],
+                                    time_launch=True)
+            ts.append(st["launch_ms"])
+        return min(ts)
+
+    bcfg, bbest = search(dict(batch_alpha=14, batch_blocks_per_cu=8),
+                         {"batch_alpha": B_ALPHA, "batch_blocks_per_cu": B_BPC}, batch,
+                         higher=False)
+    out.update(bcfg)
+    out["batch_ms"] = round(bbest, 3)
+    out["seconds"] = round(time.time() - t0, 1)
+    out["trials"] = trials
+    log(f"scale {scale}: {json.dumps({k_: v for k_, v in out.items() if k_ != 'trials'})}")
+    del csr, levels, parents
+    torch.cuda.empty_cache()
+    return out
+
+
+def write_table(entries, path):
+    lines = ["// Autotuned defaults: {scale, alpha, beta, lane_scan, bu_blocks_per_cu, batch_alpha,",
+             "// batch_blocks_per_cu}.  Written by paper_2012_13548_amd/autotune.py from its",
+             "// measurements (tuning.json); the entry nearest to log2 n is used."]
+    for e in sorted(entries, key=lambda x: x["scale"]):
+        lines.append(f"{{{e['scale']}, {float(e['alpha']):.1f}, {float(e['beta']):.1f}, "
+                     f"{e['lane_scan']}, {e['bu_blocks_per_cu']}, {float(e['batch_alpha']):.1f}, "
+                     f"{e['batch_blocks_per_cu']}}},")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--scales", type=int, nargs="+", default=[20, 22, 26])
+    ap.add_argument("--roots", type=int, default=16)
+    ap.add_argument("--rounds", type=int, default=2)
+    ap.add_argument("--out", default=".")
+    args = ap.parse_args()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    entries = [tune_scale(s, args.roots, args.rounds) for s in args.scales]
+    os.makedirs(args.out, exist_ok=True)
+    with open(os.path.join(args.out, "tuning.json"), "w") as f:
+        json.dump({"arch": "gfx950", "entries": entries}, f, indent=1)
+    write_table(entries, os.path.join(args.out, "tuned_table.inc"))
+    print(json.dumps([{k: v for k, v in e.items() if k != "trials"} for e in entries]))
+
+
+if __name__ == "__main__":
+    main()

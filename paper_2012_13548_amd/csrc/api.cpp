@@ -2,6 +2,7 @@
 // error state and dispatch to the device implementations.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -11,8 +12,18 @@
 namespace g5 {
 namespace {
 thread_local std::string t_err;
-}
+const Tuning kTuned[] = {
+#include "tuned_table.inc"
+};
+}  // namespace
 void set_error(const std::string &msg) { t_err = msg; }
+
+Tuning pick_tuning(int scale) {
+  const Tuning *best = &kTuned[0];
+  for (const Tuning &t : kTuned)
+    if (std::abs(t.scale - scale) < std::abs(best->scale - scale)) best = &t;
+  return *best;
+}
 }  // namespace g5
 
 using g5::set_error;
@@ -70,6 +81,7 @@ void g5_csr_free(g5_csr *g) {
   if (g->row_ptr) (void)hipFree(g->row_ptr);
   if (g->col_idx) (void)hipFree(g->col_idx);
   if (g->iso) (void)hipFree(g->iso);
+  if (g->hint) (void)hipFree(g->hint);
   if (g->hub_list) (void)hipFree(g->hub_list);
   if (g->hub_off) (void)hipFree(g->hub_off);
   delete g;
@@ -91,9 +103,9 @@ g5_status g5_bfs_ex(const g5_csr *g, int64_t root, int32_t *parent, int32_t *lev
   if (params) p = *params;
   if (p.direction < 0 || p.direction > 2 || p.claim < 0 || p.claim > 1 || p.bu_lane_scan < 0 ||
       p.bu_lane_scan > 16 || (p.bu_lane_scan & (p.bu_lane_scan - 1)) != 0 || p.alpha < 0 ||
-      p.beta < 0) {
+      p.beta < 0 || p.bu_blocks_per_cu < 0 || p.bu_blocks_per_cu > 32) {
     set_error("g5_bfs: direction must be 0..2, claim 0..1, bu_lane_scan 0 or a power of two "
-              "up to 16, alpha and beta >= 0");
+              "up to 16, alpha and beta >= 0, bu_blocks_per_cu 0..32");
     return G5_EINVAL;
   }
   try {
@@ -127,8 +139,9 @@ g5_status g5_bfs_batch_ex(const g5_csr *g, const int64_t *roots, int32_t k, int3
   g5_batch_params p;
   std::memset(&p, 0, sizeof(p));
   if (params) p = *params;
-  if (p.direction < 0 || p.direction > 2 || p.alpha < 0) {
-    set_error("g5_bfs_batch: direction must be 0..2 and alpha >= 0");
+  if (p.direction < 0 || p.direction > 2 || p.alpha < 0 || p.blocks_per_cu < 0 ||
+      p.blocks_per_cu > 32) {
+    set_error("g5_bfs_batch: direction must be 0..2, alpha >= 0, blocks_per_cu 0..32");
     return G5_EINVAL;
   }
   try {

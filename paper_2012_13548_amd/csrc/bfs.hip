@@ -49,8 +49,8 @@ enum Ctr : int {
 };
 
 __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ parent, int64_t n,
-                           uint64_t *__restrict__ vis, const uint64_t *__restrict__ iso,
-                           int64_t words, bool vec) {
+                           uint64_t *__restrict__ vis, uint64_t *__restrict__ prev,
+                           const uint64_t *__restrict__ iso, int64_t words, bool vec) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t n4 = vec ? n / 4 : 0;
@@ -63,7 +63,10 @@ __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ pa
     level[i] = -1;
     parent[i] = -1;
   }
-  for (int64_t i = t; i < words; i += stride) vis[i] = iso[i];
+  for (int64_t i = t; i < words; i += stride) {
+    vis[i] = iso[i];
+    prev[i] = iso[i];
+  }
 }
 
 __global__ void k_bfs_seed(int64_t root, int32_t *level, int32_t *parent, uint64_t *vis,
@@ -247,13 +250,21 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
   for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) qn[s_gbase + k] = s_out[k];
 }
 
-// Frontier queue -> frontier bitmap (bitmap cleared beforehand).
-__global__ void k_q2front(const int32_t *__restrict__ q, int64_t qlen, uint64_t *front) {
+// Frontier bitmap of the last top-down level without atomics: the vertices
+// visited now but not before that level's expansion.
+__global__ void k_front_from_vis(const uint64_t *__restrict__ vis,
+                                 const uint64_t *__restrict__ prev, uint64_t *__restrict__ front,
+                                 int64_t words) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qlen; i += stride) {
-    int32_t v = q[i];
-    atomicOr((unsigned long long *)(front + (v >> 6)), 1ull << (v & 63));
-  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+    front[i] = vis[i] & ~prev[i];
+}
+
+__global__ void k_copy_u64(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src,
+                           int64_t words) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+    dst[i] = src[i];
 }
 
 // Bottom-up step.  Wavefront per 64-bit word w of the visited bitmap; lane l
@@ -264,7 +275,8 @@ __global__ void k_q2front(const int32_t *__restrict__ q, int64_t qlen, uint64_t 
 // vertices scanned (algorithmic-byte accounting).
 template <int LANE_SCAN, bool ACCT>
 __global__ __launch_bounds__(kBlock) void k_bu_step(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, uint64_t *__restrict__ vis,
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
     int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
     int32_t next_level, unsigned long long *__restrict__ ctr) {
@@ -288,6 +300,17 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
       b = rp[v];
       e = rp[v + 1];
       k = b;
+      if (ACCT) nunvis += 1;
+      if (hint) {  // the highest-degree neighbour first: one coalesced load
+        const int32_t h = hint[v];
+        if (h >= 0 && ((front[h >> 6] >> (h & 63)) & 1)) {
+          found = true;
+          par = h;
+          k = e;
+        }
+      }
+    }
+    if (pending && !found) {
       int32_t u[LANE_SCAN];
       uint64_t fw[LANE_SCAN];
 #pragma unroll
@@ -302,11 +325,9 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
           if (ACCT) nscan += (uint64_t)(t + 1);
         }
       }
+      const int64_t k0 = k;
       k = std::min<int64_t>(k + LANE_SCAN, e);
-      if (ACCT) {
-        nunvis += 1;
-        if (!found) nscan += (uint64_t)(k - b);
-      }
+      if (ACCT && !found) nscan += (uint64_t)(k - k0);
     }
     uint64_t rem = __ballot(pending && !found && k < e);
     while (rem) {
@@ -413,7 +434,7 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   w->words = g->words;
   int64_t n = g->n, W = g->words;
   int64_t nb = (n + kDegTile - 1) / kDegTile + 1;
-  int64_t nbf = (int64_t)g->num_cu * 8 + 1;
+  int64_t nbf = (int64_t)g->num_cu * 32 + 1;  // bitmap->queue blocks: up to 32 per CU
   hipError_t e = hipSuccess;
   auto A = [&](void **p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
@@ -421,6 +442,7 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   A((void **)&w->vis, W * 8);
   A((void **)&w->front, W * 8);
   A((void **)&w->next, W * 8);
+  A((void **)&w->prev, W * 8);
   A((void **)&w->q[0], n * 4);
   A((void **)&w->q[1], n * 4);
   A((void **)&w->qoff, (n + 1) * 4);
@@ -453,6 +475,7 @@ BfsWork::~BfsWork() {
   if (vis) (void)hipFree(vis);
   if (front) (void)hipFree(front);
   if (next) (void)hipFree(next);
+  if (prev) (void)hipFree(prev);
   if (q[0]) (void)hipFree(q[0]);
   if (q[1]) (void)hipFree(q[1]);
   if (qoff) (void)hipFree(qoff);
@@ -480,21 +503,23 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   BfsWork &w = *lease.w;
   const int64_t n = g->n, W = g->words;
   const int ncu = g->num_cu;
-  const double alpha = p.alpha > 0 ? p.alpha : 14.0;
-  const double beta = p.beta > 0 ? p.beta : 24.0;
-  const int lane_scan = p.bu_lane_scan > 0 ? p.bu_lane_scan : 4;
+  const double alpha = p.alpha > 0 ? p.alpha : g->tune.alpha;
+  const double beta = p.beta > 0 ? p.beta : g->tune.beta;
+  const int lane_scan = p.bu_lane_scan > 0 ? p.bu_lane_scan : g->tune.lane_scan;
+  const int bu_bpc = p.bu_blocks_per_cu > 0 ? p.bu_blocks_per_cu : g->tune.bu_blocks_per_cu;
   const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
   const bool acct = stats && (p.flags & G5_FLAG_COUNT_BYTES);
+  const bool use_hint = !(p.flags & G5_FLAG_NO_HINT);
   unsigned long long *ctr = (unsigned long long *)w.ctr;
   uint64_t *hc = w.host_ctr;
-  const int bu_grid = ncu * 8;
+  const int bu_grid = ncu * bu_bpc;
   if (timed && !w.ev[0]) {
     for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
   }
 
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, w.ctr, (int64_t)C_NCTR);
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
-                     dim3(kBlock), 0, s, level, parent, n, w.vis, g->iso, W,
+                     dim3(kBlock), 0, s, level, parent, n, w.vis, w.prev, g->iso, W,
                      (((uintptr_t)level | (uintptr_t)parent) & 15) == 0);
   hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, root, level, parent, w.vis, w.q[0], ctr,
                      g->row_ptr);
@@ -550,10 +575,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       bool to_bu = (p.direction == G5_DIR_BOTTOMUP) ||
                    (p.direction == G5_DIR_AUTO && (double)mf > (double)m_u / alpha);
       if (to_bu) {
-        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0, s,
-                           front, W);
-        hipLaunchKernelGGL(k_q2front, dim3(grid_for(qlen, kBlock, ncu * 16)), dim3(kBlock), 0, s,
-                           w.q[cur], qlen, front);
+        hipLaunchKernelGGL(k_front_from_vis, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
+                           s, w.vis, w.prev, front, W);
         G5_LAUNCH_CHECK();
         dir = 2;
         nf_prev = qlen;
@@ -561,6 +584,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       }
       const int nxt = cur ^ 1;
       G5_HIP(hipMemsetAsync(ctr + nxt, 0, 8, s));
+      hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0, s,
+                         w.prev, w.vis, W);
       if (timed) G5_HIP(hipEventRecord(w.ev[2], s));
       if (mf > 0) {
         const int64_t tb = (mf + kTdTile - 1) / kTdTile;
@@ -606,7 +631,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
 #define G5_BU(K, A)                                                                        \
   hipLaunchKernelGGL((k_bu_step<K, A>), dim3(bu_grid), dim3(kBlock), 0, s, g->row_ptr,     \
-                     g->col_idx, w.vis, front, next, parent, level, n, W, lvl + 1, ctr)
+                     g->col_idx, use_hint ? g->hint : nullptr, w.vis, front, next, parent,    \
+                     level, n, W, lvl + 1, ctr)
 #define G5_BU_K(A)               \
   switch (lane_scan) {           \
     case 1: G5_BU(1, A); break;  \
@@ -634,8 +660,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         stats->discovered[i] = nnew;
         if (acct) {
           stats->edges[i] = (int64_t)hc[C_SCAN];
-          stats->bytes[i] = 8 * (int64_t)hc[C_UNVIS] + 4 * (int64_t)hc[C_SCAN] + 16 * W +
-                            8 * nnew;
+          stats->bytes[i] = (use_hint ? 12 : 8) * (int64_t)hc[C_UNVIS] +
+                            4 * (int64_t)hc[C_SCAN] + 16 * W + 8 * nnew;
         }
         if (timed) {
           g5_status st = elapsed(0, 1, &stats->step_ms[i]);
@@ -669,6 +695,10 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   if (stats) {
     stats->nlevels = lvl;
     stats->reached = reached;
+    stats->alpha = alpha;
+    stats->beta = beta;
+    stats->bu_lane_scan = lane_scan;
+    stats->bu_blocks_per_cu = bu_bpc;
   }
   G5_HIP(hipStreamSynchronize(s));
   return G5_OK;

@@ -12,6 +12,9 @@
 //   iso       bitmap of degree-0 vertices (used by the traversal to skip them)
 //   hubs      list of rows longer than kHubDeg and their kHubChunk-edge pieces
 //             (the batched traversal splits these rows across wavefronts)
+//   hint      for each vertex, its highest-degree neighbour (among the first
+//             kHintScan of its row; smallest id on ties): the bottom-up step
+//             tests it before reading the row
 #include <algorithm>
 
 #include "g5_internal.h"
@@ -258,6 +261,46 @@ __global__ void k_hub_chunks(const int64_t *__restrict__ rp, const int32_t *__re
   }
 }
 
+constexpr int kHintScan = 1024;
+
+__device__ __forceinline__ uint64_t hint_key(const int64_t *rp, int32_t u) {
+  // larger degree first, then smaller id
+  uint64_t d = (uint64_t)(rp[u + 1] - rp[u]);
+  return (d << 32) | (uint64_t)(0x7fffffffu - (uint32_t)u);
+}
+
+__global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci, int64_t n,
+                                              int64_t words, int32_t *__restrict__ hint) {
+  const int lane = __lane_id();
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t w = gw; w < words; w += nw) {
+    const int64_t v = w * kWave + lane;
+    int64_t b = 0, e = 0;
+    if (v < n) {
+      b = rp[v];
+      e = rp[v + 1];
+    }
+    uint64_t best = 0;
+    if (e - b <= kWave)
+      for (int64_t k = b; k < e; ++k) best = std::max(best, hint_key(rp, ci[k]));
+    uint64_t rem = __ballot(e - b > kWave);
+    while (rem) {
+      const int L = __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1;
+      const int64_t kb = __shfl(b, L, kWave);
+      const int64_t ke = std::min<int64_t>(__shfl(e, L, kWave), kb + kHintScan);
+      uint64_t m = 0;
+      for (int64_t k = kb + lane; k < ke; k += kWave) m = std::max(m, hint_key(rp, ci[k]));
+#pragma unroll
+      for (int d = kWave / 2; d >= 1; d >>= 1) m = std::max(m, (uint64_t)__shfl_xor(m, d, kWave));
+      if (lane == L) best = m;
+    }
+    if (v < n) hint[v] = best ? (int32_t)(0x7fffffffu - (uint32_t)(best & 0xffffffffu)) : -1;
+  }
+}
+
 int grid_cap(int64_t items, int per_block, int cap) {
   int64_t g = (items + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -365,6 +408,7 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
   g->device = dev;
   g->num_cu = ncu;
   g->words = (n + 63) / 64;
+  g->tune = pick_tuning(sb);
   auto fail = [&](hipError_t e, const char *what) {
     set_error(std::string("g5_build_csr: ") + what + ": " + hipGetErrorString(e));
     g5_csr_free(g);
@@ -387,6 +431,10 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
     return fail(e, "copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   g->nonisolated = (int64_t)noniso;
+  if ((e = hipMalloc(&g->hint, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
+  hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+                     g->col_idx, n, g->words, g->hint);
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
 
   // hub list (order does not matter) and its chunk prefix
   const int64_t max_hubs = (int64_t)(nnz / kHubDeg) + 1;

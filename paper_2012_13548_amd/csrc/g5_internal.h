@@ -47,6 +47,7 @@ struct BfsWork {
   uint64_t *vis = nullptr;    // visited bitmap (isolated vertices pre-set)
   uint64_t *front = nullptr;  // frontier bitmap (bottom-up input)
   uint64_t *next = nullptr;   // next-frontier bitmap (bottom-up output)
+  uint64_t *prev = nullptr;   // visited bitmap before the last top-down expansion
   int32_t *q[2] = {nullptr, nullptr};  // frontier queues
   uint32_t *qoff = nullptr;   // per-frontier-vertex edge offsets (top-down)
   uint32_t *bsum = nullptr;   // per-block partial sums
@@ -68,6 +69,17 @@ struct BatchWork {
   ~BatchWork();
 };
 
+// Defaults picked per graph from the autotuned table (tuned_table.inc).
+struct Tuning {
+  int scale;              // log2 n the entry was tuned at
+  double alpha, beta;     // single-root direction switch
+  int lane_scan;          // bottom-up lane scan width
+  int bu_blocks_per_cu;   // bottom-up grid
+  double batch_alpha;     // batched direction switch
+  int batch_blocks_per_cu;
+};
+Tuning pick_tuning(int scale);
+
 }  // namespace g5
 
 struct g5_csr {
@@ -79,6 +91,8 @@ struct g5_csr {
   int64_t *row_ptr = nullptr;  // device [n+1]
   int32_t *col_idx = nullptr;  // device [nnz]
   uint64_t *iso = nullptr;     // device [words]: bit set = degree 0 (or padding)
+  int32_t *hint = nullptr;     // device [n]: highest-degree neighbour, -1 if none
+  g5::Tuning tune{};           // defaults for this graph's scale
   int64_t num_hubs = 0;        // vertices with degree > kHubDeg
   int64_t hub_chunks = 0;      // their rows in kHubChunk-edge pieces
   int32_t *hub_list = nullptr; // device [num_hubs]

@@ -295,6 +295,76 @@ __device__ void bu_phase(const MsArgs &a, const uint64_t *front, uint64_t *next,
   }
 }
 
+// Counters of the root frontier (level 0) into slot 0 and mu0.
+__device__ void root_stats(const MsArgs &a, uint64_t *s_red) {
+  MsCtl *ctl = a.ctl;
+  const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gthreads = (int64_t)gridDim.x * kBlock;
+  uint64_t nf = 0, mf = 0, mu = 0;
+  for (int64_t v = gtid; v < a.n; v += gthreads) {
+    const uint64_t f = a.buf0[v], s = a.seen[v];
+    const int64_t d = a.rp[v + 1] - a.rp[v];
+    if (f) {
+      nf += 1;
+      mf += (uint64_t)d;
+    }
+    if (s != a.full) mu += (uint64_t)d;
+  }
+  nf = block_sum<kBlock, uint64_t>(nf, s_red);
+  mf = block_sum<kBlock, uint64_t>(mf, s_red);
+  mu = block_sum<kBlock, uint64_t>(mu, s_red);
+  if (threadIdx.x == 0) {
+    atomicAdd(&ctl->slot[0].nf, (unsigned long long)nf);
+    atomicAdd(&ctl->slot[0].mf, (unsigned long long)mf);
+    atomicAdd(&ctl->mu0, (unsigned long long)mu);
+  }
+}
+
+// One level l: expands buffer l%3 into (l+1)%3 top-down or bottom-up, clears
+// (l+2)%3, and adds the next frontier's counters into slot (l+1)%3.
+template <bool PAR>
+__device__ void level_body(const MsArgs &a, int l, bool td, uint64_t nf, uint64_t *s_red) {
+  MsCtl *ctl = a.ctl;
+  const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gthreads = (int64_t)gridDim.x * kBlock;
+  const int64_t gw = gtid / kWave, nw = gthreads / kWave;
+  Slot *nxt = &ctl->slot[(l + 1) % 3], *old = &ctl->slot[(l + 2) % 3];
+  if (gtid == 0) {
+    atomicExch(&old->nf, 0ull);
+    atomicExch(&old->mf, 0ull);
+    atomicExch(&old->dec, 0ull);
+    ctl->nlevels = (unsigned long long)(l + 1);
+    if (l < kStatLevels) {
+      ctl->dir[l] = td ? 1 : 2;
+      ctl->frontier[l] = (int64_t)nf;
+    }
+  }
+  uint64_t *bufs[3] = {a.buf0, a.buf1, a.buf2};
+  const uint64_t *front = bufs[l % 3];
+  uint64_t *next = bufs[(l + 1) % 3];
+  uint64_t *clr = bufs[(l + 2) % 3];
+  for (int64_t v = gtid; v < a.n; v += gthreads) clr[v] = 0;
+  Acc acc;
+  if (td)
+    td_phase<PAR>(a, front, next, (int8_t)(l + 1), gw, nw, acc);
+  else
+    bu_phase<PAR>(a, front, next, (int8_t)(l + 1), gw, nw, acc);
+  const uint64_t tnf = block_sum<kBlock, uint64_t>(acc.nf, s_red);
+  const uint64_t tmf = block_sum<kBlock, uint64_t>(acc.mf, s_red);
+  const uint64_t tdec = block_sum<kBlock, uint64_t>(acc.dec, s_red);
+  if (threadIdx.x == 0) {
+    if (tnf) atomicAdd(&nxt->nf, (unsigned long long)tnf);
+    if (tmf) atomicAdd(&nxt->mf, (unsigned long long)tmf);
+    if (tdec) atomicAdd(&nxt->dec, (unsigned long long)tdec);
+  }
+}
+
+__device__ __forceinline__ bool choose_td(const MsArgs &a, uint64_t mf, uint64_t mu) {
+  return a.direction == G5_DIR_TOPDOWN ||
+         (a.direction == G5_DIR_AUTO && (double)mf <= (double)mu / a.alpha);
+}
+
+// Every level in one cooperative launch, a grid barrier after each level.
 template <bool PAR>
 __global__ __launch_bounds__(kBlock) void k_msbfs(MsArgs a) {
   cg::grid_group grid = cg::this_grid();
@@ -302,65 +372,14 @@ __global__ __launch_bounds__(kBlock) void k_msbfs(MsArgs a) {
   __shared__ uint64_t s_red[kBlock / kWave];
   MsCtl *ctl = a.ctl;
   const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t gthreads = (int64_t)gridDim.x * kBlock;
-  const int64_t gw = gtid / kWave, nw = gthreads / kWave;
-
-  {  // counters of the root frontier
-    uint64_t nf = 0, mf = 0, mu = 0;
-    for (int64_t v = gtid; v < a.n; v += gthreads) {
-      const uint64_t f = a.buf0[v], s = a.seen[v];
-      const int64_t d = a.rp[v + 1] - a.rp[v];
-      if (f) {
-        nf += 1;
-        mf += (uint64_t)d;
-      }
-      if (s != a.full) mu += (uint64_t)d;
-    }
-    nf = block_sum<kBlock, uint64_t>(nf, s_red);
-    mf = block_sum<kBlock, uint64_t>(mf, s_red);
-    mu = block_sum<kBlock, uint64_t>(mu, s_red);
-    if (threadIdx.x == 0) {
-      atomicAdd(&ctl->slot[0].nf, (unsigned long long)nf);
-      atomicAdd(&ctl->slot[0].mf, (unsigned long long)mf);
-      atomicAdd(&ctl->mu0, (unsigned long long)mu);
-    }
-  }
+  root_stats(a, s_red);
   grid.sync();
   uint64_t mu = ld_agent(&ctl->mu0);
-  uint64_t *bufs[3] = {a.buf0, a.buf1, a.buf2};
   for (int l = 0;; ++l) {
-    Slot *cur = &ctl->slot[l % 3], *nxt = &ctl->slot[(l + 1) % 3], *old = &ctl->slot[(l + 2) % 3];
+    Slot *cur = &ctl->slot[l % 3], *nxt = &ctl->slot[(l + 1) % 3];
     const uint64_t nf = ld_agent(&cur->nf), mf = ld_agent(&cur->mf);
     if (nf == 0) break;
-    const bool td = a.direction == G5_DIR_TOPDOWN ||
-                    (a.direction == G5_DIR_AUTO && (double)mf <= (double)mu / a.alpha);
-    if (gtid == 0) {
-      atomicExch(&old->nf, 0ull);
-      atomicExch(&old->mf, 0ull);
-      atomicExch(&old->dec, 0ull);
-      ctl->nlevels = (unsigned long long)(l + 1);
-      if (l < kStatLevels) {
-        ctl->dir[l] = td ? 1 : 2;
-        ctl->frontier[l] = (int64_t)nf;
-      }
-    }
-    const uint64_t *front = bufs[l % 3];
-    uint64_t *next = bufs[(l + 1) % 3];
-    uint64_t *clr = bufs[(l + 2) % 3];
-    for (int64_t v = gtid; v < a.n; v += gthreads) clr[v] = 0;
-    Acc acc;
-    if (td)
-      td_phase<PAR>(a, front, next, (int8_t)(l + 1), gw, nw, acc);
-    else
-      bu_phase<PAR>(a, front, next, (int8_t)(l + 1), gw, nw, acc);
-    const uint64_t tnf = block_sum<kBlock, uint64_t>(acc.nf, s_red);
-    const uint64_t tmf = block_sum<kBlock, uint64_t>(acc.mf, s_red);
-    const uint64_t tdec = block_sum<kBlock, uint64_t>(acc.dec, s_red);
-    if (threadIdx.x == 0) {
-      if (tnf) atomicAdd(&nxt->nf, (unsigned long long)tnf);
-      if (tmf) atomicAdd(&nxt->mf, (unsigned long long)tmf);
-      if (tdec) atomicAdd(&nxt->dec, (unsigned long long)tdec);
-    }
+    level_body<PAR>(a, l, choose_td(a, mf, mu), nf, s_red);
     grid.sync();
     mu -= ld_agent(&nxt->dec);
     if (l + 1 > a.max_level && ld_agent(&nxt->nf) != 0) {
@@ -369,6 +388,20 @@ __global__ __launch_bounds__(kBlock) void k_msbfs(MsArgs a) {
       break;
     }
   }
+}
+
+// Stepped mode: the same level as a plain launch (the kernel boundary is the
+// level barrier), so batches can share the device with other work.
+__global__ __launch_bounds__(kBlock) void k_ms_root_stats(MsArgs a) {
+  __shared__ uint64_t s_red[kBlock / kWave];
+  root_stats(a, s_red);
+}
+
+template <bool PAR>
+__global__ __launch_bounds__(kBlock) void k_ms_level(MsArgs a, int l, int td,
+                                                     unsigned long long nf) {
+  __shared__ uint64_t s_red[kBlock / kWave];
+  level_body<PAR>(a, l, td != 0, nf, s_red);
 }
 
 __global__ void k_fill_i8(int8_t *__restrict__ p, int64_t len, bool vec) {
@@ -459,6 +492,66 @@ struct BatchLease {
 };
 }  // namespace
 
+// Stepped batch: one launch per level; the host reads the level counters
+// after each launch and takes the direction decision.
+g5_status batch_stepped(const g5_csr *g, BatchWork &w, const MsArgs &a, int32_t *parents,
+                        hipStream_t s, bool timed, g5_batch_stats *stats) {
+  const int blocks = g->num_cu * 8;
+  MsCtl *hc = (MsCtl *)w.host_ctl;
+  if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
+  hipLaunchKernelGGL(k_ms_root_stats, dim3(blocks), dim3(kBlock), 0, s, a);
+  G5_LAUNCH_CHECK();
+  G5_HIP(hipMemcpyAsync(hc, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
+  G5_HIP(hipStreamSynchronize(s));
+  uint64_t mu = hc->mu0;
+  bool err = false;
+  int l = 0;
+  for (;; ++l) {
+    const Slot &cur = hc->slot[l % 3];
+    const uint64_t nf = cur.nf, mf = cur.mf;
+    if (nf == 0) break;
+    const bool td = a.direction == G5_DIR_TOPDOWN ||
+                    (a.direction == G5_DIR_AUTO && (double)mf <= (double)mu / a.alpha);
+    if (parents)
+      hipLaunchKernelGGL(k_ms_level<true>, dim3(blocks), dim3(kBlock), 0, s, a, l, (int)td,
+                         (unsigned long long)nf);
+    else
+      hipLaunchKernelGGL(k_ms_level<false>, dim3(blocks), dim3(kBlock), 0, s, a, l, (int)td,
+                         (unsigned long long)nf);
+    G5_LAUNCH_CHECK();
+    G5_HIP(hipMemcpyAsync(hc, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
+    G5_HIP(hipStreamSynchronize(s));
+    const Slot &nxt = hc->slot[(l + 1) % 3];
+    mu -= nxt.dec;
+    if (l + 1 > a.max_level && nxt.nf != 0) {
+      err = true;
+      break;
+    }
+  }
+  if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
+  G5_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    *stats = g5_batch_stats{};
+    stats->nlevels = (int32_t)hc->nlevels;
+    for (int i = 0; i < std::min<int>((int)hc->nlevels, kStatLevels); ++i) {
+      stats->dir[i] = hc->dir[i];
+      stats->frontier[i] = hc->frontier[i];
+    }
+    stats->grid_blocks = blocks;
+    stats->alpha = a.alpha;
+    if (timed) {
+      float ms = 0;
+      G5_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));
+      stats->launch_ms = ms;
+    }
+  }
+  if (err) {
+    set_error("g5_bfs_batch: a level exceeds 127 (int8 levels); use g5_bfs for this root set");
+    return G5_ERANGE;
+  }
+  return G5_OK;
+}
+
 g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *parents,
                          int8_t *levels, hipStream_t s, const g5_batch_params &p,
                          g5_batch_stats *stats) {
@@ -514,9 +607,11 @@ g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *
   a.num_hubs = g->num_hubs;
   a.hub_chunks = g->hub_chunks;
   a.ctl = (MsCtl *)w.ctl;
-  a.alpha = p.alpha > 0 ? p.alpha : 14.0;
+  a.alpha = p.alpha > 0 ? p.alpha : g->tune.batch_alpha;
   a.direction = p.direction;
   a.max_level = 127;
+
+  if (p.flags & G5_FLAG_STEPPED) return batch_stepped(g, w, a, parents, s, timed, stats);
 
   const void *fn = parents ? reinterpret_cast<const void *>(&k_msbfs<true>)
                            : reinterpret_cast<const void *>(&k_msbfs<false>);
@@ -526,7 +621,8 @@ g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *
     set_error("g5_bfs_batch: the persistent kernel does not fit on a compute unit");
     return G5_EDEVICE;
   }
-  const int blocks = ncu * std::min(per_cu, 8);
+  const int bpc = p.blocks_per_cu > 0 ? p.blocks_per_cu : g->tune.batch_blocks_per_cu;
+  const int blocks = ncu * std::min(per_cu, bpc);
   void *args[] = {&a};
   if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
   G5_HIP(hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kBlock), args, 0, s));
@@ -542,6 +638,7 @@ g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *
       stats->frontier[i] = hc->frontier[i];
     }
     stats->grid_blocks = blocks;
+    stats->alpha = a.alpha;
     if (timed) {
       float ms = 0;
       G5_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));

@@ -44,3 +44,19 @@ def test_generator_device_library_loads():
     import kronecker as K
     lib = K._load_dev()
     assert hasattr(lib, "kron_edges_device") and hasattr(lib, "kron_nonisolated_device")
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors of the parameter and statistics structs have the C sizes
+    import subprocess
+    import paper_2012_13548_amd as g5
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "g5.h"\nint main(void){printf("%zu %zu %zu %zu",'
+                   ' sizeof(g5_bfs_params), sizeof(g5_bfs_stats), sizeof(g5_batch_params),'
+                   ' sizeof(g5_batch_stats));return 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert [int(x) for x in out] == [ctypes.sizeof(g5.BfsParams), ctypes.sizeof(g5.BfsStats),
+                                     ctypes.sizeof(g5.BatchParams), ctypes.sizeof(g5.BatchStats)]

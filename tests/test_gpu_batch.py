@@ -11,8 +11,10 @@ from tests.gpu_util import Case, check_batch
 pytestmark = pytest.mark.gpu
 
 MODES = [dict(), dict(direction=g5.DIR_TOPDOWN), dict(direction=g5.DIR_BOTTOMUP),
-         dict(alpha=1e-3), dict(alpha=1e6), dict(parents=False)]
-MODE_IDS = ["auto", "td", "bu", "auto-bu-early", "auto-td-long", "levels-only"]
+         dict(alpha=1e-3), dict(alpha=1e6), dict(parents=False), dict(stepped=True),
+         dict(stepped=True, parents=False, direction=g5.DIR_BOTTOMUP)]
+MODE_IDS = ["auto", "td", "bu", "auto-bu-early", "auto-td-long", "levels-only", "stepped",
+            "stepped-bu-levels"]
 
 
 @pytest.fixture(params=range(len(MODES)), ids=MODE_IDS)
@@ -76,9 +78,10 @@ def test_depth_limit():
     _, lv, _ = check_batch(c, [127])
     assert lv.max() == 127
     for roots in ([126], [0, 127]):
-        with pytest.raises(g5.G5Error) as ei:
-            g5.bfs_batch(c.csr, roots)
-        assert ei.value.status == g5.G5_ERANGE
+        for stepped in (False, True):
+            with pytest.raises(g5.G5Error) as ei:
+                g5.bfs_batch(c.csr, roots, stepped=stepped)
+            assert ei.value.status == g5.G5_ERANGE
     e, n = G.path(256)
     c = Case(e, n)
     for roots in ([127], [128], [0, 127]):

@@ -14,8 +14,9 @@ pytestmark = pytest.mark.gpu
 MODES = [dict(direction=g5.DIR_AUTO), dict(direction=g5.DIR_TOPDOWN),
          dict(direction=g5.DIR_BOTTOMUP), dict(direction=g5.DIR_AUTO, claim=g5.CLAIM_CAS),
          dict(direction=g5.DIR_AUTO, alpha=1e6, beta=1e6),
-         dict(direction=g5.DIR_AUTO, alpha=1e-3, beta=2.0)]
-MODE_IDS = ["auto", "td", "bu", "auto-cas", "auto-eager", "auto-late"]
+         dict(direction=g5.DIR_AUTO, alpha=1e-3, beta=2.0), dict(hint=False),
+         dict(direction=g5.DIR_BOTTOMUP, hint=False, lane_scan=1)]
+MODE_IDS = ["auto", "td", "bu", "auto-cas", "auto-eager", "auto-late", "nohint", "bu-nohint-1"]
 
 
 @pytest.fixture(params=range(len(MODES)), ids=MODE_IDS)
