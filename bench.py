@@ -68,6 +68,75 @@ def measured_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+COPY_PROBE_BYTES = 1 << 31  # each direction
+
+
+def copy_probe():
+    """A plain elementwise copy of known size (2 GiB read, 2 GiB written): the
+    calibration dispatch for the rocprofv3 FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.add(src, 0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+
+
+def _pmc_rows(d):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _per_dispatch(rows, counter, match):
+    """Average of `counter` (KiB) over dispatches whose kernel name satisfies match."""
+    per = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter or not match(r.get("Kernel_Name", "")):
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} samples for the requested kernel")
+    return sum(per.values()) / len(per), len(per)
+
+
+def reduce_pmc(fetch_dir, write_dir, kernel, workload, command):
+    """Calibrated HBM bytes per launch of `kernel` from a FETCH_SIZE run and a
+    WRITE_SIZE run; each counter is scaled by what it reads for the copy probe
+    (known bytes).  Stored in profiles/traffic.json with the kernel source hash,
+    so the bench reports it only while the kernel is unchanged."""
+    is_copy = lambda name: "add" in name.lower() or "Add" in name
+    is_k = lambda name: kernel in name and "true>" not in name
+    fr, wr = _pmc_rows(fetch_dir), _pmc_rows(write_dir)
+    copy_f, _ = _per_dispatch(fr, "FETCH_SIZE", is_copy)
+    copy_w, _ = _per_dispatch(wr, "WRITE_SIZE", is_copy)
+    k_f, nf = _per_dispatch(fr, "FETCH_SIZE", is_k)
+    k_w, nw = _per_dispatch(wr, "WRITE_SIZE", is_k)
+    f_factor = COPY_PROBE_BYTES / (copy_f * 1024)
+    w_factor = COPY_PROBE_BYTES / (copy_w * 1024)
+    rec = {"source_hash": source_hash(BFS_SOURCES),
+           "bytes_per_launch": int(k_f * 1024 * f_factor + k_w * 1024 * w_factor),
+           "fetch_bytes_per_launch": int(k_f * 1024 * f_factor),
+           "write_bytes_per_launch": int(k_w * 1024 * w_factor),
+           "fetch_factor": round(f_factor, 4), "write_factor": round(w_factor, 4),
+           "launches": [nf, nw], "command": command}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data[f"{kernel}@{workload}"] = rec
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps(rec))
+
+
 def run_gpu(args):
     import torch
     import kronecker as K
@@ -279,13 +348,24 @@ def main():
     ap.add_argument("--cpu-roots", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run the counter-calibration copy kernel first")
+    ap.add_argument("--reduce-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-command", default="", help="command recorded with --reduce-pmc")
     args = ap.parse_args()
+    if args.reduce_pmc:
+        reduce_pmc(args.reduce_pmc[0], args.reduce_pmc[1], "k_bu_step", f"s{args.scale}",
+                   args.pmc_command)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the many-root workload shards by roots with no communication: run one "
               "process per GPU instead)", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_probe:
+        copy_probe()
     gpu, csr, parent, level = run_gpu(args)
     import torch
     import paper_2012_13548_amd as g5
