@@ -123,6 +123,15 @@ typedef struct {
  * barriers for all of its workgroups, so it should own the device; stepped
  * batches can overlap other work on other streams. */
 #define G5_FLAG_STEPPED 8
+/* g5_bfs_ex: bottom-up rows left unresolved by a lane's own scan are packed end
+ * to end across the wavefront (one entry per lane) instead of being scanned
+ * one row per 64-lane step. */
+#define G5_FLAG_PACKED 16
+/* g5_bfs_ex: deterministic parents.  parent[v] is the smallest-id neighbour of
+ * v at level[v] - 1 (top-down steps take an atomic minimum over every frontier
+ * edge into v; bottom-up steps take the first frontier hit of the ascending
+ * row, without the neighbour hint).  Slower; results do not depend on timing. */
+#define G5_FLAG_MIN_PARENT 32
 
 #define G5_MAX_STAT_LEVELS 64
 

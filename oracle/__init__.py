@@ -14,6 +14,8 @@ Python bindings (numpy in, numpy out) for ``oracle.c``:
   checks of a BFS result (union-find reached set, tree edges, level rules).
 * :func:`teps_edges` -- m_r, the distinct undirected edges of the root's
   component (traversed edges for TEPS, Section 4.3).
+* :func:`min_parents` -- the deterministic parent choice: the smallest-id
+  neighbour one level up.
 """
 import ctypes
 import os
@@ -57,6 +59,8 @@ def _load():
         lib.orc_validate_edges.restype = ctypes.c_int
         lib.orc_teps_edges.argtypes = [P, I64, P]
         lib.orc_teps_edges.restype = I64
+        lib.orc_min_parents.argtypes = [P, P, I64, I64, P, P]
+        lib.orc_min_parents.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -170,3 +174,15 @@ def validate_edges(edges, n, root, parent, level):
 def teps_edges(csr, level):
     level = np.ascontiguousarray(level, dtype=np.int32)
     return int(_load().orc_teps_edges(csr.row_ptr.ctypes.data, csr.n, level.ctypes.data))
+
+
+def min_parents(csr, root, level):
+    """parent[v] = smallest-id neighbour of v at level[v] - 1 (root: itself)."""
+    level = np.ascontiguousarray(level, dtype=np.int32)
+    parent = np.empty(csr.n, dtype=np.int32)
+    ci = csr.col_idx if csr.col_idx.size else np.zeros(1, np.int32)
+    rc = _load().orc_min_parents(csr.row_ptr.ctypes.data, ci.ctypes.data, csr.n, int(root),
+                                 level.ctypes.data, parent.ctypes.data)
+    if rc != 0:
+        raise ValueError("a reached vertex has no neighbour one level up")
+    return parent

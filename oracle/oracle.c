@@ -23,6 +23,8 @@
  *     parent[root] = root; unreached vertices keep level -1 and parent -1.
  *   - Validation of a BFS result, and the traversed-edge count m_r used for
  *     TEPS (Section 4.3 names TEPS over 64 roots as the Graph500 metric).
+ *   - The deterministic parent choice: for a reached v other than the root,
+ *     the smallest-id neighbour one level closer to the root.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -297,4 +299,27 @@ int64_t orc_teps_edges(const int64_t *rp, int64_t n, const int32_t *level) {
   for (int64_t v = 0; v < n; ++v)
     if (level[v] >= 0) s += rp[v + 1] - rp[v];
   return s / 2;
+}
+
+/* Deterministic parents from a level array: parent[root] = root; for a reached
+ * v != root, the smallest-id neighbour u with level[u] = level[v] - 1; -1 if v
+ * is unreached.  Returns 0, or -1 if some reached v has no such neighbour. */
+int orc_min_parents(const int64_t *rp, const int32_t *ci, int64_t n, int64_t root,
+                    const int32_t *level, int32_t *parent) {
+  int bad = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    parent[v] = -1;
+    if (level[v] < 0) continue;
+    if (v == root) {
+      parent[v] = (int32_t)v;
+      continue;
+    }
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k)
+      if (level[ci[k]] == level[v] - 1) {
+        parent[v] = ci[k];  /* rows are ascending: the first match is the smallest */
+        break;
+      }
+    if (parent[v] < 0) bad = 1;
+  }
+  return bad ? -1 : 0;
 }

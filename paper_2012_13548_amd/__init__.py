@@ -38,7 +38,8 @@ import torch  # noqa: E402,F401
 lib = ctypes.CDLL(LIB_PATH)
 
 
-FLAG_TIME_STEPS, FLAG_COUNT_BYTES, FLAG_NO_HINT, FLAG_STEPPED = 1, 2, 4, 8
+FLAG_TIME_STEPS, FLAG_COUNT_BYTES, FLAG_NO_HINT, FLAG_STEPPED, FLAG_PACKED = 1, 2, 4, 8, 16
+FLAG_MIN_PARENT = 32
 
 
 class BfsParams(ctypes.Structure):
@@ -180,8 +181,8 @@ def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None)
 
 
 def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta=None,
-        lane_scan=None, claim=CLAIM_OR, hint=True, blocks_per_cu=None, stats=False,
-        time_steps=False, count_bytes=False):
+        lane_scan=None, claim=CLAIM_OR, hint=True, packed=False, min_parent=False,
+        blocks_per_cu=None, stats=False, time_steps=False, count_bytes=False):
     """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
 
     With ``stats=True`` also returns a dict of per-level directions, frontier
@@ -197,7 +198,8 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
         if t.dtype != torch.int32 or t.numel() < csr.n or not t.is_contiguous():
             raise ValueError("parent and level must be contiguous int32 tensors of length n")
     flags = ((FLAG_TIME_STEPS if time_steps else 0) | (FLAG_COUNT_BYTES if count_bytes else 0)
-             | (0 if hint else FLAG_NO_HINT))
+             | (0 if hint else FLAG_NO_HINT) | (FLAG_PACKED if packed else 0)
+             | (FLAG_MIN_PARENT if min_parent else 0))
     p = _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu)
     want = stats or flags
     st = BfsStats()

@@ -164,13 +164,24 @@ __device__ int64_t block_search(const uint32_t *__restrict__ off, int64_t len, u
   }
 }
 
-enum Claim : int { CLAIM_OR = 0, CLAIM_CAS = 1 };
+// CLAIM_MIN: parent[v] is the smallest frontier neighbour (unsigned atomic
+// min over every edge into a vertex unvisited at level start, read from the
+// snapshot taken before the expansion); the visited-bit OR still decides who
+// appends v to the next queue.
+enum Claim : int { CLAIM_OR = 0, CLAIM_CAS = 1, CLAIM_MIN = 2 };
+
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) x |= __shfl_xor(x, d, kWave);
+  return x;
+}
 
 template <int CLAIM>
 __global__ __launch_bounds__(kBlock) void k_td_expand(
     const int32_t *__restrict__ q, int64_t qlen, const uint32_t *__restrict__ qoff,
     uint32_t total, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    uint64_t *vis, int32_t *parent, int32_t *__restrict__ level, int32_t *__restrict__ qn,
+    uint64_t *vis, const uint64_t *__restrict__ prev, int32_t *parent,
+    int32_t *__restrict__ level, int32_t *__restrict__ qn,
     unsigned long long *__restrict__ qn_len, int32_t next_level,
     unsigned long long *__restrict__ err) {
   __shared__ uint32_t s_off[kTdTile + 1];
@@ -223,7 +234,15 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
       int32_t u = s_src[lo];
       uint64_t bit = 1ull << (v & 63);
       uint64_t *wp = vis + (v >> 6);
-      if (!(*wp & bit)) {
+      if (CLAIM == CLAIM_MIN) {
+        if (!(prev[v >> 6] & bit)) {
+          atomicMin((unsigned int *)(parent + v), (unsigned int)u);
+          if (!(*wp & bit)) {
+            won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
+            if (won) level[v] = next_level;
+          }
+        }
+      } else if (!(*wp & bit)) {
         if (CLAIM == CLAIM_OR) {
           won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
           if (won) parent[v] = u;
@@ -279,8 +298,11 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
     const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
     int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
-    int32_t next_level, unsigned long long *__restrict__ ctr) {
+    int32_t next_level, unsigned long long *__restrict__ ctr, bool packed) {
   __shared__ uint64_t s[kBlock / kWave];
+  __shared__ int64_t s_base[kBlock];
+  __shared__ int32_t s_row[kBlock];
+  __shared__ int32_t s_first[kBlock];
   const int lane = __lane_id();
   const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
@@ -329,7 +351,53 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
       k = std::min<int64_t>(k + LANE_SCAN, e);
       if (ACCT && !found) nscan += (uint64_t)(k - k0);
     }
-    uint64_t rem = __ballot(pending && !found && k < e);
+    if (packed) {
+      // Unresolved rows of the wavefront laid end to end, one entry per lane
+      // per 64-entry window; a row's first hit in a window is the smallest
+      // hitting lane (LDS atomic min); resolved rows stop probing.
+      const uint32_t len = (pending && !found) ? (uint32_t)(e - k) : 0u;
+      const uint32_t incl = wave_incl_scan(len);
+      const uint32_t total = __shfl(incl, kWave - 1, kWave);
+      if (total) {
+        const uint32_t pre = incl - len;
+        const int wb = (threadIdx.x / kWave) * kWave;
+        s_base[wb + lane] = k - (int64_t)pre;
+        s_first[wb + lane] = kWave;
+        uint64_t done = __ballot(len == 0);
+        int carry = 0;
+        for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
+          const bool starts = len > 0 && pre >= j0 && pre < j0 + kWave;
+          if (starts) s_row[wb + (int)(pre - j0)] = lane;
+          const uint64_t S = wave_or_u64(starts ? (1ull << (pre - j0)) : 0ull);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const uint64_t upto = S & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
+          const int r = upto ? s_row[wb + (kWave - 1 - __clzll((long long)upto))] : carry;
+          const uint32_t j = j0 + lane;
+          int32_t u = -1;
+          bool hit = false;
+          if (j < total && !((done >> r) & 1)) {
+            u = ci[s_base[wb + r] + (int64_t)j];
+            hit = (front[u >> 6] >> (u & 63)) & 1;
+          }
+          if (hit) atomicMin(&s_first[wb + r], lane);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const int fl = s_first[wb + lane];
+          const bool fresh = fl < kWave;
+          const int32_t gv = __shfl(u, fresh ? fl : lane, kWave);
+          if (fresh) {
+            found = true;
+            par = gv;
+            s_first[wb + lane] = kWave;
+            if (ACCT) nscan += (uint64_t)(j0 + fl - pre + 1);
+          }
+          done |= __ballot(fresh);
+          carry = __shfl(r, kWave - 1, kWave);
+          if (done == ~0ull) break;
+        }
+        if (ACCT && len > 0 && !found) nscan += len;
+      }
+    }
+    uint64_t rem = packed ? 0ull : __ballot(pending && !found && k < e);
     while (rem) {
       const int L = __ffsll((unsigned long long)rem) - 1;
       rem &= rem - 1;
@@ -509,7 +577,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const int bu_bpc = p.bu_blocks_per_cu > 0 ? p.bu_blocks_per_cu : g->tune.bu_blocks_per_cu;
   const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
   const bool acct = stats && (p.flags & G5_FLAG_COUNT_BYTES);
-  const bool use_hint = !(p.flags & G5_FLAG_NO_HINT);
+  const bool min_parent = (p.flags & G5_FLAG_MIN_PARENT) != 0;
+  const bool use_hint = !(p.flags & G5_FLAG_NO_HINT) && !min_parent;
+  const bool packed = (p.flags & G5_FLAG_PACKED) != 0;
   unsigned long long *ctr = (unsigned long long *)w.ctr;
   uint64_t *hc = w.host_ctr;
   const int bu_grid = ncu * bu_bpc;
@@ -589,14 +659,17 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       if (timed) G5_HIP(hipEventRecord(w.ev[2], s));
       if (mf > 0) {
         const int64_t tb = (mf + kTdTile - 1) / kTdTile;
-        if (p.claim == CLAIM_CAS)
-          hipLaunchKernelGGL(k_td_expand<CLAIM_CAS>, dim3(tb), dim3(kBlock), 0, s, w.q[cur], qlen,
-                             w.qoff, (uint32_t)mf, g->row_ptr, g->col_idx, w.vis, parent, level,
-                             w.q[nxt], ctr + nxt, lvl + 1, ctr + C_ERR);
+#define G5_TD(C)                                                                            \
+  hipLaunchKernelGGL(k_td_expand<C>, dim3(tb), dim3(kBlock), 0, s, w.q[cur], qlen, w.qoff,   \
+                     (uint32_t)mf, g->row_ptr, g->col_idx, w.vis, w.prev, parent, level,     \
+                     w.q[nxt], ctr + nxt, lvl + 1, ctr + C_ERR)
+        if (min_parent)
+          G5_TD(CLAIM_MIN);
+        else if (p.claim == CLAIM_CAS)
+          G5_TD(CLAIM_CAS);
         else
-          hipLaunchKernelGGL(k_td_expand<CLAIM_OR>, dim3(tb), dim3(kBlock), 0, s, w.q[cur], qlen,
-                             w.qoff, (uint32_t)mf, g->row_ptr, g->col_idx, w.vis, parent, level,
-                             w.q[nxt], ctr + nxt, lvl + 1, ctr + C_ERR);
+          G5_TD(CLAIM_OR);
+#undef G5_TD
         G5_LAUNCH_CHECK();
       }
       if (timed) G5_HIP(hipEventRecord(w.ev[3], s));
@@ -632,7 +705,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
 #define G5_BU(K, A)                                                                        \
   hipLaunchKernelGGL((k_bu_step<K, A>), dim3(bu_grid), dim3(kBlock), 0, s, g->row_ptr,     \
                      g->col_idx, use_hint ? g->hint : nullptr, w.vis, front, next, parent,    \
-                     level, n, W, lvl + 1, ctr)
+                     level, n, W, lvl + 1, ctr, packed)
 #define G5_BU_K(A)               \
   switch (lane_scan) {           \
     case 1: G5_BU(1, A); break;  \

@@ -15,8 +15,10 @@ MODES = [dict(direction=g5.DIR_AUTO), dict(direction=g5.DIR_TOPDOWN),
          dict(direction=g5.DIR_BOTTOMUP), dict(direction=g5.DIR_AUTO, claim=g5.CLAIM_CAS),
          dict(direction=g5.DIR_AUTO, alpha=1e6, beta=1e6),
          dict(direction=g5.DIR_AUTO, alpha=1e-3, beta=2.0), dict(hint=False),
-         dict(direction=g5.DIR_BOTTOMUP, hint=False, lane_scan=1)]
-MODE_IDS = ["auto", "td", "bu", "auto-cas", "auto-eager", "auto-late", "nohint", "bu-nohint-1"]
+         dict(direction=g5.DIR_BOTTOMUP, hint=False, lane_scan=1),
+         dict(packed=True), dict(direction=g5.DIR_BOTTOMUP, packed=True, hint=False, lane_scan=1)]
+MODE_IDS = ["auto", "td", "bu", "auto-cas", "auto-eager", "auto-late", "nohint", "bu-nohint-1",
+            "packed", "bu-packed-nohint-1"]
 
 
 @pytest.fixture(params=range(len(MODES)), ids=MODE_IDS)
@@ -168,3 +170,23 @@ def test_unaligned_outputs(kron10):
     parent, level = g5.bfs(c.csr, roots[1], parent=buf[1:c.n + 1], level=buf[c.n + 1:2 * c.n + 1])
     _, ref = g5.bfs(c.csr, roots[1])
     assert torch.equal(level, ref)
+
+
+@pytest.mark.parametrize("direction", [g5.DIR_AUTO, g5.DIR_TOPDOWN, g5.DIR_BOTTOMUP])
+@pytest.mark.parametrize("packed", [False, True])
+def test_min_parent_bit_exact(kron16, direction, packed):
+    import oracle as O
+    c, roots = kron16
+    for r in roots[:4]:
+        parent, level = c.check_root(r, direction=direction, packed=packed, min_parent=True)
+        assert np.array_equal(parent, O.min_parents(c.ocsr, r, level))
+
+
+def test_min_parent_structured(cases):
+    import oracle as O
+    for name in ("grid", "tree", "union", "star"):
+        c = cases[name]
+        for r in (0, c.n // 3):
+            for d in (g5.DIR_AUTO, g5.DIR_TOPDOWN, g5.DIR_BOTTOMUP):
+                parent, level = c.check_root(r, direction=d, min_parent=True)
+                assert np.array_equal(parent, O.min_parents(c.ocsr, r, level)), (name, r, d)

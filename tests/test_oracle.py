@@ -293,3 +293,45 @@ def test_empty_edge_list():
     assert csr.row_ptr.tolist() == [0, 0, 0, 0, 0] and csr.nnz == 0
     parent, level = O.bfs(csr, 2)
     assert level.tolist() == [-1, -1, 0, -1]
+
+
+# --------------------------------------------------------------- min parents
+def test_min_parents_closed_forms():
+    e, n = G.path(12)
+    csr, _, level = run(e, n, 4)
+    p = O.min_parents(csr, 4, level)
+    expect = np.array([1, 2, 3, 4, 4, 4, 5, 6, 7, 8, 9, 10])
+    assert np.array_equal(p, expect)
+    e, n = G.binary_tree(5)
+    csr, _, level = run(e, n, 0)
+    p = O.min_parents(csr, 0, level)
+    assert p[0] == 0 and np.array_equal(p[1:], (np.arange(1, n) - 1) // 2)
+    a, b = 6, 9
+    e, n = G.grid(a, b)
+    csr, _, level = run(e, n, 0)
+    p = O.min_parents(csr, 0, level)
+    i, j = np.divmod(np.arange(n), b)
+    expect = np.where(i > 0, (i - 1) * b + j, i * b + j - 1)
+    expect[0] = 0
+    assert np.array_equal(p, expect)
+    e, n = G.star(7)
+    csr, _, level = run(e, n, 3)
+    p = O.min_parents(csr, 3, level)
+    assert p[3] == 3 and p[0] == 3 and all(p[v] == 0 for v in range(1, n) if v != 3)
+
+
+def test_min_parents_is_a_valid_tree():
+    scale = 11
+    n = 1 << scale
+    e = K.edges_host(scale)
+    csr = O.build_csr(e, n)
+    label = O.components(e, n)
+    for r in K.select_roots(K.nonisolated_host(e, n), 4, K.root_seed(scale)):
+        _, level = O.bfs(csr, r)
+        p = O.min_parents(csr, r, level)
+        assert O.validate(csr, r, p, level, label) == 0
+        # no neighbour one level up has a smaller id than the chosen parent
+        for v in np.flatnonzero(level > 0)[:300]:
+            row = csr.row(v)
+            cand = row[level[row] == level[v] - 1]
+            assert p[v] == cand.min()
