@@ -90,15 +90,18 @@ typedef enum {
  * picked for the graph from the autotuned table compiled into the library
  * (the entry tuned at the scale nearest to log2 n). */
 typedef struct {
-  int32_t direction;    /* g5_direction */
-  double alpha;         /* top-down -> bottom-up when m_f > m_u / alpha */
-  double beta;          /* bottom-up -> top-down when n_f < n / beta and shrinking */
-  int32_t bu_lane_scan; /* neighbours a lane tests before its row goes wave-wide: 1, 2, 4, 8
-                           or 16 */
-  int32_t claim;        /* top-down claim: 0 atomic OR on the visited bitmap (default),
-                           1 compare-and-swap of parent from -1 */
-  int32_t flags;        /* G5_FLAG_* */
+  int32_t direction;      /* g5_direction */
+  int32_t bu_lane_scan;   /* neighbours a lane tests before its row goes wave-wide: 1, 2, 4, 8
+                             or 16 */
+  double alpha;           /* top-down -> bottom-up when m_f > m_u / alpha and the frontier grew */
+  double beta;            /* bottom-up -> top-down when n_f < n / beta and the frontier shrank */
+  double lds_density;     /* bottom-up steps stage the frontier (or a summary of it) in LDS when
+                             the fraction of summary bits set is expected below this */
+  int32_t claim;          /* top-down claim: 0 atomic OR on the visited bitmap, 1 compare-and-swap
+                             of parent from -1 */
+  int32_t flags;          /* G5_FLAG_* */
   int32_t bu_blocks_per_cu; /* bottom-up grid: workgroups per compute unit (1..32) */
+  int32_t lds_kb;         /* LDS for the staged frontier per workgroup, KiB (16..160) */
   int32_t reserved[4];
 } g5_bfs_params;
 
@@ -132,6 +135,12 @@ typedef struct {
  * edge into v; bottom-up steps take the first frontier hit of the ascending
  * row, without the neighbour hint).  Slower; results do not depend on timing. */
 #define G5_FLAG_MIN_PARENT 32
+/* g5_bfs_ex: bottom-up steps always probe the frontier bitmap in HBM instead of
+ * staging it (or, when it does not fit, a summary of it) in LDS. */
+#define G5_FLAG_NO_LDS 64
+/* g5_bfs_ex: bottom-up steps scan unresolved rows one row per 64-lane step
+ * even where the tuned defaults pack them (G5_FLAG_PACKED forces packing). */
+#define G5_FLAG_ROWLOOP 128
 
 #define G5_MAX_STAT_LEVELS 64
 
@@ -149,7 +158,9 @@ typedef struct {
   int64_t reached;                          /* vertices with level >= 0 */
   double alpha, beta;                       /* switch thresholds used */
   int32_t bu_lane_scan, bu_blocks_per_cu;   /* bottom-up shape used */
-  int64_t reserved[6];
+  int32_t lds_levels;                       /* bottom-up levels that staged the frontier in LDS */
+  int32_t lds_shift;                        /* log2 vertices per staged bit (0: exact bitmap) */
+  int64_t reserved[5];
 } g5_bfs_stats;
 
 /* g5_bfs with explicit parameters (NULL = defaults) and optional statistics

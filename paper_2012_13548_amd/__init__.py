@@ -39,14 +39,15 @@ lib = ctypes.CDLL(LIB_PATH)
 
 
 FLAG_TIME_STEPS, FLAG_COUNT_BYTES, FLAG_NO_HINT, FLAG_STEPPED, FLAG_PACKED = 1, 2, 4, 8, 16
-FLAG_MIN_PARENT = 32
+FLAG_MIN_PARENT, FLAG_NO_LDS, FLAG_ROWLOOP = 32, 64, 128
 
 
 class BfsParams(ctypes.Structure):
-    _fields_ = [("direction", ctypes.c_int32), ("alpha", ctypes.c_double),
-                ("beta", ctypes.c_double), ("bu_lane_scan", ctypes.c_int32),
-                ("claim", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("bu_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+    _fields_ = [("direction", ctypes.c_int32), ("bu_lane_scan", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("lds_density", ctypes.c_double), ("claim", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("bu_blocks_per_cu", ctypes.c_int32),
+                ("lds_kb", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 _L = MAX_STAT_LEVELS
@@ -59,7 +60,8 @@ class BfsStats(ctypes.Structure):
                 ("step_ms", ctypes.c_double * _L), ("reached", ctypes.c_int64),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("bu_lane_scan", ctypes.c_int32), ("bu_blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int64 * 6)]
+                ("lds_levels", ctypes.c_int32), ("lds_shift", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 5)]
 
 
 class BatchParams(ctypes.Structure):
@@ -168,21 +170,25 @@ def build_csr(edges, n):
     return Csr(out.value, edges.device)
 
 
-def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None):
+def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None, lds_kb=None,
+            lds_density=None):
     p = BfsParams()
-    p.bu_blocks_per_cu = blocks_per_cu or 0
     p.direction = direction
     p.alpha = alpha or 0.0
     p.beta = beta or 0.0
+    p.lds_density = lds_density or 0.0
     p.bu_lane_scan = lane_scan or 0
     p.claim = claim
     p.flags = flags
+    p.bu_blocks_per_cu = blocks_per_cu or 0
+    p.lds_kb = lds_kb or 0
     return p
 
 
 def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta=None,
-        lane_scan=None, claim=CLAIM_OR, hint=True, packed=False, min_parent=False,
-        blocks_per_cu=None, stats=False, time_steps=False, count_bytes=False):
+        lane_scan=None, claim=CLAIM_OR, hint=True, packed=None, min_parent=False, lds=True,
+        blocks_per_cu=None, lds_kb=None, lds_density=None, stats=False, time_steps=False,
+        count_bytes=False):
     """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
 
     With ``stats=True`` also returns a dict of per-level directions, frontier
@@ -198,10 +204,12 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
         if t.dtype != torch.int32 or t.numel() < csr.n or not t.is_contiguous():
             raise ValueError("parent and level must be contiguous int32 tensors of length n")
     flags = ((FLAG_TIME_STEPS if time_steps else 0) | (FLAG_COUNT_BYTES if count_bytes else 0)
-             | (0 if hint else FLAG_NO_HINT) | (FLAG_PACKED if packed else 0)
-             | (FLAG_MIN_PARENT if min_parent else 0))
-    p = _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu)
-    want = stats or flags
+             | (0 if hint else FLAG_NO_HINT)
+             | {None: 0, True: FLAG_PACKED, False: FLAG_ROWLOOP}[packed]
+             | (FLAG_MIN_PARENT if min_parent else 0) | (0 if lds else FLAG_NO_LDS))
+    p = _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu, lds_kb,
+                lds_density)
+    want = stats or time_steps or count_bytes
     st = BfsStats()
     _check(lib.g5_bfs_ex(csr.handle, int(root), parent.data_ptr(), level.data_ptr(),
                          _stream(csr.device), ctypes.byref(p),
@@ -210,7 +218,8 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
         return parent, level
     nl = min(st.nlevels, MAX_STAT_LEVELS)
     info = {"nlevels": st.nlevels, "reached": st.reached, "alpha": st.alpha, "beta": st.beta,
-            "lane_scan": st.bu_lane_scan, "blocks_per_cu": st.bu_blocks_per_cu}
+            "lane_scan": st.bu_lane_scan, "blocks_per_cu": st.bu_blocks_per_cu,
+            "lds_levels": st.lds_levels, "lds_shift": st.lds_shift}
     for k in ("dir", "frontier", "discovered", "edges", "bytes", "step_ms"):
         info[k] = list(getattr(st, k)[:nl])
     return parent, level, info

@@ -1,9 +1,10 @@
 """Autotuner for the traversal's thresholds and launch shapes.
 
 For each Kronecker scale, a coordinate search over
-  single root: alpha, beta (direction switch), bottom-up lane-scan width and
-               bottom-up workgroups per compute unit; objective = harmonic-mean
-               TEPS over sample roots (m_r / device time per call);
+  single root: alpha, beta (direction switch), bottom-up lane-scan width,
+               workgroups per compute unit, packed row scan, the LDS budget and
+               density threshold of the staged frontier; objective =
+               harmonic-mean TEPS over sample roots (m_r / device time per call);
   batch:       alpha and persistent-grid workgroups per compute unit;
                objective = device time of one 64-root launch with parents.
 Writes ``tuning.json`` (every trial) and ``tuned_table.inc`` (the defaults table
@@ -21,6 +22,9 @@ ALPHA = [6, 10, 14, 20, 28, 40, 56, 80, 112, 160]
 BETA = [6, 12, 24, 48, 96, 192]
 LANE = [1, 2, 4, 8, 16]
 BPC = [4, 8, 16, 32]
+PACKED = [0, 1]
+LDS_KB = [32, 64, 96, 140]
+LDS_DENSITY = [0.01, 0.03, 0.1, 0.3, 1.0]
 B_ALPHA = [2, 4, 8, 14, 28, 56, 112]
 B_BPC = [2, 4, 8]
 
@@ -61,7 +65,9 @@ def tune_scale(scale, nroots, rounds):
         for r, m in zip(sample, m_r):
             e0.record()
             g5.bfs(csr, r, parent, level, alpha=cfg["alpha"], beta=cfg["beta"],
-                   lane_scan=cfg["lane_scan"], blocks_per_cu=cfg["bu_blocks_per_cu"])
+                   lane_scan=cfg["lane_scan"], blocks_per_cu=cfg["bu_blocks_per_cu"],
+                   packed=bool(cfg["packed"]), lds_kb=cfg["lds_kb"],
+                   lds_density=cfg["lds_density"])
             e1.record()
             torch.cuda.synchronize()
             inv += (e0.elapsed_time(e1) / 1e3) / m
@@ -86,10 +92,12 @@ def tune_scale(scale, nroots, rounds):
         return cfg, best
 
     t0 = time.time()
-    single(dict(alpha=14, beta=24, lane_scan=4, bu_blocks_per_cu=8))  # warm
-    cfg, best = search(dict(alpha=14, beta=24, lane_scan=4, bu_blocks_per_cu=8),
-                       {"alpha": ALPHA, "beta": BETA, "lane_scan": LANE, "bu_blocks_per_cu": BPC},
-                       single)
+    start = dict(alpha=14, beta=24, lane_scan=4, bu_blocks_per_cu=32, packed=0, lds_kb=140,
+                 lds_density=0.3)
+    single(start)  # warm
+    cfg, best = search(start, {"alpha": ALPHA, "beta": BETA, "lane_scan": LANE,
+                               "bu_blocks_per_cu": BPC, "packed": PACKED, "lds_kb": LDS_KB,
+                               "lds_density": LDS_DENSITY}, single)
     out = {"scale": scale, **cfg, "hmean_gteps": round(best / 1e9, 3), "roots": len(sample)}
 
     k = 64
@@ -120,13 +128,15 @@ def tune_scale(scale, nroots, rounds):
 
 
 def write_table(entries, path):
-    lines = ["// Autotuned defaults: {scale, alpha, beta, lane_scan, bu_blocks_per_cu, batch_alpha,",
-             "// batch_blocks_per_cu}.  Written by paper_2012_13548_amd/autotune.py from its",
-             "// measurements (tuning.json); the entry nearest to log2 n is used."]
+    lines = ["// Autotuned defaults: {scale, alpha, beta, lane_scan, bu_blocks_per_cu, packed, lds_kb,",
+             "// lds_density, batch_alpha, batch_blocks_per_cu}.  Written by",
+             "// paper_2012_13548_amd/autotune.py from its measurements (tuning.json); the",
+             "// entry nearest to log2 n is used."]
     for e in sorted(entries, key=lambda x: x["scale"]):
         lines.append(f"{{{e['scale']}, {float(e['alpha']):.1f}, {float(e['beta']):.1f}, "
-                     f"{e['lane_scan']}, {e['bu_blocks_per_cu']}, {float(e['batch_alpha']):.1f}, "
-                     f"{e['batch_blocks_per_cu']}}},")
+                     f"{e['lane_scan']}, {e['bu_blocks_per_cu']}, {int(e['packed'])}, "
+                     f"{e['lds_kb']}, {float(e['lds_density']):.2f}, "
+                     f"{float(e['batch_alpha']):.1f}, {e['batch_blocks_per_cu']}}},")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
 

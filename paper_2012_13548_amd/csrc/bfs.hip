@@ -286,27 +286,45 @@ __global__ void k_copy_u64(uint64_t *__restrict__ dst, const uint64_t *__restric
     dst[i] = src[i];
 }
 
-// Bottom-up step.  Wavefront per 64-bit word w of the visited bitmap; lane l
-// owns vertex 64w+l.  A lane first tests LANE_SCAN neighbours itself (loads
-// issued together); rows still unresolved are then scanned by the whole
-// wavefront, 64 neighbours per step, one row at a time.  With ACCT the kernel
-// also counts the neighbours examined up to the first frontier hit and the
-// vertices scanned (algorithmic-byte accounting).
-template <int LANE_SCAN, bool ACCT>
-__global__ __launch_bounds__(kBlock) void k_bu_step(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
-    const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
-    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
-    int32_t next_level, unsigned long long *__restrict__ ctr, bool packed) {
-  __shared__ uint64_t s[kBlock / kWave];
-  __shared__ int64_t s_base[kBlock];
-  __shared__ int32_t s_row[kBlock];
-  __shared__ int32_t s_first[kBlock];
-  const int lane = __lane_id();
-  const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
+// Frontier membership for the bottom-up step: the frontier bitmap in HBM, or
+// a summary staged in LDS (bit i set when some frontier vertex lies in
+// [i << gs, (i + 1) << gs)); with gs = 0 the summary is the bitmap itself.
+struct FrontGlobal {
+  const uint64_t *front;
+  __device__ __forceinline__ bool test(int32_t u) const { return (front[u >> 6] >> (u & 63)) & 1; }
+};
+
+struct FrontLds {
+  const uint32_t *sum;
+  const uint64_t *front;
+  int gs;
+  __device__ __forceinline__ bool test(int32_t u) const {
+    const uint32_t i = (uint32_t)u >> gs;
+    if (!((sum[i >> 5] >> (i & 31)) & 1)) return false;
+    return gs == 0 || ((front[u >> 6] >> (u & 63)) & 1);
+  }
+};
+
+struct BuCount {
   uint64_t nnew = 0, mnew = 0, nscan = 0, nunvis = 0;
+};
+
+// Bottom-up step over visited words w = gw, gw + nw, ...  A wavefront owns one
+// 64-bit word; lane l owns vertex 64w+l.  An unvisited lane tests its hint
+// (highest-degree neighbour, one coalesced load), then LANE_SCAN row entries
+// with loads issued together; rows still unresolved are scanned by the whole
+// wavefront, either packed end to end (one entry per lane per 64-entry window)
+// or one row per 64-lane step.  The ballot of finders is the next-frontier
+// word and is OR-ed into the visited word by one lane: no atomics.  With ACCT
+// it counts the row entries read up to the first hit and the vertices scanned.
+template <int LANE_SCAN, bool ACCT, class Front>
+__device__ __forceinline__ void bu_words(
+    const Front &F, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const int32_t *__restrict__ hint, uint64_t *__restrict__ vis, uint64_t *__restrict__ next,
+    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words, int32_t next_level,
+    bool packed, int64_t gw, int64_t nw, int64_t *s_base, int32_t *s_row, int32_t *s_first,
+    BuCount &cnt) {
+  const int lane = __lane_id();
   for (int64_t w = gw; w < words; w += nw) {
     const uint64_t vw = vis[w];
     if (vw == ~0ull) {
@@ -322,10 +340,10 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
       b = rp[v];
       e = rp[v + 1];
       k = b;
-      if (ACCT) nunvis += 1;
+      if (ACCT) cnt.nunvis += 1;
       if (hint) {  // the highest-degree neighbour first: one coalesced load
         const int32_t h = hint[v];
-        if (h >= 0 && ((front[h >> 6] >> (h & 63)) & 1)) {
+        if (h >= 0 && F.test(h)) {
           found = true;
           par = h;
           k = e;
@@ -334,27 +352,27 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
     }
     if (pending && !found) {
       int32_t u[LANE_SCAN];
-      uint64_t fw[LANE_SCAN];
+      bool hv[LANE_SCAN];
 #pragma unroll
       for (int t = 0; t < LANE_SCAN; ++t) u[t] = (k + t < e) ? ci[k + t] : -1;
 #pragma unroll
-      for (int t = 0; t < LANE_SCAN; ++t) fw[t] = (u[t] >= 0) ? front[u[t] >> 6] : 0;
+      for (int t = 0; t < LANE_SCAN; ++t) hv[t] = u[t] >= 0 && F.test(u[t]);
 #pragma unroll
       for (int t = 0; t < LANE_SCAN; ++t) {
-        if (!found && u[t] >= 0 && ((fw[t] >> (u[t] & 63)) & 1)) {
+        if (!found && hv[t]) {
           found = true;
           par = u[t];
-          if (ACCT) nscan += (uint64_t)(t + 1);
+          if (ACCT) cnt.nscan += (uint64_t)(t + 1);
         }
       }
       const int64_t k0 = k;
       k = std::min<int64_t>(k + LANE_SCAN, e);
-      if (ACCT && !found) nscan += (uint64_t)(k - k0);
+      if (ACCT && !found) cnt.nscan += (uint64_t)(k - k0);
     }
     if (packed) {
-      // Unresolved rows of the wavefront laid end to end, one entry per lane
-      // per 64-entry window; a row's first hit in a window is the smallest
-      // hitting lane (LDS atomic min); resolved rows stop probing.
+      // Unresolved rows laid end to end, one entry per lane per 64-entry
+      // window; a row's first hit in a window is its smallest hitting lane
+      // (LDS atomic min); resolved rows stop probing.
       const uint32_t len = (pending && !found) ? (uint32_t)(e - k) : 0u;
       const uint32_t incl = wave_incl_scan(len);
       const uint32_t total = __shfl(incl, kWave - 1, kWave);
@@ -377,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
           bool hit = false;
           if (j < total && !((done >> r) & 1)) {
             u = ci[s_base[wb + r] + (int64_t)j];
-            hit = (front[u >> 6] >> (u & 63)) & 1;
+            hit = F.test(u);
           }
           if (hit) atomicMin(&s_first[wb + r], lane);
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -388,13 +406,13 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
             found = true;
             par = gv;
             s_first[wb + lane] = kWave;
-            if (ACCT) nscan += (uint64_t)(j0 + fl - pre + 1);
+            if (ACCT) cnt.nscan += (uint64_t)(j0 + fl - pre + 1);
           }
           done |= __ballot(fresh);
           carry = __shfl(r, kWave - 1, kWave);
           if (done == ~0ull) break;
         }
-        if (ACCT && len > 0 && !found) nscan += len;
+        if (ACCT && len > 0 && !found) cnt.nscan += len;
       }
     }
     uint64_t rem = packed ? 0ull : __ballot(pending && !found && k < e);
@@ -405,14 +423,14 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
       int32_t got = -1;
       int64_t seen = ke - kb;
       for (int64_t c = kb; c < ke; c += kWave) {
-        int64_t kk = c + lane;
+        const int64_t kk = c + lane;
         bool hit = false;
         int32_t u = -1;
         if (kk < ke) {
           u = ci[kk];
-          hit = (front[u >> 6] >> (u & 63)) & 1;
+          hit = F.test(u);
         }
-        uint64_t hm = __ballot(hit);
+        const uint64_t hm = __ballot(hit);
         if (hm) {
           const int hl = __ffsll((unsigned long long)hm) - 1;
           got = __shfl(u, hl, kWave);
@@ -425,33 +443,114 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
           found = true;
           par = got;
         }
-        if (ACCT) nscan += (uint64_t)seen;
+        if (ACCT) cnt.nscan += (uint64_t)seen;
       }
     }
     const uint64_t fm = __ballot(found);
     if (found) {
       parent[v] = par;
       level[v] = next_level;
-      mnew += (uint64_t)(e - b);
+      cnt.mnew += (uint64_t)(e - b);
     }
     if (lane == 0) {
       next[w] = fm;
       if (fm) vis[w] = vw | fm;
-      nnew += (uint64_t)__popcll(fm);
+      cnt.nnew += (uint64_t)__popcll(fm);
     }
   }
-  uint64_t tn = block_sum<kBlock, uint64_t>(nnew, s);
-  uint64_t tm = block_sum<kBlock, uint64_t>(mnew, s);
+}
+
+template <int NT, bool ACCT>
+__device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
+                                         unsigned long long *__restrict__ ctr) {
+  const uint64_t tn = block_sum<NT, uint64_t>(c.nnew, s);
+  const uint64_t tm = block_sum<NT, uint64_t>(c.mnew, s);
   if (threadIdx.x == 0) {
     if (tn) atomicAdd(ctr + C_NNEW, (unsigned long long)tn);
     if (tm) atomicAdd(ctr + C_MNEW, (unsigned long long)tm);
   }
   if (ACCT) {
-    uint64_t ts = block_sum<kBlock, uint64_t>(nscan, s);
-    uint64_t tu = block_sum<kBlock, uint64_t>(nunvis, s);
+    const uint64_t ts = block_sum<NT, uint64_t>(c.nscan, s);
+    const uint64_t tu = block_sum<NT, uint64_t>(c.nunvis, s);
     if (threadIdx.x == 0) {
       atomicAdd(ctr + C_SCAN, (unsigned long long)ts);
       atomicAdd(ctr + C_UNVIS, (unsigned long long)tu);
+    }
+  }
+}
+
+// Bottom-up step probing the frontier bitmap in HBM (L2/MALL-resident).
+template <int LANE_SCAN, bool ACCT>
+__global__ __launch_bounds__(kBlock) void k_bu_step(
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
+    const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
+    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
+    int32_t next_level, unsigned long long *__restrict__ ctr, bool packed) {
+  __shared__ uint64_t s[kBlock / kWave];
+  __shared__ int64_t s_base[kBlock];
+  __shared__ int32_t s_row[kBlock];
+  __shared__ int32_t s_first[kBlock];
+  const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
+  BuCount c;
+  bu_words<LANE_SCAN, ACCT>(FrontGlobal{front}, rp, ci, hint, vis, next, parent, level, words,
+                            next_level, packed, gw, nw, s_base, s_row, s_first, c);
+  bu_flush<kBlock, ACCT>(c, s, ctr);
+}
+
+// Bottom-up step with the frontier summary staged in LDS (dynamic shared
+// memory, sum_words 32-bit words): probes of vertices whose summary bit is
+// clear never leave the compute unit.
+constexpr int kLdsBlock = 1024;
+
+template <int LANE_SCAN, bool ACCT>
+__global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
+    const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
+    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
+    int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
+    const uint32_t *__restrict__ sum, int64_t sum_words, int gs) {
+  extern __shared__ uint32_t s_sum[];
+  __shared__ uint64_t s[kLdsBlock / kWave];
+  __shared__ int64_t s_base[kLdsBlock];
+  __shared__ int32_t s_row[kLdsBlock];
+  __shared__ int32_t s_first[kLdsBlock];
+  for (int64_t i = threadIdx.x; i < sum_words; i += kLdsBlock) s_sum[i] = sum[i];
+  __syncthreads();
+  const int64_t gw = ((int64_t)blockIdx.x * kLdsBlock + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * kLdsBlock) / kWave;
+  BuCount c;
+  bu_words<LANE_SCAN, ACCT>(FrontLds{s_sum, front, gs}, rp, ci, hint, vis, next, parent, level,
+                            words, next_level, packed, gw, nw, s_base, s_row, s_first, c);
+  bu_flush<kLdsBlock, ACCT>(c, s, ctr);
+}
+
+// Frontier summary: bit i of sum = OR of front bits [i << gs, (i + 1) << gs).
+// sum must be zeroed first.  One thread per frontier word.
+__global__ void k_front_summary(const uint64_t *__restrict__ front, int64_t words, int gs,
+                                uint32_t *__restrict__ sum) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
+    const uint64_t x = front[w];
+    if (!x) continue;
+    if (gs >= 6) {
+      const uint64_t i = (uint64_t)w >> (gs - 6);
+      atomicOr(sum + (i >> 5), 1u << (i & 31));
+    } else {
+      const int per = 64 >> gs;  // summary bits from this word
+      const uint64_t gm = (gs == 0) ? 1ull : ((1ull << (1 << gs)) - 1);
+      uint64_t m = 0;
+      for (int j = 0; j < per; ++j)
+        if ((x >> (j << gs)) & gm) m |= 1ull << j;
+      const uint64_t base = (uint64_t)w * per;  // aligned to per (a power of two)
+      if (per >= 32) {
+        for (int h = 0; h < per / 32; ++h)
+          if ((uint32_t)(m >> (32 * h))) atomicOr(sum + (base >> 5) + h, (uint32_t)(m >> (32 * h)));
+      } else {
+        atomicOr(sum + (base >> 5), (uint32_t)m << (base & 31));
+      }
     }
   }
 }
@@ -496,6 +595,18 @@ int grid_for(int64_t items, int per_block, int cap) {
   return (int)g;
 }
 
+// Allows a kernel `bytes` of dynamic LDS (once per kernel and size).
+g5_status lds_ready(const void *fn, int64_t bytes) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void *, int64_t>> done;
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto &d : done)
+    if (d.first == fn && d.second >= bytes) return G5_OK;
+  G5_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done.emplace_back(fn, bytes);
+  return G5_OK;
+}
+
 g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   BfsWork *w = new BfsWork();
   w->n = g->n;
@@ -516,6 +627,16 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   A((void **)&w->qoff, (n + 1) * 4);
   A((void **)&w->bsum, std::max(nb, nbf) * 4);
   A((void **)&w->ctr, C_NCTR * 8);
+  // frontier summary for the LDS bottom-up step: as fine as the LDS allows
+  const int64_t static_lds = 20 * 1024;  // k_bu_step_lds's own arrays, with margin
+  const int64_t bits = (g->lds_bytes - static_lds) * 8;
+  if (bits >= 1024) {
+    int gs = 0;
+    while (((n + (1ll << gs) - 1) >> gs) > bits) ++gs;
+    w->sum_gs = gs;
+    w->sum_words = (((n + (1ll << gs) - 1) >> gs) + 31) / 32;
+    A((void **)&w->sum, ((w->sum_words + 1) / 2) * 8);
+  }
   if (e == hipSuccess) e = hipHostMalloc((void **)&w->host_ctr, C_NCTR * 8, hipHostMallocDefault);
   if (e != hipSuccess) {
     set_error(std::string("g5_bfs workspace: ") + hipGetErrorString(e));
@@ -544,6 +665,7 @@ BfsWork::~BfsWork() {
   if (front) (void)hipFree(front);
   if (next) (void)hipFree(next);
   if (prev) (void)hipFree(prev);
+  if (sum) (void)hipFree(sum);
   if (q[0]) (void)hipFree(q[0]);
   if (q[1]) (void)hipFree(q[1]);
   if (qoff) (void)hipFree(qoff);
@@ -575,11 +697,22 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const double beta = p.beta > 0 ? p.beta : g->tune.beta;
   const int lane_scan = p.bu_lane_scan > 0 ? p.bu_lane_scan : g->tune.lane_scan;
   const int bu_bpc = p.bu_blocks_per_cu > 0 ? p.bu_blocks_per_cu : g->tune.bu_blocks_per_cu;
+  const double lds_density = p.lds_density > 0 ? p.lds_density : g->tune.lds_density;
+  const int lds_kb = p.lds_kb > 0 ? p.lds_kb : g->tune.lds_kb;
+  const bool packed = (p.flags & G5_FLAG_PACKED) || (g->tune.packed && !(p.flags & G5_FLAG_ROWLOOP));
+  // staged frontier: summary granularity for this call's LDS budget
+  int lds_gs = w.sum_gs;
+  int64_t lds_words = w.sum_words;
+  if (w.sum) {
+    const int64_t bits = std::min<int64_t>((int64_t)lds_kb * 1024, g->lds_bytes - 20 * 1024) * 8;
+    while (lds_gs < 40 && ((n + (1ll << lds_gs) - 1) >> lds_gs) > bits) ++lds_gs;
+    lds_words = (((n + (1ll << lds_gs) - 1) >> lds_gs) + 31) / 32;
+  }
+  int lds_levels = 0;
   const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
   const bool acct = stats && (p.flags & G5_FLAG_COUNT_BYTES);
   const bool min_parent = (p.flags & G5_FLAG_MIN_PARENT) != 0;
   const bool use_hint = !(p.flags & G5_FLAG_NO_HINT) && !min_parent;
-  const bool packed = (p.flags & G5_FLAG_PACKED) != 0;
   unsigned long long *ctr = (unsigned long long *)w.ctr;
   uint64_t *hc = w.host_ctr;
   const int bu_grid = ncu * bu_bpc;
@@ -602,6 +735,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   int dir = 1;                // 1 top-down, 2 bottom-up
   int64_t m_u = -1;           // directed entries of unvisited vertices
   int64_t nf_prev = 0;
+  int64_t last_nf = 0;        // frontier size of the previous level
   int32_t lvl = 0;
   int64_t reached = 1;
   double deg_ms = 0;          // top-down degree scan time of the current level
@@ -642,8 +776,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         m_u -= mf;
       }
       q_deg_counted = false;
+      const bool growing = qlen > last_nf;
       bool to_bu = (p.direction == G5_DIR_BOTTOMUP) ||
-                   (p.direction == G5_DIR_AUTO && (double)mf > (double)m_u / alpha);
+                   (p.direction == G5_DIR_AUTO && growing && (double)mf > (double)m_u / alpha);
       if (to_bu) {
         hipLaunchKernelGGL(k_front_from_vis, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
                            s, w.vis, w.prev, front, W);
@@ -695,32 +830,65 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         }
       }
       cur = nxt;
+      last_nf = qlen;
       qlen = found;
       reached += qlen;
       ++lvl;
     } else {
       G5_HIP(hipMemsetAsync(ctr + C_NNEW, 0, 16, s));
       if (acct) G5_HIP(hipMemsetAsync(ctr + C_SCAN, 0, 16, s));
+      const bool use_lds = w.sum && !(p.flags & G5_FLAG_NO_LDS) &&
+                           (double)nf_prev * (double)(1ll << std::min(lds_gs, 62)) <
+                               lds_density * (double)n;
+      if (use_lds) {
+        ++lds_levels;
+        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for((lds_words + 1) / 2, kBlock, ncu * 16)),
+                           dim3(kBlock), 0, s, (uint64_t *)w.sum, (lds_words + 1) / 2);
+        hipLaunchKernelGGL(k_front_summary, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
+                           s, front, W, lds_gs, w.sum);
+      }
       if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
+#define G5_BUL(K, A)                                                                        \
+  do {                                                                                      \
+    const void *fn_ = (const void *)&k_bu_step_lds<K, A>;                                    \
+    g5_status st_ = lds_ready(fn_, lds_words * 4);                                          \
+    if (st_ != G5_OK) return st_;                                                           \
+    int per_cu_ = 1;                                                                        \
+    G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_, fn_, kLdsBlock,           \
+                                                        (size_t)lds_words * 4));            \
+    hipLaunchKernelGGL((k_bu_step_lds<K, A>), dim3(ncu * std::max(per_cu_, 1)),             \
+                       dim3(kLdsBlock), lds_words * 4, s, g->row_ptr, g->col_idx,            \
+                       use_hint ? g->hint : nullptr, w.vis, front, next, parent, level, n, W, \
+                       lvl + 1, ctr, packed, w.sum, lds_words, lds_gs);                     \
+  } while (0)
 #define G5_BU(K, A)                                                                        \
   hipLaunchKernelGGL((k_bu_step<K, A>), dim3(bu_grid), dim3(kBlock), 0, s, g->row_ptr,     \
                      g->col_idx, use_hint ? g->hint : nullptr, w.vis, front, next, parent,    \
                      level, n, W, lvl + 1, ctr, packed)
-#define G5_BU_K(A)               \
+#define G5_BU_K(M, A)            \
   switch (lane_scan) {           \
-    case 1: G5_BU(1, A); break;  \
-    case 2: G5_BU(2, A); break;  \
-    case 8: G5_BU(8, A); break;  \
-    case 16: G5_BU(16, A); break; \
-    default: G5_BU(4, A); break; \
+    case 1: M(1, A); break;      \
+    case 2: M(2, A); break;      \
+    case 8: M(8, A); break;      \
+    case 16: M(16, A); break;    \
+    default: M(4, A); break;     \
   }
-      if (acct) {
-        G5_BU_K(true);
+      if (use_lds) {
+        if (acct) {
+          G5_BU_K(G5_BUL, true);
+        } else {
+          G5_BU_K(G5_BUL, false);
+        }
       } else {
-        G5_BU_K(false);
+        if (acct) {
+          G5_BU_K(G5_BU, true);
+        } else {
+          G5_BU_K(G5_BU, false);
+        }
       }
 #undef G5_BU_K
 #undef G5_BU
+#undef G5_BUL
       G5_LAUNCH_CHECK();
       if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
       G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
@@ -743,6 +911,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       }
       m_u -= (int64_t)hc[C_MNEW];
       reached += nnew;
+      last_nf = nf_prev;
       ++lvl;
       if (nnew == 0) break;
       bool to_td = p.direction == G5_DIR_TOPDOWN ||
@@ -772,6 +941,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     stats->beta = beta;
     stats->bu_lane_scan = lane_scan;
     stats->bu_blocks_per_cu = bu_bpc;
+    stats->lds_levels = lds_levels;
+    stats->lds_shift = lds_gs;
   }
   G5_HIP(hipStreamSynchronize(s));
   return G5_OK;

@@ -409,6 +409,12 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
   g->num_cu = ncu;
   g->words = (n + 63) / 64;
   g->tune = pick_tuning(sb);
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        lds > 0)
+      g->lds_bytes = lds;
+  }
   auto fail = [&](hipError_t e, const char *what) {
     set_error(std::string("g5_build_csr: ") + what + ": " + hipGetErrorString(e));
     g5_csr_free(g);

@@ -48,6 +48,9 @@ struct BfsWork {
   uint64_t *front = nullptr;  // frontier bitmap (bottom-up input)
   uint64_t *next = nullptr;   // next-frontier bitmap (bottom-up output)
   uint64_t *prev = nullptr;   // visited bitmap before the last top-down expansion
+  uint32_t *sum = nullptr;    // frontier summary staged in LDS by bottom-up steps
+  int64_t sum_words = 0;      // its 32-bit words
+  int sum_gs = 0;             // log2 of the vertices per summary bit
   int32_t *q[2] = {nullptr, nullptr};  // frontier queues
   uint32_t *qoff = nullptr;   // per-frontier-vertex edge offsets (top-down)
   uint32_t *bsum = nullptr;   // per-block partial sums
@@ -75,6 +78,9 @@ struct Tuning {
   double alpha, beta;     // single-root direction switch
   int lane_scan;          // bottom-up lane scan width
   int bu_blocks_per_cu;   // bottom-up grid
+  int packed;             // bottom-up packed row scan
+  int lds_kb;             // LDS budget of the staged frontier per workgroup
+  double lds_density;     // stage the frontier in LDS below this summary density
   double batch_alpha;     // batched direction switch
   int batch_blocks_per_cu;
 };
@@ -87,6 +93,7 @@ struct g5_csr {
   int sb = 1;                  // bits of a vertex id in a sort key
   int device = 0;
   int num_cu = 256;
+  int64_t lds_bytes = 65536;   // LDS a workgroup may use on this device
   int64_t nonisolated = 0;     // vertices of degree >= 1
   int64_t *row_ptr = nullptr;  // device [n+1]
   int32_t *col_idx = nullptr;  // device [nnz]

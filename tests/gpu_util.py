@@ -34,8 +34,10 @@ class Case:
 
     def check_root(self, root, **kw):
         import paper_2012_13548_amd as g5
-        parent, level = g5.bfs(self.csr, root, **kw)
+        parent, level, st = g5.bfs(self.csr, root, stats=True, **kw)
         parent, level = parent.cpu().numpy(), level.cpu().numpy()
+        # every reached vertex was claimed exactly once (queue and bitmap counts)
+        assert st["reached"] == int((level >= 0).sum()), (root, kw, st["reached"])
         _, olevel = O.bfs(self.ocsr, root)
         bad = np.flatnonzero(level != olevel)
         assert bad.size == 0, (f"root {root} {kw}: {bad.size} levels differ, first at "

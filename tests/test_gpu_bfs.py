@@ -16,9 +16,13 @@ MODES = [dict(direction=g5.DIR_AUTO), dict(direction=g5.DIR_TOPDOWN),
          dict(direction=g5.DIR_AUTO, alpha=1e6, beta=1e6),
          dict(direction=g5.DIR_AUTO, alpha=1e-3, beta=2.0), dict(hint=False),
          dict(direction=g5.DIR_BOTTOMUP, hint=False, lane_scan=1),
-         dict(packed=True), dict(direction=g5.DIR_BOTTOMUP, packed=True, hint=False, lane_scan=1)]
+         dict(packed=True), dict(direction=g5.DIR_BOTTOMUP, packed=True, hint=False, lane_scan=1),
+         dict(lds=False), dict(direction=g5.DIR_BOTTOMUP, lds=False, packed=True),
+         dict(direction=g5.DIR_BOTTOMUP, lds_kb=16, lds_density=1.0, packed=True),
+         dict(direction=g5.DIR_BOTTOMUP, lds_kb=16, lds_density=1.0, packed=False)]
 MODE_IDS = ["auto", "td", "bu", "auto-cas", "auto-eager", "auto-late", "nohint", "bu-nohint-1",
-            "packed", "bu-packed-nohint-1"]
+            "packed", "bu-packed-nohint-1", "nolds", "bu-nolds-packed", "bu-lds16-packed",
+            "bu-lds16-rows"]
 
 
 @pytest.fixture(params=range(len(MODES)), ids=MODE_IDS)
