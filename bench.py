@@ -93,8 +93,9 @@ def _pmc_rows(d):
         return list(csv.DictReader(f))
 
 
-def _per_dispatch(rows, counter, match):
-    """Average of `counter` (KiB) over dispatches whose kernel name satisfies match."""
+def _per_dispatch(rows, counter, match, largest=False):
+    """Average (or, with largest, maximum) of `counter` (KiB) over dispatches
+    whose kernel name satisfies match."""
     per = {}
     for r in rows:
         if r.get("Counter_Name") != counter or not match(r.get("Kernel_Name", "")):
@@ -103,6 +104,8 @@ def _per_dispatch(rows, counter, match):
         per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
     if not per:
         raise SystemExit(f"no {counter} samples for the requested kernel")
+    if largest:
+        return max(per.values()), 1
     return sum(per.values()) / len(per), len(per)
 
 
@@ -111,11 +114,12 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command):
     WRITE_SIZE run; each counter is scaled by what it reads for the copy probe
     (known bytes).  Stored in profiles/traffic.json with the kernel source hash,
     so the bench reports it only while the kernel is unchanged."""
-    is_copy = lambda name: "add" in name.lower() or "Add" in name
-    is_k = lambda name: kernel in name and "true>" not in name
+    # the copy probe: torch's elementwise add over 2 GiB, the largest such dispatch
+    is_copy = lambda name: "elementwise_kernel" in name and "_add<long>" in name
+    is_k = lambda name: (kernel + "<") in name and "true>" not in name
     fr, wr = _pmc_rows(fetch_dir), _pmc_rows(write_dir)
-    copy_f, _ = _per_dispatch(fr, "FETCH_SIZE", is_copy)
-    copy_w, _ = _per_dispatch(wr, "WRITE_SIZE", is_copy)
+    copy_f, _ = _per_dispatch(fr, "FETCH_SIZE", is_copy, largest=True)
+    copy_w, _ = _per_dispatch(wr, "WRITE_SIZE", is_copy, largest=True)
     k_f, nf = _per_dispatch(fr, "FETCH_SIZE", is_k)
     k_w, nw = _per_dispatch(wr, "WRITE_SIZE", is_k)
     f_factor = COPY_PROBE_BYTES / (copy_f * 1024)

@@ -102,20 +102,22 @@ typedef struct {
   int32_t flags;          /* G5_FLAG_* */
   int32_t bu_blocks_per_cu; /* bottom-up grid: workgroups per compute unit (1..32) */
   int32_t lds_kb;         /* LDS for the staged frontier per workgroup, KiB (16..160) */
-  int32_t reserved[4];
+  int32_t bu_words_per_wave; /* bottom-up: visited words a wavefront works on at once: 1, 2, 4 */
+  int32_t reserved[3];
 } g5_bfs_params;
 
 /* Time each level's step with HIP events on `stream` (step_ms in the stats). */
 #define G5_FLAG_TIME_STEPS 1
 /* Count the algorithmic bytes and edges of each level (slower kernels; use in
  * an untimed run).  Bytes per level:
- *   top-down   20 per frontier vertex (queue entry + two row offsets)
+ *   top-down   12 per frontier vertex (queue entry + two 32-bit row offsets)
  *              + 4 per frontier edge + 12 per discovered vertex (level, parent,
  *              queue entry);
- *   bottom-up  8 per unvisited non-isolated vertex (its row offset; 12 with the
- *              neighbour hint) + 4 per row entry read up to the first frontier
- *              hit + n/4 (visited words read, next-frontier words written)
- *              + 8 per discovered vertex (level, parent).
+ *   bottom-up  4 per unvisited non-isolated vertex (its neighbour hint) + 4 per
+ *              vertex whose hint missed (its 32-bit row offset) + 4 per row
+ *              entry read up to the first frontier hit + n/4 (visited words
+ *              read, next-frontier words written) + 8 per discovered vertex
+ *              (level, parent).
  * Frontier-bitmap probes (one per examined neighbour) are not counted. */
 #define G5_FLAG_COUNT_BYTES 2
 /* Do not test each vertex's highest-degree neighbour (built by g5_build_csr)

@@ -21,6 +21,8 @@
 //   switch    top-down -> bottom-up when m_f > m_u / alpha; back when
 //             n_f < n / beta and the frontier shrinks.
 #include <algorithm>
+#include <atomic>
+#include <cstring>
 
 #include "g5_internal.h"
 
@@ -34,23 +36,36 @@ constexpr int kTdItems = 4;
 constexpr int kTdTile = kBlock * kTdItems;    // edges per top-down block
 constexpr int kScanBlock = 1024;
 
-// Device counters of one traversal (uint64 slots of BfsWork::ctr).
+// Device counters of one traversal (uint64 slots of BfsWork::ctr).  The last
+// kernel of a level copies them, with a sequence number, to pinned host memory
+// the host polls (publish), so a level costs one host wait and no copies.
 enum Ctr : int {
   C_QLEN0 = 0,  // length of queue 0
   C_QLEN1 = 1,  // length of queue 1
   C_MF = 2,     // degree sum of the scanned frontier queue
-  C_NNEW = 3,   // vertices found by a bottom-up step
-  C_MNEW = 4,   // their degree sum
+  C_NNEW = 3,   // vertices found by a bottom-up step (reset after publishing)
   C_RDEG = 5,   // degree of the root
   C_ERR = 6,    // nonzero if a kernel met an impossible state
-  C_SCAN = 7,   // neighbours examined by a bottom-up step (byte counting only)
+  C_SCAN = 7,   // row entries read by a bottom-up step (byte counting only)
   C_UNVIS = 8,  // unvisited non-isolated vertices it scanned (byte counting only)
+  C_ROWS = 9,   // those that read their row offsets (hint missed; byte counting only)
   C_NCTR = 16
 };
 
+// Copies the counters to host memory, then releases the sequence number.
+__device__ void publish(const unsigned long long *ctr, unsigned long long *host,
+                        unsigned long long seq) {
+  for (int i = 0; i < C_NCTR; ++i)
+    __hip_atomic_store(host + i, __hip_atomic_load(ctr + i, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(host + C_NCTR, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ parent, int64_t n,
-                           uint64_t *__restrict__ vis, uint64_t *__restrict__ prev,
-                           const uint64_t *__restrict__ iso, int64_t words, bool vec) {
+                           uint64_t *__restrict__ vis, uint64_t *__restrict__ prev0,
+                           uint64_t *__restrict__ prev1, const uint64_t *__restrict__ iso,
+                           int64_t words, bool vec) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t n4 = vec ? n / 4 : 0;
@@ -65,7 +80,8 @@ __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ pa
   }
   for (int64_t i = t; i < words; i += stride) {
     vis[i] = iso[i];
-    prev[i] = iso[i];
+    prev0[i] = iso[i];
+    prev1[i] = iso[i];
   }
 }
 
@@ -77,7 +93,7 @@ __global__ void k_bfs_seed(int64_t root, int32_t *level, int32_t *parent, uint64
   q0[0] = (int32_t)root;
   ctr[C_QLEN0] = 1;
   ctr[C_QLEN1] = 0;
-  ctr[C_RDEG] = (unsigned long long)(rp[root + 1] - rp[root]);
+  ctr[C_RDEG] = (unsigned long long)(rp[root + 1] - rp[root]);  // 64-bit offsets
 }
 
 __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
@@ -85,35 +101,77 @@ __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
 }
 
-// Degrees of Q[b*1024 .. +1024): block-local exclusive prefix into qoff,
-// block total into bsum[b].
-__global__ __launch_bounds__(kBlock) void k_td_deg(const int32_t *__restrict__ q, int64_t qlen,
-                                                   const int64_t *__restrict__ rp,
+// Degrees of the frontier queue in 1024-entry chunks (chunk c: block-local
+// exclusive prefix into qoff, total into bsum[c]); grid-stride over chunks, the
+// queue length read from the device.  The same launch snapshots the visited
+// bitmap into `snap` before this level's expansion.
+__global__ __launch_bounds__(kBlock) void k_td_deg(const int32_t *__restrict__ q,
+                                                   const unsigned long long *__restrict__ qlen_p,
+                                                   const uint32_t *__restrict__ rp,
                                                    uint32_t *__restrict__ qoff,
-                                                   uint32_t *__restrict__ bsum) {
+                                                   uint32_t *__restrict__ bsum,
+                                                   uint64_t *__restrict__ snap,
+                                                   const uint64_t *__restrict__ vis,
+                                                   int64_t words) {
   __shared__ uint32_t s[kBlock / kWave];
-  int64_t b = (int64_t)blockIdx.x * kDegTile + (int64_t)threadIdx.x * kDegItems;
-  uint32_t d[kDegItems];
-  uint32_t sum = 0;
+  const int64_t qlen = (int64_t)*qlen_p;
+  const int64_t nchunks = (qlen + kDegTile - 1) / kDegTile;
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int64_t b = c * kDegTile + (int64_t)threadIdx.x * kDegItems;
+    uint32_t d[kDegItems];
+    uint32_t sum = 0;
 #pragma unroll
-  for (int j = 0; j < kDegItems; ++j) {
-    int64_t i = b + j;
-    d[j] = 0;
-    if (i < qlen) {
-      int32_t u = q[i];
-      d[j] = (uint32_t)(rp[u + 1] - rp[u]);
+    for (int j = 0; j < kDegItems; ++j) {
+      const int64_t i = b + j;
+      d[j] = 0;
+      if (i < qlen) {
+        const int32_t u = q[i];
+        d[j] = rp[u + 1] - rp[u];
+      }
+      sum += d[j];
     }
-    sum += d[j];
-  }
-  uint32_t tot;
-  uint32_t run = block_excl_scan<kBlock, uint32_t>(sum, s, tot);
+    uint32_t tot;
+    uint32_t run = block_excl_scan<kBlock, uint32_t>(sum, s, tot);
 #pragma unroll
-  for (int j = 0; j < kDegItems; ++j) {
-    int64_t i = b + j;
-    if (i < qlen) qoff[i] = run;
-    run += d[j];
+    for (int j = 0; j < kDegItems; ++j) {
+      const int64_t i = b + j;
+      if (i < qlen) qoff[i] = run;
+      run += d[j];
+    }
+    if (threadIdx.x == 0) bsum[c] = tot;
   }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride)
+    snap[i] = vis[i];
+}
+
+// Exclusive scan of the chunk totals (single block): bsum becomes the chunk
+// offsets, ctr[C_MF] the frontier's degree sum; clears the next queue's length
+// and publishes the counters.
+__global__ __launch_bounds__(kScanBlock) void k_td_scan(uint32_t *__restrict__ bsum,
+                                                        unsigned long long *__restrict__ ctr,
+                                                        int cur,
+                                                        unsigned long long *__restrict__ host,
+                                                        unsigned long long seq) {
+  __shared__ uint32_t s[kScanBlock / kWave];
+  const int64_t qlen = (int64_t)ctr[C_QLEN0 + cur];
+  const int64_t len = (qlen + kDegTile - 1) / kDegTile;
+  const int64_t per = (len + kScanBlock - 1) / kScanBlock;
+  const int64_t b = per * threadIdx.x, e = std::min<int64_t>(b + per, len);
+  uint32_t sum = 0;
+  for (int64_t i = b; i < e; ++i) sum += bsum[i];
+  uint32_t tot;
+  uint32_t run = block_excl_scan<kScanBlock, uint32_t>(sum, s, tot);
+  for (int64_t i = b; i < e; ++i) {
+    const uint32_t x = bsum[i];
+    bsum[i] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) {
+    ctr[C_MF] = tot;
+    ctr[C_QLEN0 + (cur ^ 1)] = 0;
+    publish(ctr, host, seq);
+  }
 }
 
 // In-place exclusive scan of bsum[0..len) (single block); total -> *out.
@@ -135,28 +193,30 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_bsum(uint32_t *__restrict__
   if (threadIdx.x == 0) *out = tot;
 }
 
-// qoff[i] += bsum[i / 1024]; qoff[qlen] = total.
-__global__ void k_td_fix(uint32_t *__restrict__ qoff, int64_t qlen,
-                         const uint32_t *__restrict__ bsum,
-                         const unsigned long long *__restrict__ total) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= qlen; i += stride)
-    qoff[i] = (i == qlen) ? (uint32_t)*total : qoff[i] + bsum[i / kDegTile];
-}
+// Global edge offset of frontier entry i: chunk offset + in-chunk prefix.
+struct FrontOffsets {
+  const uint32_t *qoff, *boff;
+  int64_t qlen;
+  uint32_t total;
+  __device__ __forceinline__ uint32_t operator()(int64_t i) const {
+    return i >= qlen ? total : qoff[i] + boff[i / kDegTile];
+  }
+};
 
-// Largest i in [0, len) with off[i] <= e (off non-decreasing, off[0] = 0 <= e):
+// Largest i in [0, len) with off(i) <= e (off non-decreasing, off(0) = 0 <= e):
 // a 256-way search, one probe per thread per round.
-__device__ int64_t block_search(const uint32_t *__restrict__ off, int64_t len, uint32_t e) {
+template <class Off>
+__device__ int64_t block_search(const Off &off, int64_t len, uint32_t e) {
   int64_t lo = 0, hi = len;
   while (true) {
     int64_t span = hi - lo;
     if (span <= kBlock) {
       int64_t p = lo + threadIdx.x;
-      int c = __syncthreads_count(p < hi && off[p] <= e);
+      int c = __syncthreads_count(p < hi && off(p) <= e);
       return lo + c - 1;
     }
     int64_t p = lo + (span * (int64_t)threadIdx.x) / kBlock;
-    int c = __syncthreads_count(off[p] <= e);
+    int c = __syncthreads_count(off(p) <= e);
     int64_t nlo = lo + (span * (int64_t)(c - 1)) / kBlock;
     int64_t nhi = (c < kBlock) ? lo + (span * (int64_t)c) / kBlock : hi;
     lo = nlo;
@@ -179,7 +239,8 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
 template <int CLAIM>
 __global__ __launch_bounds__(kBlock) void k_td_expand(
     const int32_t *__restrict__ q, int64_t qlen, const uint32_t *__restrict__ qoff,
-    uint32_t total, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const uint32_t *__restrict__ boff, uint32_t total, const uint32_t *__restrict__ rp,
+    const int32_t *__restrict__ ci,
     uint64_t *vis, const uint64_t *__restrict__ prev, int32_t *parent,
     int32_t *__restrict__ level, int32_t *__restrict__ qn,
     unsigned long long *__restrict__ qn_len, int32_t next_level,
@@ -193,22 +254,23 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
   const uint32_t e0 = blockIdx.x * (uint32_t)kTdTile;
   if (e0 >= total) return;
   const uint32_t e1 = (uint32_t)std::min<uint64_t>((uint64_t)e0 + kTdTile, total);
-  const int64_t i0 = block_search(qoff, qlen, e0);
-  const int64_t i1 = block_search(qoff, qlen, e1 - 1);
+  const FrontOffsets off{qoff, boff, qlen, total};
+  const int64_t i0 = block_search(off, qlen, e0);
+  const int64_t i1 = block_search(off, qlen, e1 - 1);
   const int S = (int)(i1 - i0 + 1);
   if (S > kTdTile) {  // only degree-0 vertices could do this, and none are queued
     if (threadIdx.x == 0) atomicOr(err, 1ull);
     return;
   }
   for (int k = threadIdx.x; k < S; k += kBlock) {
-    uint32_t o = qoff[i0 + k];
+    uint32_t o = off(i0 + k);
     int32_t u = q[i0 + k];
     s_off[k] = o;
     s_src[k] = u;
-    s_base[k] = rp[u] - (int64_t)o;
+    s_base[k] = (int64_t)rp[u] - (int64_t)o;
   }
   if (threadIdx.x == 0) {
-    s_off[S] = qoff[i1 + 1];
+    s_off[S] = off(i1 + 1);
     s_cnt = 0;
   }
   __syncthreads();
@@ -279,12 +341,6 @@ __global__ void k_front_from_vis(const uint64_t *__restrict__ vis,
     front[i] = vis[i] & ~prev[i];
 }
 
-__global__ void k_copy_u64(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src,
-                           int64_t words) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
-    dst[i] = src[i];
-}
 
 // Frontier membership for the bottom-up step: the frontier bitmap in HBM, or
 // a summary staged in LDS (bit i set when some frontier vertex lies in
@@ -306,187 +362,252 @@ struct FrontLds {
 };
 
 struct BuCount {
-  uint64_t nnew = 0, mnew = 0, nscan = 0, nunvis = 0;
+  uint64_t nnew = 0, nscan = 0, nunvis = 0, nrows = 0;
 };
 
-// Bottom-up step over visited words w = gw, gw + nw, ...  A wavefront owns one
-// 64-bit word; lane l owns vertex 64w+l.  An unvisited lane tests its hint
-// (highest-degree neighbour, one coalesced load), then LANE_SCAN row entries
-// with loads issued together; rows still unresolved are scanned by the whole
-// wavefront, either packed end to end (one entry per lane per 64-entry window)
-// or one row per 64-lane step.  The ballot of finders is the next-frontier
-// word and is OR-ed into the visited word by one lane: no atomics.  With ACCT
-// it counts the row entries read up to the first hit and the vertices scanned.
-template <int LANE_SCAN, bool ACCT, class Front>
+// Bottom-up step.  A wavefront owns 64-bit visited words (lane l of word w
+// owns vertex 64w+l) and takes WPW consecutive words at a time so that the
+// independent loads of all of them (visited words, row offsets, hints, hint
+// probes, first row entries and their probes) are in flight together.  An
+// unvisited lane tests its hint (highest-degree neighbour), then LANE_SCAN row
+// entries; rows still unresolved are scanned by the whole wavefront, either
+// packed end to end (one entry per lane per 64-entry window) or one row per
+// 64-lane step.  The ballot of finders is the next-frontier word and is OR-ed
+// into the visited word by one lane: no atomics.  With ACCT it counts the row
+// entries read up to the first hit and the vertices scanned.
+template <class Front, bool ACCT>
+__device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__restrict__ ci,
+                                            bool packed, bool pending, int64_t k, int64_t e,
+                                            bool &found, int32_t &par, int64_t *s_base,
+                                            int32_t *s_row, int32_t *s_first, BuCount &cnt) {
+  const int lane = __lane_id();
+  if (packed) {
+    // Unresolved rows laid end to end, one entry per lane per 64-entry window;
+    // a row's first hit in a window is its smallest hitting lane (LDS atomic
+    // min); resolved rows stop probing.
+    const uint32_t len = (pending && !found) ? (uint32_t)(e - k) : 0u;
+    const uint32_t incl = wave_incl_scan(len);
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    if (total) {
+      const uint32_t pre = incl - len;
+      const int wb = (threadIdx.x / kWave) * kWave;
+      s_base[wb + lane] = k - (int64_t)pre;
+      s_first[wb + lane] = kWave;
+      uint64_t done = __ballot(len == 0);
+      int carry = 0;
+      for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
+        const bool starts = len > 0 && pre >= j0 && pre < j0 + kWave;
+        if (starts) s_row[wb + (int)(pre - j0)] = lane;
+        const uint64_t S = wave_or_u64(starts ? (1ull << (pre - j0)) : 0ull);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const uint64_t upto = S & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
+        const int r = upto ? s_row[wb + (kWave - 1 - __clzll((long long)upto))] : carry;
+        const uint32_t j = j0 + lane;
+        int32_t u = -1;
+        bool hit = false;
+        if (j < total && !((done >> r) & 1)) {
+          u = ci[s_base[wb + r] + (int64_t)j];
+          hit = F.test(u);
+        }
+        if (hit) atomicMin(&s_first[wb + r], lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int fl = s_first[wb + lane];
+        const bool fresh = fl < kWave;
+        const int32_t gv = __shfl(u, fresh ? fl : lane, kWave);
+        if (fresh) {
+          found = true;
+          par = gv;
+          s_first[wb + lane] = kWave;
+          if (ACCT) cnt.nscan += (uint64_t)(j0 + fl - pre + 1);
+        }
+        done |= __ballot(fresh);
+        carry = __shfl(r, kWave - 1, kWave);
+        if (done == ~0ull) break;
+      }
+      if (ACCT && len > 0 && !found) cnt.nscan += len;
+    }
+    return;
+  }
+  uint64_t rem = __ballot(pending && !found && k < e);
+  while (rem) {
+    const int L = __ffsll((unsigned long long)rem) - 1;
+    rem &= rem - 1;
+    const int64_t kb = __shfl(k, L, kWave), ke = __shfl(e, L, kWave);
+    int32_t got = -1;
+    int64_t seen = ke - kb;
+    for (int64_t c = kb; c < ke; c += kWave) {
+      const int64_t kk = c + lane;
+      bool hit = false;
+      int32_t u = -1;
+      if (kk < ke) {
+        u = ci[kk];
+        hit = F.test(u);
+      }
+      const uint64_t hm = __ballot(hit);
+      if (hm) {
+        const int hl = __ffsll((unsigned long long)hm) - 1;
+        got = __shfl(u, hl, kWave);
+        seen = c - kb + hl + 1;
+        break;
+      }
+    }
+    if (lane == L) {
+      if (got >= 0) {
+        found = true;
+        par = got;
+      }
+      if (ACCT) cnt.nscan += (uint64_t)seen;
+    }
+  }
+}
+
+template <int LANE_SCAN, int WPW, bool ACCT, class Front>
 __device__ __forceinline__ void bu_words(
-    const Front &F, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const Front &F, const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const int32_t *__restrict__ hint, uint64_t *__restrict__ vis, uint64_t *__restrict__ next,
     int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words, int32_t next_level,
     bool packed, int64_t gw, int64_t nw, int64_t *s_base, int32_t *s_row, int32_t *s_first,
     BuCount &cnt) {
   const int lane = __lane_id();
-  for (int64_t w = gw; w < words; w += nw) {
-    const uint64_t vw = vis[w];
-    if (vw == ~0ull) {
-      if (lane == 0) next[w] = 0;
-      continue;
+  for (int64_t w0 = gw * WPW; w0 < words; w0 += nw * WPW) {
+    uint64_t vw[WPW];
+    bool pend[WPW], found[WPW];
+    int64_t b[WPW], e[WPW], k[WPW];
+    int32_t par[WPW], h[WPW];
+#pragma unroll
+    for (int j = 0; j < WPW; ++j) vw[j] = (w0 + j < words) ? vis[w0 + j] : ~0ull;
+#pragma unroll
+    for (int j = 0; j < WPW; ++j) {
+      const int64_t v = (w0 + j) * kWave + lane;
+      pend[j] = !((vw[j] >> lane) & 1);  // padding lanes past n are pre-set in iso
+      found[j] = false;
+      par[j] = -1;
+      b[j] = e[j] = 0;
+      h[j] = -1;
+      if (pend[j] && hint) h[j] = hint[v];
+      if (ACCT && pend[j]) cnt.nunvis += 1;
     }
-    const int64_t v = w * kWave + lane;
-    const bool pending = !((vw >> lane) & 1);  // padding lanes past n are pre-set in iso
-    int64_t b = 0, e = 0, k = 0;
-    bool found = false;
-    int32_t par = -1;
-    if (pending) {
-      b = rp[v];
-      e = rp[v + 1];
-      k = b;
-      if (ACCT) cnt.nunvis += 1;
-      if (hint) {  // the highest-degree neighbour first: one coalesced load
-        const int32_t h = hint[v];
-        if (h >= 0 && F.test(h)) {
-          found = true;
-          par = h;
-          k = e;
-        }
+#pragma unroll
+    for (int j = 0; j < WPW; ++j) {  // the highest-degree neighbour first
+      if (h[j] >= 0 && F.test(h[j])) {
+        found[j] = true;
+        par[j] = h[j];
       }
     }
-    if (pending && !found) {
-      int32_t u[LANE_SCAN];
+#pragma unroll
+    for (int j = 0; j < WPW; ++j) {  // row offsets only where the hint missed
+      const int64_t v = (w0 + j) * kWave + lane;
+      if (pend[j] && !found[j]) {
+        b[j] = rp[v];
+        e[j] = rp[v + 1];
+        if (ACCT) cnt.nrows += 1;
+      }
+      k[j] = b[j];
+    }
+    int32_t u[WPW][LANE_SCAN];
+#pragma unroll
+    for (int j = 0; j < WPW; ++j)
+#pragma unroll
+      for (int t = 0; t < LANE_SCAN; ++t)
+        u[j][t] = (pend[j] && !found[j] && k[j] + t < e[j]) ? ci[k[j] + t] : -1;
+#pragma unroll
+    for (int j = 0; j < WPW; ++j) {
       bool hv[LANE_SCAN];
 #pragma unroll
-      for (int t = 0; t < LANE_SCAN; ++t) u[t] = (k + t < e) ? ci[k + t] : -1;
+      for (int t = 0; t < LANE_SCAN; ++t) hv[t] = u[j][t] >= 0 && F.test(u[j][t]);
+      if (pend[j] && !found[j]) {
 #pragma unroll
-      for (int t = 0; t < LANE_SCAN; ++t) hv[t] = u[t] >= 0 && F.test(u[t]);
+        for (int t = 0; t < LANE_SCAN; ++t) {
+          if (!found[j] && hv[t]) {
+            found[j] = true;
+            par[j] = u[j][t];
+            if (ACCT) cnt.nscan += (uint64_t)(t + 1);
+          }
+        }
+        const int64_t k0 = k[j];
+        k[j] = std::min<int64_t>(k[j] + LANE_SCAN, e[j]);
+        if (ACCT && !found[j]) cnt.nscan += (uint64_t)(k[j] - k0);
+      }
+    }
 #pragma unroll
-      for (int t = 0; t < LANE_SCAN; ++t) {
-        if (!found && hv[t]) {
-          found = true;
-          par = u[t];
-          if (ACCT) cnt.nscan += (uint64_t)(t + 1);
-        }
+    for (int j = 0; j < WPW; ++j) {
+      const int64_t w = w0 + j;
+      if (w >= words) break;
+      if (vw[j] == ~0ull) {
+        if (lane == 0) next[w] = 0;
+        continue;
       }
-      const int64_t k0 = k;
-      k = std::min<int64_t>(k + LANE_SCAN, e);
-      if (ACCT && !found) cnt.nscan += (uint64_t)(k - k0);
-    }
-    if (packed) {
-      // Unresolved rows laid end to end, one entry per lane per 64-entry
-      // window; a row's first hit in a window is its smallest hitting lane
-      // (LDS atomic min); resolved rows stop probing.
-      const uint32_t len = (pending && !found) ? (uint32_t)(e - k) : 0u;
-      const uint32_t incl = wave_incl_scan(len);
-      const uint32_t total = __shfl(incl, kWave - 1, kWave);
-      if (total) {
-        const uint32_t pre = incl - len;
-        const int wb = (threadIdx.x / kWave) * kWave;
-        s_base[wb + lane] = k - (int64_t)pre;
-        s_first[wb + lane] = kWave;
-        uint64_t done = __ballot(len == 0);
-        int carry = 0;
-        for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
-          const bool starts = len > 0 && pre >= j0 && pre < j0 + kWave;
-          if (starts) s_row[wb + (int)(pre - j0)] = lane;
-          const uint64_t S = wave_or_u64(starts ? (1ull << (pre - j0)) : 0ull);
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          const uint64_t upto = S & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
-          const int r = upto ? s_row[wb + (kWave - 1 - __clzll((long long)upto))] : carry;
-          const uint32_t j = j0 + lane;
-          int32_t u = -1;
-          bool hit = false;
-          if (j < total && !((done >> r) & 1)) {
-            u = ci[s_base[wb + r] + (int64_t)j];
-            hit = F.test(u);
-          }
-          if (hit) atomicMin(&s_first[wb + r], lane);
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          const int fl = s_first[wb + lane];
-          const bool fresh = fl < kWave;
-          const int32_t gv = __shfl(u, fresh ? fl : lane, kWave);
-          if (fresh) {
-            found = true;
-            par = gv;
-            s_first[wb + lane] = kWave;
-            if (ACCT) cnt.nscan += (uint64_t)(j0 + fl - pre + 1);
-          }
-          done |= __ballot(fresh);
-          carry = __shfl(r, kWave - 1, kWave);
-          if (done == ~0ull) break;
-        }
-        if (ACCT && len > 0 && !found) cnt.nscan += len;
+      bu_row_rest<Front, ACCT>(F, ci, packed, pend[j], k[j], e[j], found[j], par[j], s_base,
+                               s_row, s_first, cnt);
+      const uint64_t fm = __ballot(found[j]);
+      if (found[j]) {
+        const int64_t v = w * kWave + lane;
+        parent[v] = par[j];
+        level[v] = next_level;
       }
-    }
-    uint64_t rem = packed ? 0ull : __ballot(pending && !found && k < e);
-    while (rem) {
-      const int L = __ffsll((unsigned long long)rem) - 1;
-      rem &= rem - 1;
-      const int64_t kb = __shfl(k, L, kWave), ke = __shfl(e, L, kWave);
-      int32_t got = -1;
-      int64_t seen = ke - kb;
-      for (int64_t c = kb; c < ke; c += kWave) {
-        const int64_t kk = c + lane;
-        bool hit = false;
-        int32_t u = -1;
-        if (kk < ke) {
-          u = ci[kk];
-          hit = F.test(u);
-        }
-        const uint64_t hm = __ballot(hit);
-        if (hm) {
-          const int hl = __ffsll((unsigned long long)hm) - 1;
-          got = __shfl(u, hl, kWave);
-          seen = c - kb + hl + 1;
-          break;
-        }
+      if (lane == 0) {
+        next[w] = fm;
+        if (fm) vis[w] = vw[j] | fm;
+        cnt.nnew += (uint64_t)__popcll(fm);
       }
-      if (lane == L) {
-        if (got >= 0) {
-          found = true;
-          par = got;
-        }
-        if (ACCT) cnt.nscan += (uint64_t)seen;
-      }
-    }
-    const uint64_t fm = __ballot(found);
-    if (found) {
-      parent[v] = par;
-      level[v] = next_level;
-      cnt.mnew += (uint64_t)(e - b);
-    }
-    if (lane == 0) {
-      next[w] = fm;
-      if (fm) vis[w] = vw | fm;
-      cnt.nnew += (uint64_t)__popcll(fm);
     }
   }
 }
 
+// Adds the workgroup's discoveries and takes a ticket in the same 64-bit
+// atomic (count in the low 40 bits, finished workgroups above), so the last
+// workgroup knows the total without a memory fence; it publishes the counters
+// to the host and resets them for the next bottom-up step.  The accounting
+// counters of COUNT_BYTES runs live at other addresses and are fenced.
+constexpr int kTicketShift = 40;
+
 template <int NT, bool ACCT>
 __device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
-                                         unsigned long long *__restrict__ ctr) {
+                                         unsigned long long *__restrict__ ctr,
+                                         unsigned long long *__restrict__ host,
+                                         unsigned long long seq) {
+  __shared__ unsigned long long s_old;
   const uint64_t tn = block_sum<NT, uint64_t>(c.nnew, s);
-  const uint64_t tm = block_sum<NT, uint64_t>(c.mnew, s);
-  if (threadIdx.x == 0) {
-    if (tn) atomicAdd(ctr + C_NNEW, (unsigned long long)tn);
-    if (tm) atomicAdd(ctr + C_MNEW, (unsigned long long)tm);
-  }
+  uint64_t ts = 0, tu = 0, tr = 0;
   if (ACCT) {
-    const uint64_t ts = block_sum<NT, uint64_t>(c.nscan, s);
-    const uint64_t tu = block_sum<NT, uint64_t>(c.nunvis, s);
-    if (threadIdx.x == 0) {
+    ts = block_sum<NT, uint64_t>(c.nscan, s);
+    tu = block_sum<NT, uint64_t>(c.nunvis, s);
+    tr = block_sum<NT, uint64_t>(c.nrows, s);
+  }
+  if (threadIdx.x == 0) {
+    if (ACCT) {
       atomicAdd(ctr + C_SCAN, (unsigned long long)ts);
       atomicAdd(ctr + C_UNVIS, (unsigned long long)tu);
+      atomicAdd(ctr + C_ROWS, (unsigned long long)tr);
+      __threadfence();
+    }
+    s_old = atomicAdd(ctr + C_NNEW, (1ull << kTicketShift) | (unsigned long long)tn);
+  }
+  __syncthreads();
+  const unsigned long long old = s_old;
+  if ((old >> kTicketShift) + 1 == gridDim.x && threadIdx.x == 0) {
+    if (ACCT) __threadfence();
+    // the counters without the ticket bits, as the host reads them
+    atomicExch(ctr + C_NNEW, (old & ((1ull << kTicketShift) - 1)) + tn);
+    publish(ctr, host, seq);
+    atomicExch(ctr + C_NNEW, 0ull);
+    if (ACCT) {
+      atomicExch(ctr + C_SCAN, 0ull);
+      atomicExch(ctr + C_UNVIS, 0ull);
+      atomicExch(ctr + C_ROWS, 0ull);
     }
   }
 }
 
 // Bottom-up step probing the frontier bitmap in HBM (L2/MALL-resident).
-template <int LANE_SCAN, bool ACCT>
+template <int LANE_SCAN, int WPW, bool ACCT>
 __global__ __launch_bounds__(kBlock) void k_bu_step(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
     int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
-    int32_t next_level, unsigned long long *__restrict__ ctr, bool packed) {
+    int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
+    unsigned long long *__restrict__ host, unsigned long long seq) {
   __shared__ uint64_t s[kBlock / kWave];
   __shared__ int64_t s_base[kBlock];
   __shared__ int32_t s_row[kBlock];
@@ -494,9 +615,9 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
   const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
   BuCount c;
-  bu_words<LANE_SCAN, ACCT>(FrontGlobal{front}, rp, ci, hint, vis, next, parent, level, words,
-                            next_level, packed, gw, nw, s_base, s_row, s_first, c);
-  bu_flush<kBlock, ACCT>(c, s, ctr);
+  bu_words<LANE_SCAN, WPW, ACCT>(FrontGlobal{front}, rp, ci, hint, vis, next, parent, level,
+                                 words, next_level, packed, gw, nw, s_base, s_row, s_first, c);
+  bu_flush<kBlock, ACCT>(c, s, ctr, host, seq);
 }
 
 // Bottom-up step with the frontier summary staged in LDS (dynamic shared
@@ -504,14 +625,15 @@ __global__ __launch_bounds__(kBlock) void k_bu_step(
 // clear never leave the compute unit.
 constexpr int kLdsBlock = 1024;
 
-template <int LANE_SCAN, bool ACCT>
+template <int LANE_SCAN, int WPW, bool ACCT>
 __global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
     int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
     int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
-    const uint32_t *__restrict__ sum, int64_t sum_words, int gs) {
+    const uint32_t *__restrict__ sum, int64_t sum_words, int gs,
+    unsigned long long *__restrict__ host, unsigned long long seq) {
   extern __shared__ uint32_t s_sum[];
   __shared__ uint64_t s[kLdsBlock / kWave];
   __shared__ int64_t s_base[kLdsBlock];
@@ -522,9 +644,10 @@ __global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
   const int64_t gw = ((int64_t)blockIdx.x * kLdsBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kLdsBlock) / kWave;
   BuCount c;
-  bu_words<LANE_SCAN, ACCT>(FrontLds{s_sum, front, gs}, rp, ci, hint, vis, next, parent, level,
-                            words, next_level, packed, gw, nw, s_base, s_row, s_first, c);
-  bu_flush<kLdsBlock, ACCT>(c, s, ctr);
+  bu_words<LANE_SCAN, WPW, ACCT>(FrontLds{s_sum, front, gs}, rp, ci, hint, vis, next, parent,
+                                 level, words, next_level, packed, gw, nw, s_base, s_row, s_first,
+                                 c);
+  bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq);
 }
 
 // Frontier summary: bit i of sum = OR of front bits [i << gs, (i + 1) << gs).
@@ -621,7 +744,8 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   A((void **)&w->vis, W * 8);
   A((void **)&w->front, W * 8);
   A((void **)&w->next, W * 8);
-  A((void **)&w->prev, W * 8);
+  A((void **)&w->snap[0], W * 8);
+  A((void **)&w->snap[1], W * 8);
   A((void **)&w->q[0], n * 4);
   A((void **)&w->q[1], n * 4);
   A((void **)&w->qoff, (n + 1) * 4);
@@ -637,7 +761,12 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
     w->sum_words = (((n + (1ll << gs) - 1) >> gs) + 31) / 32;
     A((void **)&w->sum, ((w->sum_words + 1) / 2) * 8);
   }
-  if (e == hipSuccess) e = hipHostMalloc((void **)&w->host_ctr, C_NCTR * 8, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&w->host_pub, 32 * 8, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) {
+    std::memset(w->host_pub, 0, 32 * 8);
+    e = hipHostGetDevicePointer((void **)&w->host_pub_dev, w->host_pub, 0);
+  }
   if (e != hipSuccess) {
     set_error(std::string("g5_bfs workspace: ") + hipGetErrorString(e));
     delete w;
@@ -664,16 +793,40 @@ BfsWork::~BfsWork() {
   if (vis) (void)hipFree(vis);
   if (front) (void)hipFree(front);
   if (next) (void)hipFree(next);
-  if (prev) (void)hipFree(prev);
+  for (auto *p : snap)
+    if (p) (void)hipFree(p);
   if (sum) (void)hipFree(sum);
   if (q[0]) (void)hipFree(q[0]);
   if (q[1]) (void)hipFree(q[1]);
   if (qoff) (void)hipFree(qoff);
   if (bsum) (void)hipFree(bsum);
   if (ctr) (void)hipFree(ctr);
-  if (host_ctr) (void)hipHostFree(host_ctr);
-  for (auto &e : ev)
-    if (e) (void)hipEventDestroy(e);
+  if (host_pub) (void)hipHostFree(host_pub);
+  for (auto &e : ev) (void)hipEventDestroy(e);
+}
+
+// Waits until a kernel on `s` has published sequence number `want` to the
+// mapped host counters; falls back to the stream's status so a failed launch
+// cannot leave the host spinning.
+static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want) {
+  volatile uint64_t *h = w.host_pub;
+  for (uint32_t spin = 0;; ++spin) {
+    if (h[C_NCTR] == want) break;
+    if ((spin & 1023) == 1023) {
+      hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        if (h[C_NCTR] == want) break;
+        set_error("g5_bfs: a level finished without publishing its counters");
+        return G5_EDEVICE;
+      }
+      if (e != hipErrorNotReady) {
+        set_error(std::string("g5_bfs: ") + hipGetErrorString(e));
+        return G5_EDEVICE;
+      }
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return G5_OK;
 }
 
 g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
@@ -699,7 +852,12 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const int bu_bpc = p.bu_blocks_per_cu > 0 ? p.bu_blocks_per_cu : g->tune.bu_blocks_per_cu;
   const double lds_density = p.lds_density > 0 ? p.lds_density : g->tune.lds_density;
   const int lds_kb = p.lds_kb > 0 ? p.lds_kb : g->tune.lds_kb;
+  const int wpw = p.bu_words_per_wave > 0 ? p.bu_words_per_wave : g->tune.words_per_wave;
   const bool packed = (p.flags & G5_FLAG_PACKED) || (g->tune.packed && !(p.flags & G5_FLAG_ROWLOOP));
+  const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
+  const bool acct = stats && (p.flags & G5_FLAG_COUNT_BYTES);
+  const bool min_parent = (p.flags & G5_FLAG_MIN_PARENT) != 0;
+  const bool use_hint = !(p.flags & G5_FLAG_NO_HINT) && !min_parent;
   // staged frontier: summary granularity for this call's LDS budget
   int lds_gs = w.sum_gs;
   int64_t lds_words = w.sum_words;
@@ -709,20 +867,31 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     lds_words = (((n + (1ll << lds_gs) - 1) >> lds_gs) + 31) / 32;
   }
   int lds_levels = 0;
-  const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
-  const bool acct = stats && (p.flags & G5_FLAG_COUNT_BYTES);
-  const bool min_parent = (p.flags & G5_FLAG_MIN_PARENT) != 0;
-  const bool use_hint = !(p.flags & G5_FLAG_NO_HINT) && !min_parent;
   unsigned long long *ctr = (unsigned long long *)w.ctr;
-  uint64_t *hc = w.host_ctr;
+  unsigned long long *hpub = (unsigned long long *)w.host_pub_dev;
+  const volatile uint64_t *hc = w.host_pub;
   const int bu_grid = ncu * bu_bpc;
-  if (timed && !w.ev[0]) {
+  const int deg_grid = ncu * 8;
+  if (timed && w.ev.empty()) {
+    w.ev.resize(4 * G5_MAX_STAT_LEVELS);
     for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
   }
+  auto ev_at = [&](int lv, int k) -> hipEvent_t {
+    return (timed && lv < G5_MAX_STAT_LEVELS) ? w.ev[4 * lv + k] : nullptr;
+  };
+  auto rec = [&](int lv, int k) -> g5_status {
+    if (hipEvent_t e = ev_at(lv, k)) G5_HIP(hipEventRecord(e, s));
+    return G5_OK;
+  };
+#define G5_REC(lv, k)                 \
+  do {                                \
+    g5_status st_ = rec(lv, k);       \
+    if (st_ != G5_OK) return st_;     \
+  } while (0)
 
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, w.ctr, (int64_t)C_NCTR);
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
-                     dim3(kBlock), 0, s, level, parent, n, w.vis, w.prev, g->iso, W,
+                     dim3(kBlock), 0, s, level, parent, n, w.vis, w.snap[0], w.snap[1], g->iso, W,
                      (((uintptr_t)level | (uintptr_t)parent) & 15) == 0);
   hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, root, level, parent, w.vis, w.q[0], ctr,
                      g->row_ptr);
@@ -730,74 +899,74 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
 
   int cur = 0;                // queue holding the current frontier (top-down)
   int64_t qlen = 1;
-  bool q_deg_counted = true;  // the frontier's degrees are already out of m_u
+  // m_u: directed entries of vertices not yet discovered by a top-down level (an
+  // upper bound on the unvisited vertices' edges once bottom-up levels ran; the
+  // switch back to bottom-up also needs a growing frontier)
+  int64_t m_u = -1;
   bool first = true;
+  bool q_from_bu = false;     // the queue was filled from a bottom-up bitmap
   int dir = 1;                // 1 top-down, 2 bottom-up
-  int64_t m_u = -1;           // directed entries of unvisited vertices
   int64_t nf_prev = 0;
   int64_t last_nf = 0;        // frontier size of the previous level
   int32_t lvl = 0;
   int64_t reached = 1;
-  double deg_ms = 0;          // top-down degree scan time of the current level
+  int td_stat = -1;           // stats slot of the last top-down level (discoveries pending)
   uint64_t *front = w.front, *next = w.next;
   if (stats) *stats = g5_bfs_stats{};
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
-  auto elapsed = [&](int a, int b, double *ms) -> g5_status {
-    float f = 0;
-    G5_HIP(hipEventElapsedTime(&f, w.ev[a], w.ev[b]));
-    *ms = f;
-    return G5_OK;
-  };
 
   while (true) {
     if (dir == 1) {
-      if (qlen == 0) break;
-      // degree prefix sum of the frontier queue
-      const int64_t nb = (qlen + kDegTile - 1) / kDegTile;
-      if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
-      hipLaunchKernelGGL(k_td_deg, dim3(nb), dim3(kBlock), 0, s, w.q[cur], qlen, g->row_ptr,
-                         w.qoff, w.bsum);
-      hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, s, w.bsum, nb, ctr + C_MF);
-      hipLaunchKernelGGL(k_td_fix, dim3(grid_for(qlen + 1, kBlock, ncu * 16)), dim3(kBlock), 0,
-                         s, w.qoff, qlen, w.bsum, (const unsigned long long *)(ctr + C_MF));
+      // degree prefix sum of the frontier queue (+ visited snapshot), then publish
+      G5_REC(lvl, 0);
+      hipLaunchKernelGGL(k_td_deg, dim3(deg_grid), dim3(kBlock), 0, s, w.q[cur],
+                         (const unsigned long long *)(ctr + C_QLEN0 + cur), g->rp32, w.qoff,
+                         w.bsum, w.snap[lvl & 1], w.vis, W);
+      hipLaunchKernelGGL(k_td_scan, dim3(1), dim3(kScanBlock), 0, s, w.bsum, ctr, cur, hpub,
+                         (unsigned long long)++w.seq);
       G5_LAUNCH_CHECK();
-      if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
-      G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
-      G5_HIP(hipStreamSynchronize(s));
-      if (timed) {
-        g5_status st = elapsed(0, 1, &deg_ms);
+      G5_REC(lvl, 1);
+      {
+        g5_status st = wait_published(w, s, w.seq);
         if (st != G5_OK) return st;
       }
+      if (hc[C_ERR]) {
+        set_error("g5_bfs: top-down tile met more frontier rows than edges");
+        return G5_EDEVICE;
+      }
+      qlen = (int64_t)hc[C_QLEN0 + cur];
       const int64_t mf = (int64_t)hc[C_MF];
+      if (td_stat >= 0) stats->discovered[td_stat] = qlen;
+      if (!first && !q_from_bu) reached += qlen;
+      if (qlen == 0) break;
       if (first) {
         m_u = g->nnz - (int64_t)hc[C_RDEG];
         first = false;
-      } else if (!q_deg_counted) {
+      } else {
         m_u -= mf;
       }
-      q_deg_counted = false;
+      q_from_bu = false;
       const bool growing = qlen > last_nf;
-      bool to_bu = (p.direction == G5_DIR_BOTTOMUP) ||
-                   (p.direction == G5_DIR_AUTO && growing && (double)mf > (double)m_u / alpha);
+      const bool to_bu = (p.direction == G5_DIR_BOTTOMUP) ||
+                         (p.direction == G5_DIR_AUTO && growing && (double)mf > (double)m_u / alpha);
       if (to_bu) {
+        // frontier bitmap = visited now, not visited before the last expansion
         hipLaunchKernelGGL(k_front_from_vis, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
-                           s, w.vis, w.prev, front, W);
+                           s, w.vis, w.snap[(lvl + 1) & 1], front, W);
         G5_LAUNCH_CHECK();
         dir = 2;
         nf_prev = qlen;
+        td_stat = -1;
         continue;  // this level runs bottom-up
       }
       const int nxt = cur ^ 1;
-      G5_HIP(hipMemsetAsync(ctr + nxt, 0, 8, s));
-      hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0, s,
-                         w.prev, w.vis, W);
-      if (timed) G5_HIP(hipEventRecord(w.ev[2], s));
+      G5_REC(lvl, 2);
       if (mf > 0) {
         const int64_t tb = (mf + kTdTile - 1) / kTdTile;
 #define G5_TD(C)                                                                            \
   hipLaunchKernelGGL(k_td_expand<C>, dim3(tb), dim3(kBlock), 0, s, w.q[cur], qlen, w.qoff,   \
-                     (uint32_t)mf, g->row_ptr, g->col_idx, w.vis, w.prev, parent, level,     \
-                     w.q[nxt], ctr + nxt, lvl + 1, ctr + C_ERR)
+                     w.bsum, (uint32_t)mf, g->rp32, g->col_idx, w.vis, w.snap[lvl & 1],       \
+                     parent, level, w.q[nxt], ctr + C_QLEN0 + nxt, lvl + 1, ctr + C_ERR)
         if (min_parent)
           G5_TD(CLAIM_MIN);
         else if (p.claim == CLAIM_CAS)
@@ -807,36 +976,21 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
 #undef G5_TD
         G5_LAUNCH_CHECK();
       }
-      if (timed) G5_HIP(hipEventRecord(w.ev[3], s));
-      G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
-      G5_HIP(hipStreamSynchronize(s));
-      if (hc[C_ERR]) {
-        set_error("g5_bfs: top-down tile met more frontier rows than edges");
-        return G5_EDEVICE;
-      }
-      const int64_t found = (int64_t)hc[nxt];
+      G5_REC(lvl, 3);
       if (slot() >= 0) {
-        int i = slot();
+        const int i = slot();
         stats->dir[i] = 1;
         stats->frontier[i] = qlen;
-        stats->discovered[i] = found;
         stats->edges[i] = mf;
-        if (acct) stats->bytes[i] = 20 * qlen + 4 * mf + 12 * found;
-        if (timed) {
-          double ms = 0;
-          g5_status st = elapsed(2, 3, &ms);
-          if (st != G5_OK) return st;
-          stats->step_ms[i] = deg_ms + ms;
-        }
+        td_stat = i;
+      } else {
+        td_stat = -1;
       }
       cur = nxt;
       last_nf = qlen;
-      qlen = found;
-      reached += qlen;
       ++lvl;
     } else {
-      G5_HIP(hipMemsetAsync(ctr + C_NNEW, 0, 16, s));
-      if (acct) G5_HIP(hipMemsetAsync(ctr + C_SCAN, 0, 16, s));
+      if (acct && slot() >= 0) stats->dir[slot()] = 2;
       const bool use_lds = w.sum && !(p.flags & G5_FLAG_NO_LDS) &&
                            (double)nf_prev * (double)(1ll << std::min(lds_gs, 62)) <
                                lds_density * (double)n;
@@ -847,31 +1001,38 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         hipLaunchKernelGGL(k_front_summary, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
                            s, front, W, lds_gs, w.sum);
       }
-      if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
-#define G5_BUL(K, A)                                                                        \
+      G5_REC(lvl, 0);
+      const unsigned long long sq = ++w.seq;
+#define G5_BUL(K, P, A)                                                                     \
   do {                                                                                      \
-    const void *fn_ = (const void *)&k_bu_step_lds<K, A>;                                    \
+    const void *fn_ = (const void *)&k_bu_step_lds<K, P, A>;                                 \
     g5_status st_ = lds_ready(fn_, lds_words * 4);                                          \
     if (st_ != G5_OK) return st_;                                                           \
     int per_cu_ = 1;                                                                        \
     G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_, fn_, kLdsBlock,           \
                                                         (size_t)lds_words * 4));            \
-    hipLaunchKernelGGL((k_bu_step_lds<K, A>), dim3(ncu * std::max(per_cu_, 1)),             \
-                       dim3(kLdsBlock), lds_words * 4, s, g->row_ptr, g->col_idx,            \
+    hipLaunchKernelGGL((k_bu_step_lds<K, P, A>), dim3(ncu * std::max(per_cu_, 1)),          \
+                       dim3(kLdsBlock), lds_words * 4, s, g->rp32, g->col_idx,               \
                        use_hint ? g->hint : nullptr, w.vis, front, next, parent, level, n, W, \
-                       lvl + 1, ctr, packed, w.sum, lds_words, lds_gs);                     \
+                       lvl + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub, sq);           \
   } while (0)
-#define G5_BU(K, A)                                                                        \
-  hipLaunchKernelGGL((k_bu_step<K, A>), dim3(bu_grid), dim3(kBlock), 0, s, g->row_ptr,     \
-                     g->col_idx, use_hint ? g->hint : nullptr, w.vis, front, next, parent,    \
-                     level, n, W, lvl + 1, ctr, packed)
-#define G5_BU_K(M, A)            \
-  switch (lane_scan) {           \
-    case 1: M(1, A); break;      \
-    case 2: M(2, A); break;      \
-    case 8: M(8, A); break;      \
-    case 16: M(16, A); break;    \
-    default: M(4, A); break;     \
+#define G5_BU(K, P, A)                                                                      \
+  hipLaunchKernelGGL((k_bu_step<K, P, A>), dim3(bu_grid), dim3(kBlock), 0, s, g->rp32,     \
+                     g->col_idx, use_hint ? g->hint : nullptr, w.vis, front, next, parent,  \
+                     level, n, W, lvl + 1, ctr, packed, hpub, sq)
+#define G5_BU_P(M, K, A)           \
+  switch (wpw) {                   \
+    case 2: M(K, 2, A); break;     \
+    case 4: M(K, 4, A); break;     \
+    default: M(K, 1, A); break;    \
+  }
+#define G5_BU_K(M, A)                   \
+  switch (lane_scan) {                  \
+    case 1: G5_BU_P(M, 1, A); break;    \
+    case 2: G5_BU_P(M, 2, A); break;    \
+    case 8: G5_BU_P(M, 8, A); break;    \
+    case 16: G5_BU_P(M, 16, A); break;  \
+    default: G5_BU_P(M, 4, A); break;   \
   }
       if (use_lds) {
         if (acct) {
@@ -887,36 +1048,35 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         }
       }
 #undef G5_BU_K
+#undef G5_BU_P
 #undef G5_BU
 #undef G5_BUL
       G5_LAUNCH_CHECK();
-      if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
-      G5_HIP(hipMemcpyAsync(hc, w.ctr, C_NCTR * 8, hipMemcpyDeviceToHost, s));
-      G5_HIP(hipStreamSynchronize(s));
+      G5_REC(lvl, 1);
+      {
+        g5_status st = wait_published(w, s, sq);
+        if (st != G5_OK) return st;
+      }
       const int64_t nnew = (int64_t)hc[C_NNEW];
       if (slot() >= 0) {
-        int i = slot();
+        const int i = slot();
         stats->dir[i] = 2;
         stats->frontier[i] = nf_prev;
         stats->discovered[i] = nnew;
         if (acct) {
           stats->edges[i] = (int64_t)hc[C_SCAN];
-          stats->bytes[i] = (use_hint ? 12 : 8) * (int64_t)hc[C_UNVIS] +
-                            4 * (int64_t)hc[C_SCAN] + 16 * W + 8 * nnew;
-        }
-        if (timed) {
-          g5_status st = elapsed(0, 1, &stats->step_ms[i]);
-          if (st != G5_OK) return st;
+          stats->bytes[i] = (use_hint ? 4 : 0) * (int64_t)hc[C_UNVIS] +
+                            4 * (int64_t)hc[C_ROWS] + 4 * (int64_t)hc[C_SCAN] + 16 * W +
+                            8 * nnew;
         }
       }
-      m_u -= (int64_t)hc[C_MNEW];
       reached += nnew;
       last_nf = nf_prev;
       ++lvl;
       if (nnew == 0) break;
-      bool to_td = p.direction == G5_DIR_TOPDOWN ||
-                   (p.direction == G5_DIR_AUTO && (double)nnew < (double)n / beta &&
-                    nnew < nf_prev);
+      const bool to_td = p.direction == G5_DIR_TOPDOWN ||
+                         (p.direction == G5_DIR_AUTO && (double)nnew < (double)n / beta &&
+                          nnew < nf_prev);
       nf_prev = nnew;
       std::swap(front, next);  // `front` now holds the new frontier
       if (to_td) {
@@ -924,16 +1084,18 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         const int fb = (int)((W + chunk - 1) / chunk);
         hipLaunchKernelGGL(k_front_count, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum);
         hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, s, w.bsum, (int64_t)fb,
-                           ctr + cur);
+                           ctr + C_QLEN0 + cur);
         hipLaunchKernelGGL(k_front_write, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum,
                            w.q[cur]);
         G5_LAUNCH_CHECK();
         qlen = nnew;
-        q_deg_counted = true;
+        q_from_bu = true;
         dir = 1;
       }
     }
   }
+#undef G5_REC
+  G5_HIP(hipStreamSynchronize(s));
   if (stats) {
     stats->nlevels = lvl;
     stats->reached = reached;
@@ -943,8 +1105,23 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     stats->bu_blocks_per_cu = bu_bpc;
     stats->lds_levels = lds_levels;
     stats->lds_shift = lds_gs;
+    if (acct)
+      for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i)
+        if (stats->dir[i] == 1)
+          stats->bytes[i] = 12 * stats->frontier[i] + 4 * stats->edges[i] +
+                            12 * stats->discovered[i];
+    if (timed)
+      for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i) {
+        float a = 0, b = 0;
+        if (stats->dir[i] == 1) {
+          G5_HIP(hipEventElapsedTime(&a, w.ev[4 * i], w.ev[4 * i + 1]));
+          G5_HIP(hipEventElapsedTime(&b, w.ev[4 * i + 2], w.ev[4 * i + 3]));
+        } else {
+          G5_HIP(hipEventElapsedTime(&a, w.ev[4 * i], w.ev[4 * i + 1]));
+        }
+        stats->step_ms[i] = a + b;
+      }
   }
-  G5_HIP(hipStreamSynchronize(s));
   return G5_OK;
 }
 

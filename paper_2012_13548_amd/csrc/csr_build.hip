@@ -12,6 +12,7 @@
 //   iso       bitmap of degree-0 vertices (used by the traversal to skip them)
 //   hubs      list of rows longer than kHubDeg and their kHubChunk-edge pieces
 //             (the batched traversal splits these rows across wavefronts)
+//   rp32      32-bit copy of row_ptr for the traversal (nnz < 2^32 is required)
 //   hint      for each vertex, its highest-degree neighbour (among the first
 //             kHintScan of its row; smallest id on ties): the bottom-up step
 //             tests it before reading the row
@@ -301,6 +302,12 @@ __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
   }
 }
 
+__global__ void k_rp32(const int64_t *__restrict__ rp, int64_t len, uint32_t *__restrict__ out) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
+    out[i] = (uint32_t)rp[i];
+}
+
 int grid_cap(int64_t items, int per_block, int cap) {
   int64_t g = (items + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -437,6 +444,9 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
     return fail(e, "copy");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   g->nonisolated = (int64_t)noniso;
+  if ((e = hipMalloc(&g->rp32, (n + 1) * sizeof(uint32_t))) != hipSuccess) return fail(e, "rp32");
+  hipLaunchKernelGGL(k_rp32, dim3(grid_cap(n + 1, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+                     n + 1, g->rp32);
   if ((e = hipMalloc(&g->hint, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
   hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
                      g->col_idx, n, g->words, g->hint);

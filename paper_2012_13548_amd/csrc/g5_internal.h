@@ -47,16 +47,19 @@ struct BfsWork {
   uint64_t *vis = nullptr;    // visited bitmap (isolated vertices pre-set)
   uint64_t *front = nullptr;  // frontier bitmap (bottom-up input)
   uint64_t *next = nullptr;   // next-frontier bitmap (bottom-up output)
-  uint64_t *prev = nullptr;   // visited bitmap before the last top-down expansion
+  uint64_t *snap[2] = {nullptr, nullptr};  // visited bitmap before each top-down
+                                           // expansion, by level parity
   uint32_t *sum = nullptr;    // frontier summary staged in LDS by bottom-up steps
   int64_t sum_words = 0;      // its 32-bit words
   int sum_gs = 0;             // log2 of the vertices per summary bit
   int32_t *q[2] = {nullptr, nullptr};  // frontier queues
   uint32_t *qoff = nullptr;   // per-frontier-vertex edge offsets (top-down)
-  uint32_t *bsum = nullptr;   // per-block partial sums
-  uint64_t *ctr = nullptr;    // device counters (see BfsCounters in bfs.hip)
-  uint64_t *host_ctr = nullptr;  // pinned mirror of ctr
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // step timing
+  uint32_t *bsum = nullptr;   // per-chunk partial sums
+  uint64_t *ctr = nullptr;    // device counters (Ctr in bfs.hip)
+  uint64_t *host_pub = nullptr;   // pinned, mapped: counters published by kernels + seq
+  uint64_t *host_pub_dev = nullptr;  // its device address
+  uint64_t seq = 0;           // last sequence number published
+  std::vector<hipEvent_t> ev; // step timing: 4 per level
   ~BfsWork();
 };
 
@@ -78,6 +81,7 @@ struct Tuning {
   double alpha, beta;     // single-root direction switch
   int lane_scan;          // bottom-up lane scan width
   int bu_blocks_per_cu;   // bottom-up grid
+  int words_per_wave;     // bottom-up visited words per wavefront at once
   int packed;             // bottom-up packed row scan
   int lds_kb;             // LDS budget of the staged frontier per workgroup
   double lds_density;     // stage the frontier in LDS below this summary density
@@ -98,6 +102,7 @@ struct g5_csr {
   int64_t *row_ptr = nullptr;  // device [n+1]
   int32_t *col_idx = nullptr;  // device [nnz]
   uint64_t *iso = nullptr;     // device [words]: bit set = degree 0 (or padding)
+  uint32_t *rp32 = nullptr;    // device [n+1]: row_ptr as 32-bit offsets
   int32_t *hint = nullptr;     // device [n]: highest-degree neighbour, -1 if none
   g5::Tuning tune{};           // defaults for this graph's scale
   int64_t num_hubs = 0;        // vertices with degree > kHubDeg
