@@ -102,7 +102,7 @@ typedef struct {
   int32_t flags;          /* G5_FLAG_* */
   int32_t bu_blocks_per_cu; /* bottom-up grid: workgroups per compute unit (1..32) */
   int32_t lds_kb;         /* LDS for the staged frontier per workgroup, KiB (16..160) */
-  int32_t bu_words_per_wave; /* bottom-up: visited words a wavefront works on at once: 1, 2, 4 */
+  int32_t bu_vertices_per_lane; /* bottom-up: unvisited vertices a lane works on at once: 1 or 2 */
   int32_t reserved[3];
 } g5_bfs_params;
 

@@ -22,7 +22,7 @@ ALPHA = [6, 10, 14, 20, 28, 40, 56, 80, 112, 160]
 BETA = [6, 12, 24, 48, 96, 192]
 LANE = [1, 2, 4, 8, 16]
 BPC = [4, 8, 16, 32]
-WPW = [1, 2, 4]
+VPL = [1, 2]
 PACKED = [0, 1]
 LDS_KB = [32, 64, 96, 140]
 LDS_DENSITY = [0.01, 0.03, 0.1, 0.3, 1.0]
@@ -67,7 +67,7 @@ def tune_scale(scale, nroots, rounds):
             e0.record()
             g5.bfs(csr, r, parent, level, alpha=cfg["alpha"], beta=cfg["beta"],
                    lane_scan=cfg["lane_scan"], blocks_per_cu=cfg["bu_blocks_per_cu"],
-                   words_per_wave=cfg["words_per_wave"],
+                   vertices_per_lane=cfg["vertices_per_lane"],
                    packed=bool(cfg["packed"]), lds_kb=cfg["lds_kb"],
                    lds_density=cfg["lds_density"])
             e1.record()
@@ -94,11 +94,11 @@ def tune_scale(scale, nroots, rounds):
         return cfg, best
 
     t0 = time.time()
-    start = dict(alpha=20, beta=96, lane_scan=8, bu_blocks_per_cu=32, words_per_wave=1, packed=0,
+    start = dict(alpha=20, beta=96, lane_scan=8, bu_blocks_per_cu=32, vertices_per_lane=1, packed=0,
                  lds_kb=140, lds_density=0.03)
     single(start)  # warm
     cfg, best = search(start, {"alpha": ALPHA, "beta": BETA, "lane_scan": LANE,
-                               "bu_blocks_per_cu": BPC, "words_per_wave": WPW,
+                               "bu_blocks_per_cu": BPC, "vertices_per_lane": VPL,
                                "packed": PACKED, "lds_kb": LDS_KB,
                                "lds_density": LDS_DENSITY}, single)
     out = {"scale": scale, **cfg, "hmean_gteps": round(best / 1e9, 3), "roots": len(sample)}
@@ -131,13 +131,13 @@ def tune_scale(scale, nroots, rounds):
 
 
 def write_table(entries, path):
-    lines = ["// Autotuned defaults: {scale, alpha, beta, lane_scan, bu_blocks_per_cu, words_per_wave,",
+    lines = ["// Autotuned defaults: {scale, alpha, beta, lane_scan, bu_blocks_per_cu, vertices_per_lane,",
              "// packed, lds_kb, lds_density, batch_alpha, batch_blocks_per_cu}.  Written by",
              "// paper_2012_13548_amd/autotune.py from its measurements (tuning.json); the",
              "// entry nearest to log2 n is used."]
     for e in sorted(entries, key=lambda x: x["scale"]):
         lines.append(f"{{{e['scale']}, {float(e['alpha']):.1f}, {float(e['beta']):.1f}, "
-                     f"{e['lane_scan']}, {e['bu_blocks_per_cu']}, {e['words_per_wave']}, "
+                     f"{e['lane_scan']}, {e['bu_blocks_per_cu']}, {e['vertices_per_lane']}, "
                      f"{int(e['packed'])}, "
                      f"{e['lds_kb']}, {float(e['lds_density']):.2f}, "
                      f"{float(e['batch_alpha']):.1f}, {e['batch_blocks_per_cu']}}},")

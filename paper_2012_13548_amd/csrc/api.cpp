@@ -82,6 +82,8 @@ void g5_csr_free(g5_csr *g) {
   if (g->col_idx) (void)hipFree(g->col_idx);
   if (g->iso) (void)hipFree(g->iso);
   if (g->hint) (void)hipFree(g->hint);
+  if (g->hot) (void)hipFree(g->hot);
+  if (g->hint_id) (void)hipFree(g->hint_id);
   if (g->rp32) (void)hipFree(g->rp32);
   if (g->hub_list) (void)hipFree(g->hub_list);
   if (g->hub_off) (void)hipFree(g->hub_off);
@@ -106,11 +108,11 @@ g5_status g5_bfs_ex(const g5_csr *g, int64_t root, int32_t *parent, int32_t *lev
       p.bu_lane_scan > 16 || (p.bu_lane_scan & (p.bu_lane_scan - 1)) != 0 || p.alpha < 0 ||
       p.beta < 0 || p.lds_density < 0 || p.bu_blocks_per_cu < 0 || p.bu_blocks_per_cu > 32 ||
       (p.lds_kb != 0 && (p.lds_kb < 16 || p.lds_kb > 160)) ||
-      (p.bu_words_per_wave != 0 && p.bu_words_per_wave != 1 && p.bu_words_per_wave != 2 &&
-       p.bu_words_per_wave != 4)) {
+      (p.bu_vertices_per_lane != 0 && p.bu_vertices_per_lane != 1 &&
+       p.bu_vertices_per_lane != 2)) {
     set_error("g5_bfs: direction must be 0..2, claim 0..1, bu_lane_scan 0 or a power of two "
               "up to 16, alpha, beta, lds_density >= 0, bu_blocks_per_cu 0..32, lds_kb 0 or "
-              "16..160, bu_words_per_wave 0, 1, 2 or 4");
+              "16..160, bu_vertices_per_lane 0, 1 or 2");
     return G5_EINVAL;
   }
   try {

@@ -49,6 +49,7 @@ enum Ctr : int {
   C_SCAN = 7,   // row entries read by a bottom-up step (byte counting only)
   C_UNVIS = 8,  // unvisited non-isolated vertices it scanned (byte counting only)
   C_ROWS = 9,   // those that read their row offsets (hint missed; byte counting only)
+  C_HINT = 10,  // vertices found by their hint (byte counting only)
   C_NCTR = 16
 };
 
@@ -62,21 +63,23 @@ __device__ void publish(const unsigned long long *ctr, unsigned long long *host,
   __hip_atomic_store(host + C_NCTR, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// level = -1 and parent = fill (the hint targets) or -1; visited bitmap and its
+// snapshots = the isolated vertices.
 __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ parent, int64_t n,
-                           uint64_t *__restrict__ vis, uint64_t *__restrict__ prev0,
-                           uint64_t *__restrict__ prev1, const uint64_t *__restrict__ iso,
-                           int64_t words, bool vec) {
+                           const int32_t *__restrict__ fill, uint64_t *__restrict__ vis,
+                           uint64_t *__restrict__ prev0, uint64_t *__restrict__ prev1,
+                           const uint64_t *__restrict__ iso, int64_t words, bool vec) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t n4 = vec ? n / 4 : 0;
   int4 m1 = make_int4(-1, -1, -1, -1);
   for (int64_t i = t; i < n4; i += stride) {
     reinterpret_cast<int4 *>(level)[i] = m1;
-    reinterpret_cast<int4 *>(parent)[i] = m1;
+    reinterpret_cast<int4 *>(parent)[i] = fill ? reinterpret_cast<const int4 *>(fill)[i] : m1;
   }
   for (int64_t i = n4 * 4 + t; i < n; i += stride) {
     level[i] = -1;
-    parent[i] = -1;
+    parent[i] = fill ? fill[i] : -1;
   }
   for (int64_t i = t; i < words; i += stride) {
     vis[i] = iso[i];
@@ -361,20 +364,33 @@ struct FrontLds {
   }
 };
 
+// fh bit r = frontier bit of hot[r]; one wavefront per 64 targets.
+__global__ __launch_bounds__(kBlock) void k_fh_build(const uint64_t *__restrict__ front,
+                                                     const int32_t *__restrict__ hot,
+                                                     int64_t num_hot, uint64_t *__restrict__ fh) {
+  const int lane = __lane_id();
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) - lane; i0 < num_hot;
+       i0 += stride) {
+    const int64_t i = i0 + lane;
+    bool b = false;
+    if (i < num_hot) {
+      const int32_t t = hot[i];
+      b = (front[t >> 6] >> (t & 63)) & 1;
+    }
+    const uint64_t m = __ballot(b);
+    if (lane == 0) fh[i0 >> 6] = m;
+  }
+}
+
 struct BuCount {
-  uint64_t nnew = 0, nscan = 0, nunvis = 0, nrows = 0;
+  uint64_t nnew = 0, nscan = 0, nunvis = 0, nrows = 0, nhint = 0;
 };
 
-// Bottom-up step.  A wavefront owns 64-bit visited words (lane l of word w
-// owns vertex 64w+l) and takes WPW consecutive words at a time so that the
-// independent loads of all of them (visited words, row offsets, hints, hint
-// probes, first row entries and their probes) are in flight together.  An
-// unvisited lane tests its hint (highest-degree neighbour), then LANE_SCAN row
-// entries; rows still unresolved are scanned by the whole wavefront, either
-// packed end to end (one entry per lane per 64-entry window) or one row per
-// 64-lane step.  The ballot of finders is the next-frontier word and is OR-ed
-// into the visited word by one lane: no atomics.  With ACCT it counts the row
-// entries read up to the first hit and the vertices scanned.
+// Rows a lane's own scan left unresolved are scanned by the whole wavefront,
+// either packed end to end (one entry per lane per 64-entry window) or one row
+// per 64-lane step.  With ACCT it counts the row entries read up to the first
+// hit.
 template <class Front, bool ACCT>
 __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__restrict__ ci,
                                             bool packed, bool pending, int64_t k, int64_t e,
@@ -461,96 +477,150 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
   }
 }
 
-template <int LANE_SCAN, int WPW, bool ACCT, class Front>
-__device__ __forceinline__ void bu_words(
-    const Front &F, const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ hint, uint64_t *__restrict__ vis, uint64_t *__restrict__ next,
-    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words, int32_t next_level,
-    bool packed, int64_t gw, int64_t nw, int64_t *s_base, int32_t *s_row, int32_t *s_first,
-    BuCount &cnt) {
+// Position of the r-th set bit (from 0) of x; r < popcount(x).
+__device__ __forceinline__ int select_bit(uint64_t x, uint32_t r) {
+  int b = 0;
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    const uint32_t c = (uint32_t)__popcll(x & ((1ull << s) - 1));
+    if (r >= c) {
+      r -= c;
+      x >>= s;
+      b += s;
+    }
+  }
+  return b;
+}
+
+// Bottom-up step (the bottom-up direction of Beamer, Asanovic and Patterson),
+// vertex-parallel.  A wavefront owns chunks of 64 visited words (4096
+// vertices): lane l loads word l of the chunk, a prefix sum of the unvisited
+// counts numbers the chunk's unvisited vertices, and each 64-lane round hands
+// the next 64 of them (R per lane with R rounds in flight) to the lanes, which
+// find their vertex by a binary search over the prefix and a bit select.  Lanes
+// thus work only on unvisited vertices, and a chunk whose vertices are all
+// visited costs one coalesced load.
+//
+// Per vertex: the hint first (its highest-degree neighbour; a hot target is
+// tested in fh, the frontier bits of the hot targets staged in LDS, any other
+// one in the frontier), then LANE_SCAN row entries, then the wavefront-wide
+// scan.  Finders write level (and parent, unless the parent array was
+// pre-filled with every vertex's hint target, hint_id == nullptr, and the hint
+// was the hit) and OR their bit into the chunk's next-frontier words in LDS,
+// written out with the visited words at the end: no global atomics.
+template <int LANE_SCAN, int R, bool ACCT, class Front>
+__device__ __forceinline__ void bu_chunks(
+    const Front &F, const uint64_t *fh, const uint32_t *__restrict__ rp,
+    const int32_t *__restrict__ ci, const int32_t *__restrict__ hint,
+    const int32_t *__restrict__ hint_id, uint64_t *__restrict__ vis,
+    uint64_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ level,
+    int64_t words, int32_t next_level, bool packed, int64_t gw, int64_t nw, int64_t *s_base,
+    int32_t *s_row, int32_t *s_first, unsigned long long *s_nx, BuCount &cnt) {
   const int lane = __lane_id();
-  for (int64_t w0 = gw * WPW; w0 < words; w0 += nw * WPW) {
-    uint64_t vw[WPW];
-    bool pend[WPW], found[WPW];
-    int64_t b[WPW], e[WPW], k[WPW];
-    int32_t par[WPW], h[WPW];
+  unsigned long long *nx = s_nx + (threadIdx.x / kWave) * kWave;
+  const int64_t chunks = (words + kWave - 1) / kWave;
+  for (int64_t c = gw; c < chunks; c += nw) {
+    const int64_t w = c * kWave + lane;
+    const uint64_t vw = (w < words) ? vis[w] : ~0ull;  // padding lanes past n are pre-set in iso
+    const uint64_t un = ~vw;
+    const uint32_t cl = (uint32_t)__popcll(un);
+    const uint32_t incl = wave_incl_scan(cl);
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    const uint32_t excl = incl - cl;
+    nx[lane] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t base = 0; base < total; base += kWave * R) {
+      bool act[R], found[R], via[R];
+      int64_t v[R], b[R], e[R], k[R];
+      int32_t par[R], h[R];
+      int wl[R], bit[R];
 #pragma unroll
-    for (int j = 0; j < WPW; ++j) vw[j] = (w0 + j < words) ? vis[w0 + j] : ~0ull;
+      for (int j = 0; j < R; ++j) {
+        const uint32_t idx = base + (uint32_t)(j * kWave + lane);
+        act[j] = idx < total;
+        int pos = 0;  // last word whose exclusive prefix is <= idx
 #pragma unroll
-    for (int j = 0; j < WPW; ++j) {
-      const int64_t v = (w0 + j) * kWave + lane;
-      pend[j] = !((vw[j] >> lane) & 1);  // padding lanes past n are pre-set in iso
-      found[j] = false;
-      par[j] = -1;
-      b[j] = e[j] = 0;
-      h[j] = -1;
-      if (pend[j] && hint) h[j] = hint[v];
-      if (ACCT && pend[j]) cnt.nunvis += 1;
-    }
-#pragma unroll
-    for (int j = 0; j < WPW; ++j) {  // the highest-degree neighbour first
-      if (h[j] >= 0 && F.test(h[j])) {
-        found[j] = true;
-        par[j] = h[j];
+        for (int st = 32; st >= 1; st >>= 1)
+          if (__shfl(excl, pos + st, kWave) <= idx) pos += st;
+        const uint32_t r = idx - __shfl(excl, pos, kWave);
+        const uint64_t word = __shfl(un, pos, kWave);
+        wl[j] = pos;
+        bit[j] = act[j] ? select_bit(word, r) : 0;
+        v[j] = (c * kWave + pos) * kWave + bit[j];
+        par[j] = -1;
+        b[j] = e[j] = 0;
+        h[j] = (act[j] && hint) ? hint[v[j]] : -1;
+        if (ACCT && act[j]) cnt.nunvis += 1;
       }
-    }
 #pragma unroll
-    for (int j = 0; j < WPW; ++j) {  // row offsets only where the hint missed
-      const int64_t v = (w0 + j) * kWave + lane;
-      if (pend[j] && !found[j]) {
-        b[j] = rp[v];
-        e[j] = rp[v + 1];
-        if (ACCT) cnt.nrows += 1;
-      }
-      k[j] = b[j];
-    }
-    int32_t u[WPW][LANE_SCAN];
-#pragma unroll
-    for (int j = 0; j < WPW; ++j)
-#pragma unroll
-      for (int t = 0; t < LANE_SCAN; ++t)
-        u[j][t] = (pend[j] && !found[j] && k[j] + t < e[j]) ? ci[k[j] + t] : -1;
-#pragma unroll
-    for (int j = 0; j < WPW; ++j) {
-      bool hv[LANE_SCAN];
-#pragma unroll
-      for (int t = 0; t < LANE_SCAN; ++t) hv[t] = u[j][t] >= 0 && F.test(u[j][t]);
-      if (pend[j] && !found[j]) {
-#pragma unroll
-        for (int t = 0; t < LANE_SCAN; ++t) {
-          if (!found[j] && hv[t]) {
-            found[j] = true;
-            par[j] = u[j][t];
-            if (ACCT) cnt.nscan += (uint64_t)(t + 1);
-          }
+      for (int j = 0; j < R; ++j) {  // the highest-degree neighbour first
+        if (h[j] >= 0) {
+          via[j] = F.test(h[j]);
+          par[j] = h[j];
+        } else if (h[j] != -1) {
+          const uint32_t r = (uint32_t)h[j] & 0x7fffffffu;
+          via[j] = (fh[r >> 6] >> (r & 63)) & 1;
+        } else {
+          via[j] = false;
         }
-        const int64_t k0 = k[j];
-        k[j] = std::min<int64_t>(k[j] + LANE_SCAN, e[j]);
-        if (ACCT && !found[j]) cnt.nscan += (uint64_t)(k[j] - k0);
+        found[j] = via[j];
+        if (ACCT && via[j]) cnt.nhint += 1;
       }
-    }
 #pragma unroll
-    for (int j = 0; j < WPW; ++j) {
-      const int64_t w = w0 + j;
-      if (w >= words) break;
-      if (vw[j] == ~0ull) {
-        if (lane == 0) next[w] = 0;
-        continue;
+      for (int j = 0; j < R; ++j) {  // row offsets only where the hint missed
+        if (act[j] && !found[j]) {
+          b[j] = rp[v[j]];
+          e[j] = rp[v[j] + 1];
+          if (ACCT) cnt.nrows += 1;
+        }
+        k[j] = b[j];
       }
-      bu_row_rest<Front, ACCT>(F, ci, packed, pend[j], k[j], e[j], found[j], par[j], s_base,
-                               s_row, s_first, cnt);
-      const uint64_t fm = __ballot(found[j]);
-      if (found[j]) {
-        const int64_t v = w * kWave + lane;
-        parent[v] = par[j];
-        level[v] = next_level;
+      int32_t u[R][LANE_SCAN];
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int t = 0; t < LANE_SCAN; ++t)
+          u[j][t] = (act[j] && !found[j] && k[j] + t < e[j]) ? ci[k[j] + t] : -1;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        bool hv[LANE_SCAN];
+#pragma unroll
+        for (int t = 0; t < LANE_SCAN; ++t) hv[t] = u[j][t] >= 0 && F.test(u[j][t]);
+        if (act[j] && !found[j]) {
+#pragma unroll
+          for (int t = 0; t < LANE_SCAN; ++t) {
+            if (!found[j] && hv[t]) {
+              found[j] = true;
+              par[j] = u[j][t];
+              if (ACCT) cnt.nscan += (uint64_t)(t + 1);
+            }
+          }
+          const int64_t k0 = k[j];
+          k[j] = std::min<int64_t>(k[j] + LANE_SCAN, e[j]);
+          if (ACCT && !found[j]) cnt.nscan += (uint64_t)(k[j] - k0);
+        }
       }
-      if (lane == 0) {
-        next[w] = fm;
-        if (fm) vis[w] = vw[j] | fm;
-        cnt.nnew += (uint64_t)__popcll(fm);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        bu_row_rest<Front, ACCT>(F, ci, packed, act[j], k[j], e[j], found[j], par[j], s_base,
+                                 s_row, s_first, cnt);
+        if (found[j]) {
+          if (!via[j])
+            parent[v[j]] = par[j];
+          else if (hint_id)
+            parent[v[j]] = par[j] >= 0 ? par[j] : hint_id[v[j]];
+          level[v[j]] = next_level;
+          atomicOr(&nx[wl[j]], 1ull << bit[j]);
+        }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint64_t m = nx[lane];
+    if (w < words) {
+      next[w] = m;
+      if (m) vis[w] = vw | m;
+    }
+    cnt.nnew += (uint64_t)__popcll(m);
   }
 }
 
@@ -568,17 +638,19 @@ __device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
                                          unsigned long long seq) {
   __shared__ unsigned long long s_old;
   const uint64_t tn = block_sum<NT, uint64_t>(c.nnew, s);
-  uint64_t ts = 0, tu = 0, tr = 0;
+  uint64_t ts = 0, tu = 0, tr = 0, th = 0;
   if (ACCT) {
     ts = block_sum<NT, uint64_t>(c.nscan, s);
     tu = block_sum<NT, uint64_t>(c.nunvis, s);
     tr = block_sum<NT, uint64_t>(c.nrows, s);
+    th = block_sum<NT, uint64_t>(c.nhint, s);
   }
   if (threadIdx.x == 0) {
     if (ACCT) {
       atomicAdd(ctr + C_SCAN, (unsigned long long)ts);
       atomicAdd(ctr + C_UNVIS, (unsigned long long)tu);
       atomicAdd(ctr + C_ROWS, (unsigned long long)tr);
+      atomicAdd(ctr + C_HINT, (unsigned long long)th);
       __threadfence();
     }
     s_old = atomicAdd(ctr + C_NNEW, (1ull << kTicketShift) | (unsigned long long)tn);
@@ -595,59 +667,92 @@ __device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
       atomicExch(ctr + C_SCAN, 0ull);
       atomicExch(ctr + C_UNVIS, 0ull);
       atomicExch(ctr + C_ROWS, 0ull);
+      atomicExch(ctr + C_HINT, 0ull);
     }
   }
 }
 
-// Bottom-up step probing the frontier bitmap in HBM (L2/MALL-resident).
-template <int LANE_SCAN, int WPW, bool ACCT>
-__global__ __launch_bounds__(kBlock) void k_bu_step(
+// Bottom-up step probing the frontier bitmap in HBM (L2/MALL-resident); the
+// hot-target bits (fh_words words) are staged in dynamic LDS.
+constexpr int kBuBlock = 512;
+
+template <int LANE_SCAN, int R, bool ACCT>
+__global__ __launch_bounds__(kBuBlock) void k_bu_step(
     const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
+    const int32_t *__restrict__ hint, const int32_t *__restrict__ hint_id,
+    const uint64_t *__restrict__ fh, int64_t fh_words, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
-    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
+    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words,
     int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
     unsigned long long *__restrict__ host, unsigned long long seq) {
-  __shared__ uint64_t s[kBlock / kWave];
-  __shared__ int64_t s_base[kBlock];
-  __shared__ int32_t s_row[kBlock];
-  __shared__ int32_t s_first[kBlock];
-  const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
+  extern __shared__ uint64_t s_fh[];
+  __shared__ uint64_t s[kBuBlock / kWave];
+  __shared__ int64_t s_base[kBuBlock];
+  __shared__ int32_t s_row[kBuBlock];
+  __shared__ int32_t s_first[kBuBlock];
+  __shared__ unsigned long long s_nx[kBuBlock];
+  for (int64_t i = threadIdx.x; i < fh_words; i += kBuBlock) s_fh[i] = fh[i];
+  __syncthreads();
+  const int64_t gw = ((int64_t)blockIdx.x * kBuBlock + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * kBuBlock) / kWave;
   BuCount c;
-  bu_words<LANE_SCAN, WPW, ACCT>(FrontGlobal{front}, rp, ci, hint, vis, next, parent, level,
-                                 words, next_level, packed, gw, nw, s_base, s_row, s_first, c);
-  bu_flush<kBlock, ACCT>(c, s, ctr, host, seq);
+  bu_chunks<LANE_SCAN, R, ACCT>(FrontGlobal{front}, s_fh, rp, ci, hint, hint_id, vis, next,
+                                parent, level, words, next_level, packed, gw, nw, s_base, s_row,
+                                s_first, s_nx, c);
+  bu_flush<kBuBlock, ACCT>(c, s, ctr, host, seq);
 }
 
-// Bottom-up step with the frontier summary staged in LDS (dynamic shared
-// memory, sum_words 32-bit words): probes of vertices whose summary bit is
-// clear never leave the compute unit.
+// Bottom-up step with the frontier summary staged in LDS as well (dynamic
+// LDS: sum_words 32-bit summary words, padded to 8 bytes, then the fh_words
+// hot-target words): probes of vertices whose summary bit is clear never leave
+// the compute unit.
 constexpr int kLdsBlock = 1024;
+// k_bu_step_lds's own LDS arrays (about 24 KiB), with margin
+constexpr int64_t kBuStaticLds = 28 * 1024;
 
-template <int LANE_SCAN, int WPW, bool ACCT>
+template <int LANE_SCAN, int R, bool ACCT>
 __global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
     const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ hint, uint64_t *__restrict__ vis,
+    const int32_t *__restrict__ hint, const int32_t *__restrict__ hint_id,
+    const uint64_t *__restrict__ fh, int64_t fh_words, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
-    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t n, int64_t words,
+    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words,
     int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
     const uint32_t *__restrict__ sum, int64_t sum_words, int gs,
     unsigned long long *__restrict__ host, unsigned long long seq) {
-  extern __shared__ uint32_t s_sum[];
+  extern __shared__ uint64_t s_dyn[];
+  uint32_t *s_sum = reinterpret_cast<uint32_t *>(s_dyn);
+  uint64_t *s_fh = s_dyn + (sum_words + 1) / 2;
   __shared__ uint64_t s[kLdsBlock / kWave];
   __shared__ int64_t s_base[kLdsBlock];
   __shared__ int32_t s_row[kLdsBlock];
   __shared__ int32_t s_first[kLdsBlock];
+  __shared__ unsigned long long s_nx[kLdsBlock];
   for (int64_t i = threadIdx.x; i < sum_words; i += kLdsBlock) s_sum[i] = sum[i];
+  for (int64_t i = threadIdx.x; i < fh_words; i += kLdsBlock) s_fh[i] = fh[i];
   __syncthreads();
   const int64_t gw = ((int64_t)blockIdx.x * kLdsBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kLdsBlock) / kWave;
   BuCount c;
-  bu_words<LANE_SCAN, WPW, ACCT>(FrontLds{s_sum, front, gs}, rp, ci, hint, vis, next, parent,
-                                 level, words, next_level, packed, gw, nw, s_base, s_row, s_first,
-                                 c);
+  bu_chunks<LANE_SCAN, R, ACCT>(FrontLds{s_sum, front, gs}, s_fh, rp, ci, hint, hint_id, vis,
+                                next, parent, level, words, next_level, packed, gw, nw, s_base,
+                                s_row, s_first, s_nx, c);
   bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq);
+}
+
+// After a traversal whose parent array was pre-filled with hint targets: the
+// unreached non-isolated vertices get parent -1.
+__global__ void k_unreached(const uint64_t *__restrict__ vis, const uint64_t *__restrict__ iso,
+                            int64_t words, int32_t *__restrict__ parent) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
+    uint64_t m = ~(vis[w] | iso[w]);  // padding bits past n are set in iso
+    while (m) {
+      const int b = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      parent[w * kWave + b] = -1;
+    }
+  }
 }
 
 // Frontier summary: bit i of sum = OR of front bits [i << gs, (i + 1) << gs).
@@ -718,6 +823,21 @@ int grid_for(int64_t items, int per_block, int cap) {
   return (int)g;
 }
 
+// Workgroups of `fn` that fit on one compute unit (cached per kernel).
+int resident_per_cu(const void *fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::vector<std::pair<std::pair<const void *, size_t>, int>> done;
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto &d : done)
+    if (d.first.first == fn && d.first.second == lds) return d.second;
+  int per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  done.push_back({{fn, lds}, per_cu});
+  return per_cu;
+}
+
 // Allows a kernel `bytes` of dynamic LDS (once per kernel and size).
 g5_status lds_ready(const void *fn, int64_t bytes) {
   static std::mutex mu;
@@ -751,9 +871,9 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   A((void **)&w->qoff, (n + 1) * 4);
   A((void **)&w->bsum, std::max(nb, nbf) * 4);
   A((void **)&w->ctr, C_NCTR * 8);
+  if (g->num_hot > 0) A((void **)&w->fh, ((g->num_hot + 63) / 64) * 8);
   // frontier summary for the LDS bottom-up step: as fine as the LDS allows
-  const int64_t static_lds = 20 * 1024;  // k_bu_step_lds's own arrays, with margin
-  const int64_t bits = (g->lds_bytes - static_lds) * 8;
+  const int64_t bits = (g->lds_bytes - kBuStaticLds - ((g->num_hot + 63) / 64) * 8) * 8;
   if (bits >= 1024) {
     int gs = 0;
     while (((n + (1ll << gs) - 1) >> gs) > bits) ++gs;
@@ -796,6 +916,7 @@ BfsWork::~BfsWork() {
   for (auto *p : snap)
     if (p) (void)hipFree(p);
   if (sum) (void)hipFree(sum);
+  if (fh) (void)hipFree(fh);
   if (q[0]) (void)hipFree(q[0]);
   if (q[1]) (void)hipFree(q[1]);
   if (qoff) (void)hipFree(qoff);
@@ -852,7 +973,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const int bu_bpc = p.bu_blocks_per_cu > 0 ? p.bu_blocks_per_cu : g->tune.bu_blocks_per_cu;
   const double lds_density = p.lds_density > 0 ? p.lds_density : g->tune.lds_density;
   const int lds_kb = p.lds_kb > 0 ? p.lds_kb : g->tune.lds_kb;
-  const int wpw = p.bu_words_per_wave > 0 ? p.bu_words_per_wave : g->tune.words_per_wave;
+  const int vpl = p.bu_vertices_per_lane > 0 ? p.bu_vertices_per_lane : g->tune.vertices_per_lane;
   const bool packed = (p.flags & G5_FLAG_PACKED) || (g->tune.packed && !(p.flags & G5_FLAG_ROWLOOP));
   const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
   const bool acct = stats && (p.flags & G5_FLAG_COUNT_BYTES);
@@ -862,7 +983,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   int lds_gs = w.sum_gs;
   int64_t lds_words = w.sum_words;
   if (w.sum) {
-    const int64_t bits = std::min<int64_t>((int64_t)lds_kb * 1024, g->lds_bytes - 20 * 1024) * 8;
+    const int64_t fh_bytes = use_hint ? ((g->num_hot + 63) / 64) * 8 : 0;
+    const int64_t bits =
+        std::min<int64_t>((int64_t)lds_kb * 1024, g->lds_bytes - kBuStaticLds - fh_bytes) * 8;
     while (lds_gs < 40 && ((n + (1ll << lds_gs) - 1) >> lds_gs) > bits) ++lds_gs;
     lds_words = (((n + (1ll << lds_gs) - 1) >> lds_gs) + 31) / 32;
   }
@@ -890,8 +1013,13 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   } while (0)
 
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, w.ctr, (int64_t)C_NCTR);
+  // With hints and claims by OR, parent starts as every vertex's hint target:
+  // a bottom-up hit on the hint then writes no parent (unreached vertices are
+  // reset at the end).  Compare-and-swap claims need parent -1.
+  const bool prefill = use_hint && p.claim != CLAIM_CAS;
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
-                     dim3(kBlock), 0, s, level, parent, n, w.vis, w.snap[0], w.snap[1], g->iso, W,
+                     dim3(kBlock), 0, s, level, parent, n, prefill ? g->hint_id : nullptr, w.vis,
+                     w.snap[0], w.snap[1], g->iso, W,
                      (((uintptr_t)level | (uintptr_t)parent) & 15) == 0);
   hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, root, level, parent, w.vis, w.q[0], ctr,
                      g->row_ptr);
@@ -1001,31 +1129,43 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         hipLaunchKernelGGL(k_front_summary, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
                            s, front, W, lds_gs, w.sum);
       }
+      const int32_t *hint = use_hint ? g->hint : nullptr;
+      const int32_t *hint_id = prefill ? nullptr : g->hint_id;
+      const int64_t fh_words = use_hint ? (g->num_hot + 63) / 64 : 0;
+      if (fh_words)
+        hipLaunchKernelGGL(k_fh_build, dim3(grid_for(g->num_hot, kBlock, ncu * 8)), dim3(kBlock),
+                           0, s, front, g->hot, g->num_hot, w.fh);
       G5_REC(lvl, 0);
       const unsigned long long sq = ++w.seq;
 #define G5_BUL(K, P, A)                                                                     \
   do {                                                                                      \
     const void *fn_ = (const void *)&k_bu_step_lds<K, P, A>;                                 \
-    g5_status st_ = lds_ready(fn_, lds_words * 4);                                          \
+    const size_t dyn_ = (size_t)((lds_words + 1) / 2 + fh_words) * 8;                        \
+    g5_status st_ = lds_ready(fn_, (int64_t)dyn_);                                          \
     if (st_ != G5_OK) return st_;                                                           \
-    int per_cu_ = 1;                                                                        \
-    G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_, fn_, kLdsBlock,           \
-                                                        (size_t)lds_words * 4));            \
-    hipLaunchKernelGGL((k_bu_step_lds<K, P, A>), dim3(ncu * std::max(per_cu_, 1)),          \
-                       dim3(kLdsBlock), lds_words * 4, s, g->rp32, g->col_idx,               \
-                       use_hint ? g->hint : nullptr, w.vis, front, next, parent, level, n, W, \
-                       lvl + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub, sq);           \
+    const int per_cu_ = resident_per_cu(fn_, kLdsBlock, dyn_);                              \
+    hipLaunchKernelGGL((k_bu_step_lds<K, P, A>), dim3(ncu * per_cu_), dim3(kLdsBlock), dyn_, s, \
+                       g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words, w.vis, front, next, \
+                       parent, level, W, lvl + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub,  \
+                       sq);                                                                 \
   } while (0)
 #define G5_BU(K, P, A)                                                                      \
-  hipLaunchKernelGGL((k_bu_step<K, P, A>), dim3(bu_grid), dim3(kBlock), 0, s, g->rp32,     \
-                     g->col_idx, use_hint ? g->hint : nullptr, w.vis, front, next, parent,  \
-                     level, n, W, lvl + 1, ctr, packed, hpub, sq)
-#define G5_BU_P(M, K, A)           \
-  switch (wpw) {                   \
-    case 2: M(K, 2, A); break;     \
-    case 4: M(K, 4, A); break;     \
-    default: M(K, 1, A); break;    \
-  }
+  do {                                                                                      \
+    const void *fn_ = (const void *)&k_bu_step<K, P, A>;                                     \
+    const size_t dyn_ = (size_t)fh_words * 8;                                               \
+    g5_status st_ = lds_ready(fn_, (int64_t)dyn_);                                          \
+    if (st_ != G5_OK) return st_;                                                           \
+    const int per_cu_ = resident_per_cu(fn_, kBuBlock, dyn_);                               \
+    hipLaunchKernelGGL((k_bu_step<K, P, A>), dim3(ncu * std::min(bu_bpc, per_cu_)),         \
+                       dim3(kBuBlock), dyn_, s, g->rp32, g->col_idx, hint, hint_id, w.fh,      \
+                       fh_words, w.vis, front, next, parent, level, W, lvl + 1, ctr, packed,   \
+                       hpub, sq);                                                           \
+  } while (0)
+#define G5_BU_P(M, K, A)          \
+  if (vpl == 2)                   \
+    M(K, 2, A);                   \
+  else                            \
+    M(K, 1, A);
 #define G5_BU_K(M, A)                   \
   switch (lane_scan) {                  \
     case 1: G5_BU_P(M, 1, A); break;    \
@@ -1065,9 +1205,11 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         stats->discovered[i] = nnew;
         if (acct) {
           stats->edges[i] = (int64_t)hc[C_SCAN];
+          // parent is not written for hint hits when it was pre-filled
+          const int64_t pw = prefill ? nnew - (int64_t)hc[C_HINT] : nnew;
           stats->bytes[i] = (use_hint ? 4 : 0) * (int64_t)hc[C_UNVIS] +
                             4 * (int64_t)hc[C_ROWS] + 4 * (int64_t)hc[C_SCAN] + 16 * W +
-                            8 * nnew;
+                            4 * nnew + 4 * pw;
         }
       }
       reached += nnew;
@@ -1095,6 +1237,10 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     }
   }
 #undef G5_REC
+  if (prefill)
+    hipLaunchKernelGGL(k_unreached, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0, s,
+                       w.vis, g->iso, W, parent);
+  G5_LAUNCH_CHECK();
   G5_HIP(hipStreamSynchronize(s));
   if (stats) {
     stats->nlevels = lvl;

@@ -15,7 +15,12 @@
 //   rp32      32-bit copy of row_ptr for the traversal (nnz < 2^32 is required)
 //   hint      for each vertex, its highest-degree neighbour (among the first
 //             kHintScan of its row; smallest id on ties): the bottom-up step
-//             tests it before reading the row
+//             tests it before reading the row (hint_id keeps the ids)
+//   hot       the hint targets named by the most vertices (at most kHotMax of
+//             them and at most n/16, in vertex order) get a compact index; a vertex whose hint is
+//             one of them stores INT32_MIN | index instead of the id, so the
+//             bottom-up step tests a per-level bitmap of kHotMax bits (small
+//             enough to stay in L2) instead of a random word of the frontier
 #include <algorithm>
 
 #include "g5_internal.h"
@@ -302,6 +307,76 @@ __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
   }
 }
 
+constexpr int kHotBins = 1024;
+constexpr int kHotTile = 4096;  // vertices per workgroup when numbering hot targets
+
+// cnt[t] = number of vertices whose hint is t
+__global__ void k_hint_count(const int32_t *__restrict__ hint, int64_t n,
+                             uint32_t *__restrict__ cnt) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t h = hint[v];
+    if (h >= 0) atomicAdd(cnt + h, 1u);
+  }
+}
+
+// hist[c] = number of targets named by c vertices (c >= kHotBins - 1 share the last bin)
+__global__ __launch_bounds__(256) void k_hint_hist(const uint32_t *__restrict__ cnt, int64_t n,
+                                                   uint32_t *__restrict__ hist) {
+  __shared__ uint32_t h[kHotBins];
+  for (int i = threadIdx.x; i < kHotBins; i += 256) h[i] = 0;
+  __syncthreads();
+  int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const uint32_t c = cnt[i];
+    if (c) atomicAdd(h + std::min<uint32_t>(c, kHotBins - 1), 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHotBins; i += 256)
+    if (h[i]) atomicAdd(hist + i, h[i]);
+}
+
+__global__ __launch_bounds__(256) void k_hot_count(const uint32_t *__restrict__ cnt, int64_t n,
+                                                   uint32_t cmin, uint32_t *__restrict__ bsum) {
+  __shared__ uint32_t s[256 / kWave];
+  const int64_t b = (int64_t)blockIdx.x * kHotTile, e = std::min<int64_t>(b + kHotTile, n);
+  uint32_t c = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) c += cnt[i] >= cmin;
+  const uint32_t tot = block_sum<256, uint32_t>(c, s);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Numbers the selected targets in vertex order: hot[r] = t and, in place,
+// cnt[t] = r (0xffffffff for targets not selected).
+__global__ __launch_bounds__(256) void k_hot_write(uint32_t *__restrict__ cnt, int64_t n,
+                                                   uint32_t cmin, const uint64_t *__restrict__ boff,
+                                                   int32_t *__restrict__ hot) {
+  __shared__ uint32_t s[256 / kWave];
+  const int64_t b = (int64_t)blockIdx.x * kHotTile, e = std::min<int64_t>(b + kHotTile, n);
+  uint32_t base = (uint32_t)boff[blockIdx.x];
+  for (int64_t i0 = b; i0 < e; i0 += 256) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool sel = i < e && cnt[i] >= cmin;
+    uint32_t tot;
+    const uint32_t pos = base + block_excl_scan<256, uint32_t>(sel ? 1u : 0u, s, tot);
+    if (sel) hot[pos] = (int32_t)i;
+    if (i < e) cnt[i] = sel ? pos : 0xffffffffu;
+    base += tot;
+  }
+}
+
+__global__ void k_hint_encode(int32_t *__restrict__ hint, int64_t n,
+                              const uint32_t *__restrict__ rank) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t h = hint[v];
+    if (h >= 0) {
+      const uint32_t r = rank[h];
+      if (r != 0xffffffffu) hint[v] = (int32_t)(0x80000000u | r);
+    }
+  }
+}
+
 __global__ void k_rp32(const int64_t *__restrict__ rp, int64_t len, uint32_t *__restrict__ out) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
@@ -317,6 +392,7 @@ int grid_cap(int64_t items, int per_block, int cap) {
 
 struct DevBuf {
   void *p = nullptr;
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes); }
   ~DevBuf() {
     if (p) (void)hipFree(p);
   }
@@ -451,6 +527,57 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
   hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
                      g->col_idx, n, g->words, g->hint);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+  // the targets as ids (the traversal pre-fills parent with them)
+  if ((e = hipMalloc(&g->hint_id, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
+  if ((e = hipMemcpyAsync(g->hint_id, g->hint, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) !=
+      hipSuccess)
+    return fail(e, "copy");
+  {
+    // hot hint targets: the most-named ones, at most kHotMax, numbered in vertex order
+    const int64_t nb = (n + kHotTile - 1) / kHotTile;
+    DevBuf cnt, hist, bsum, boff;
+    if ((e = cnt.alloc(n * 4)) != hipSuccess || (e = hist.alloc(kHotBins * 4)) != hipSuccess ||
+        (e = bsum.alloc(nb * 4)) != hipSuccess || (e = boff.alloc(nb * 8)) != hipSuccess)
+      return fail(e, "hot hints");
+    if ((e = hipMemsetAsync(cnt.p, 0, n * 4, s)) != hipSuccess ||
+        (e = hipMemsetAsync(hist.p, 0, kHotBins * 4, s)) != hipSuccess)
+      return fail(e, "memset");
+    hipLaunchKernelGGL(k_hint_count, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s, g->hint,
+                       n, (uint32_t *)cnt.p);
+    hipLaunchKernelGGL(k_hint_hist, dim3(grid_cap(n, 256, ncu * 4)), dim3(256), 0, s,
+                       (const uint32_t *)cnt.p, n, (uint32_t *)hist.p);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+    std::vector<uint32_t> hh(kHotBins);
+    if ((e = hipMemcpyAsync(hh.data(), hist.p, kHotBins * 4, hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return fail(e, "copy");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+    // at most kHotMax targets, and at most one per 16 vertices (a frontier bitmap
+    // of a smaller graph stays in L2 by itself)
+    const uint64_t cap = (uint64_t)std::min<int64_t>(kHotMax, std::max<int64_t>(64, n >> 4));
+    uint64_t above = 0;
+    uint32_t cmin = kHotBins;
+    for (int c = kHotBins - 1; c >= 1; --c) {
+      if (above + hh[c] > cap) break;
+      above += hh[c];
+      cmin = (uint32_t)c;
+    }
+    if (above > 0) {
+      if ((e = hipMalloc(&g->hot, above * sizeof(int32_t))) != hipSuccess)
+        return fail(e, "hot hints");
+      hipLaunchKernelGGL(k_hot_count, dim3((unsigned)nb), dim3(256), 0, s,
+                         (const uint32_t *)cnt.p, n, cmin, (uint32_t *)bsum.p);
+      hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(kScanBlock), 0, s, (const uint32_t *)bsum.p,
+                         (uint64_t *)boff.p, nb, (uint64_t *)nullptr);
+      hipLaunchKernelGGL(k_hot_write, dim3((unsigned)nb), dim3(256), 0, s, (uint32_t *)cnt.p, n,
+                         cmin, (const uint64_t *)boff.p, g->hot);
+      hipLaunchKernelGGL(k_hint_encode, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s,
+                         g->hint, n, (const uint32_t *)cnt.p);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+      g->num_hot = (int64_t)above;
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+  }
 
   // hub list (order does not matter) and its chunk prefix
   const int64_t max_hubs = (int64_t)(nnz / kHubDeg) + 1;

@@ -18,6 +18,9 @@ constexpr int kWave = 64;
 // kHubChunk-edge work items by the batched traversal.
 constexpr int kHubDeg = 4096;
 constexpr int kHubChunk = 1024;
+// Hint targets given a compact per-level frontier bitmap (2^18 bits = 32 KiB,
+// staged in LDS by the bottom-up step).
+constexpr int64_t kHotMax = 1 << 18;
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);
@@ -52,6 +55,7 @@ struct BfsWork {
   uint32_t *sum = nullptr;    // frontier summary staged in LDS by bottom-up steps
   int64_t sum_words = 0;      // its 32-bit words
   int sum_gs = 0;             // log2 of the vertices per summary bit
+  uint64_t *fh = nullptr;     // frontier bits of the hot hint targets (bottom-up input)
   int32_t *q[2] = {nullptr, nullptr};  // frontier queues
   uint32_t *qoff = nullptr;   // per-frontier-vertex edge offsets (top-down)
   uint32_t *bsum = nullptr;   // per-chunk partial sums
@@ -81,7 +85,7 @@ struct Tuning {
   double alpha, beta;     // single-root direction switch
   int lane_scan;          // bottom-up lane scan width
   int bu_blocks_per_cu;   // bottom-up grid
-  int words_per_wave;     // bottom-up visited words per wavefront at once
+  int vertices_per_lane;  // bottom-up unvisited vertices per lane at once
   int packed;             // bottom-up packed row scan
   int lds_kb;             // LDS budget of the staged frontier per workgroup
   double lds_density;     // stage the frontier in LDS below this summary density
@@ -103,7 +107,11 @@ struct g5_csr {
   int32_t *col_idx = nullptr;  // device [nnz]
   uint64_t *iso = nullptr;     // device [words]: bit set = degree 0 (or padding)
   uint32_t *rp32 = nullptr;    // device [n+1]: row_ptr as 32-bit offsets
-  int32_t *hint = nullptr;     // device [n]: highest-degree neighbour, -1 if none
+  int32_t *hint = nullptr;     // device [n]: highest-degree neighbour, -1 if none, or
+                               // INT32_MIN | i when that neighbour is hot[i]
+  int32_t *hint_id = nullptr;  // device [n]: highest-degree neighbour id, -1 if none
+  int32_t *hot = nullptr;      // device [num_hot]: hint targets with a compact frontier bit
+  int64_t num_hot = 0;         // at most kHotMax
   g5::Tuning tune{};           // defaults for this graph's scale
   int64_t num_hubs = 0;        // vertices with degree > kHubDeg
   int64_t hub_chunks = 0;      // their rows in kHubChunk-edge pieces
