@@ -348,19 +348,29 @@ __global__ void k_front_from_vis(const uint64_t *__restrict__ vis,
 // Frontier membership for the bottom-up step: the frontier bitmap in HBM, or
 // a summary staged in LDS (bit i set when some frontier vertex lies in
 // [i << gs, (i + 1) << gs)); with gs = 0 the summary is the bitmap itself.
+// pre(u): 0 = not in the frontier, 1 = in it, 2 = ask the bitmap's 32-bit word
+// word(u).  Splitting the test lets a lane issue all of its bitmap loads
+// before using any of them.
 struct FrontGlobal {
-  const uint64_t *front;
-  __device__ __forceinline__ bool test(int32_t u) const { return (front[u >> 6] >> (u & 63)) & 1; }
+  const uint32_t *front;  // the frontier bitmap as 32-bit words
+  __device__ __forceinline__ int pre(int32_t) const { return 2; }
+  __device__ __forceinline__ uint32_t word(int32_t u) const { return front[u >> 5]; }
+  __device__ __forceinline__ bool test(int32_t u) const { return (word(u) >> (u & 31)) & 1; }
 };
 
 struct FrontLds {
   const uint32_t *sum;
-  const uint64_t *front;
+  const uint32_t *front;
   int gs;
-  __device__ __forceinline__ bool test(int32_t u) const {
+  __device__ __forceinline__ int pre(int32_t u) const {
     const uint32_t i = (uint32_t)u >> gs;
-    if (!((sum[i >> 5] >> (i & 31)) & 1)) return false;
-    return gs == 0 || ((front[u >> 6] >> (u & 63)) & 1);
+    if (!((sum[i >> 5] >> (i & 31)) & 1)) return 0;
+    return gs == 0 ? 1 : 2;
+  }
+  __device__ __forceinline__ uint32_t word(int32_t u) const { return front[u >> 5]; }
+  __device__ __forceinline__ bool test(int32_t u) const {
+    const int p = pre(u);
+    return p == 1 || (p == 2 && ((word(u) >> (u & 31)) & 1));
   }
 };
 
@@ -531,8 +541,8 @@ __device__ __forceinline__ void bu_chunks(
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     for (uint32_t base = 0; base < total; base += kWave * R) {
       bool act[R], found[R], via[R];
-      int64_t v[R], b[R], e[R], k[R];
-      int32_t par[R], h[R];
+      int32_t v[R], par[R], h[R];
+      uint32_t b[R], e[R], k[R];  // row offsets (nnz < 2^32)
       int wl[R], bit[R];
 #pragma unroll
       for (int j = 0; j < R; ++j) {
@@ -546,46 +556,94 @@ __device__ __forceinline__ void bu_chunks(
         const uint64_t word = __shfl(un, pos, kWave);
         wl[j] = pos;
         bit[j] = act[j] ? select_bit(word, r) : 0;
-        v[j] = (c * kWave + pos) * kWave + bit[j];
+        v[j] = (int32_t)((c * kWave + pos) * kWave + bit[j]);
         par[j] = -1;
         b[j] = e[j] = 0;
         h[j] = (act[j] && hint) ? hint[v[j]] : -1;
         if (ACCT && act[j]) cnt.nunvis += 1;
       }
+      // The hint (highest-degree neighbour): a hot target's bit is in fh (LDS);
+      // another target needs the frontier, whose word is loaded together with
+      // the row offsets (taken unless the hint is already known to hit).
+      // A vertex whose hint is its only neighbour has no row to read.
+      int hp[R];
+      bool only[R];
 #pragma unroll
-      for (int j = 0; j < R; ++j) {  // the highest-degree neighbour first
+      for (int j = 0; j < R; ++j) {
+        hp[j] = 0;
+        only[j] = h[j] != -1 && (h[j] & kHintOnly);
         if (h[j] >= 0) {
-          via[j] = F.test(h[j]);
+          h[j] &= ~kHintOnly;
+          hp[j] = F.pre(h[j]);
           par[j] = h[j];
         } else if (h[j] != -1) {
-          const uint32_t r = (uint32_t)h[j] & 0x7fffffffu;
-          via[j] = (fh[r >> 6] >> (r & 63)) & 1;
-        } else {
-          via[j] = false;
+          const uint32_t r = (uint32_t)h[j] & (uint32_t)(kHintOnly - 1);
+          hp[j] = (int)((fh[r >> 6] >> (r & 63)) & 1);
         }
-        found[j] = via[j];
-        if (ACCT && via[j]) cnt.nhint += 1;
+      }
+      uint32_t hw[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        hw[j] = (hp[j] == 2) ? F.word(h[j]) : 0u;
+        if (act[j] && hp[j] != 1 && !only[j]) {
+          uint32_t be[2];
+          __builtin_memcpy(be, rp + v[j], 8);  // both row offsets in one 8-byte load
+          b[j] = be[0];
+          e[j] = be[1];
+        }
       }
 #pragma unroll
-      for (int j = 0; j < R; ++j) {  // row offsets only where the hint missed
-        if (act[j] && !found[j]) {
-          b[j] = rp[v[j]];
-          e[j] = rp[v[j] + 1];
-          if (ACCT) cnt.nrows += 1;
-        }
+      for (int j = 0; j < R; ++j) {
+        via[j] = hp[j] == 1 || (hp[j] == 2 && ((hw[j] >> (h[j] & 31)) & 1));
+        found[j] = via[j];
+        if (found[j]) e[j] = b[j];   // nothing left to scan
         k[j] = b[j];
+        if (ACCT && via[j]) cnt.nhint += 1;
+        if (ACCT && act[j] && !found[j] && !only[j]) cnt.nrows += 1;
       }
+      // the first LANE_SCAN entries of the row in LANE_SCAN/4 16-byte loads (col_idx
+      // is padded past nnz, so reading beyond the row's end stays in bounds)
       int32_t u[R][LANE_SCAN];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (act[j] && !found[j] && k[j] < e[j]) {
+          __builtin_memcpy(u[j], ci + k[j], LANE_SCAN * sizeof(int32_t));
+#pragma unroll
+          for (int t = 0; t < LANE_SCAN; ++t)
+            if (k[j] + t >= e[j]) u[j][t] = -1;
+        } else {
+#pragma unroll
+          for (int t = 0; t < LANE_SCAN; ++t) u[j][t] = -1;
+        }
+      }
+      // their frontier tests: summary bits first (bit t of sure / need: entry t
+      // is in the frontier / needs its bitmap word), then every needed word,
+      // then the bits, so the loads are in flight together
+      uint32_t sure[R], need[R];
+      uint32_t uw[R][LANE_SCAN];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        sure[j] = need[j] = 0;
+#pragma unroll
+        for (int t = 0; t < LANE_SCAN; ++t) {
+          const int p = F.pre(u[j][t] < 0 ? 0 : u[j][t]);  // unconditional: no branch per entry
+          if (u[j][t] >= 0) {
+            sure[j] |= (uint32_t)(p == 1) << t;
+            need[j] |= (uint32_t)(p == 2) << t;
+          }
+        }
+      }
 #pragma unroll
       for (int j = 0; j < R; ++j)
 #pragma unroll
         for (int t = 0; t < LANE_SCAN; ++t)
-          u[j][t] = (act[j] && !found[j] && k[j] + t < e[j]) ? ci[k[j] + t] : -1;
+          uw[j][t] = ((need[j] >> t) & 1) ? F.word(u[j][t]) : 0u;
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         bool hv[LANE_SCAN];
 #pragma unroll
-        for (int t = 0; t < LANE_SCAN; ++t) hv[t] = u[j][t] >= 0 && F.test(u[j][t]);
+        for (int t = 0; t < LANE_SCAN; ++t)
+          hv[t] = ((sure[j] >> t) & 1) || (((need[j] >> t) & 1) && ((uw[j][t] >> (u[j][t] & 31)) & 1));
         if (act[j] && !found[j]) {
 #pragma unroll
           for (int t = 0; t < LANE_SCAN; ++t) {
@@ -595,15 +653,15 @@ __device__ __forceinline__ void bu_chunks(
               if (ACCT) cnt.nscan += (uint64_t)(t + 1);
             }
           }
-          const int64_t k0 = k[j];
-          k[j] = std::min<int64_t>(k[j] + LANE_SCAN, e[j]);
+          const uint32_t k0 = k[j];
+          k[j] = std::min<uint32_t>(k[j] + LANE_SCAN, e[j]);
           if (ACCT && !found[j]) cnt.nscan += (uint64_t)(k[j] - k0);
         }
       }
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        bu_row_rest<Front, ACCT>(F, ci, packed, act[j], k[j], e[j], found[j], par[j], s_base,
-                                 s_row, s_first, cnt);
+        bu_row_rest<Front, ACCT>(F, ci, packed, act[j], (int64_t)k[j], (int64_t)e[j], found[j],
+                                 par[j], s_base, s_row, s_first, cnt);
         if (found[j]) {
           if (!via[j])
             parent[v[j]] = par[j];
@@ -696,7 +754,7 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
   const int64_t gw = ((int64_t)blockIdx.x * kBuBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kBuBlock) / kWave;
   BuCount c;
-  bu_chunks<LANE_SCAN, R, ACCT>(FrontGlobal{front}, s_fh, rp, ci, hint, hint_id, vis, next,
+  bu_chunks<LANE_SCAN, R, ACCT>(FrontGlobal{(const uint32_t *)front}, s_fh, rp, ci, hint, hint_id, vis, next,
                                 parent, level, words, next_level, packed, gw, nw, s_base, s_row,
                                 s_first, s_nx, c);
   bu_flush<kBuBlock, ACCT>(c, s, ctr, host, seq);
@@ -734,7 +792,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
   const int64_t gw = ((int64_t)blockIdx.x * kLdsBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kLdsBlock) / kWave;
   BuCount c;
-  bu_chunks<LANE_SCAN, R, ACCT>(FrontLds{s_sum, front, gs}, s_fh, rp, ci, hint, hint_id, vis,
+  bu_chunks<LANE_SCAN, R, ACCT>(FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, vis,
                                 next, parent, level, words, next_level, packed, gw, nw, s_base,
                                 s_row, s_first, s_nx, c);
   bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq);

@@ -15,7 +15,8 @@
 //   rp32      32-bit copy of row_ptr for the traversal (nnz < 2^32 is required)
 //   hint      for each vertex, its highest-degree neighbour (among the first
 //             kHintScan of its row; smallest id on ties): the bottom-up step
-//             tests it before reading the row (hint_id keeps the ids)
+//             tests it before reading the row (hint_id keeps the ids); bit 30
+//             marks a target that is the vertex's only neighbour (no row to read)
 //   hot       the hint targets named by the most vertices (at most kHotMax of
 //             them and at most n/16, in vertex order) get a compact index; a vertex whose hint is
 //             one of them stores INT32_MIN | index instead of the id, so the
@@ -275,9 +276,12 @@ __device__ __forceinline__ uint64_t hint_key(const int64_t *rp, int32_t u) {
   return (d << 32) | (uint64_t)(0x7fffffffu - (uint32_t)u);
 }
 
+// hint_id[v] = the target (or -1); hint[v] = the same with kHintOnly set when
+// it is v's only neighbour (only used while n <= 2^30, so ids leave bit 30 free).
 __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
                                               const int32_t *__restrict__ ci, int64_t n,
-                                              int64_t words, int32_t *__restrict__ hint) {
+                                              int64_t words, int32_t *__restrict__ hint,
+                                              int32_t *__restrict__ hint_id) {
   const int lane = __lane_id();
   const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -303,7 +307,11 @@ __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
       for (int d = kWave / 2; d >= 1; d >>= 1) m = std::max(m, (uint64_t)__shfl_xor(m, d, kWave));
       if (lane == L) best = m;
     }
-    if (v < n) hint[v] = best ? (int32_t)(0x7fffffffu - (uint32_t)(best & 0xffffffffu)) : -1;
+    if (v < n) {
+      const int32_t t = best ? (int32_t)(0x7fffffffu - (uint32_t)(best & 0xffffffffu)) : -1;
+      hint_id[v] = t;
+      hint[v] = (t >= 0 && e - b == 1 && n <= (1ll << 30)) ? (t | kHintOnly) : t;
+    }
   }
 }
 
@@ -316,7 +324,7 @@ __global__ void k_hint_count(const int32_t *__restrict__ hint, int64_t n,
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     const int32_t h = hint[v];
-    if (h >= 0) atomicAdd(cnt + h, 1u);
+    if (h >= 0) atomicAdd(cnt + (h & ~kHintOnly), 1u);
   }
 }
 
@@ -371,8 +379,8 @@ __global__ void k_hint_encode(int32_t *__restrict__ hint, int64_t n,
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     const int32_t h = hint[v];
     if (h >= 0) {
-      const uint32_t r = rank[h];
-      if (r != 0xffffffffu) hint[v] = (int32_t)(0x80000000u | r);
+      const uint32_t r = rank[h & ~kHintOnly];
+      if (r != 0xffffffffu) hint[v] = (int32_t)(0x80000000u | (h & kHintOnly) | r);
     }
   }
 }
@@ -506,8 +514,10 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
   hipError_t e;
   if ((e = hipMalloc(&g->row_ptr, (n + 1) * sizeof(int64_t))) != hipSuccess)
     return fail(e, "row_ptr");
-  if ((e = hipMalloc(&g->col_idx, std::max<uint64_t>(nnz, 1) * sizeof(int32_t))) != hipSuccess)
+  if ((e = hipMalloc(&g->col_idx, (nnz + kColPad) * sizeof(int32_t))) != hipSuccess)
     return fail(e, "col_idx");
+  if ((e = hipMemsetAsync(g->col_idx + nnz, 0, kColPad * sizeof(int32_t), s)) != hipSuccess)
+    return fail(e, "memset");
   if ((e = hipMalloc(&g->iso, g->words * sizeof(uint64_t))) != hipSuccess)
     return fail(e, "iso");
   hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(kCompactBlock), 0, s, keys, ntot, sent, sb,
@@ -524,14 +534,10 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
   hipLaunchKernelGGL(k_rp32, dim3(grid_cap(n + 1, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr,
                      n + 1, g->rp32);
   if ((e = hipMalloc(&g->hint, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
-  hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
-                     g->col_idx, n, g->words, g->hint);
-  if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
-  // the targets as ids (the traversal pre-fills parent with them)
   if ((e = hipMalloc(&g->hint_id, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
-  if ((e = hipMemcpyAsync(g->hint_id, g->hint, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) !=
-      hipSuccess)
-    return fail(e, "copy");
+  hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+                     g->col_idx, n, g->words, g->hint, g->hint_id);
+  if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
   {
     // hot hint targets: the most-named ones, at most kHotMax, numbered in vertex order
     const int64_t nb = (n + kHotTile - 1) / kHotTile;

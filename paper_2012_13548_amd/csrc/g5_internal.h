@@ -21,6 +21,10 @@ constexpr int kHubChunk = 1024;
 // Hint targets given a compact per-level frontier bitmap (2^18 bits = 32 KiB,
 // staged in LDS by the bottom-up step).
 constexpr int64_t kHotMax = 1 << 18;
+// Hint word flag: the hint target is the vertex's only neighbour.
+constexpr int32_t kHintOnly = 1 << 30;
+// Zeroed col_idx entries past nnz, so fixed-width row reads stay in bounds.
+constexpr int64_t kColPad = 16;
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);
@@ -108,7 +112,8 @@ struct g5_csr {
   uint64_t *iso = nullptr;     // device [words]: bit set = degree 0 (or padding)
   uint32_t *rp32 = nullptr;    // device [n+1]: row_ptr as 32-bit offsets
   int32_t *hint = nullptr;     // device [n]: highest-degree neighbour, -1 if none, or
-                               // INT32_MIN | i when that neighbour is hot[i]
+                               // INT32_MIN | i when that neighbour is hot[i]; | kHintOnly
+                               // when it is the only neighbour
   int32_t *hint_id = nullptr;  // device [n]: highest-degree neighbour id, -1 if none
   int32_t *hot = nullptr;      // device [num_hot]: hint targets with a compact frontier bit
   int64_t num_hot = 0;         // at most kHotMax
