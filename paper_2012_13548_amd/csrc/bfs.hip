@@ -50,17 +50,27 @@ enum Ctr : int {
   C_UNVIS = 8,  // unvisited non-isolated vertices it scanned (byte counting only)
   C_ROWS = 9,   // those that read their row offsets (hint missed; byte counting only)
   C_HINT = 10,  // vertices found by their hint (byte counting only)
+  C_NPUB = 11,  // slots copied to the host
   C_NCTR = 16
 };
 
-// Copies the counters to host memory, then releases the sequence number.
+// Copies the counters to host memory.  Each 8-byte slot carries the low 16
+// bits of the sequence number above a 48-bit value, so every slot is complete
+// by itself and no release fence (a write-back of L2) is needed; the host waits
+// until all slots show the sequence number.  All loads are issued before the
+// first store so their latencies overlap.
+constexpr int kPubShift = 48;
 __device__ void publish(const unsigned long long *ctr, unsigned long long *host,
                         unsigned long long seq) {
-  for (int i = 0; i < C_NCTR; ++i)
-    __hip_atomic_store(host + i, __hip_atomic_load(ctr + i, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(host + C_NCTR, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  unsigned long long v[C_NPUB];
+#pragma unroll
+  for (int i = 0; i < C_NPUB; ++i)
+    v[i] = __hip_atomic_load(ctr + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long tag = (seq & 0xffffull) << kPubShift;
+#pragma unroll
+  for (int i = 0; i < C_NPUB; ++i)
+    __hip_atomic_store(host + i, tag | (v[i] & ((1ull << kPubShift) - 1)), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // level = -1 and parent = fill (the hint targets) or -1; visited bitmap and its
@@ -72,10 +82,13 @@ __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ pa
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t n4 = vec ? n / 4 : 0;
-  int4 m1 = make_int4(-1, -1, -1, -1);
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  const v4i m1 = {-1, -1, -1, -1};
+  // streaming (non-temporal) accesses: the arrays are far larger than L2
   for (int64_t i = t; i < n4; i += stride) {
-    reinterpret_cast<int4 *>(level)[i] = m1;
-    reinterpret_cast<int4 *>(parent)[i] = fill ? reinterpret_cast<const int4 *>(fill)[i] : m1;
+    __builtin_nontemporal_store(m1, reinterpret_cast<v4i *>(level) + i);
+    const v4i f = fill ? __builtin_nontemporal_load(reinterpret_cast<const v4i *>(fill) + i) : m1;
+    __builtin_nontemporal_store(f, reinterpret_cast<v4i *>(parent) + i);
   }
   for (int64_t i = n4 * 4 + t; i < n; i += stride) {
     level[i] = -1;
@@ -985,16 +998,22 @@ BfsWork::~BfsWork() {
 }
 
 // Waits until a kernel on `s` has published sequence number `want` to the
-// mapped host counters; falls back to the stream's status so a failed launch
-// cannot leave the host spinning.
-static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want) {
+// mapped host counters and copies their values to out[0, C_NPUB); falls back to
+// the stream's status so a failed launch cannot leave the host spinning.
+static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want, int64_t *out) {
   volatile uint64_t *h = w.host_pub;
+  const uint64_t tag = want & 0xffff;
+  auto ready = [&]() {
+    for (int i = 0; i < C_NPUB; ++i)
+      if ((h[i] >> kPubShift) != tag) return false;
+    return true;
+  };
   for (uint32_t spin = 0;; ++spin) {
-    if (h[C_NCTR] == want) break;
+    if (ready()) break;
     if ((spin & 1023) == 1023) {
       hipError_t e = hipStreamQuery(s);
       if (e == hipSuccess) {
-        if (h[C_NCTR] == want) break;
+        if (ready()) break;
         set_error("g5_bfs: a level finished without publishing its counters");
         return G5_EDEVICE;
       }
@@ -1004,7 +1023,7 @@ static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want) {
       }
     }
   }
-  std::atomic_thread_fence(std::memory_order_acquire);
+  for (int i = 0; i < C_NPUB; ++i) out[i] = (int64_t)(h[i] & ((1ull << kPubShift) - 1));
   return G5_OK;
 }
 
@@ -1050,7 +1069,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   int lds_levels = 0;
   unsigned long long *ctr = (unsigned long long *)w.ctr;
   unsigned long long *hpub = (unsigned long long *)w.host_pub_dev;
-  const volatile uint64_t *hc = w.host_pub;
+  int64_t hc[C_NPUB] = {};  // the counters last published
   const int bu_grid = ncu * bu_bpc;
   const int deg_grid = ncu * 8;
   if (timed && w.ev.empty()) {
@@ -1113,7 +1132,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       G5_LAUNCH_CHECK();
       G5_REC(lvl, 1);
       {
-        g5_status st = wait_published(w, s, w.seq);
+        g5_status st = wait_published(w, s, w.seq, hc);
         if (st != G5_OK) return st;
       }
       if (hc[C_ERR]) {
@@ -1252,7 +1271,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       G5_LAUNCH_CHECK();
       G5_REC(lvl, 1);
       {
-        g5_status st = wait_published(w, s, sq);
+        g5_status st = wait_published(w, s, sq, hc);
         if (st != G5_OK) return st;
       }
       const int64_t nnew = (int64_t)hc[C_NNEW];
