@@ -48,7 +48,7 @@ class BfsParams(ctypes.Structure):
                 ("lds_density", ctypes.c_double), ("claim", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("bu_blocks_per_cu", ctypes.c_int32),
                 ("lds_kb", ctypes.c_int32), ("bu_vertices_per_lane", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("td_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 _L = MAX_STAT_LEVELS
@@ -172,9 +172,10 @@ def build_csr(edges, n):
 
 
 def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None, lds_kb=None,
-            lds_density=None, vertices_per_lane=None):
+            lds_density=None, vertices_per_lane=None, td_blocks_per_cu=None):
     p = BfsParams()
     p.bu_vertices_per_lane = vertices_per_lane or 0
+    p.td_blocks_per_cu = td_blocks_per_cu or 0
     p.direction = direction
     p.alpha = alpha or 0.0
     p.beta = beta or 0.0
@@ -189,7 +190,8 @@ def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None,
 
 def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta=None,
         lane_scan=None, claim=CLAIM_OR, hint=True, packed=None, min_parent=False, lds=True,
-        blocks_per_cu=None, lds_kb=None, lds_density=None, vertices_per_lane=None, stats=False,
+        blocks_per_cu=None, lds_kb=None, lds_density=None, vertices_per_lane=None,
+        td_blocks_per_cu=None, stats=False,
         time_steps=False, count_bytes=False):
     """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
 
@@ -210,7 +212,7 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
              | {None: 0, True: FLAG_PACKED, False: FLAG_ROWLOOP}[packed]
              | (FLAG_MIN_PARENT if min_parent else 0) | (0 if lds else FLAG_NO_LDS))
     p = _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu, lds_kb,
-                lds_density, vertices_per_lane)
+                lds_density, vertices_per_lane, td_blocks_per_cu)
     want = stats or time_steps or count_bytes
     st = BfsStats()
     _check(lib.g5_bfs_ex(csr.handle, int(root), parent.data_ptr(), level.data_ptr(),

@@ -109,10 +109,11 @@ g5_status g5_bfs_ex(const g5_csr *g, int64_t root, int32_t *parent, int32_t *lev
       p.beta < 0 || p.lds_density < 0 || p.bu_blocks_per_cu < 0 || p.bu_blocks_per_cu > 32 ||
       (p.lds_kb != 0 && (p.lds_kb < 16 || p.lds_kb > 160)) ||
       (p.bu_vertices_per_lane != 0 && p.bu_vertices_per_lane != 1 &&
-       p.bu_vertices_per_lane != 2)) {
+       p.bu_vertices_per_lane != 2) ||
+      p.td_blocks_per_cu < 0 || p.td_blocks_per_cu > 256) {
     set_error("g5_bfs: direction must be 0..2, claim 0..1, bu_lane_scan 0 or a power of two "
               "up to 16, alpha, beta, lds_density >= 0, bu_blocks_per_cu 0..32, lds_kb 0 or "
-              "16..160, bu_vertices_per_lane 0, 1 or 2");
+              "16..160, bu_vertices_per_lane 0, 1 or 2, td_blocks_per_cu 0..256");
     return G5_EINVAL;
   }
   try {

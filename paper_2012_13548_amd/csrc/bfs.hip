@@ -44,13 +44,18 @@ enum Ctr : int {
   C_QLEN1 = 1,  // length of queue 1
   C_MF = 2,     // degree sum of the scanned frontier queue
   C_NNEW = 3,   // vertices found by a bottom-up step (reset after publishing)
+  C_GO = 4,     // 1: this top-down level expands (decided by the degree scan)
   C_RDEG = 5,   // degree of the root
   C_ERR = 6,    // nonzero if a kernel met an impossible state
   C_SCAN = 7,   // row entries read by a bottom-up step (byte counting only)
   C_UNVIS = 8,  // unvisited non-isolated vertices it scanned (byte counting only)
   C_ROWS = 9,   // those that read their row offsets (hint missed; byte counting only)
   C_HINT = 10,  // vertices found by their hint (byte counting only)
-  C_NPUB = 11,  // slots copied to the host
+  C_BUGO = 11,  // 1: the next level is bottom-up too (decided by the last bottom-up step)
+  C_NPUB = 12,  // slots copied to the host
+  C_MU = 12,    // m_u: edges of the vertices no top-down level has discovered yet
+  C_LASTNF = 13,  // frontier size of the previous level
+  C_NFIN = 14,  // input frontier size of the next bottom-up step
   C_NCTR = 16
 };
 
@@ -60,6 +65,11 @@ enum Ctr : int {
 // until all slots show the sequence number.  All loads are issued before the
 // first store so their latencies overlap.
 constexpr int kPubShift = 48;
+// kPubBufs host buffers of kPubSlots slots, by sequence number: with the next
+// levels queued ahead, sequences k + 1 and k + 2 may be published before the
+// host has read k.
+constexpr int kPubSlots = 16;
+constexpr int kPubBufs = 4;
 __device__ void publish(const unsigned long long *ctr, unsigned long long *host,
                         unsigned long long seq) {
   unsigned long long v[C_NPUB];
@@ -67,9 +77,10 @@ __device__ void publish(const unsigned long long *ctr, unsigned long long *host,
   for (int i = 0; i < C_NPUB; ++i)
     v[i] = __hip_atomic_load(ctr + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const unsigned long long tag = (seq & 0xffffull) << kPubShift;
+  unsigned long long *h = host + (seq % kPubBufs) * kPubSlots;
 #pragma unroll
   for (int i = 0; i < C_NPUB; ++i)
-    __hip_atomic_store(host + i, tag | (v[i] & ((1ull << kPubShift) - 1)), __ATOMIC_RELAXED,
+    __hip_atomic_store(h + i, tag | (v[i] & ((1ull << kPubShift) - 1)), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -101,15 +112,46 @@ __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ pa
   }
 }
 
+// Direction of a top-down level (the rule the host reads from the published
+// counters): queue slot qs holds its frontier Q (qlen vertices, mf edges).
+// m_u (edges of vertices no top-down level has discovered) drops by m_f except
+// at the root's level; switch to bottom-up when Q grew and m_f > m_u / alpha.
+// ctr[C_GO] = 1 lets the level's queued degree pass and expansion run.  Clears
+// the slot of the queue that this level fills and publishes.
+__device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, int dirmode, double alpha,
+                          uint64_t mf, unsigned long long *host, unsigned long long seq) {
+  auto ld = [&](int i) {
+    return (int64_t)__hip_atomic_load(ctr + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  const int64_t qlen = ld(C_QLEN0 + qs);
+  int64_t mu = ld(C_MU);
+  if (lvl > 0) mu -= (int64_t)mf;
+  const bool growing = qlen > ld(C_LASTNF);
+  const bool to_bu = dirmode == G5_DIR_BOTTOMUP ||
+                     (dirmode == G5_DIR_AUTO && growing && (double)mf > (double)mu / alpha);
+  const bool go = qlen > 0 && !to_bu;
+  ctr[C_MU] = (unsigned long long)mu;
+  ctr[C_MF] = mf;
+  ctr[C_GO] = go ? 1ull : 0ull;
+  if (go) ctr[C_LASTNF] = (unsigned long long)qlen;
+  ctr[C_QLEN0 + (qs ^ 1)] = 0;
+  publish(ctr, host, seq);
+}
+
+// Root's level: queue {root} with its degree, and the counters.
 __global__ void k_bfs_seed(int64_t root, int32_t *level, int32_t *parent, uint64_t *vis,
-                           int32_t *q0, unsigned long long *ctr, const int64_t *rp) {
+                           int32_t *q0, uint32_t *qd0, unsigned long long *ctr, const int64_t *rp,
+                           int64_t nnz) {
   level[root] = 0;
   parent[root] = (int32_t)root;
   vis[root >> 6] |= 1ull << (root & 63);
+  const int64_t rdeg = rp[root + 1] - rp[root];  // 64-bit offsets
   q0[0] = (int32_t)root;
+  qd0[0] = (uint32_t)rdeg;
   ctr[C_QLEN0] = 1;
-  ctr[C_QLEN1] = 0;
-  ctr[C_RDEG] = (unsigned long long)(rp[root + 1] - rp[root]);  // 64-bit offsets
+  ctr[C_RDEG] = (unsigned long long)rdeg;
+  ctr[C_MU] = (unsigned long long)(nnz - rdeg);
+  ctr[C_LASTNF] = 0;
 }
 
 __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
@@ -117,20 +159,21 @@ __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
 }
 
-// Degrees of the frontier queue in 1024-entry chunks (chunk c: block-local
-// exclusive prefix into qoff, total into bsum[c]); grid-stride over chunks, the
-// queue length read from the device.  The same launch snapshots the visited
-// bitmap into `snap` before this level's expansion.
-__global__ __launch_bounds__(kBlock) void k_td_deg(const int32_t *__restrict__ q,
-                                                   const unsigned long long *__restrict__ qlen_p,
-                                                   const uint32_t *__restrict__ rp,
-                                                   uint32_t *__restrict__ qoff,
+// Degree pass of a top-down level: the queue's degrees (written with the queue)
+// become, per 1024-entry chunk c, the block-local exclusive prefix in qoff and
+// the total in bsum[c]; grid-stride over chunks, the queue length read from the
+// device (0 when it was queued ahead behind a level that did not expand, so
+// the pass does nothing).  The same launch snapshots the visited bitmap into
+// `snap` before this level's expansion.
+__global__ __launch_bounds__(kBlock) void k_td_deg(const unsigned long long *__restrict__ cctr,
+                                                   int cur, uint32_t *__restrict__ qoff,
                                                    uint32_t *__restrict__ bsum,
                                                    uint64_t *__restrict__ snap,
                                                    const uint64_t *__restrict__ vis,
                                                    int64_t words) {
   __shared__ uint32_t s[kBlock / kWave];
-  const int64_t qlen = (int64_t)*qlen_p;
+  const int64_t qlen = (int64_t)cctr[C_QLEN0 + cur];
+  if (qlen == 0) return;
   const int64_t nchunks = (qlen + kDegTile - 1) / kDegTile;
   for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
     const int64_t b = c * kDegTile + (int64_t)threadIdx.x * kDegItems;
@@ -139,11 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_td_deg(const int32_t *__restrict__ q
 #pragma unroll
     for (int j = 0; j < kDegItems; ++j) {
       const int64_t i = b + j;
-      d[j] = 0;
-      if (i < qlen) {
-        const int32_t u = q[i];
-        d[j] = rp[u + 1] - rp[u];
-      }
+      d[j] = i < qlen ? qoff[i] : 0u;
       sum += d[j];
     }
     uint32_t tot;
@@ -161,12 +200,13 @@ __global__ __launch_bounds__(kBlock) void k_td_deg(const int32_t *__restrict__ q
     snap[i] = vis[i];
 }
 
-// Exclusive scan of the chunk totals (single block): bsum becomes the chunk
-// offsets, ctr[C_MF] the frontier's degree sum; clears the next queue's length
-// and publishes the counters.
+// Exclusive scan of the chunk totals of a top-down level's degree pass (single
+// block): bsum becomes the chunk offsets and their total is the frontier's
+// m_f; then the level's direction decision (td_decide), published.
 __global__ __launch_bounds__(kScanBlock) void k_td_scan(uint32_t *__restrict__ bsum,
                                                         unsigned long long *__restrict__ ctr,
-                                                        int cur,
+                                                        int cur, int32_t lvl, int dirmode,
+                                                        double alpha,
                                                         unsigned long long *__restrict__ host,
                                                         unsigned long long seq) {
   __shared__ uint32_t s[kScanBlock / kWave];
@@ -183,17 +223,16 @@ __global__ __launch_bounds__(kScanBlock) void k_td_scan(uint32_t *__restrict__ b
     bsum[i] = run;
     run += x;
   }
-  if (threadIdx.x == 0) {
-    ctr[C_MF] = tot;
-    ctr[C_QLEN0 + (cur ^ 1)] = 0;
-    publish(ctr, host, seq);
-  }
+  if (threadIdx.x == 0) td_decide(ctr, cur, lvl, dirmode, alpha, tot, host, seq);
 }
 
-// In-place exclusive scan of bsum[0..len) (single block); total -> *out.
+// In-place exclusive scan of bsum[0..len) (single block); total -> *out, and
+// v2 -> *out2 when given.
 __global__ __launch_bounds__(kScanBlock) void k_scan_bsum(uint32_t *__restrict__ bsum,
                                                           int64_t len,
-                                                          unsigned long long *__restrict__ out) {
+                                                          unsigned long long *__restrict__ out,
+                                                          unsigned long long *__restrict__ out2,
+                                                          unsigned long long v2) {
   __shared__ uint32_t s[kScanBlock / kWave];
   int64_t per = (len + kScanBlock - 1) / kScanBlock;
   int64_t b = per * threadIdx.x, e = std::min<int64_t>(b + per, len);
@@ -206,7 +245,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_bsum(uint32_t *__restrict__
     bsum[i] = run;
     run += x;
   }
-  if (threadIdx.x == 0) *out = tot;
+  if (threadIdx.x == 0) {
+    *out = tot;
+    if (out2) *out2 = v2;
+  }
 }
 
 // Global edge offset of frontier entry i: chunk offset + in-chunk prefix.
@@ -252,106 +294,125 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
   return x;
 }
 
+// Top-down expansion (runs only if the level's scan set ctr[C_GO]); a block
+// takes 1024-edge tiles of the frontier's edges (total ctr[C_MF]) in turn.
+// Each claimed vertex is appended to the next queue with its degree.
+
 template <int CLAIM>
 __global__ __launch_bounds__(kBlock) void k_td_expand(
-    const int32_t *__restrict__ q, int64_t qlen, const uint32_t *__restrict__ qoff,
-    const uint32_t *__restrict__ boff, uint32_t total, const uint32_t *__restrict__ rp,
-    const int32_t *__restrict__ ci,
+    const int32_t *__restrict__ q, const uint32_t *__restrict__ qoff,
+    const uint32_t *__restrict__ boff, unsigned long long *__restrict__ ctr, int cur,
+    const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     uint64_t *vis, const uint64_t *__restrict__ prev, int32_t *parent,
-    int32_t *__restrict__ level, int32_t *__restrict__ qn,
-    unsigned long long *__restrict__ qn_len, int32_t next_level,
-    unsigned long long *__restrict__ err) {
+    int32_t *__restrict__ level, int32_t *__restrict__ qn, uint32_t *__restrict__ qdn,
+    int32_t next_level) {
   __shared__ uint32_t s_off[kTdTile + 1];
   __shared__ int32_t s_src[kTdTile];
   __shared__ int64_t s_base[kTdTile];
   __shared__ int32_t s_out[kTdTile];
   __shared__ uint32_t s_cnt;
   __shared__ unsigned long long s_gbase;
-  const uint32_t e0 = blockIdx.x * (uint32_t)kTdTile;
-  if (e0 >= total) return;
-  const uint32_t e1 = (uint32_t)std::min<uint64_t>((uint64_t)e0 + kTdTile, total);
+  if (!ctr[C_GO]) return;
+  const int nxt = cur ^ 1;
+  unsigned long long *qn_len = ctr + C_QLEN0 + nxt;
+  const int64_t qlen = (int64_t)ctr[C_QLEN0 + cur];
+  const uint32_t total = (uint32_t)ctr[C_MF];
   const FrontOffsets off{qoff, boff, qlen, total};
-  const int64_t i0 = block_search(off, qlen, e0);
-  const int64_t i1 = block_search(off, qlen, e1 - 1);
-  const int S = (int)(i1 - i0 + 1);
-  if (S > kTdTile) {  // only degree-0 vertices could do this, and none are queued
-    if (threadIdx.x == 0) atomicOr(err, 1ull);
-    return;
-  }
-  for (int k = threadIdx.x; k < S; k += kBlock) {
-    uint32_t o = off(i0 + k);
-    int32_t u = q[i0 + k];
-    s_off[k] = o;
-    s_src[k] = u;
-    s_base[k] = (int64_t)rp[u] - (int64_t)o;
-  }
-  if (threadIdx.x == 0) {
-    s_off[S] = off(i1 + 1);
-    s_cnt = 0;
-  }
-  __syncthreads();
   const int lane = __lane_id();
   const uint64_t lt = lanemask_lt();
-  int klo = 0;
+  for (uint64_t tile = blockIdx.x; tile * kTdTile < total; tile += gridDim.x) {
+    const uint32_t e0 = (uint32_t)(tile * kTdTile);
+    const uint32_t e1 = (uint32_t)std::min<uint64_t>((uint64_t)e0 + kTdTile, total);
+    const int64_t i0 = block_search(off, qlen, e0);
+    const int64_t i1 = block_search(off, qlen, e1 - 1);
+    const int S = (int)(i1 - i0 + 1);
+    if (S > kTdTile) {  // only degree-0 vertices could do this, and none are queued
+      if (threadIdx.x == 0) atomicOr(ctr + C_ERR, 1ull);
+      break;
+    }
+    for (int k = threadIdx.x; k < S; k += kBlock) {
+      uint32_t o = off(i0 + k);
+      int32_t u = q[i0 + k];
+      s_off[k] = o;
+      s_src[k] = u;
+      s_base[k] = (int64_t)rp[u] - (int64_t)o;
+    }
+    if (threadIdx.x == 0) {
+      s_off[S] = off(i1 + 1);
+      s_cnt = 0;
+    }
+    __syncthreads();
+    int klo = 0;
 #pragma unroll
-  for (int j = 0; j < kTdItems; ++j) {
-    uint32_t e = e0 + j * kBlock + threadIdx.x;
-    bool won = false;
-    int32_t v = 0;
-    if (e < e1) {
-      int lo = klo, hi = S;
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (s_off[mid] <= e)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      klo = lo;
-      v = ci[s_base[lo] + (int64_t)e];
-      int32_t u = s_src[lo];
-      uint64_t bit = 1ull << (v & 63);
-      uint64_t *wp = vis + (v >> 6);
-      if (CLAIM == CLAIM_MIN) {
-        if (!(prev[v >> 6] & bit)) {
-          atomicMin((unsigned int *)(parent + v), (unsigned int)u);
-          if (!(*wp & bit)) {
-            won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
-            if (won) level[v] = next_level;
+    for (int j = 0; j < kTdItems; ++j) {
+      uint32_t e = e0 + j * kBlock + threadIdx.x;
+      bool won = false;
+      int32_t v = 0;
+      if (e < e1) {
+        int lo = klo, hi = S;
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (s_off[mid] <= e)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        klo = lo;
+        v = ci[s_base[lo] + (int64_t)e];
+        int32_t u = s_src[lo];
+        uint64_t bit = 1ull << (v & 63);
+        uint64_t *wp = vis + (v >> 6);
+        if (CLAIM == CLAIM_MIN) {
+          if (!(prev[v >> 6] & bit)) {
+            atomicMin((unsigned int *)(parent + v), (unsigned int)u);
+            if (!(*wp & bit)) {
+              won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
+              if (won) level[v] = next_level;
+            }
           }
+        } else if (!(*wp & bit)) {
+          if (CLAIM == CLAIM_OR) {
+            won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
+            if (won) parent[v] = u;
+          } else {
+            won = atomicCAS(parent + v, -1, u) == -1;
+            if (won) atomicOr((unsigned long long *)wp, (unsigned long long)bit);
+          }
+          if (won) level[v] = next_level;
         }
-      } else if (!(*wp & bit)) {
-        if (CLAIM == CLAIM_OR) {
-          won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
-          if (won) parent[v] = u;
-        } else {
-          won = atomicCAS(parent + v, -1, u) == -1;
-          if (won) atomicOr((unsigned long long *)wp, (unsigned long long)bit);
-        }
-        if (won) level[v] = next_level;
+      }
+      uint64_t bal = __ballot(won);
+      if (bal) {
+        uint32_t wbase = 0;
+        if (lane == 0) wbase = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
+        wbase = __shfl(wbase, 0, kWave);
+        if (won) s_out[wbase + __popcll(bal & lt)] = v;
       }
     }
-    uint64_t bal = __ballot(won);
-    if (bal) {
-      uint32_t wbase = 0;
-      if (lane == 0) wbase = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
-      wbase = __shfl(wbase, 0, kWave);
-      if (won) s_out[wbase + __popcll(bal & lt)] = v;
+    __syncthreads();
+    const uint32_t cnt = s_cnt;
+    if (cnt) {
+      if (threadIdx.x == 0) s_gbase = atomicAdd(qn_len, (unsigned long long)cnt);
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
+        const int32_t v = s_out[k];
+        uint32_t be[2];
+        __builtin_memcpy(be, rp + v, 8);
+        const uint32_t d = be[1] - be[0];
+        qn[s_gbase + k] = v;
+        qdn[s_gbase + k] = d;
+      }
     }
+    __syncthreads();  // the shared arrays are reused by the next tile
   }
-  __syncthreads();
-  const uint32_t cnt = s_cnt;
-  if (cnt == 0) return;
-  if (threadIdx.x == 0) s_gbase = atomicAdd(qn_len, (unsigned long long)cnt);
-  __syncthreads();
-  for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) qn[s_gbase + k] = s_out[k];
 }
 
 // Frontier bitmap of the last top-down level without atomics: the vertices
 // visited now but not before that level's expansion.
 __global__ void k_front_from_vis(const uint64_t *__restrict__ vis,
                                  const uint64_t *__restrict__ prev, uint64_t *__restrict__ front,
-                                 int64_t words) {
+                                 int64_t words, unsigned long long *__restrict__ ctr, int64_t nf) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_NFIN] = (unsigned long long)nf;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
     front[i] = vis[i] & ~prev[i];
@@ -697,16 +758,26 @@ __device__ __forceinline__ void bu_chunks(
 
 // Adds the workgroup's discoveries and takes a ticket in the same 64-bit
 // atomic (count in the low 40 bits, finished workgroups above), so the last
-// workgroup knows the total without a memory fence; it publishes the counters
-// to the host and resets them for the next bottom-up step.  The accounting
-// counters of COUNT_BYTES runs live at other addresses and are fenced.
+// workgroup knows the total without a memory fence.  That workgroup takes the
+// next level's direction decision (the rule the host applies to the published
+// counters: back to top-down when n_f < n / beta and the frontier shrank;
+// ctr[C_BUGO] = 1 lets an already queued next bottom-up step run), publishes
+// the counters to the host and resets them for the next bottom-up step.  The
+// accounting counters of COUNT_BYTES runs live at other addresses and are
+// fenced.
 constexpr int kTicketShift = 40;
+
+struct BuNext {
+  int dirmode;
+  double beta;
+  int64_t n;
+};
 
 template <int NT, bool ACCT>
 __device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
                                          unsigned long long *__restrict__ ctr,
                                          unsigned long long *__restrict__ host,
-                                         unsigned long long seq) {
+                                         unsigned long long seq, const BuNext &nx) {
   __shared__ unsigned long long s_old;
   const uint64_t tn = block_sum<NT, uint64_t>(c.nnew, s);
   uint64_t ts = 0, tu = 0, tr = 0, th = 0;
@@ -731,7 +802,14 @@ __device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
   if ((old >> kTicketShift) + 1 == gridDim.x && threadIdx.x == 0) {
     if (ACCT) __threadfence();
     // the counters without the ticket bits, as the host reads them
-    atomicExch(ctr + C_NNEW, (old & ((1ull << kTicketShift) - 1)) + tn);
+    const uint64_t nnew = (old & ((1ull << kTicketShift) - 1)) + tn;
+    const uint64_t nf_in = ctr[C_NFIN];
+    const bool to_td = nx.dirmode == G5_DIR_TOPDOWN ||
+                       (nx.dirmode == G5_DIR_AUTO && (double)nnew < (double)nx.n / nx.beta &&
+                        nnew < nf_in);
+    ctr[C_BUGO] = (nnew > 0 && !to_td) ? 1ull : 0ull;
+    ctr[C_NFIN] = nnew;
+    atomicExch(ctr + C_NNEW, nnew);
     publish(ctr, host, seq);
     atomicExch(ctr + C_NNEW, 0ull);
     if (ACCT) {
@@ -755,8 +833,9 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
     int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words,
     int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
-    unsigned long long *__restrict__ host, unsigned long long seq) {
+    unsigned long long *__restrict__ host, unsigned long long seq, bool check_go, BuNext bn) {
   extern __shared__ uint64_t s_fh[];
+  if (check_go && !ctr[C_BUGO]) return;  // queued ahead; the last step chose top-down
   __shared__ uint64_t s[kBuBlock / kWave];
   __shared__ int64_t s_base[kBuBlock];
   __shared__ int32_t s_row[kBuBlock];
@@ -770,7 +849,7 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
   bu_chunks<LANE_SCAN, R, ACCT>(FrontGlobal{(const uint32_t *)front}, s_fh, rp, ci, hint, hint_id, vis, next,
                                 parent, level, words, next_level, packed, gw, nw, s_base, s_row,
                                 s_first, s_nx, c);
-  bu_flush<kBuBlock, ACCT>(c, s, ctr, host, seq);
+  bu_flush<kBuBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
 
 // Bottom-up step with the frontier summary staged in LDS as well (dynamic
@@ -790,7 +869,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
     int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words,
     int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
     const uint32_t *__restrict__ sum, int64_t sum_words, int gs,
-    unsigned long long *__restrict__ host, unsigned long long seq) {
+    unsigned long long *__restrict__ host, unsigned long long seq, BuNext bn) {
   extern __shared__ uint64_t s_dyn[];
   uint32_t *s_sum = reinterpret_cast<uint32_t *>(s_dyn);
   uint64_t *s_fh = s_dyn + (sum_words + 1) / 2;
@@ -808,7 +887,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
   bu_chunks<LANE_SCAN, R, ACCT>(FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, vis,
                                 next, parent, level, words, next_level, packed, gw, nw, s_base,
                                 s_row, s_first, s_nx, c);
-  bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq);
+  bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
 
 // After a traversal whose parent array was pre-filled with hint targets: the
@@ -854,7 +933,8 @@ __global__ void k_front_summary(const uint64_t *__restrict__ front, int64_t word
   }
 }
 
-// Bitmap -> queue in vertex order: block b owns words [b*chunk, (b+1)*chunk).
+// Bitmap -> queue in vertex order, with each entry's degree:
+// block b owns words [b*chunk, (b+1)*chunk).
 __global__ __launch_bounds__(kBlock) void k_front_count(const uint64_t *__restrict__ bm,
                                                         int64_t words, int64_t chunk,
                                                         uint32_t *__restrict__ bsum) {
@@ -869,7 +949,9 @@ __global__ __launch_bounds__(kBlock) void k_front_count(const uint64_t *__restri
 __global__ __launch_bounds__(kBlock) void k_front_write(const uint64_t *__restrict__ bm,
                                                         int64_t words, int64_t chunk,
                                                         const uint32_t *__restrict__ boff,
-                                                        int32_t *__restrict__ q) {
+                                                        int32_t *__restrict__ q,
+                                                        uint32_t *__restrict__ qd,
+                                                        const uint32_t *__restrict__ rp) {
   __shared__ uint32_t s[kBlock / kWave];
   int64_t b = (int64_t)blockIdx.x * chunk, e = std::min<int64_t>(b + chunk, words);
   uint32_t base = boff[blockIdx.x];
@@ -881,7 +963,11 @@ __global__ __launch_bounds__(kBlock) void k_front_write(const uint64_t *__restri
     while (x) {
       int bit = __ffsll((unsigned long long)x) - 1;
       x &= x - 1;
-      q[pos++] = (int32_t)(w * kWave + bit);
+      const int32_t v = (int32_t)(w * kWave + bit);
+      uint32_t be[2];
+      __builtin_memcpy(be, rp + v, 8);
+      q[pos] = v;
+      qd[pos++] = be[1] - be[0];
     }
     base += tot;
   }
@@ -939,7 +1025,8 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   A((void **)&w->snap[1], W * 8);
   A((void **)&w->q[0], n * 4);
   A((void **)&w->q[1], n * 4);
-  A((void **)&w->qoff, (n + 1) * 4);
+  A((void **)&w->qoff[0], (n + 1) * 4);
+  A((void **)&w->qoff[1], (n + 1) * 4);
   A((void **)&w->bsum, std::max(nb, nbf) * 4);
   A((void **)&w->ctr, C_NCTR * 8);
   if (g->num_hot > 0) A((void **)&w->fh, ((g->num_hot + 63) / 64) * 8);
@@ -953,9 +1040,10 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
     A((void **)&w->sum, ((w->sum_words + 1) / 2) * 8);
   }
   if (e == hipSuccess)
-    e = hipHostMalloc((void **)&w->host_pub, 32 * 8, hipHostMallocMapped | hipHostMallocCoherent);
+    e = hipHostMalloc((void **)&w->host_pub, kPubBufs * kPubSlots * 8,
+                      hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) {
-    std::memset(w->host_pub, 0, 32 * 8);
+    std::memset(w->host_pub, 0, kPubBufs * kPubSlots * 8);
     e = hipHostGetDevicePointer((void **)&w->host_pub_dev, w->host_pub, 0);
   }
   if (e != hipSuccess) {
@@ -990,7 +1078,8 @@ BfsWork::~BfsWork() {
   if (fh) (void)hipFree(fh);
   if (q[0]) (void)hipFree(q[0]);
   if (q[1]) (void)hipFree(q[1]);
-  if (qoff) (void)hipFree(qoff);
+  for (auto *p : qoff)
+    if (p) (void)hipFree(p);
   if (bsum) (void)hipFree(bsum);
   if (ctr) (void)hipFree(ctr);
   if (host_pub) (void)hipHostFree(host_pub);
@@ -1001,7 +1090,7 @@ BfsWork::~BfsWork() {
 // mapped host counters and copies their values to out[0, C_NPUB); falls back to
 // the stream's status so a failed launch cannot leave the host spinning.
 static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want, int64_t *out) {
-  volatile uint64_t *h = w.host_pub;
+  volatile uint64_t *h = w.host_pub + (want % kPubBufs) * kPubSlots;
   const uint64_t tag = want & 0xffff;
   auto ready = [&]() {
     for (int i = 0; i < C_NPUB; ++i)
@@ -1073,11 +1162,11 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const int bu_grid = ncu * bu_bpc;
   const int deg_grid = ncu * 8;
   if (timed && w.ev.empty()) {
-    w.ev.resize(4 * G5_MAX_STAT_LEVELS);
+    w.ev.resize(2 * G5_MAX_STAT_LEVELS);
     for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
   }
   auto ev_at = [&](int lv, int k) -> hipEvent_t {
-    return (timed && lv < G5_MAX_STAT_LEVELS) ? w.ev[4 * lv + k] : nullptr;
+    return (timed && lv < G5_MAX_STAT_LEVELS) ? w.ev[2 * lv + k] : nullptr;
   };
   auto rec = [&](int lv, int k) -> g5_status {
     if (hipEvent_t e = ev_at(lv, k)) G5_HIP(hipEventRecord(e, s));
@@ -1098,122 +1187,85 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                      dim3(kBlock), 0, s, level, parent, n, prefill ? g->hint_id : nullptr, w.vis,
                      w.snap[0], w.snap[1], g->iso, W,
                      (((uintptr_t)level | (uintptr_t)parent) & 15) == 0);
-  hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, root, level, parent, w.vis, w.q[0], ctr,
-                     g->row_ptr);
+  hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, root, level, parent, w.vis, w.q[0],
+                     w.qoff[0], ctr, g->row_ptr, g->nnz);
   G5_LAUNCH_CHECK();
 
   int cur = 0;                // queue holding the current frontier (top-down)
-  int64_t qlen = 1;
-  // m_u: directed entries of vertices not yet discovered by a top-down level (an
-  // upper bound on the unvisited vertices' edges once bottom-up levels ran; the
-  // switch back to bottom-up also needs a growing frontier)
-  int64_t m_u = -1;
-  bool first = true;
   bool q_from_bu = false;     // the queue was filled from a bottom-up bitmap
   int dir = 1;                // 1 top-down, 2 bottom-up
-  int64_t nf_prev = 0;
+  int64_t nf_prev = 0;        // input frontier size of the bottom-up step
   int64_t last_nf = 0;        // frontier size of the previous level
   int32_t lvl = 0;
   int64_t reached = 1;
-  int td_stat = -1;           // stats slot of the last top-down level (discoveries pending)
+  bool bu_queued = false;     // this level's bottom-up step was queued ahead (sequence bu_seq)
+  unsigned long long bu_seq = 0;
+  // top-down: level lvl's kernels are queued and its scan publishes its
+  // direction under dec_seq
+  unsigned long long dec_seq = 0;
   uint64_t *front = w.front, *next = w.next;
   if (stats) *stats = g5_bfs_stats{};
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
+  const BuNext bn{p.direction, beta, n};
+  const int32_t *hint = use_hint ? g->hint : nullptr;
+  const int32_t *hint_id = prefill ? nullptr : g->hint_id;
+  const int64_t fh_words = use_hint ? (g->num_hot + 63) / 64 : 0;
+  // expansion grid: the workgroups that fit at once (tiles then advance as one
+  // window over the frontier's edges), unless set
+  const int td_per_cu =
+      p.td_blocks_per_cu > 0
+          ? p.td_blocks_per_cu
+          : resident_per_cu(min_parent ? (const void *)&k_td_expand<CLAIM_MIN>
+                                       : (p.claim == CLAIM_CAS ? (const void *)&k_td_expand<CLAIM_CAS>
+                                                               : (const void *)&k_td_expand<CLAIM_OR>),
+                            kBlock, 0);
+  const int td_grid = ncu * td_per_cu;
 
-  while (true) {
-    if (dir == 1) {
-      // degree prefix sum of the frontier queue (+ visited snapshot), then publish
-      G5_REC(lvl, 0);
-      hipLaunchKernelGGL(k_td_deg, dim3(deg_grid), dim3(kBlock), 0, s, w.q[cur],
-                         (const unsigned long long *)(ctr + C_QLEN0 + cur), g->rp32, w.qoff,
-                         w.bsum, w.snap[lvl & 1], w.vis, W);
-      hipLaunchKernelGGL(k_td_scan, dim3(1), dim3(kScanBlock), 0, s, w.bsum, ctr, cur, hpub,
-                         (unsigned long long)++w.seq);
-      G5_LAUNCH_CHECK();
-      G5_REC(lvl, 1);
-      {
-        g5_status st = wait_published(w, s, w.seq, hc);
-        if (st != G5_OK) return st;
-      }
-      if (hc[C_ERR]) {
-        set_error("g5_bfs: top-down tile met more frontier rows than edges");
-        return G5_EDEVICE;
-      }
-      qlen = (int64_t)hc[C_QLEN0 + cur];
-      const int64_t mf = (int64_t)hc[C_MF];
-      if (td_stat >= 0) stats->discovered[td_stat] = qlen;
-      if (!first && !q_from_bu) reached += qlen;
-      if (qlen == 0) break;
-      if (first) {
-        m_u = g->nnz - (int64_t)hc[C_RDEG];
-        first = false;
-      } else {
-        m_u -= mf;
-      }
-      q_from_bu = false;
-      const bool growing = qlen > last_nf;
-      const bool to_bu = (p.direction == G5_DIR_BOTTOMUP) ||
-                         (p.direction == G5_DIR_AUTO && growing && (double)mf > (double)m_u / alpha);
-      if (to_bu) {
-        // frontier bitmap = visited now, not visited before the last expansion
-        hipLaunchKernelGGL(k_front_from_vis, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
-                           s, w.vis, w.snap[(lvl + 1) & 1], front, W);
-        G5_LAUNCH_CHECK();
-        dir = 2;
-        nf_prev = qlen;
-        td_stat = -1;
-        continue;  // this level runs bottom-up
-      }
-      const int nxt = cur ^ 1;
-      G5_REC(lvl, 2);
-      if (mf > 0) {
-        const int64_t tb = (mf + kTdTile - 1) / kTdTile;
-#define G5_TD(C)                                                                            \
-  hipLaunchKernelGGL(k_td_expand<C>, dim3(tb), dim3(kBlock), 0, s, w.q[cur], qlen, w.qoff,   \
-                     w.bsum, (uint32_t)mf, g->rp32, g->col_idx, w.vis, w.snap[lvl & 1],       \
-                     parent, level, w.q[nxt], ctr + C_QLEN0 + nxt, lvl + 1, ctr + C_ERR)
-        if (min_parent)
-          G5_TD(CLAIM_MIN);
-        else if (p.claim == CLAIM_CAS)
-          G5_TD(CLAIM_CAS);
-        else
-          G5_TD(CLAIM_OR);
+  // Top-down level lv from queue slot c: degree pass (+ visited snapshot), chunk
+  // scan with the level's direction decision (published under sq), expansion
+  // (runs only if the level stays top-down).  Queued ahead behind a level that
+  // did not expand, the level's queue is empty and nothing happens.
+  auto launch_td = [&](int32_t lv, int c, unsigned long long sq) -> g5_status {
+    const int nx = c ^ 1;
+    {
+      g5_status st_ = rec(lv, 0);
+      if (st_ != G5_OK) return st_;
+    }
+    hipLaunchKernelGGL(k_td_deg, dim3(deg_grid), dim3(kBlock), 0, s,
+                       (const unsigned long long *)ctr, c, w.qoff[c], w.bsum, w.snap[lv & 1],
+                       w.vis, W);
+    hipLaunchKernelGGL(k_td_scan, dim3(1), dim3(kScanBlock), 0, s, w.bsum, ctr, c, lv,
+                       p.direction, alpha, hpub, sq);
+#define G5_TD(C)                                                                             \
+  hipLaunchKernelGGL(k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c],    \
+                     w.bsum, ctr, c, g->rp32, g->col_idx, w.vis, w.snap[lv & 1], parent, level, \
+                     w.q[nx], w.qoff[nx], lv + 1)
+    if (min_parent)
+      G5_TD(CLAIM_MIN);
+    else if (p.claim == CLAIM_CAS)
+      G5_TD(CLAIM_CAS);
+    else
+      G5_TD(CLAIM_OR);
 #undef G5_TD
-        G5_LAUNCH_CHECK();
-      }
-      G5_REC(lvl, 3);
-      if (slot() >= 0) {
-        const int i = slot();
-        stats->dir[i] = 1;
-        stats->frontier[i] = qlen;
-        stats->edges[i] = mf;
-        td_stat = i;
-      } else {
-        td_stat = -1;
-      }
-      cur = nxt;
-      last_nf = qlen;
-      ++lvl;
-    } else {
-      if (acct && slot() >= 0) stats->dir[slot()] = 2;
-      const bool use_lds = w.sum && !(p.flags & G5_FLAG_NO_LDS) &&
-                           (double)nf_prev * (double)(1ll << std::min(lds_gs, 62)) <
-                               lds_density * (double)n;
-      if (use_lds) {
-        ++lds_levels;
-        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for((lds_words + 1) / 2, kBlock, ncu * 16)),
-                           dim3(kBlock), 0, s, (uint64_t *)w.sum, (lds_words + 1) / 2);
-        hipLaunchKernelGGL(k_front_summary, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
-                           s, front, W, lds_gs, w.sum);
-      }
-      const int32_t *hint = use_hint ? g->hint : nullptr;
-      const int32_t *hint_id = prefill ? nullptr : g->hint_id;
-      const int64_t fh_words = use_hint ? (g->num_hot + 63) / 64 : 0;
-      if (fh_words)
-        hipLaunchKernelGGL(k_fh_build, dim3(grid_for(g->num_hot, kBlock, ncu * 8)), dim3(kBlock),
-                           0, s, front, g->hot, g->num_hot, w.fh);
-      G5_REC(lvl, 0);
-      const unsigned long long sq = ++w.seq;
+    G5_LAUNCH_CHECK();
+    return rec(lv, 1);
+  };
+
+  auto launch_bu = [&](int32_t lv, const uint64_t *f, uint64_t *nfp, bool lds, bool check,
+                       unsigned long long sq) -> g5_status {
+    if (lds) {
+      hipLaunchKernelGGL(k_zero_u64, dim3(grid_for((lds_words + 1) / 2, kBlock, ncu * 16)),
+                         dim3(kBlock), 0, s, (uint64_t *)w.sum, (lds_words + 1) / 2);
+      hipLaunchKernelGGL(k_front_summary, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
+                         s, f, W, lds_gs, w.sum);
+    }
+    if (fh_words)
+      hipLaunchKernelGGL(k_fh_build, dim3(grid_for(g->num_hot, kBlock, ncu * 8)), dim3(kBlock),
+                         0, s, f, g->hot, g->num_hot, w.fh);
+    {
+      g5_status st_ = rec(lv, 0);
+      if (st_ != G5_OK) return st_;
+    }
 #define G5_BUL(K, P, A)                                                                     \
   do {                                                                                      \
     const void *fn_ = (const void *)&k_bu_step_lds<K, P, A>;                                 \
@@ -1222,9 +1274,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     if (st_ != G5_OK) return st_;                                                           \
     const int per_cu_ = resident_per_cu(fn_, kLdsBlock, dyn_);                              \
     hipLaunchKernelGGL((k_bu_step_lds<K, P, A>), dim3(ncu * per_cu_), dim3(kLdsBlock), dyn_, s, \
-                       g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words, w.vis, front, next, \
-                       parent, level, W, lvl + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub,  \
-                       sq);                                                                 \
+                       g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words, w.vis, f, nfp,     \
+                       parent, level, W, lv + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub,   \
+                       sq, bn);                                                             \
   } while (0)
 #define G5_BU(K, P, A)                                                                      \
   do {                                                                                      \
@@ -1235,8 +1287,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     const int per_cu_ = resident_per_cu(fn_, kBuBlock, dyn_);                               \
     hipLaunchKernelGGL((k_bu_step<K, P, A>), dim3(ncu * std::min(bu_bpc, per_cu_)),         \
                        dim3(kBuBlock), dyn_, s, g->rp32, g->col_idx, hint, hint_id, w.fh,      \
-                       fh_words, w.vis, front, next, parent, level, W, lvl + 1, ctr, packed,   \
-                       hpub, sq);                                                           \
+                       fh_words, w.vis, f, nfp, parent, level, W, lv + 1, ctr, packed, hpub,  \
+                       sq, check, bn);                                                      \
   } while (0)
 #define G5_BU_P(M, K, A)          \
   if (vpl == 2)                   \
@@ -1251,66 +1303,143 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     case 16: G5_BU_P(M, 16, A); break;  \
     default: G5_BU_P(M, 4, A); break;   \
   }
-      if (use_lds) {
-        if (acct) {
-          G5_BU_K(G5_BUL, true);
-        } else {
-          G5_BU_K(G5_BUL, false);
-        }
+    if (lds) {  // never queued ahead
+      if (acct) {
+        G5_BU_K(G5_BUL, true);
       } else {
-        if (acct) {
-          G5_BU_K(G5_BU, true);
-        } else {
-          G5_BU_K(G5_BU, false);
-        }
+        G5_BU_K(G5_BUL, false);
       }
+    } else {
+      if (acct) {
+        G5_BU_K(G5_BU, true);
+      } else {
+        G5_BU_K(G5_BU, false);
+      }
+    }
 #undef G5_BU_K
 #undef G5_BU_P
 #undef G5_BU
 #undef G5_BUL
-      G5_LAUNCH_CHECK();
-      G5_REC(lvl, 1);
+    G5_LAUNCH_CHECK();
+    return rec(lv, 1);
+  };
+
+  // the root's level
+  dec_seq = ++w.seq;
+  {
+    g5_status st = launch_td(0, 0, dec_seq);
+    if (st != G5_OK) return st;
+  }
+  while (true) {
+    if (dir == 1) {
+      // level lvl's kernels are queued; queue level lvl + 1's behind them (they
+      // run only if level lvl + 1 stays top-down), then read level lvl's decision
+      const int nxt = cur ^ 1;
+      const unsigned long long spec_seq = ++w.seq;
       {
-        g5_status st = wait_published(w, s, sq, hc);
+        g5_status st = launch_td(lvl + 1, nxt, spec_seq);
         if (st != G5_OK) return st;
       }
-      const int64_t nnew = (int64_t)hc[C_NNEW];
+      {
+        g5_status st = wait_published(w, s, dec_seq, hc);
+        if (st != G5_OK) return st;
+      }
+      if (hc[C_ERR]) {
+        set_error("g5_bfs: top-down tile met more frontier rows than edges");
+        return G5_EDEVICE;
+      }
+      const int64_t qlen = hc[C_QLEN0 + cur];
+      const int64_t mf = hc[C_MF];
+      if (lvl > 0 && !q_from_bu) {  // the previous top-down level's discoveries
+        reached += qlen;
+        if (lvl - 1 < G5_MAX_STAT_LEVELS && stats) stats->discovered[lvl - 1] = qlen;
+      }
+      if (qlen == 0) break;  // the queued kernels do nothing
+      q_from_bu = false;
+      if (!hc[C_GO]) {
+        // bottom-up from here: frontier bitmap = visited now, not visited
+        // before the last expansion
+        hipLaunchKernelGGL(k_front_from_vis, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
+                           s, w.vis, w.snap[(lvl + 1) & 1], front, W, ctr, qlen);
+        G5_LAUNCH_CHECK();
+        dir = 2;
+        nf_prev = qlen;
+        continue;  // this level runs bottom-up
+      }
+      if (slot() >= 0) {
+        const int i = slot();
+        stats->dir[i] = 1;
+        stats->frontier[i] = qlen;
+        stats->edges[i] = mf;
+      }
+      dec_seq = spec_seq;
+      cur = nxt;
+      last_nf = qlen;
+      ++lvl;
+    } else {
+      if (!bu_queued) {
+        const bool use_lds = w.sum && !(p.flags & G5_FLAG_NO_LDS) &&
+                             (double)nf_prev * (double)(1ll << std::min(lds_gs, 62)) <
+                                 lds_density * (double)n;
+        if (use_lds) ++lds_levels;
+        bu_seq = ++w.seq;
+        g5_status st = launch_bu(lvl, front, next, use_lds, false, bu_seq);
+        if (st != G5_OK) return st;
+      }
+      // queue the next level's step too; it runs only if this one chooses
+      // bottom-up again
+      const unsigned long long spec_seq = ++w.seq;
+      {
+        g5_status st = launch_bu(lvl + 1, next, front, false, true, spec_seq);
+        if (st != G5_OK) return st;
+      }
+      {
+        g5_status st = wait_published(w, s, bu_seq, hc);
+        if (st != G5_OK) return st;
+      }
+      const int64_t nnew = hc[C_NNEW];
       if (slot() >= 0) {
         const int i = slot();
         stats->dir[i] = 2;
         stats->frontier[i] = nf_prev;
         stats->discovered[i] = nnew;
         if (acct) {
-          stats->edges[i] = (int64_t)hc[C_SCAN];
+          stats->edges[i] = hc[C_SCAN];
           // parent is not written for hint hits when it was pre-filled
-          const int64_t pw = prefill ? nnew - (int64_t)hc[C_HINT] : nnew;
-          stats->bytes[i] = (use_hint ? 4 : 0) * (int64_t)hc[C_UNVIS] +
-                            4 * (int64_t)hc[C_ROWS] + 4 * (int64_t)hc[C_SCAN] + 16 * W +
-                            4 * nnew + 4 * pw;
+          const int64_t pw = prefill ? nnew - hc[C_HINT] : nnew;
+          stats->bytes[i] = (use_hint ? 4 : 0) * hc[C_UNVIS] + 4 * hc[C_ROWS] +
+                            4 * hc[C_SCAN] + 16 * W + 4 * nnew + 4 * pw;
         }
       }
       reached += nnew;
       last_nf = nf_prev;
       ++lvl;
-      if (nnew == 0) break;
-      const bool to_td = p.direction == G5_DIR_TOPDOWN ||
-                         (p.direction == G5_DIR_AUTO && (double)nnew < (double)n / beta &&
-                          nnew < nf_prev);
+      if (nnew == 0) break;  // the queued step does nothing
       nf_prev = nnew;
       std::swap(front, next);  // `front` now holds the new frontier
-      if (to_td) {
-        const int64_t chunk = (W + bu_grid - 1) / bu_grid;
-        const int fb = (int)((W + chunk - 1) / chunk);
-        hipLaunchKernelGGL(k_front_count, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum);
-        hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, s, w.bsum, (int64_t)fb,
-                           ctr + C_QLEN0 + cur);
-        hipLaunchKernelGGL(k_front_write, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum,
-                           w.q[cur]);
-        G5_LAUNCH_CHECK();
-        qlen = nnew;
-        q_from_bu = true;
-        dir = 1;
+      if (hc[C_BUGO]) {        // the queued step is this level's
+        bu_queued = true;
+        bu_seq = spec_seq;
+        continue;
       }
+      // top-down from here: bitmap -> queue (with degrees), the level's
+      // decision, and its kernels
+      bu_queued = false;
+      const int64_t chunk = (W + bu_grid - 1) / bu_grid;
+      const int fb = (int)((W + chunk - 1) / chunk);
+      hipLaunchKernelGGL(k_front_count, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum);
+      hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, s, w.bsum, (int64_t)fb,
+                         ctr + C_QLEN0 + cur, ctr + C_LASTNF, (unsigned long long)last_nf);
+      hipLaunchKernelGGL(k_front_write, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum,
+                         w.q[cur], w.qoff[cur], g->rp32);
+      G5_LAUNCH_CHECK();
+      dec_seq = ++w.seq;
+      {
+        g5_status st = launch_td(lvl, cur, dec_seq);
+        if (st != G5_OK) return st;
+      }
+      q_from_bu = true;
+      dir = 1;
     }
   }
 #undef G5_REC
@@ -1335,14 +1464,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                             12 * stats->discovered[i];
     if (timed)
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i) {
-        float a = 0, b = 0;
-        if (stats->dir[i] == 1) {
-          G5_HIP(hipEventElapsedTime(&a, w.ev[4 * i], w.ev[4 * i + 1]));
-          G5_HIP(hipEventElapsedTime(&b, w.ev[4 * i + 2], w.ev[4 * i + 3]));
-        } else {
-          G5_HIP(hipEventElapsedTime(&a, w.ev[4 * i], w.ev[4 * i + 1]));
-        }
-        stats->step_ms[i] = a + b;
+        float a = 0;
+        G5_HIP(hipEventElapsedTime(&a, w.ev[2 * i], w.ev[2 * i + 1]));
+        stats->step_ms[i] = a;
       }
   }
   return G5_OK;
