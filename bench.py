@@ -93,20 +93,34 @@ def _pmc_rows(d):
         return list(csv.DictReader(f))
 
 
-def _per_dispatch(rows, counter, match, largest=False):
+def _per_dispatch(rows, counter, match, largest=False, min_kib=0.0):
     """Average (or, with largest, maximum) of `counter` (KiB) over dispatches
-    whose kernel name satisfies match."""
+    whose kernel name satisfies match and whose value exceeds min_kib."""
     per = {}
     for r in rows:
         if r.get("Counter_Name") != counter or not match(r.get("Kernel_Name", "")):
             continue
         key = r.get("Dispatch_Id") or r.get("Correlation_Id")
         per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    per = {k: v for k, v in per.items() if v > min_kib}
     if not per:
         raise SystemExit(f"no {counter} samples for the requested kernel")
     if largest:
         return max(per.values()), 1
     return sum(per.values()) / len(per), len(per)
+
+
+def is_bu_step(name):
+    """The bottom-up step kernels of timed runs (with or without the LDS-staged
+    summary; not the byte-counting variants)."""
+    return ("k_bu_step<" in name or "k_bu_step_lds<" in name) and "true>" not in name
+
+
+# A bottom-up step queued ahead of the host's decision exits at once when the
+# level turns top-down; such dispatches move no data (a working one at least
+# reads and writes the visited and next-frontier words).
+NOOP_KIB = 1024.0
+NOOP_US = 10.0
 
 
 def reduce_pmc(fetch_dir, write_dir, kernel, workload, command):
@@ -116,12 +130,12 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command):
     so the bench reports it only while the kernel is unchanged."""
     # the copy probe: torch's elementwise add over 2 GiB, the largest such dispatch
     is_copy = lambda name: "elementwise_kernel" in name and "_add<long>" in name
-    is_k = lambda name: (kernel + "<") in name and "true>" not in name
+    assert kernel == "k_bu_step", "counters are reduced for the bottom-up step"
     fr, wr = _pmc_rows(fetch_dir), _pmc_rows(write_dir)
     copy_f, _ = _per_dispatch(fr, "FETCH_SIZE", is_copy, largest=True)
     copy_w, _ = _per_dispatch(wr, "WRITE_SIZE", is_copy, largest=True)
-    k_f, nf = _per_dispatch(fr, "FETCH_SIZE", is_k)
-    k_w, nw = _per_dispatch(wr, "WRITE_SIZE", is_k)
+    k_f, nf = _per_dispatch(fr, "FETCH_SIZE", is_bu_step, min_kib=NOOP_KIB)
+    k_w, nw = _per_dispatch(wr, "WRITE_SIZE", is_bu_step, min_kib=NOOP_KIB)
     f_factor = COPY_PROBE_BYTES / (copy_f * 1024)
     w_factor = COPY_PROBE_BYTES / (copy_w * 1024)
     rec = {"source_hash": source_hash(BFS_SOURCES),
@@ -139,6 +153,48 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command):
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     print(json.dumps(rec))
+
+
+def summarize_trace(db, command, bench_json=None):
+    """Markdown summary of a rocprofv3 kernel trace (its SQLite database): the
+    busiest kernels, and the bottom-up step's average over working launches,
+    which is what the bench's avg_launch_ms measures with HIP events."""
+    import re
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = list(c.execute("select name, start, end from kernels"))
+
+    def short(n):
+        n = n.replace("g5::(anonymous namespace)::", "").replace("void ", "")
+        return re.sub(r"\(.*$", "", n)[:60]
+
+    agg = {}
+    for name, t0, t1 in rows:
+        a = agg.setdefault(short(name), [0, 0.0])
+        a[0] += 1
+        a[1] += (t1 - t0) / 1e3
+    total = sum(a[1] for a in agg.values())
+    out = ["# Kernel trace: scale-26 single-root BFS benchmark", "",
+           "Command (from the repository root on the GPU box):", "", "```", command, "```", "",
+           "Durations are rocprofv3 kernel-trace dispatch times (microseconds), over the",
+           "whole command (graph generation and CSR build, accounting pass, warm-up and",
+           "timed steps, and any batch run or probe it includes).", "",
+           "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:24]:
+        out.append(f"| `{k}` | {n} | {t:.1f} | {t / n:.2f} | {100 * t / total:.1f} |")
+    bu = [(t1 - t0) / 1e3 for name, t0, t1 in rows if is_bu_step(name)]
+    work = [d for d in bu if d > NOOP_US]
+    out += ["", "## Bottom-up step (k_bu_step and k_bu_step_lds, timed variants)", "",
+            f"* dispatches: {len(bu)}, of which {len(bu) - len(work)} are steps queued ahead "
+            f"that exited at once (< {NOOP_US:.0f} us)",
+            f"* working dispatches: {len(work)}, average {sum(work) / max(len(work), 1):.2f} us"]
+    if bench_json:
+        with open(bench_json) as f:
+            line = [l for l in f if l.startswith("{")][-1]
+        r = json.loads(line)["roofline"]
+        out.append(f"* the same run's bench line: kernel {r['kernel']}, {r['launches']} timed "
+                   f"launches, avg_launch_ms {r['avg_launch_ms']} (HIP events)")
+    print("\n".join(out))
 
 
 def run_gpu(args):
@@ -357,7 +413,14 @@ def main():
     ap.add_argument("--reduce-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--pmc-command", default="", help="command recorded with --reduce-pmc")
+    ap.add_argument("--summarize-trace", nargs="+", metavar=("DB", "BENCH_JSON"),
+                    help="print a markdown summary of a rocprofv3 kernel-trace database")
+    ap.add_argument("--trace-command", default="", help="command recorded with --summarize-trace")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace[0], args.trace_command,
+                        args.summarize_trace[1] if len(args.summarize_trace) > 1 else None)
+        return
     if args.reduce_pmc:
         reduce_pmc(args.reduce_pmc[0], args.reduce_pmc[1], "k_bu_step", f"s{args.scale}",
                    args.pmc_command)
