@@ -111,14 +111,15 @@ typedef struct {
 #define G5_FLAG_TIME_STEPS 1
 /* Count the algorithmic bytes and edges of each level (slower kernels; use in
  * an untimed run).  Bytes per level:
- *   top-down   12 per frontier vertex (queue entry + two 32-bit row offsets)
- *              + 4 per frontier edge + 12 per discovered vertex (level, parent,
- *              queue entry);
+ *   top-down   12 per frontier vertex (queue entry, its degree/offset word, its
+ *              row start) + 4 per frontier edge + 24 per discovered vertex
+ *              (level, parent, queue entry, its degree and its two row offsets);
  *   bottom-up  4 per unvisited non-isolated vertex (its neighbour hint) + 4 per
  *              vertex whose hint missed (its 32-bit row offset) + 4 per row
  *              entry read up to the first frontier hit + n/4 (visited words
- *              read, next-frontier words written) + 8 per discovered vertex
- *              (level, parent).
+ *              read, next-frontier words written) + 4 per discovered vertex
+ *              (level) + 4 per parent written (a hint hit writes none when the
+ *              parent array was pre-filled with the hint targets).
  * Frontier-bitmap probes (one per examined neighbour) are not counted. */
 #define G5_FLAG_COUNT_BYTES 2
 /* Do not test each vertex's highest-degree neighbour (built by g5_build_csr)

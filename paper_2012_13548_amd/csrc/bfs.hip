@@ -1461,7 +1461,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i)
         if (stats->dir[i] == 1)
           stats->bytes[i] = 12 * stats->frontier[i] + 4 * stats->edges[i] +
-                            12 * stats->discovered[i];
+                            24 * stats->discovered[i];
     if (timed)
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i) {
         float a = 0;
