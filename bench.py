@@ -112,8 +112,11 @@ def _per_dispatch(rows, counter, match, largest=False, min_kib=0.0):
 
 def is_bu_step(name):
     """The bottom-up step kernels of timed runs (with or without the LDS-staged
-    summary; not the byte-counting variants)."""
-    return ("k_bu_step<" in name or "k_bu_step_lds<" in name) and "true>" not in name
+    summary; not the byte-counting variants, whose third template argument is
+    true)."""
+    import re
+    m = re.search(r"k_bu_step(?:_lds)?<\d+, \d+, (true|false)", name)
+    return bool(m) and m.group(1) == "false"
 
 
 # A bottom-up step queued ahead of the host's decision exits at once when the
