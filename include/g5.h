@@ -105,6 +105,8 @@ typedef struct {
   int32_t bu_vertices_per_lane; /* bottom-up: unvisited vertices a lane works on at once: 1 or 2 */
   int32_t td_blocks_per_cu; /* top-down expansion grid: workgroups per compute unit (1..256) */
   int32_t reserved[2];
+  double gamma;           /* also top-down -> bottom-up when the frontier grew and m_f > gamma *
+                             (unvisited non-isolated vertices); 0 takes the default, < 0 disables */
 } g5_bfs_params;
 
 /* Time each level's step with HIP events on `stream` (step_ms in the stats). */
@@ -125,10 +127,9 @@ typedef struct {
 /* Do not test each vertex's highest-degree neighbour (built by g5_build_csr)
  * before its row in bottom-up steps. */
 #define G5_FLAG_NO_HINT 4
-/* g5_bfs_batch_ex: one plain launch per level instead of one cooperative
- * persistent launch (same results).  A persistent launch waits at grid-wide
- * barriers for all of its workgroups, so it should own the device; stepped
- * batches can overlap other work on other streams. */
+/* g5_bfs_batch_ex: one plain launch per level (the default; the flag is kept
+ * for callers that set it).  Stepped batches can overlap other work on other
+ * streams, and on MI355X they are also faster than the persistent launch. */
 #define G5_FLAG_STEPPED 8
 /* g5_bfs_ex: bottom-up rows left unresolved by a lane's own scan are packed end
  * to end across the wavefront (one entry per lane) instead of being scanned
@@ -145,6 +146,10 @@ typedef struct {
 /* g5_bfs_ex: bottom-up steps scan unresolved rows one row per 64-lane step
  * even where the tuned defaults pack them (G5_FLAG_PACKED forces packing). */
 #define G5_FLAG_ROWLOOP 128
+/* g5_bfs_batch_ex: every level in one cooperative persistent launch with a
+ * grid barrier per level (same results).  It waits at the barriers for all of
+ * its workgroups, so it should own the device. */
+#define G5_FLAG_PERSISTENT 512
 
 #define G5_MAX_STAT_LEVELS 64
 
@@ -193,8 +198,8 @@ typedef struct {
   double alpha;      /* top-down while m_f <= m_u / alpha (tuned default), where m_f is the degree
                         sum of vertices with a nonzero frontier mask and m_u the degree sum of
                         vertices not yet reached by every root */
-  int32_t flags;     /* G5_FLAG_TIME_STEPS: time the launch(es); G5_FLAG_STEPPED */
-  int32_t blocks_per_cu; /* persistent grid: workgroups per compute unit (capped by occupancy) */
+  int32_t flags;     /* G5_FLAG_TIME_STEPS: time the launch(es); G5_FLAG_PERSISTENT */
+  int32_t blocks_per_cu; /* grid: workgroups per compute unit (persistent: capped by occupancy) */
   int32_t reserved[4];
 } g5_batch_params;
 

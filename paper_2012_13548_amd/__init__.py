@@ -39,7 +39,7 @@ lib = ctypes.CDLL(LIB_PATH)
 
 
 FLAG_TIME_STEPS, FLAG_COUNT_BYTES, FLAG_NO_HINT, FLAG_STEPPED, FLAG_PACKED = 1, 2, 4, 8, 16
-FLAG_MIN_PARENT, FLAG_NO_LDS, FLAG_ROWLOOP = 32, 64, 128
+FLAG_MIN_PARENT, FLAG_NO_LDS, FLAG_ROWLOOP, FLAG_PERSISTENT = 32, 64, 128, 512
 
 
 class BfsParams(ctypes.Structure):
@@ -48,7 +48,8 @@ class BfsParams(ctypes.Structure):
                 ("lds_density", ctypes.c_double), ("claim", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("bu_blocks_per_cu", ctypes.c_int32),
                 ("lds_kb", ctypes.c_int32), ("bu_vertices_per_lane", ctypes.c_int32),
-                ("td_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("td_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+                ("gamma", ctypes.c_double)]
 
 
 _L = MAX_STAT_LEVELS
@@ -172,10 +173,11 @@ def build_csr(edges, n):
 
 
 def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None, lds_kb=None,
-            lds_density=None, vertices_per_lane=None, td_blocks_per_cu=None):
+            lds_density=None, vertices_per_lane=None, td_blocks_per_cu=None, gamma=None):
     p = BfsParams()
     p.bu_vertices_per_lane = vertices_per_lane or 0
     p.td_blocks_per_cu = td_blocks_per_cu or 0
+    p.gamma = gamma or 0.0
     p.direction = direction
     p.alpha = alpha or 0.0
     p.beta = beta or 0.0
@@ -191,7 +193,7 @@ def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None,
 def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta=None,
         lane_scan=None, claim=CLAIM_OR, hint=True, packed=None, min_parent=False, lds=True,
         blocks_per_cu=None, lds_kb=None, lds_density=None, vertices_per_lane=None,
-        td_blocks_per_cu=None, stats=False,
+        td_blocks_per_cu=None, gamma=None, stats=False,
         time_steps=False, count_bytes=False):
     """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
 
@@ -212,7 +214,7 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
              | {None: 0, True: FLAG_PACKED, False: FLAG_ROWLOOP}[packed]
              | (FLAG_MIN_PARENT if min_parent else 0) | (0 if lds else FLAG_NO_LDS))
     p = _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu, lds_kb,
-                lds_density, vertices_per_lane, td_blocks_per_cu)
+                lds_density, vertices_per_lane, td_blocks_per_cu, gamma)
     want = stats or time_steps or count_bytes
     st = BfsStats()
     _check(lib.g5_bfs_ex(csr.handle, int(root), parent.data_ptr(), level.data_ptr(),
@@ -230,9 +232,11 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
 
 
 def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=DIR_AUTO,
-              alpha=None, blocks_per_cu=None, stepped=False, stats=False, time_launch=False):
-    """Batched BFS from 1..64 roots in one persistent launch (``stepped=True``:
-    one plain launch per level, which may overlap other streams' work).
+              alpha=None, blocks_per_cu=None, stepped=True, persistent=False, stats=False,
+              time_launch=False):
+    """Batched BFS from 1..64 roots, one plain launch per level (these may
+    overlap other streams' work); ``persistent=True``: every level in one
+    cooperative launch.  ``stepped`` is accepted for older callers.
 
     Returns (parents int32 [k, n] or None, levels int8 [k, n]) and, with
     ``stats=True``, a dict of per-level directions and frontier sizes.
@@ -251,7 +255,8 @@ def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=
     p = BatchParams()
     p.direction = direction
     p.alpha = alpha or 0.0
-    p.flags = (FLAG_TIME_STEPS if time_launch else 0) | (FLAG_STEPPED if stepped else 0)
+    p.flags = ((FLAG_TIME_STEPS if time_launch else 0) | (FLAG_STEPPED if stepped else 0)
+               | (FLAG_PERSISTENT if persistent else 0))
     p.blocks_per_cu = blocks_per_cu or 0
     st = BatchStats()
     want = stats or time_launch

@@ -5,8 +5,8 @@ For each Kronecker scale, a coordinate search over
                workgroups per compute unit, packed row scan, the LDS budget and
                density threshold of the staged frontier; objective =
                harmonic-mean TEPS over sample roots (m_r / device time per call);
-  batch:       alpha and persistent-grid workgroups per compute unit;
-               objective = device time of one 64-root launch with parents.
+  batch:       alpha and workgroups per compute unit of its per-level launches;
+               objective = device time of one 64-root batch with parents.
 Writes ``tuning.json`` (every trial) and ``tuned_table.inc`` (the defaults table
 compiled into libg5; g5_build_csr picks the entry nearest to log2 n).
 
@@ -26,8 +26,9 @@ VPL = [1, 2]
 PACKED = [0, 1]
 LDS_KB = [32, 64, 96, 140]
 LDS_DENSITY = [0.01, 0.03, 0.1, 0.3, 1.0]
+GAMMA = [-1.0, 0.7, 1.0, 1.4, 2.0, 3.0]
 B_ALPHA = [2, 4, 8, 14, 28, 56, 112]
-B_BPC = [2, 4, 8]
+B_BPC = [2, 4, 8, 16, 32]
 
 
 def log(msg):
@@ -69,7 +70,7 @@ def tune_scale(scale, nroots, rounds):
                    lane_scan=cfg["lane_scan"], blocks_per_cu=cfg["bu_blocks_per_cu"],
                    vertices_per_lane=cfg["vertices_per_lane"],
                    packed=bool(cfg["packed"]), lds_kb=cfg["lds_kb"],
-                   lds_density=cfg["lds_density"])
+                   lds_density=cfg["lds_density"], gamma=cfg["gamma"])
             e1.record()
             torch.cuda.synchronize()
             inv += (e0.elapsed_time(e1) / 1e3) / m
@@ -94,13 +95,13 @@ def tune_scale(scale, nroots, rounds):
         return cfg, best
 
     t0 = time.time()
-    start = dict(alpha=20, beta=96, lane_scan=8, bu_blocks_per_cu=32, vertices_per_lane=1, packed=0,
-                 lds_kb=140, lds_density=0.03)
+    start = dict(alpha=20, beta=96, lane_scan=8, bu_blocks_per_cu=32, vertices_per_lane=1, packed=1,
+                 lds_kb=140, lds_density=0.3, gamma=-1.0)
     single(start)  # warm
     cfg, best = search(start, {"alpha": ALPHA, "beta": BETA, "lane_scan": LANE,
                                "bu_blocks_per_cu": BPC, "vertices_per_lane": VPL,
                                "packed": PACKED, "lds_kb": LDS_KB,
-                               "lds_density": LDS_DENSITY}, single)
+                               "lds_density": LDS_DENSITY, "gamma": GAMMA}, single)
     out = {"scale": scale, **cfg, "hmean_gteps": round(best / 1e9, 3), "roots": len(sample)}
 
     k = 64
@@ -132,7 +133,7 @@ def tune_scale(scale, nroots, rounds):
 
 def write_table(entries, path):
     lines = ["// Autotuned defaults: {scale, alpha, beta, lane_scan, bu_blocks_per_cu, vertices_per_lane,",
-             "// packed, lds_kb, lds_density, batch_alpha, batch_blocks_per_cu}.  Written by",
+             "// packed, lds_kb, lds_density, batch_alpha, batch_blocks_per_cu, gamma}.  Written by",
              "// paper_2012_13548_amd/autotune.py from its measurements (tuning.json); the",
              "// entry nearest to log2 n is used."]
     for e in sorted(entries, key=lambda x: x["scale"]):
@@ -140,7 +141,8 @@ def write_table(entries, path):
                      f"{e['lane_scan']}, {e['bu_blocks_per_cu']}, {e['vertices_per_lane']}, "
                      f"{int(e['packed'])}, "
                      f"{e['lds_kb']}, {float(e['lds_density']):.2f}, "
-                     f"{float(e['batch_alpha']):.1f}, {e['batch_blocks_per_cu']}}},")
+                     f"{float(e['batch_alpha']):.1f}, {e['batch_blocks_per_cu']}, "
+                     f"{float(e.get('gamma', 0.0)):.2f}}},")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -56,6 +56,7 @@ enum Ctr : int {
   C_MU = 12,    // m_u: edges of the vertices no top-down level has discovered yet
   C_LASTNF = 13,  // frontier size of the previous level
   C_NFIN = 14,  // input frontier size of the next bottom-up step
+  C_UNV = 15,   // non-isolated vertices not reached yet
   C_NCTR = 16
 };
 
@@ -118,19 +119,32 @@ __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ pa
 // at the root's level; switch to bottom-up when Q grew and m_f > m_u / alpha.
 // ctr[C_GO] = 1 lets the level's queued degree pass and expansion run.  Clears
 // the slot of the queue that this level fills and publishes.
-__device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, int dirmode, double alpha,
-                          uint64_t mf, unsigned long long *host, unsigned long long seq) {
+struct TdRule {
+  int dirmode;
+  double alpha;
+  double gamma;  // > 0: also switch when m_f > gamma * unvisited non-isolated vertices
+};
+
+__device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool from_bu,
+                          const TdRule &rule, uint64_t mf, unsigned long long *host,
+                          unsigned long long seq) {
   auto ld = [&](int i) {
     return (int64_t)__hip_atomic_load(ctr + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
   const int64_t qlen = ld(C_QLEN0 + qs);
   int64_t mu = ld(C_MU);
   if (lvl > 0) mu -= (int64_t)mf;
+  int64_t unv = ld(C_UNV);
+  if (lvl > 0 && !from_bu) unv -= qlen;  // this frontier was found by a top-down level
   const bool growing = qlen > ld(C_LASTNF);
-  const bool to_bu = dirmode == G5_DIR_BOTTOMUP ||
-                     (dirmode == G5_DIR_AUTO && growing && (double)mf > (double)mu / alpha);
+  const bool to_bu =
+      rule.dirmode == G5_DIR_BOTTOMUP ||
+      (rule.dirmode == G5_DIR_AUTO && growing &&
+       ((double)mf > (double)mu / rule.alpha ||
+        (rule.gamma > 0 && (double)mf > rule.gamma * (double)unv)));
   const bool go = qlen > 0 && !to_bu;
   ctr[C_MU] = (unsigned long long)mu;
+  ctr[C_UNV] = (unsigned long long)unv;
   ctr[C_MF] = mf;
   ctr[C_GO] = go ? 1ull : 0ull;
   if (go) ctr[C_LASTNF] = (unsigned long long)qlen;
@@ -141,7 +155,7 @@ __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, int dirm
 // Root's level: queue {root} with its degree, and the counters.
 __global__ void k_bfs_seed(int64_t root, int32_t *level, int32_t *parent, uint64_t *vis,
                            int32_t *q0, uint32_t *qd0, unsigned long long *ctr, const int64_t *rp,
-                           int64_t nnz) {
+                           int64_t nnz, int64_t nonisolated) {
   level[root] = 0;
   parent[root] = (int32_t)root;
   vis[root >> 6] |= 1ull << (root & 63);
@@ -151,6 +165,7 @@ __global__ void k_bfs_seed(int64_t root, int32_t *level, int32_t *parent, uint64
   ctr[C_QLEN0] = 1;
   ctr[C_RDEG] = (unsigned long long)rdeg;
   ctr[C_MU] = (unsigned long long)(nnz - rdeg);
+  ctr[C_UNV] = (unsigned long long)(nonisolated - (rdeg > 0 ? 1 : 0));
   ctr[C_LASTNF] = 0;
 }
 
@@ -205,8 +220,8 @@ __global__ __launch_bounds__(kBlock) void k_td_deg(const unsigned long long *__r
 // m_f; then the level's direction decision (td_decide), published.
 __global__ __launch_bounds__(kScanBlock) void k_td_scan(uint32_t *__restrict__ bsum,
                                                         unsigned long long *__restrict__ ctr,
-                                                        int cur, int32_t lvl, int dirmode,
-                                                        double alpha,
+                                                        int cur, int32_t lvl, bool from_bu,
+                                                        TdRule rule,
                                                         unsigned long long *__restrict__ host,
                                                         unsigned long long seq) {
   __shared__ uint32_t s[kScanBlock / kWave];
@@ -223,7 +238,7 @@ __global__ __launch_bounds__(kScanBlock) void k_td_scan(uint32_t *__restrict__ b
     bsum[i] = run;
     run += x;
   }
-  if (threadIdx.x == 0) td_decide(ctr, cur, lvl, dirmode, alpha, tot, host, seq);
+  if (threadIdx.x == 0) td_decide(ctr, cur, lvl, from_bu, rule, tot, host, seq);
 }
 
 // In-place exclusive scan of bsum[0..len) (single block); total -> *out, and
@@ -809,6 +824,7 @@ __device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
                         nnew < nf_in);
     ctr[C_BUGO] = (nnew > 0 && !to_td) ? 1ull : 0ull;
     ctr[C_NFIN] = nnew;
+    ctr[C_UNV] = __hip_atomic_load(ctr + C_UNV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - nnew;
     atomicExch(ctr + C_NNEW, nnew);
     publish(ctr, host, seq);
     atomicExch(ctr + C_NNEW, 0ull);
@@ -1135,6 +1151,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const int ncu = g->num_cu;
   const double alpha = p.alpha > 0 ? p.alpha : g->tune.alpha;
   const double beta = p.beta > 0 ? p.beta : g->tune.beta;
+  const double gamma = p.gamma != 0 ? p.gamma : g->tune.gamma;  // < 0 disables
   const int lane_scan = p.bu_lane_scan > 0 ? p.bu_lane_scan : g->tune.lane_scan;
   const int bu_bpc = p.bu_blocks_per_cu > 0 ? p.bu_blocks_per_cu : g->tune.bu_blocks_per_cu;
   const double lds_density = p.lds_density > 0 ? p.lds_density : g->tune.lds_density;
@@ -1188,7 +1205,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                      w.snap[0], w.snap[1], g->iso, W,
                      (((uintptr_t)level | (uintptr_t)parent) & 15) == 0);
   hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, root, level, parent, w.vis, w.q[0],
-                     w.qoff[0], ctr, g->row_ptr, g->nnz);
+                     w.qoff[0], ctr, g->row_ptr, g->nnz, g->nonisolated);
   G5_LAUNCH_CHECK();
 
   int cur = 0;                // queue holding the current frontier (top-down)
@@ -1207,6 +1224,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   if (stats) *stats = g5_bfs_stats{};
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
   const BuNext bn{p.direction, beta, n};
+  const TdRule rule{p.direction, alpha, gamma};
   const int32_t *hint = use_hint ? g->hint : nullptr;
   const int32_t *hint_id = prefill ? nullptr : g->hint_id;
   const int64_t fh_words = use_hint ? (g->num_hot + 63) / 64 : 0;
@@ -1225,7 +1243,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   // scan with the level's direction decision (published under sq), expansion
   // (runs only if the level stays top-down).  Queued ahead behind a level that
   // did not expand, the level's queue is empty and nothing happens.
-  auto launch_td = [&](int32_t lv, int c, unsigned long long sq) -> g5_status {
+  auto launch_td = [&](int32_t lv, int c, unsigned long long sq, bool from_bu) -> g5_status {
     const int nx = c ^ 1;
     {
       g5_status st_ = rec(lv, 0);
@@ -1234,8 +1252,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     hipLaunchKernelGGL(k_td_deg, dim3(deg_grid), dim3(kBlock), 0, s,
                        (const unsigned long long *)ctr, c, w.qoff[c], w.bsum, w.snap[lv & 1],
                        w.vis, W);
-    hipLaunchKernelGGL(k_td_scan, dim3(1), dim3(kScanBlock), 0, s, w.bsum, ctr, c, lv,
-                       p.direction, alpha, hpub, sq);
+    hipLaunchKernelGGL(k_td_scan, dim3(1), dim3(kScanBlock), 0, s, w.bsum, ctr, c, lv, from_bu,
+                       rule, hpub, sq);
 #define G5_TD(C)                                                                             \
   hipLaunchKernelGGL(k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c],    \
                      w.bsum, ctr, c, g->rp32, g->col_idx, w.vis, w.snap[lv & 1], parent, level, \
@@ -1327,7 +1345,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   // the root's level
   dec_seq = ++w.seq;
   {
-    g5_status st = launch_td(0, 0, dec_seq);
+    g5_status st = launch_td(0, 0, dec_seq, false);
     if (st != G5_OK) return st;
   }
   while (true) {
@@ -1337,7 +1355,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       const int nxt = cur ^ 1;
       const unsigned long long spec_seq = ++w.seq;
       {
-        g5_status st = launch_td(lvl + 1, nxt, spec_seq);
+        g5_status st = launch_td(lvl + 1, nxt, spec_seq, false);
         if (st != G5_OK) return st;
       }
       {
@@ -1435,7 +1453,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       G5_LAUNCH_CHECK();
       dec_seq = ++w.seq;
       {
-        g5_status st = launch_td(lvl, cur, dec_seq);
+        g5_status st = launch_td(lvl, cur, dec_seq, true);
         if (st != G5_OK) return st;
       }
       q_from_bu = true;

@@ -96,6 +96,7 @@ struct Tuning {
   double lds_density;     // stage the frontier in LDS below this summary density
   double batch_alpha;     // batched direction switch
   int batch_blocks_per_cu;
+  double gamma;           // single-root switch also when m_f > gamma * unvisited vertices
 };
 Tuning pick_tuning(int scale);
 

@@ -495,8 +495,8 @@ struct BatchLease {
 // Stepped batch: one launch per level; the host reads the level counters
 // after each launch and takes the direction decision.
 g5_status batch_stepped(const g5_csr *g, BatchWork &w, const MsArgs &a, int32_t *parents,
-                        hipStream_t s, bool timed, g5_batch_stats *stats) {
-  const int blocks = g->num_cu * 8;
+                        hipStream_t s, bool timed, g5_batch_stats *stats, int bpc) {
+  const int blocks = g->num_cu * bpc;
   MsCtl *hc = (MsCtl *)w.host_ctl;
   if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
   hipLaunchKernelGGL(k_ms_root_stats, dim3(blocks), dim3(kBlock), 0, s, a);
@@ -611,7 +611,9 @@ g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *
   a.direction = p.direction;
   a.max_level = 127;
 
-  if (p.flags & G5_FLAG_STEPPED) return batch_stepped(g, w, a, parents, s, timed, stats);
+  const int bpc = p.blocks_per_cu > 0 ? p.blocks_per_cu : g->tune.batch_blocks_per_cu;
+  if (!(p.flags & G5_FLAG_PERSISTENT))
+    return batch_stepped(g, w, a, parents, s, timed, stats, bpc);
 
   const void *fn = parents ? reinterpret_cast<const void *>(&k_msbfs<true>)
                            : reinterpret_cast<const void *>(&k_msbfs<false>);
@@ -621,7 +623,6 @@ g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *
     set_error("g5_bfs_batch: the persistent kernel does not fit on a compute unit");
     return G5_EDEVICE;
   }
-  const int bpc = p.blocks_per_cu > 0 ? p.blocks_per_cu : g->tune.batch_blocks_per_cu;
   const int blocks = ncu * std::min(per_cu, bpc);
   void *args[] = {&a};
   if (timed) G5_HIP(hipEventRecord(w.ev[0], s));

@@ -11,10 +11,10 @@ from tests.gpu_util import Case, check_batch
 pytestmark = pytest.mark.gpu
 
 MODES = [dict(), dict(direction=g5.DIR_TOPDOWN), dict(direction=g5.DIR_BOTTOMUP),
-         dict(alpha=1e-3), dict(alpha=1e6), dict(parents=False), dict(stepped=True),
-         dict(stepped=True, parents=False, direction=g5.DIR_BOTTOMUP)]
-MODE_IDS = ["auto", "td", "bu", "auto-bu-early", "auto-td-long", "levels-only", "stepped",
-            "stepped-bu-levels"]
+         dict(alpha=1e-3), dict(alpha=1e6), dict(parents=False), dict(persistent=True),
+         dict(persistent=True, parents=False, direction=g5.DIR_BOTTOMUP)]
+MODE_IDS = ["auto", "td", "bu", "auto-bu-early", "auto-td-long", "levels-only", "persistent",
+            "persistent-bu-levels"]
 
 
 @pytest.fixture(params=range(len(MODES)), ids=MODE_IDS)
@@ -78,9 +78,9 @@ def test_depth_limit():
     _, lv, _ = check_batch(c, [127])
     assert lv.max() == 127
     for roots in ([126], [0, 127]):
-        for stepped in (False, True):
+        for persistent in (False, True):
             with pytest.raises(g5.G5Error) as ei:
-                g5.bfs_batch(c.csr, roots, stepped=stepped)
+                g5.bfs_batch(c.csr, roots, persistent=persistent)
             assert ei.value.status == g5.G5_ERANGE
     e, n = G.path(256)
     c = Case(e, n)

@@ -21,10 +21,11 @@ MODES = [dict(direction=g5.DIR_AUTO), dict(direction=g5.DIR_TOPDOWN),
          dict(direction=g5.DIR_BOTTOMUP, lds_kb=16, lds_density=1.0, packed=True),
          dict(direction=g5.DIR_BOTTOMUP, lds_kb=16, lds_density=1.0, packed=False),
          dict(vertices_per_lane=2), dict(direction=g5.DIR_BOTTOMUP, vertices_per_lane=2, packed=True),
-         dict(direction=g5.DIR_BOTTOMUP, vertices_per_lane=2, lds_density=1.0, lane_scan=16)]
+         dict(direction=g5.DIR_BOTTOMUP, vertices_per_lane=2, lds_density=1.0, lane_scan=16),
+         dict(gamma=0.5, alpha=2.0)]
 MODE_IDS = ["auto", "td", "bu", "auto-cas", "auto-eager", "auto-late", "nohint", "bu-nohint-1",
             "packed", "bu-packed-nohint-1", "nolds", "bu-nolds-packed", "bu-lds16-packed",
-            "bu-lds16-rows", "vpl2", "bu-vpl2-packed", "bu-vpl2-lds-16"]
+            "bu-lds16-rows", "vpl2", "bu-vpl2-packed", "bu-vpl2-lds-16", "gamma-early"]
 
 
 @pytest.fixture(params=range(len(MODES)), ids=MODE_IDS)
