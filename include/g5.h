@@ -103,7 +103,8 @@ typedef struct {
   int32_t bu_blocks_per_cu; /* bottom-up grid: workgroups per compute unit (1..32) */
   int32_t lds_kb;         /* LDS for the staged frontier per workgroup, KiB (16..160) */
   int32_t bu_vertices_per_lane; /* bottom-up: unvisited vertices a lane works on at once: 1 or 2 */
-  int32_t td_blocks_per_cu; /* top-down expansion grid: workgroups per compute unit (1..256) */
+  int32_t td_blocks_per_cu; /* top-down expansion grid: workgroups per compute unit (1..256);
+                               0 = those that fit at once, at most 6 */
   int32_t reserved[2];
   double gamma;           /* also top-down -> bottom-up when the frontier grew and m_f > gamma *
                              (unvisited non-isolated vertices); 0 takes the default, < 0 disables */

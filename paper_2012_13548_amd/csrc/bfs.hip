@@ -8,12 +8,15 @@
 // neighbours, then update); the top-down step here does the same with one
 // edge per lane after a prefix sum of frontier degrees.
 //
-//   top-down  (paper's parallel BFS): frontier queue Q -> degree prefix sum ->
-//             every edge of Q gets one lane (each block owns 1024 consecutive
-//             edges, so hubs are split across blocks and small rows are packed
-//             together) -> claim the neighbour with an atomic on the visited
-//             bitmap (or a compare-and-swap on parent) -> compact winners into
-//             Q' by ballot + LDS prefix + one global atomic per block.
+//   top-down  (paper's parallel BFS): frontier queue Q whose entries carry
+//             their first edge's index in Q's edge list -> every edge of Q gets
+//             one lane (each block owns 1024 consecutive edges, so hubs are
+//             split across blocks and small rows are packed together) -> claim
+//             the neighbour with an atomic on the visited bitmap (or a
+//             compare-and-swap on parent) -> compact winners into Q' by ballot
+//             + LDS prefix; one 64-bit atomic per block adds (entries, degree
+//             sum) to Q''s counter, which places the block's entries and their
+//             edge indices at once, so Q' needs no separate prefix-sum pass.
 //   bottom-up (Beamer, Asanovic, Patterson, SC'12): one lane per unvisited
 //             vertex (a wavefront covers one 64-bit visited word); scan the
 //             row until a neighbour in the frontier bitmap is found; the ballot
@@ -30,11 +33,11 @@ namespace g5 {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kDegItems = 4;
-constexpr int kDegTile = kBlock * kDegItems;  // frontier entries per degree block
 constexpr int kTdItems = 4;
 constexpr int kTdTile = kBlock * kTdItems;    // edges per top-down block
-constexpr int kScanBlock = 1024;
+// Expansion workgroups per compute unit by default: a wider window of tiles in
+// flight (8, all that fit) made the large expansions of a scale-26 graph slower.
+constexpr int kTdBlocksPerCu = 6;
 
 // Device counters of one traversal (uint64 slots of BfsWork::ctr).  The last
 // kernel of a level copies them, with a sequence number, to pinned host memory
@@ -57,7 +60,9 @@ enum Ctr : int {
   C_LASTNF = 13,  // frontier size of the previous level
   C_NFIN = 14,  // input frontier size of the next bottom-up step
   C_UNV = 15,   // non-isolated vertices not reached yet
-  C_NCTR = 16
+  C_QP0 = 16,   // queue 0: entries << 32 | degree sum (appended to by one atomic per block)
+  C_QP1 = 17,   // queue 1: the same
+  C_NCTR = 18
 };
 
 // Copies the counters to host memory.  Each 8-byte slot carries the low 16
@@ -85,12 +90,19 @@ __device__ void publish(const unsigned long long *ctr, unsigned long long *host,
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// level = -1 and parent = fill (the hint targets) or -1; visited bitmap and its
-// snapshots = the isolated vertices.
-__global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ parent, int64_t n,
+// Start of a traversal from `root`: level = -1 and parent = fill (the hint
+// targets) or -1, except at the root (level 0, its own parent); visited bitmap
+// = the isolated vertices and the root, its snapshots = the isolated vertices;
+// counters zeroed, then queue 0 = {root} (edge index 0, its degree in the
+// queue's counter) and the direction state of the root's level.
+__global__ void k_bfs_init(int64_t root, int32_t *__restrict__ level,
+                           int32_t *__restrict__ parent, int64_t n,
                            const int32_t *__restrict__ fill, uint64_t *__restrict__ vis,
                            uint64_t *__restrict__ prev0, uint64_t *__restrict__ prev1,
-                           const uint64_t *__restrict__ iso, int64_t words, bool vec) {
+                           const uint64_t *__restrict__ iso, int64_t words, bool vec,
+                           int32_t *__restrict__ q0, uint32_t *__restrict__ qo0,
+                           unsigned long long *__restrict__ ctr, const int64_t *__restrict__ rp,
+                           int64_t nnz, int64_t nonisolated) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t n4 = vec ? n / 4 : 0;
@@ -98,18 +110,36 @@ __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ pa
   const v4i m1 = {-1, -1, -1, -1};
   // streaming (non-temporal) accesses: the arrays are far larger than L2
   for (int64_t i = t; i < n4; i += stride) {
-    __builtin_nontemporal_store(m1, reinterpret_cast<v4i *>(level) + i);
-    const v4i f = fill ? __builtin_nontemporal_load(reinterpret_cast<const v4i *>(fill) + i) : m1;
+    v4i lv = m1;
+    v4i f = fill ? __builtin_nontemporal_load(reinterpret_cast<const v4i *>(fill) + i) : m1;
+    if (i == (root >> 2)) {
+      lv[root & 3] = 0;
+      f[root & 3] = (int32_t)root;
+    }
+    __builtin_nontemporal_store(lv, reinterpret_cast<v4i *>(level) + i);
     __builtin_nontemporal_store(f, reinterpret_cast<v4i *>(parent) + i);
   }
   for (int64_t i = n4 * 4 + t; i < n; i += stride) {
-    level[i] = -1;
-    parent[i] = fill ? fill[i] : -1;
+    level[i] = i == root ? 0 : -1;
+    parent[i] = i == root ? (int32_t)root : (fill ? fill[i] : -1);
   }
+  const int64_t rw = root >> 6;
   for (int64_t i = t; i < words; i += stride) {
-    vis[i] = iso[i];
-    prev0[i] = iso[i];
-    prev1[i] = iso[i];
+    const uint64_t x = iso[i];
+    vis[i] = i == rw ? x | (1ull << (root & 63)) : x;
+    prev0[i] = x;
+    prev1[i] = x;
+  }
+  if (t == 0) {
+    for (int i = 0; i < C_NCTR; ++i) ctr[i] = 0;
+    const int64_t rdeg = rp[root + 1] - rp[root];  // 64-bit offsets
+    q0[0] = (int32_t)root;
+    qo0[0] = 0;
+    ctr[C_QLEN0] = 1;
+    ctr[C_QP0] = (1ull << 32) | (unsigned long long)rdeg;
+    ctr[C_RDEG] = (unsigned long long)rdeg;
+    ctr[C_MU] = (unsigned long long)(nnz - rdeg);
+    ctr[C_UNV] = (unsigned long long)(nonisolated - (rdeg > 0 ? 1 : 0));
   }
 }
 
@@ -117,8 +147,8 @@ __global__ void k_bfs_init(int32_t *__restrict__ level, int32_t *__restrict__ pa
 // counters): queue slot qs holds its frontier Q (qlen vertices, mf edges).
 // m_u (edges of vertices no top-down level has discovered) drops by m_f except
 // at the root's level; switch to bottom-up when Q grew and m_f > m_u / alpha.
-// ctr[C_GO] = 1 lets the level's queued degree pass and expansion run.  Clears
-// the slot of the queue that this level fills and publishes.
+// ctr[C_GO] = 1 lets the level's queued expansion run.  Records Q for the
+// host, clears the counters of the queue that this level fills and publishes.
 struct TdRule {
   int dirmode;
   double alpha;
@@ -126,12 +156,11 @@ struct TdRule {
 };
 
 __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool from_bu,
-                          const TdRule &rule, uint64_t mf, unsigned long long *host,
-                          unsigned long long seq) {
+                          const TdRule &rule, int64_t qlen, uint64_t mf,
+                          unsigned long long *host, unsigned long long seq) {
   auto ld = [&](int i) {
     return (int64_t)__hip_atomic_load(ctr + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
-  const int64_t qlen = ld(C_QLEN0 + qs);
   int64_t mu = ld(C_MU);
   if (lvl > 0) mu -= (int64_t)mf;
   int64_t unv = ld(C_UNV);
@@ -148,25 +177,10 @@ __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool fro
   ctr[C_MF] = mf;
   ctr[C_GO] = go ? 1ull : 0ull;
   if (go) ctr[C_LASTNF] = (unsigned long long)qlen;
+  ctr[C_QLEN0 + qs] = (unsigned long long)qlen;
   ctr[C_QLEN0 + (qs ^ 1)] = 0;
+  ctr[C_QP0 + (qs ^ 1)] = 0;
   publish(ctr, host, seq);
-}
-
-// Root's level: queue {root} with its degree, and the counters.
-__global__ void k_bfs_seed(int64_t root, int32_t *level, int32_t *parent, uint64_t *vis,
-                           int32_t *q0, uint32_t *qd0, unsigned long long *ctr, const int64_t *rp,
-                           int64_t nnz, int64_t nonisolated) {
-  level[root] = 0;
-  parent[root] = (int32_t)root;
-  vis[root >> 6] |= 1ull << (root & 63);
-  const int64_t rdeg = rp[root + 1] - rp[root];  // 64-bit offsets
-  q0[0] = (int32_t)root;
-  qd0[0] = (uint32_t)rdeg;
-  ctr[C_QLEN0] = 1;
-  ctr[C_RDEG] = (unsigned long long)rdeg;
-  ctr[C_MU] = (unsigned long long)(nnz - rdeg);
-  ctr[C_UNV] = (unsigned long long)(nonisolated - (rdeg > 0 ? 1 : 0));
-  ctr[C_LASTNF] = 0;
 }
 
 __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
@@ -174,105 +188,37 @@ __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
 }
 
-// Degree pass of a top-down level: the queue's degrees (written with the queue)
-// become, per 1024-entry chunk c, the block-local exclusive prefix in qoff and
-// the total in bsum[c]; grid-stride over chunks, the queue length read from the
-// device (0 when it was queued ahead behind a level that did not expand, so
-// the pass does nothing).  The same launch snapshots the visited bitmap into
-// `snap` before this level's expansion.
-__global__ __launch_bounds__(kBlock) void k_td_deg(const unsigned long long *__restrict__ cctr,
-                                                   int cur, uint32_t *__restrict__ qoff,
-                                                   uint32_t *__restrict__ bsum,
-                                                   uint64_t *__restrict__ snap,
-                                                   const uint64_t *__restrict__ vis,
-                                                   int64_t words) {
-  __shared__ uint32_t s[kBlock / kWave];
-  const int64_t qlen = (int64_t)cctr[C_QLEN0 + cur];
+// First kernel of a top-down level: the queue's counter gives Q and m_f, thread
+// 0 takes the level's direction decision (td_decide) and publishes it, and the
+// grid snapshots the visited bitmap into `snap` before the level's expansion.
+// Queued ahead behind a level that did not expand, the queue is empty: the
+// decision says so and the snapshot is skipped.
+__global__ __launch_bounds__(kBlock) void k_td_decide(unsigned long long *__restrict__ ctr,
+                                                      int cur, int32_t lvl, bool from_bu,
+                                                      TdRule rule,
+                                                      unsigned long long *__restrict__ host,
+                                                      unsigned long long seq,
+                                                      uint64_t *__restrict__ snap,
+                                                      const uint64_t *__restrict__ vis,
+                                                      int64_t words) {
+  const unsigned long long qp = ctr[C_QP0 + cur];
+  const int64_t qlen = (int64_t)(qp >> 32);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    td_decide(ctr, cur, lvl, from_bu, rule, qlen, qp & 0xffffffffull, host, seq);
   if (qlen == 0) return;
-  const int64_t nchunks = (qlen + kDegTile - 1) / kDegTile;
-  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const int64_t b = c * kDegTile + (int64_t)threadIdx.x * kDegItems;
-    uint32_t d[kDegItems];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int j = 0; j < kDegItems; ++j) {
-      const int64_t i = b + j;
-      d[j] = i < qlen ? qoff[i] : 0u;
-      sum += d[j];
-    }
-    uint32_t tot;
-    uint32_t run = block_excl_scan<kBlock, uint32_t>(sum, s, tot);
-#pragma unroll
-    for (int j = 0; j < kDegItems; ++j) {
-      const int64_t i = b + j;
-      if (i < qlen) qoff[i] = run;
-      run += d[j];
-    }
-    if (threadIdx.x == 0) bsum[c] = tot;
-  }
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride)
     snap[i] = vis[i];
 }
 
-// Exclusive scan of the chunk totals of a top-down level's degree pass (single
-// block): bsum becomes the chunk offsets and their total is the frontier's
-// m_f; then the level's direction decision (td_decide), published.
-__global__ __launch_bounds__(kScanBlock) void k_td_scan(uint32_t *__restrict__ bsum,
-                                                        unsigned long long *__restrict__ ctr,
-                                                        int cur, int32_t lvl, bool from_bu,
-                                                        TdRule rule,
-                                                        unsigned long long *__restrict__ host,
-                                                        unsigned long long seq) {
-  __shared__ uint32_t s[kScanBlock / kWave];
-  const int64_t qlen = (int64_t)ctr[C_QLEN0 + cur];
-  const int64_t len = (qlen + kDegTile - 1) / kDegTile;
-  const int64_t per = (len + kScanBlock - 1) / kScanBlock;
-  const int64_t b = per * threadIdx.x, e = std::min<int64_t>(b + per, len);
-  uint32_t sum = 0;
-  for (int64_t i = b; i < e; ++i) sum += bsum[i];
-  uint32_t tot;
-  uint32_t run = block_excl_scan<kScanBlock, uint32_t>(sum, s, tot);
-  for (int64_t i = b; i < e; ++i) {
-    const uint32_t x = bsum[i];
-    bsum[i] = run;
-    run += x;
-  }
-  if (threadIdx.x == 0) td_decide(ctr, cur, lvl, from_bu, rule, tot, host, seq);
-}
-
-// In-place exclusive scan of bsum[0..len) (single block); total -> *out, and
-// v2 -> *out2 when given.
-__global__ __launch_bounds__(kScanBlock) void k_scan_bsum(uint32_t *__restrict__ bsum,
-                                                          int64_t len,
-                                                          unsigned long long *__restrict__ out,
-                                                          unsigned long long *__restrict__ out2,
-                                                          unsigned long long v2) {
-  __shared__ uint32_t s[kScanBlock / kWave];
-  int64_t per = (len + kScanBlock - 1) / kScanBlock;
-  int64_t b = per * threadIdx.x, e = std::min<int64_t>(b + per, len);
-  uint32_t sum = 0;
-  for (int64_t i = b; i < e; ++i) sum += bsum[i];
-  uint32_t tot;
-  uint32_t run = block_excl_scan<kScanBlock, uint32_t>(sum, s, tot);
-  for (int64_t i = b; i < e; ++i) {
-    uint32_t x = bsum[i];
-    bsum[i] = run;
-    run += x;
-  }
-  if (threadIdx.x == 0) {
-    *out = tot;
-    if (out2) *out2 = v2;
-  }
-}
-
-// Global edge offset of frontier entry i: chunk offset + in-chunk prefix.
+// Edge index of frontier entry i in the frontier's edge list (non-decreasing
+// in i; the total past the last entry).
 struct FrontOffsets {
-  const uint32_t *qoff, *boff;
+  const uint32_t *qoff;
   int64_t qlen;
   uint32_t total;
   __device__ __forceinline__ uint32_t operator()(int64_t i) const {
-    return i >= qlen ? total : qoff[i] + boff[i / kDegTile];
+    return i >= qlen ? total : qoff[i];
   }
 };
 
@@ -309,32 +255,32 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
   return x;
 }
 
-// Top-down expansion (runs only if the level's scan set ctr[C_GO]); a block
-// takes 1024-edge tiles of the frontier's edges (total ctr[C_MF]) in turn.
-// Each claimed vertex is appended to the next queue with its degree.
+// Top-down expansion (runs only if the level's decision set ctr[C_GO]); a
+// block takes 1024-edge tiles of the frontier's edges (total ctr[C_MF]) in
+// turn.  A tile's claimed vertices go to the next queue together: their
+// degrees' block prefix sum, then one atomic on the queue's packed counter
+// (entries << 32 | degree sum) gives the tile both its queue positions and
+// its entries' edge indices.
 
 template <int CLAIM>
 __global__ __launch_bounds__(kBlock) void k_td_expand(
     const int32_t *__restrict__ q, const uint32_t *__restrict__ qoff,
-    const uint32_t *__restrict__ boff, unsigned long long *__restrict__ ctr, int cur,
+    unsigned long long *__restrict__ ctr, int cur,
     const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     uint64_t *vis, const uint64_t *__restrict__ prev, int32_t *parent,
-    int32_t *__restrict__ level, int32_t *__restrict__ qn, uint32_t *__restrict__ qdn,
+    int32_t *__restrict__ level, int32_t *__restrict__ qn, uint32_t *__restrict__ qon,
     int32_t next_level) {
   __shared__ uint32_t s_off[kTdTile + 1];
   __shared__ int32_t s_src[kTdTile];
   __shared__ int64_t s_base[kTdTile];
-  __shared__ int32_t s_out[kTdTile];
-  __shared__ uint32_t s_cnt;
+  __shared__ unsigned long long s_scan[kBlock / kWave];
   __shared__ unsigned long long s_gbase;
   if (!ctr[C_GO]) return;
   const int nxt = cur ^ 1;
-  unsigned long long *qn_len = ctr + C_QLEN0 + nxt;
+  unsigned long long *qn_pack = ctr + C_QP0 + nxt;
   const int64_t qlen = (int64_t)ctr[C_QLEN0 + cur];
   const uint32_t total = (uint32_t)ctr[C_MF];
-  const FrontOffsets off{qoff, boff, qlen, total};
-  const int lane = __lane_id();
-  const uint64_t lt = lanemask_lt();
+  const FrontOffsets off{qoff, qlen, total};
   for (uint64_t tile = blockIdx.x; tile * kTdTile < total; tile += gridDim.x) {
     const uint32_t e0 = (uint32_t)(tile * kTdTile);
     const uint32_t e1 = (uint32_t)std::min<uint64_t>((uint64_t)e0 + kTdTile, total);
@@ -352,12 +298,14 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
       s_src[k] = u;
       s_base[k] = (int64_t)rp[u] - (int64_t)o;
     }
-    if (threadIdx.x == 0) {
-      s_off[S] = off(i1 + 1);
-      s_cnt = 0;
-    }
+    if (threadIdx.x == 0) s_off[S] = off(i1 + 1);
     __syncthreads();
     int klo = 0;
+    // this thread's winners; a winner's degree is loaded at once, so the loads
+    // overlap the remaining edges
+    int32_t wv[kTdItems];
+    uint32_t wdeg[kTdItems];
+    uint32_t wmask = 0;
 #pragma unroll
     for (int j = 0; j < kTdItems; ++j) {
       uint32_t e = e0 + j * kBlock + threadIdx.x;
@@ -396,26 +344,43 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
           if (won) level[v] = next_level;
         }
       }
-      uint64_t bal = __ballot(won);
-      if (bal) {
-        uint32_t wbase = 0;
-        if (lane == 0) wbase = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
-        wbase = __shfl(wbase, 0, kWave);
-        if (won) s_out[wbase + __popcll(bal & lt)] = v;
-      }
-    }
-    __syncthreads();
-    const uint32_t cnt = s_cnt;
-    if (cnt) {
-      if (threadIdx.x == 0) s_gbase = atomicAdd(qn_len, (unsigned long long)cnt);
-      __syncthreads();
-      for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
-        const int32_t v = s_out[k];
+      wv[j] = v;
+      wdeg[j] = 0;
+      if (won) {
+        wmask |= 1u << j;
         uint32_t be[2];
         __builtin_memcpy(be, rp + v, 8);
-        const uint32_t d = be[1] - be[0];
-        qn[s_gbase + k] = v;
-        qdn[s_gbase + k] = d;
+        wdeg[j] = be[1] - be[0];
+      }
+    }
+    // the tile's winners in thread order: one block scan of (count << 32 | degree
+    // sum) and one atomic on the queue's counter give positions and edge indices
+    unsigned long long mine = (unsigned long long)__popc(wmask) << 32;
+#pragma unroll
+    for (int j = 0; j < kTdItems; ++j) mine += wdeg[j];
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan<kBlock, unsigned long long>(mine, s_scan, tot);
+    const uint32_t cnt = (uint32_t)(tot >> 32);  // block-uniform
+    if (cnt) {
+      // every thread has left the edge loop (the scan synchronised): stage the
+      // entries at their tile positions in s_src (vertex) and s_off (edge
+      // index from the tile's first), then write them out coalesced
+      uint32_t p = (uint32_t)(ex >> 32), eo = (uint32_t)ex;
+#pragma unroll
+      for (int j = 0; j < kTdItems; ++j)
+        if ((wmask >> j) & 1) {
+          s_src[p] = wv[j];
+          s_off[p] = eo;
+          ++p;
+          eo += wdeg[j];
+        }
+      if (threadIdx.x == 0) s_gbase = atomicAdd(qn_pack, tot);
+      __syncthreads();
+      const unsigned long long gb = s_gbase;
+      const uint64_t pos = gb >> 32;
+      for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
+        qn[pos + k] = s_src[k];
+        qon[pos + k] = (uint32_t)gb + s_off[k];
       }
     }
     __syncthreads();  // the shared arrays are reused by the next tile
@@ -828,6 +793,8 @@ __device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
     atomicExch(ctr + C_NNEW, nnew);
     publish(ctr, host, seq);
     atomicExch(ctr + C_NNEW, 0ull);
+    ctr[C_QP0] = 0;  // a switch back to top-down fills a queue from zero
+    ctr[C_QP1] = 0;
     if (ACCT) {
       atomicExch(ctr + C_SCAN, 0ull);
       atomicExch(ctr + C_UNVIS, 0ull);
@@ -949,43 +916,64 @@ __global__ void k_front_summary(const uint64_t *__restrict__ front, int64_t word
   }
 }
 
-// Bitmap -> queue in vertex order, with each entry's degree:
-// block b owns words [b*chunk, (b+1)*chunk).
-__global__ __launch_bounds__(kBlock) void k_front_count(const uint64_t *__restrict__ bm,
-                                                        int64_t words, int64_t chunk,
-                                                        uint32_t *__restrict__ bsum) {
-  __shared__ uint32_t s[kBlock / kWave];
-  int64_t b = (int64_t)blockIdx.x * chunk, e = std::min<int64_t>(b + chunk, words);
-  uint32_t c = 0;
-  for (int64_t w = b + threadIdx.x; w < e; w += kBlock) c += (uint32_t)__popcll(bm[w]);
-  uint32_t tot = block_sum<kBlock, uint32_t>(c, s);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
+// Bitmap -> queue of the next top-down level: in each round a block takes the
+// next kFqWords words (kFqWords / kBlock consecutive words per thread), numbers
+// their vertices and degrees by a block prefix sum of (count << 32 | degree
+// sum), and one atomic on the queue's packed counter (zero before) places them
+// and their edge indices.  Block 0 also sets the direction state's previous
+// frontier size.
+constexpr int kFqPer = 16;
+constexpr int64_t kFqWords = (int64_t)kBlock * kFqPer;
 
-__global__ __launch_bounds__(kBlock) void k_front_write(const uint64_t *__restrict__ bm,
-                                                        int64_t words, int64_t chunk,
-                                                        const uint32_t *__restrict__ boff,
+__global__ __launch_bounds__(kBlock) void k_front_queue(const uint64_t *__restrict__ bm,
+                                                        int64_t words,
+                                                        const uint32_t *__restrict__ rp,
                                                         int32_t *__restrict__ q,
-                                                        uint32_t *__restrict__ qd,
-                                                        const uint32_t *__restrict__ rp) {
-  __shared__ uint32_t s[kBlock / kWave];
-  int64_t b = (int64_t)blockIdx.x * chunk, e = std::min<int64_t>(b + chunk, words);
-  uint32_t base = boff[blockIdx.x];
-  for (int64_t w0 = b; w0 < e; w0 += kBlock) {
-    int64_t w = w0 + threadIdx.x;
-    uint64_t x = (w < e) ? bm[w] : 0;
-    uint32_t tot;
-    uint32_t pos = base + block_excl_scan<kBlock, uint32_t>((uint32_t)__popcll(x), s, tot);
-    while (x) {
-      int bit = __ffsll((unsigned long long)x) - 1;
-      x &= x - 1;
-      const int32_t v = (int32_t)(w * kWave + bit);
-      uint32_t be[2];
-      __builtin_memcpy(be, rp + v, 8);
-      q[pos] = v;
-      qd[pos++] = be[1] - be[0];
+                                                        uint32_t *__restrict__ qo,
+                                                        unsigned long long *__restrict__ ctr,
+                                                        int cur, int64_t last_nf) {
+  __shared__ unsigned long long s[kBlock / kWave];
+  __shared__ unsigned long long s_g;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_LASTNF] = (unsigned long long)last_nf;
+  for (int64_t r0 = (int64_t)blockIdx.x * kFqWords; r0 < words;
+       r0 += (int64_t)gridDim.x * kFqWords) {
+    const int64_t w0 = r0 + (int64_t)threadIdx.x * kFqPer;
+    unsigned long long mine = 0;  // count << 32 | degree sum of this thread's words
+    for (int j = 0; j < kFqPer; ++j) {
+      const int64_t w = w0 + j;
+      uint64_t x = w < words ? bm[w] : 0ull;
+      mine += (unsigned long long)__popcll(x) << 32;
+      while (x) {
+        const int32_t v = (int32_t)(w * kWave + __ffsll((unsigned long long)x) - 1);
+        x &= x - 1;
+        uint32_t be[2];
+        __builtin_memcpy(be, rp + v, 8);
+        mine += be[1] - be[0];
+      }
     }
-    base += tot;
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan<kBlock, unsigned long long>(mine, s, tot);
+    if (tot == 0) continue;  // uniform: tot is the block's sum
+    if (threadIdx.x == 0) s_g = atomicAdd(ctr + C_QP0 + cur, tot);
+    __syncthreads();
+    const unsigned long long g = s_g + ex;
+    uint64_t pos = g >> 32;
+    uint32_t off = (uint32_t)g;
+    __syncthreads();  // s_g is rewritten by the next round
+    if (!(mine >> 32)) continue;
+    for (int j = 0; j < kFqPer; ++j) {
+      const int64_t w = w0 + j;
+      uint64_t x = w < words ? bm[w] : 0ull;
+      while (x) {
+        const int32_t v = (int32_t)(w * kWave + __ffsll((unsigned long long)x) - 1);
+        x &= x - 1;
+        uint32_t be[2];
+        __builtin_memcpy(be, rp + v, 8);
+        q[pos] = v;
+        qo[pos++] = off;
+        off += be[1] - be[0];
+      }
+    }
   }
 }
 
@@ -1028,8 +1016,6 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   w->n = g->n;
   w->words = g->words;
   int64_t n = g->n, W = g->words;
-  int64_t nb = (n + kDegTile - 1) / kDegTile + 1;
-  int64_t nbf = (int64_t)g->num_cu * 32 + 1;  // bitmap->queue blocks: up to 32 per CU
   hipError_t e = hipSuccess;
   auto A = [&](void **p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
@@ -1043,7 +1029,6 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   A((void **)&w->q[1], n * 4);
   A((void **)&w->qoff[0], (n + 1) * 4);
   A((void **)&w->qoff[1], (n + 1) * 4);
-  A((void **)&w->bsum, std::max(nb, nbf) * 4);
   A((void **)&w->ctr, C_NCTR * 8);
   if (g->num_hot > 0) A((void **)&w->fh, ((g->num_hot + 63) / 64) * 8);
   // frontier summary for the LDS bottom-up step: as fine as the LDS allows
@@ -1096,7 +1081,6 @@ BfsWork::~BfsWork() {
   if (q[1]) (void)hipFree(q[1]);
   for (auto *p : qoff)
     if (p) (void)hipFree(p);
-  if (bsum) (void)hipFree(bsum);
   if (ctr) (void)hipFree(ctr);
   if (host_pub) (void)hipHostFree(host_pub);
   for (auto &e : ev) (void)hipEventDestroy(e);
@@ -1176,8 +1160,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   unsigned long long *ctr = (unsigned long long *)w.ctr;
   unsigned long long *hpub = (unsigned long long *)w.host_pub_dev;
   int64_t hc[C_NPUB] = {};  // the counters last published
-  const int bu_grid = ncu * bu_bpc;
-  const int deg_grid = ncu * 8;
+  const int decide_grid = grid_for(W, kBlock, ncu * 8);
   if (timed && w.ev.empty()) {
     w.ev.resize(2 * G5_MAX_STAT_LEVELS);
     for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
@@ -1195,17 +1178,15 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     if (st_ != G5_OK) return st_;     \
   } while (0)
 
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, w.ctr, (int64_t)C_NCTR);
   // With hints and claims by OR, parent starts as every vertex's hint target:
   // a bottom-up hit on the hint then writes no parent (unreached vertices are
   // reset at the end).  Compare-and-swap claims need parent -1.
   const bool prefill = use_hint && p.claim != CLAIM_CAS;
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
-                     dim3(kBlock), 0, s, level, parent, n, prefill ? g->hint_id : nullptr, w.vis,
-                     w.snap[0], w.snap[1], g->iso, W,
-                     (((uintptr_t)level | (uintptr_t)parent) & 15) == 0);
-  hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, root, level, parent, w.vis, w.q[0],
-                     w.qoff[0], ctr, g->row_ptr, g->nnz, g->nonisolated);
+                     dim3(kBlock), 0, s, root, level, parent, n,
+                     prefill ? g->hint_id : nullptr, w.vis, w.snap[0], w.snap[1], g->iso, W,
+                     (((uintptr_t)level | (uintptr_t)parent) & 15) == 0, w.q[0], w.qoff[0], ctr,
+                     g->row_ptr, g->nnz, g->nonisolated);
   G5_LAUNCH_CHECK();
 
   int cur = 0;                // queue holding the current frontier (top-down)
@@ -1228,36 +1209,35 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const int32_t *hint = use_hint ? g->hint : nullptr;
   const int32_t *hint_id = prefill ? nullptr : g->hint_id;
   const int64_t fh_words = use_hint ? (g->num_hot + 63) / 64 : 0;
-  // expansion grid: the workgroups that fit at once (tiles then advance as one
-  // window over the frontier's edges), unless set
+  // expansion grid: the workgroups that fit at once, at most kTdBlocksPerCu per
+  // compute unit (tiles then advance as one window over the frontier's edges),
+  // unless set
   const int td_per_cu =
       p.td_blocks_per_cu > 0
           ? p.td_blocks_per_cu
-          : resident_per_cu(min_parent ? (const void *)&k_td_expand<CLAIM_MIN>
-                                       : (p.claim == CLAIM_CAS ? (const void *)&k_td_expand<CLAIM_CAS>
-                                                               : (const void *)&k_td_expand<CLAIM_OR>),
-                            kBlock, 0);
+          : std::min(kTdBlocksPerCu,
+                     resident_per_cu(min_parent ? (const void *)&k_td_expand<CLAIM_MIN>
+                                     : (p.claim == CLAIM_CAS ? (const void *)&k_td_expand<CLAIM_CAS>
+                                                             : (const void *)&k_td_expand<CLAIM_OR>),
+                                     kBlock, 0));
   const int td_grid = ncu * td_per_cu;
 
-  // Top-down level lv from queue slot c: degree pass (+ visited snapshot), chunk
-  // scan with the level's direction decision (published under sq), expansion
-  // (runs only if the level stays top-down).  Queued ahead behind a level that
-  // did not expand, the level's queue is empty and nothing happens.
+  // Top-down level lv from queue slot c: the level's direction decision
+  // (published under sq) with the visited snapshot, then the expansion (runs
+  // only if the level stays top-down).  Queued ahead behind a level that did not
+  // expand, the level's queue is empty and nothing happens.
   auto launch_td = [&](int32_t lv, int c, unsigned long long sq, bool from_bu) -> g5_status {
     const int nx = c ^ 1;
     {
       g5_status st_ = rec(lv, 0);
       if (st_ != G5_OK) return st_;
     }
-    hipLaunchKernelGGL(k_td_deg, dim3(deg_grid), dim3(kBlock), 0, s,
-                       (const unsigned long long *)ctr, c, w.qoff[c], w.bsum, w.snap[lv & 1],
-                       w.vis, W);
-    hipLaunchKernelGGL(k_td_scan, dim3(1), dim3(kScanBlock), 0, s, w.bsum, ctr, c, lv, from_bu,
-                       rule, hpub, sq);
-#define G5_TD(C)                                                                             \
-  hipLaunchKernelGGL(k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c],    \
-                     w.bsum, ctr, c, g->rp32, g->col_idx, w.vis, w.snap[lv & 1], parent, level, \
-                     w.q[nx], w.qoff[nx], lv + 1)
+    hipLaunchKernelGGL(k_td_decide, dim3(decide_grid), dim3(kBlock), 0, s, ctr, c, lv, from_bu,
+                       rule, hpub, sq, w.snap[lv & 1], (const uint64_t *)w.vis, W);
+#define G5_TD(C)                                                                              \
+  hipLaunchKernelGGL(k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, \
+                     c, g->rp32, g->col_idx, w.vis, w.snap[lv & 1], parent, level, w.q[nx],     \
+                     w.qoff[nx], lv + 1)
     if (min_parent)
       G5_TD(CLAIM_MIN);
     else if (p.claim == CLAIM_CAS)
@@ -1440,16 +1420,12 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         bu_seq = spec_seq;
         continue;
       }
-      // top-down from here: bitmap -> queue (with degrees), the level's
+      // top-down from here: bitmap -> queue (with edge indices), the level's
       // decision, and its kernels
       bu_queued = false;
-      const int64_t chunk = (W + bu_grid - 1) / bu_grid;
-      const int fb = (int)((W + chunk - 1) / chunk);
-      hipLaunchKernelGGL(k_front_count, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum);
-      hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, s, w.bsum, (int64_t)fb,
-                         ctr + C_QLEN0 + cur, ctr + C_LASTNF, (unsigned long long)last_nf);
-      hipLaunchKernelGGL(k_front_write, dim3(fb), dim3(kBlock), 0, s, front, W, chunk, w.bsum,
-                         w.q[cur], w.qoff[cur], g->rp32);
+      hipLaunchKernelGGL(k_front_queue, dim3(grid_for(W, (int)kFqWords, ncu)), dim3(kBlock), 0, s,
+                         (const uint64_t *)front, W, g->rp32, w.q[cur], w.qoff[cur], ctr, cur,
+                         last_nf);
       G5_LAUNCH_CHECK();
       dec_seq = ++w.seq;
       {

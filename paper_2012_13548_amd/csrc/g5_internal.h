@@ -61,9 +61,8 @@ struct BfsWork {
   int sum_gs = 0;             // log2 of the vertices per summary bit
   uint64_t *fh = nullptr;     // frontier bits of the hot hint targets (bottom-up input)
   int32_t *q[2] = {nullptr, nullptr};  // frontier queues
-  uint32_t *qoff[2] = {nullptr, nullptr};  // per queue entry: its degree, then (after the
-                                           // degree pass) its edge offset in its chunk
-  uint32_t *bsum = nullptr;   // per-chunk partial sums
+  uint32_t *qoff[2] = {nullptr, nullptr};  // per queue entry: the index of its first edge
+                                           // in the queue's edge list
   uint64_t *ctr = nullptr;    // device counters (Ctr in bfs.hip)
   uint64_t *host_pub = nullptr;   // pinned, mapped: counters published by kernels + seq
   uint64_t *host_pub_dev = nullptr;  // its device address
