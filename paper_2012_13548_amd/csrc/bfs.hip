@@ -62,7 +62,9 @@ enum Ctr : int {
   C_UNV = 15,   // non-isolated vertices not reached yet
   C_QP0 = 16,   // queue 0: entries << 32 | degree sum (appended to by one atomic per block)
   C_QP1 = 17,   // queue 1: the same
-  C_NCTR = 18
+  C_XP0 = 18,   // lvl + 1 when the last top-down level of even lvl expanded, else 0
+  C_XP1 = 19,   // the same for odd levels
+  C_NCTR = 20
 };
 
 // Copies the counters to host memory.  Each 8-byte slot carries the low 16
@@ -177,10 +179,25 @@ __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool fro
   ctr[C_MF] = mf;
   ctr[C_GO] = go ? 1ull : 0ull;
   if (go) ctr[C_LASTNF] = (unsigned long long)qlen;
+  ctr[C_XP0 + (lvl & 1)] = go ? (unsigned long long)(lvl + 1) : 0ull;
   ctr[C_QLEN0 + qs] = (unsigned long long)qlen;
   ctr[C_QLEN0 + (qs ^ 1)] = 0;
   ctr[C_QP0 + (qs ^ 1)] = 0;
   publish(ctr, host, seq);
+}
+
+// parent = -1 for the non-isolated vertices not visited (grid-stride over words).
+__device__ __forceinline__ void unreached_words(const uint64_t *__restrict__ vis,
+                                                const uint64_t *__restrict__ iso, int64_t words,
+                                                int32_t *__restrict__ parent, int64_t stride) {
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
+    uint64_t m = ~(vis[w] | iso[w]);  // padding bits past n are set in iso
+    while (m) {
+      const int b = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      parent[w * kWave + b] = -1;
+    }
+  }
 }
 
 __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
@@ -191,8 +208,11 @@ __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
 // First kernel of a top-down level: the queue's counter gives Q and m_f, thread
 // 0 takes the level's direction decision (td_decide) and publishes it, and the
 // grid snapshots the visited bitmap into `snap` before the level's expansion.
-// Queued ahead behind a level that did not expand, the queue is empty: the
-// decision says so and the snapshot is skipped.
+// An empty queue skips the snapshot: either it was queued ahead behind a level
+// that did not expand, or the previous level expanded and found nothing, which
+// ends the traversal; then, when `fix` (the parent array pre-filled with hint
+// targets) is given, the grid also resets the parent of the unreached
+// non-isolated vertices to -1.
 __global__ __launch_bounds__(kBlock) void k_td_decide(unsigned long long *__restrict__ ctr,
                                                       int cur, int32_t lvl, bool from_bu,
                                                       TdRule rule,
@@ -200,13 +220,21 @@ __global__ __launch_bounds__(kBlock) void k_td_decide(unsigned long long *__rest
                                                       unsigned long long seq,
                                                       uint64_t *__restrict__ snap,
                                                       const uint64_t *__restrict__ vis,
-                                                      int64_t words) {
+                                                      int64_t words,
+                                                      const uint64_t *__restrict__ iso,
+                                                      int32_t *__restrict__ fix) {
   const unsigned long long qp = ctr[C_QP0 + cur];
   const int64_t qlen = (int64_t)(qp >> 32);
+  // read before thread 0 writes this level's tag (the other parity slot)
+  const bool ended = qlen == 0 && lvl > 0 &&
+                     ctr[C_XP0 + ((lvl - 1) & 1)] == (unsigned long long)lvl;
   if (blockIdx.x == 0 && threadIdx.x == 0)
     td_decide(ctr, cur, lvl, from_bu, rule, qlen, qp & 0xffffffffull, host, seq);
-  if (qlen == 0) return;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
+  if (qlen == 0) {
+    if (ended && fix) unreached_words(vis, iso, words, fix, stride);
+    return;
+  }
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride)
     snap[i] = vis[i];
 }
@@ -389,13 +417,29 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
 
 // Frontier bitmap of the last top-down level without atomics: the vertices
 // visited now but not before that level's expansion.
-__global__ void k_front_from_vis(const uint64_t *__restrict__ vis,
-                                 const uint64_t *__restrict__ prev, uint64_t *__restrict__ front,
-                                 int64_t words, unsigned long long *__restrict__ ctr, int64_t nf) {
+// The same launch builds fh (bit r = frontier bit of hot[r], one wavefront per
+// 64 hot targets) from the same two bitmaps, so the first bottom-up step needs
+// no separate pass for it.
+__global__ __launch_bounds__(kBlock) void k_front_from_vis(
+    const uint64_t *__restrict__ vis, const uint64_t *__restrict__ prev,
+    uint64_t *__restrict__ front, int64_t words, unsigned long long *__restrict__ ctr, int64_t nf,
+    const int32_t *__restrict__ hot, int64_t num_hot, uint64_t *__restrict__ fh) {
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_NFIN] = (unsigned long long)nf;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride)
     front[i] = vis[i] & ~prev[i];
+  const int lane = __lane_id();
+  for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) - lane; i0 < num_hot;
+       i0 += stride) {
+    const int64_t i = i0 + lane;
+    bool b = false;
+    if (i < num_hot) {
+      const int32_t t = hot[i];
+      b = ((vis[t >> 6] & ~prev[t >> 6]) >> (t & 63)) & 1;
+    }
+    const uint64_t m = __ballot(b);
+    if (lane == 0) fh[i0 >> 6] = m;
+  }
 }
 
 
@@ -877,15 +921,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
 // unreached non-isolated vertices get parent -1.
 __global__ void k_unreached(const uint64_t *__restrict__ vis, const uint64_t *__restrict__ iso,
                             int64_t words, int32_t *__restrict__ parent) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
-    uint64_t m = ~(vis[w] | iso[w]);  // padding bits past n are set in iso
-    while (m) {
-      const int b = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      parent[w * kWave + b] = -1;
-    }
-  }
+  unreached_words(vis, iso, words, parent, (int64_t)gridDim.x * blockDim.x);
 }
 
 // Frontier summary: bit i of sum = OR of front bits [i << gs, (i + 1) << gs).
@@ -1191,6 +1227,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
 
   int cur = 0;                // queue holding the current frontier (top-down)
   bool q_from_bu = false;     // the queue was filled from a bottom-up bitmap
+  bool ended_td = false;      // the traversal ended on an empty top-down queue
   int dir = 1;                // 1 top-down, 2 bottom-up
   int64_t nf_prev = 0;        // input frontier size of the bottom-up step
   int64_t last_nf = 0;        // frontier size of the previous level
@@ -1233,7 +1270,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       if (st_ != G5_OK) return st_;
     }
     hipLaunchKernelGGL(k_td_decide, dim3(decide_grid), dim3(kBlock), 0, s, ctr, c, lv, from_bu,
-                       rule, hpub, sq, w.snap[lv & 1], (const uint64_t *)w.vis, W);
+                       rule, hpub, sq, w.snap[lv & 1], (const uint64_t *)w.vis, W,
+                       (const uint64_t *)g->iso, prefill ? parent : nullptr);
 #define G5_TD(C)                                                                              \
   hipLaunchKernelGGL(k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, \
                      c, g->rp32, g->col_idx, w.vis, w.snap[lv & 1], parent, level, w.q[nx],     \
@@ -1249,15 +1287,16 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     return rec(lv, 1);
   };
 
+  // fh_ready: fh already holds the frontier bits of the hot targets
   auto launch_bu = [&](int32_t lv, const uint64_t *f, uint64_t *nfp, bool lds, bool check,
-                       unsigned long long sq) -> g5_status {
+                       unsigned long long sq, bool fh_ready) -> g5_status {
     if (lds) {
       hipLaunchKernelGGL(k_zero_u64, dim3(grid_for((lds_words + 1) / 2, kBlock, ncu * 16)),
                          dim3(kBlock), 0, s, (uint64_t *)w.sum, (lds_words + 1) / 2);
       hipLaunchKernelGGL(k_front_summary, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
                          s, f, W, lds_gs, w.sum);
     }
-    if (fh_words)
+    if (fh_words && !fh_ready)
       hipLaunchKernelGGL(k_fh_build, dim3(grid_for(g->num_hot, kBlock, ncu * 8)), dim3(kBlock),
                          0, s, f, g->hot, g->num_hot, w.fh);
     {
@@ -1352,13 +1391,17 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         reached += qlen;
         if (lvl - 1 < G5_MAX_STAT_LEVELS && stats) stats->discovered[lvl - 1] = qlen;
       }
-      if (qlen == 0) break;  // the queued kernels do nothing
+      if (qlen == 0) {  // the queued kernels do nothing
+        ended_td = true;  // this level's decision kernel reset the unreached parents
+        break;
+      }
       q_from_bu = false;
       if (!hc[C_GO]) {
         // bottom-up from here: frontier bitmap = visited now, not visited
         // before the last expansion
         hipLaunchKernelGGL(k_front_from_vis, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
-                           s, w.vis, w.snap[(lvl + 1) & 1], front, W, ctr, qlen);
+                           s, w.vis, w.snap[(lvl + 1) & 1], front, W, ctr, qlen, g->hot,
+                           fh_words ? g->num_hot : (int64_t)0, w.fh);
         G5_LAUNCH_CHECK();
         dir = 2;
         nf_prev = qlen;
@@ -1381,14 +1424,15 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                                  lds_density * (double)n;
         if (use_lds) ++lds_levels;
         bu_seq = ++w.seq;
-        g5_status st = launch_bu(lvl, front, next, use_lds, false, bu_seq);
+        // the first step after top-down: k_front_from_vis built fh
+        g5_status st = launch_bu(lvl, front, next, use_lds, false, bu_seq, true);
         if (st != G5_OK) return st;
       }
       // queue the next level's step too; it runs only if this one chooses
       // bottom-up again
       const unsigned long long spec_seq = ++w.seq;
       {
-        g5_status st = launch_bu(lvl + 1, next, front, false, true, spec_seq);
+        g5_status st = launch_bu(lvl + 1, next, front, false, true, spec_seq, false);
         if (st != G5_OK) return st;
       }
       {
@@ -1437,7 +1481,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     }
   }
 #undef G5_REC
-  if (prefill)
+  if (prefill && !ended_td)
     hipLaunchKernelGGL(k_unreached, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0, s,
                        w.vis, g->iso, W, parent);
   G5_LAUNCH_CHECK();
