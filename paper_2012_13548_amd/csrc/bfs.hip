@@ -1235,9 +1235,6 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   int64_t reached = 1;
   bool bu_queued = false;     // this level's bottom-up step was queued ahead (sequence bu_seq)
   unsigned long long bu_seq = 0;
-  // top-down: level lvl's kernels are queued and its scan publishes its
-  // direction under dec_seq
-  unsigned long long dec_seq = 0;
   uint64_t *front = w.front, *next = w.next;
   if (stats) *stats = g5_bfs_stats{};
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
@@ -1361,24 +1358,35 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     return rec(lv, 1);
   };
 
-  // the root's level
-  dec_seq = ++w.seq;
+  // Top-down levels are queued kTdAhead levels beyond the one whose decision
+  // the host waits for; td_seq[L % 4] is level L's publication sequence.  A
+  // level queued behind one that did not expand finds its queue empty and does
+  // nothing.  Queueing two levels ahead measured slower at scale 26: the
+  // device rarely waited for the host, and every switch or end ran one more
+  // empty level.  (At most kTdAhead + 1 publications are unread, fewer than
+  // kPubBufs.)
+  constexpr int kTdAhead = 1;
+  unsigned long long td_seq[4] = {0, 0, 0, 0};
+  int32_t td_queued = 0;  // highest top-down level queued
+  td_seq[0] = ++w.seq;
   {
-    g5_status st = launch_td(0, 0, dec_seq, false);
+    g5_status st = launch_td(0, 0, td_seq[0], false);
     if (st != G5_OK) return st;
   }
   while (true) {
     if (dir == 1) {
-      // level lvl's kernels are queued; queue level lvl + 1's behind them (they
-      // run only if level lvl + 1 stays top-down), then read level lvl's decision
+      // level lvl's kernels are queued; queue the next levels behind them, then
+      // read level lvl's decision
       const int nxt = cur ^ 1;
-      const unsigned long long spec_seq = ++w.seq;
-      {
-        g5_status st = launch_td(lvl + 1, nxt, spec_seq, false);
+      while (td_queued < lvl + kTdAhead) {
+        ++td_queued;
+        const unsigned long long sq = ++w.seq;
+        td_seq[td_queued & 3] = sq;
+        g5_status st = launch_td(td_queued, cur ^ ((td_queued - lvl) & 1), sq, false);
         if (st != G5_OK) return st;
       }
       {
-        g5_status st = wait_published(w, s, dec_seq, hc);
+        g5_status st = wait_published(w, s, td_seq[lvl & 3], hc);
         if (st != G5_OK) return st;
       }
       if (hc[C_ERR]) {
@@ -1413,7 +1421,6 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         stats->frontier[i] = qlen;
         stats->edges[i] = mf;
       }
-      dec_seq = spec_seq;
       cur = nxt;
       last_nf = qlen;
       ++lvl;
@@ -1471,9 +1478,10 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                          (const uint64_t *)front, W, g->rp32, w.q[cur], w.qoff[cur], ctr, cur,
                          last_nf);
       G5_LAUNCH_CHECK();
-      dec_seq = ++w.seq;
+      td_queued = lvl;  // top-down levels queued before the bottom-up steps did nothing
+      td_seq[lvl & 3] = ++w.seq;
       {
-        g5_status st = launch_td(lvl, cur, dec_seq, true);
+        g5_status st = launch_td(lvl, cur, td_seq[lvl & 3], true);
         if (st != G5_OK) return st;
       }
       q_from_bu = true;

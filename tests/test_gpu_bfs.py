@@ -119,6 +119,17 @@ def test_lane_scan_variants(kron10, lane_scan):
         c.check_root(r, lane_scan=lane_scan)
 
 
+@pytest.mark.parametrize("td_blocks_per_cu", [1, 3, 17])
+@pytest.mark.parametrize("direction", [g5.DIR_TOPDOWN, g5.DIR_AUTO])
+def test_expansion_grid_variants(kron16, td_blocks_per_cu, direction):
+    # tiles advance over the frontier's edges in grid-stride rounds; a small grid
+    # takes many rounds per workgroup, so every tile's appends share the queue's
+    # packed counter across rounds
+    c, roots = kron16
+    for r in roots[:3]:
+        c.check_root(r, direction=direction, td_blocks_per_cu=td_blocks_per_cu)
+
+
 @pytest.fixture(scope="module")
 def kron16():
     scale = 16
