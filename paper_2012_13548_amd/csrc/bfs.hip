@@ -952,14 +952,19 @@ __global__ void k_front_summary(const uint64_t *__restrict__ front, int64_t word
   }
 }
 
-// Bitmap -> queue of the next top-down level: in each round a block takes the
-// next kFqWords words (kFqWords / kBlock consecutive words per thread), numbers
-// their vertices and degrees by a block prefix sum of (count << 32 | degree
-// sum), and one atomic on the queue's packed counter (zero before) places them
-// and their edge indices.  Block 0 also sets the direction state's previous
-// frontier size.
+// Bitmap -> queue of the next top-down level, in rounds of kFqWords words per
+// block (kFqPer consecutive words per thread).  A round's vertices are
+// numbered by a block prefix sum of popcounts; when at most kFqCap of them
+// (the usual case: the switch happens at fewer than n / beta vertices) they are
+// staged in LDS in vertex order, their degrees loaded in parallel, and a block
+// prefix sum of the degrees plus one atomic on the queue's packed counter
+// (entries << 32 | degree sum, zero before) places them with their edge
+// indices.  A denser round walks each thread's words serially instead.  Block
+// 0 also sets the direction state's previous frontier size.
 constexpr int kFqPer = 16;
 constexpr int64_t kFqWords = (int64_t)kBlock * kFqPer;
+constexpr uint32_t kFqCap = 2048;
+constexpr int kFqItems = kFqCap / kBlock;  // staged vertices per thread at most
 
 __global__ __launch_bounds__(kBlock) void k_front_queue(const uint64_t *__restrict__ bm,
                                                         int64_t words,
@@ -968,17 +973,70 @@ __global__ __launch_bounds__(kBlock) void k_front_queue(const uint64_t *__restri
                                                         uint32_t *__restrict__ qo,
                                                         unsigned long long *__restrict__ ctr,
                                                         int cur, int64_t last_nf) {
+  __shared__ int32_t s_v[kFqCap];
+  __shared__ uint32_t s32[kBlock / kWave];
   __shared__ unsigned long long s[kBlock / kWave];
   __shared__ unsigned long long s_g;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_LASTNF] = (unsigned long long)last_nf;
   for (int64_t r0 = (int64_t)blockIdx.x * kFqWords; r0 < words;
        r0 += (int64_t)gridDim.x * kFqWords) {
     const int64_t w0 = r0 + (int64_t)threadIdx.x * kFqPer;
-    unsigned long long mine = 0;  // count << 32 | degree sum of this thread's words
+    uint32_t cnt = 0;
+    for (int j = 0; j < kFqPer; ++j)
+      if (w0 + j < words) cnt += (uint32_t)__popcll(bm[w0 + j]);
+    uint32_t total;
+    const uint32_t first = block_excl_scan<kBlock, uint32_t>(cnt, s32, total);
+    if (total == 0) continue;  // uniform: the block's sum
+    if (total <= kFqCap) {
+      uint32_t p = first;
+      for (int j = 0; j < kFqPer && p < first + cnt; ++j) {
+        uint64_t x = w0 + j < words ? bm[w0 + j] : 0ull;
+        while (x) {
+          s_v[p++] = (int32_t)((w0 + j) * kWave + __ffsll((unsigned long long)x) - 1);
+          x &= x - 1;
+        }
+      }
+      __syncthreads();
+      // thread t: the staged entries [k0, k1), their degrees loaded together
+      const uint32_t per = (total + kBlock - 1) / kBlock;
+      const uint32_t k0 = std::min<uint32_t>(total, threadIdx.x * per);
+      const uint32_t k1 = std::min<uint32_t>(total, k0 + per);
+      uint32_t d[kFqItems];
+      uint32_t sum = 0;
+#pragma unroll
+      for (int j = 0; j < kFqItems; ++j) {
+        d[j] = 0;
+        if (k0 + j < k1) {
+          uint32_t be[2];
+          __builtin_memcpy(be, rp + s_v[k0 + j], 8);
+          d[j] = be[1] - be[0];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kFqItems; ++j) sum += d[j];
+      unsigned long long tot;
+      const unsigned long long ex = block_excl_scan<kBlock, unsigned long long>(
+          ((unsigned long long)(k1 - k0) << 32) | sum, s, tot);
+      if (threadIdx.x == 0) s_g = atomicAdd(ctr + C_QP0 + cur, tot);
+      __syncthreads();
+      const unsigned long long g = s_g + ex;
+      const uint64_t pos = g >> 32;
+      uint32_t off = (uint32_t)g;
+#pragma unroll
+      for (int j = 0; j < kFqItems; ++j)
+        if (k0 + j < k1) {
+          q[pos + j] = s_v[k0 + j];
+          qo[pos + j] = off;
+          off += d[j];
+        }
+      __syncthreads();  // s_v and s_g are rewritten by the next round
+      continue;
+    }
+    // dense round: each thread walks its own words
+    unsigned long long mine = (unsigned long long)cnt << 32;  // count << 32 | degree sum
     for (int j = 0; j < kFqPer; ++j) {
       const int64_t w = w0 + j;
       uint64_t x = w < words ? bm[w] : 0ull;
-      mine += (unsigned long long)__popcll(x) << 32;
       while (x) {
         const int32_t v = (int32_t)(w * kWave + __ffsll((unsigned long long)x) - 1);
         x &= x - 1;
@@ -989,14 +1047,13 @@ __global__ __launch_bounds__(kBlock) void k_front_queue(const uint64_t *__restri
     }
     unsigned long long tot;
     const unsigned long long ex = block_excl_scan<kBlock, unsigned long long>(mine, s, tot);
-    if (tot == 0) continue;  // uniform: tot is the block's sum
     if (threadIdx.x == 0) s_g = atomicAdd(ctr + C_QP0 + cur, tot);
     __syncthreads();
     const unsigned long long g = s_g + ex;
     uint64_t pos = g >> 32;
     uint32_t off = (uint32_t)g;
     __syncthreads();  // s_g is rewritten by the next round
-    if (!(mine >> 32)) continue;
+    if (!cnt) continue;
     for (int j = 0; j < kFqPer; ++j) {
       const int64_t w = w0 + j;
       uint64_t x = w < words ? bm[w] : 0ull;
