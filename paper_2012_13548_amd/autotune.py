@@ -24,7 +24,7 @@ LANE = [1, 2, 4, 8, 16]
 BPC = [4, 8, 16, 32]
 VPL = [1, 2]
 PACKED = [0, 1]
-LDS_KB = [32, 64, 96, 140]
+LDS_KB = [16, 24, 32, 64, 140]
 LDS_DENSITY = [0.01, 0.03, 0.1, 0.3, 1.0]
 GAMMA = [-1.0, 0.7, 1.0, 1.4, 2.0, 3.0]
 B_ALPHA = [2, 4, 8, 14, 28, 56, 112]
@@ -96,7 +96,7 @@ def tune_scale(scale, nroots, rounds):
 
     t0 = time.time()
     start = dict(alpha=20, beta=96, lane_scan=8, bu_blocks_per_cu=32, vertices_per_lane=1, packed=1,
-                 lds_kb=140, lds_density=0.3, gamma=-1.0)
+                 lds_kb=16, lds_density=0.3, gamma=-1.0)
     single(start)  # warm
     cfg, best = search(start, {"alpha": ALPHA, "beta": BETA, "lane_scan": LANE,
                                "bu_blocks_per_cu": BPC, "vertices_per_lane": VPL,

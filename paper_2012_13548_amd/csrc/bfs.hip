@@ -887,8 +887,12 @@ constexpr int kLdsBlock = 1024;
 // k_bu_step_lds's own LDS arrays (about 24 KiB), with margin
 constexpr int64_t kBuStaticLds = 28 * 1024;
 
+// At most 64 VGPRs (8 waves per SIMD, a few values spilled): with a staged
+// frontier of up to ~55 KB (summary + fh) two workgroups share a compute unit,
+// 32 waves instead of 16, which made the sparse-frontier steps of a scale-26
+// graph ~27 % faster; with more LDS one workgroup fits and the spills only cost.
 template <int LANE_SCAN, int R, bool ACCT>
-__global__ __launch_bounds__(kLdsBlock) void k_bu_step_lds(
+__global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_bu_step_lds(
     const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const int32_t *__restrict__ hint, const int32_t *__restrict__ hint_id,
     const uint64_t *__restrict__ fh, int64_t fh_words, uint64_t *__restrict__ vis,
