@@ -92,7 +92,7 @@ typedef enum {
 typedef struct {
   int32_t direction;      /* g5_direction */
   int32_t bu_lane_scan;   /* neighbours a lane tests before its row goes wave-wide: 1, 2, 4, 8
-                             or 16 */
+                             or 16 (steps with the frontier staged in LDS use at most 4) */
   double alpha;           /* top-down -> bottom-up when m_f > m_u / alpha and the frontier grew */
   double beta;            /* bottom-up -> top-down when n_f < n / beta and the frontier shrank */
   double lds_density;     /* bottom-up steps stage the frontier (or a summary of it) in LDS when
