@@ -92,12 +92,12 @@ __device__ void publish(const unsigned long long *ctr, unsigned long long *host,
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Start of a traversal from `root`: level = -1 and parent = fill (the hint
-// targets) or -1, except at the root (level 0, its own parent); visited bitmap
-// = the isolated vertices and the root, its snapshots = the isolated vertices;
-// counters zeroed, then queue 0 = {root} (edge index 0, its degree in the
-// queue's counter) and the direction state of the root's level.
-__global__ void k_bfs_init(int64_t root, int32_t *__restrict__ level,
+// Start of a traversal from `root`: byte levels = 0xff and parent = fill (the
+// hint targets) or -1, except at the root (level 0, its own parent); visited
+// bitmap = the isolated vertices and the root, its snapshots = the isolated
+// vertices; counters zeroed, then queue 0 = {root} (edge index 0, its degree in
+// the queue's counter) and the direction state of the root's level.
+__global__ void k_bfs_init(int64_t root, uint8_t *__restrict__ lev8,
                            int32_t *__restrict__ parent, int64_t n,
                            const int32_t *__restrict__ fill, uint64_t *__restrict__ vis,
                            uint64_t *__restrict__ prev0, uint64_t *__restrict__ prev1,
@@ -112,18 +112,17 @@ __global__ void k_bfs_init(int64_t root, int32_t *__restrict__ level,
   const v4i m1 = {-1, -1, -1, -1};
   // streaming (non-temporal) accesses: the arrays are far larger than L2
   for (int64_t i = t; i < n4; i += stride) {
-    v4i lv = m1;
     v4i f = fill ? __builtin_nontemporal_load(reinterpret_cast<const v4i *>(fill) + i) : m1;
-    if (i == (root >> 2)) {
-      lv[root & 3] = 0;
-      f[root & 3] = (int32_t)root;
-    }
-    __builtin_nontemporal_store(lv, reinterpret_cast<v4i *>(level) + i);
+    if (i == (root >> 2)) f[root & 3] = (int32_t)root;
     __builtin_nontemporal_store(f, reinterpret_cast<v4i *>(parent) + i);
   }
-  for (int64_t i = n4 * 4 + t; i < n; i += stride) {
-    level[i] = i == root ? 0 : -1;
+  for (int64_t i = n4 * 4 + t; i < n; i += stride)
     parent[i] = i == root ? (int32_t)root : (fill ? fill[i] : -1);
+  // lev8 is 16-byte aligned and padded to a multiple of 16 bytes
+  for (int64_t i = t; i < (n + 15) / 16; i += stride) {
+    v4i x = m1;
+    if (i == (root >> 4)) reinterpret_cast<uint8_t *>(&x)[root & 15] = 0;
+    __builtin_nontemporal_store(x, reinterpret_cast<v4i *>(lev8) + i);
   }
   const int64_t rw = root >> 6;
   for (int64_t i = t; i < words; i += stride) {
@@ -186,6 +185,41 @@ __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool fro
   publish(ctr, host, seq);
 }
 
+// Levels are kept as bytes (lev8, 0xff = not reached) while they fit, so the
+// scattered level writes of a traversal touch a quarter of the bytes; the
+// int32 output is written once, by a streaming pass at the end (or, on a graph
+// deeper than kByteLevels, before the first level that would not fit, after
+// which kernels write int32 levels directly: lev8 == nullptr).
+constexpr int32_t kByteLevels = 254;  // levels 0..254 fit a byte beside 0xff
+
+__device__ __forceinline__ void put_level(uint8_t *lev8, int32_t *level, int32_t v,
+                                          int32_t lvl) {
+  if (lev8)
+    lev8[v] = (uint8_t)lvl;
+  else
+    level[v] = lvl;
+}
+
+// level = lev8 widened (0xff -> -1), 4 vertices per thread, grid-stride.
+__device__ __forceinline__ void expand_levels(const uint8_t *__restrict__ lev8,
+                                              int32_t *__restrict__ level, int64_t n, bool vec,
+                                              int64_t stride) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n4 = vec ? n / 4 : 0;
+  for (int64_t i = t; i < n4; i += stride) {
+    const uint32_t x = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(lev8) + i);
+    v4i o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t b = (x >> (8 * j)) & 0xffu;
+      o[j] = b == 0xffu ? -1 : (int)b;
+    }
+    __builtin_nontemporal_store(o, reinterpret_cast<v4i *>(level) + i);
+  }
+  for (int64_t i = n4 * 4 + t; i < n; i += stride) level[i] = lev8[i] == 0xff ? -1 : lev8[i];
+}
+
 // parent = -1 for the non-isolated vertices not visited (grid-stride over words).
 __device__ __forceinline__ void unreached_words(const uint64_t *__restrict__ vis,
                                                 const uint64_t *__restrict__ iso, int64_t words,
@@ -210,9 +244,9 @@ __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
 // grid snapshots the visited bitmap into `snap` before the level's expansion.
 // An empty queue skips the snapshot: either it was queued ahead behind a level
 // that did not expand, or the previous level expanded and found nothing, which
-// ends the traversal; then, when `fix` (the parent array pre-filled with hint
-// targets) is given, the grid also resets the parent of the unreached
-// non-isolated vertices to -1.
+// ends the traversal; then the grid also resets the parent of the unreached
+// non-isolated vertices to -1 when `fix` (the parent array pre-filled with
+// hint targets) is given, and widens the byte levels into `level` when lev8 is.
 __global__ __launch_bounds__(kBlock) void k_td_decide(unsigned long long *__restrict__ ctr,
                                                       int cur, int32_t lvl, bool from_bu,
                                                       TdRule rule,
@@ -222,7 +256,10 @@ __global__ __launch_bounds__(kBlock) void k_td_decide(unsigned long long *__rest
                                                       const uint64_t *__restrict__ vis,
                                                       int64_t words,
                                                       const uint64_t *__restrict__ iso,
-                                                      int32_t *__restrict__ fix) {
+                                                      int32_t *__restrict__ fix,
+                                                      const uint8_t *__restrict__ lev8,
+                                                      int32_t *__restrict__ level, int64_t n,
+                                                      bool vec) {
   const unsigned long long qp = ctr[C_QP0 + cur];
   const int64_t qlen = (int64_t)(qp >> 32);
   // read before thread 0 writes this level's tag (the other parity slot)
@@ -233,6 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_td_decide(unsigned long long *__rest
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   if (qlen == 0) {
     if (ended && fix) unreached_words(vis, iso, words, fix, stride);
+    if (ended && lev8) expand_levels(lev8, level, n, vec, stride);
     return;
   }
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride)
@@ -296,8 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
     unsigned long long *__restrict__ ctr, int cur,
     const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     uint64_t *vis, const uint64_t *__restrict__ prev, int32_t *parent,
-    int32_t *__restrict__ level, int32_t *__restrict__ qn, uint32_t *__restrict__ qon,
-    int32_t next_level) {
+    int32_t *__restrict__ level, uint8_t *__restrict__ lev8, int32_t *__restrict__ qn,
+    uint32_t *__restrict__ qon, int32_t next_level) {
   __shared__ uint32_t s_off[kTdTile + 1];
   __shared__ int32_t s_src[kTdTile];
   __shared__ int64_t s_base[kTdTile];
@@ -358,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
             atomicMin((unsigned int *)(parent + v), (unsigned int)u);
             if (!(*wp & bit)) {
               won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
-              if (won) level[v] = next_level;
+              if (won) put_level(lev8, level, v, next_level);
             }
           }
         } else if (!(*wp & bit)) {
@@ -369,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
             won = atomicCAS(parent + v, -1, u) == -1;
             if (won) atomicOr((unsigned long long *)wp, (unsigned long long)bit);
           }
-          if (won) level[v] = next_level;
+          if (won) put_level(lev8, level, v, next_level);
         }
       }
       wv[j] = v;
@@ -622,7 +660,8 @@ __device__ __forceinline__ void bu_chunks(
     const int32_t *__restrict__ ci, const int32_t *__restrict__ hint,
     const int32_t *__restrict__ hint_id, uint64_t *__restrict__ vis,
     uint64_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ level,
-    int64_t words, int32_t next_level, bool packed, int64_t gw, int64_t nw, int64_t *s_base,
+    uint8_t *__restrict__ lev8, int64_t words, int32_t next_level, bool packed, int64_t gw,
+    int64_t nw, int64_t *s_base,
     int32_t *s_row, int32_t *s_first, unsigned long long *s_nx, BuCount &cnt) {
   const int lane = __lane_id();
   unsigned long long *nx = s_nx + (threadIdx.x / kWave) * kWave;
@@ -765,7 +804,7 @@ __device__ __forceinline__ void bu_chunks(
             parent[v[j]] = par[j];
           else if (hint_id)
             parent[v[j]] = par[j] >= 0 ? par[j] : hint_id[v[j]];
-          level[v[j]] = next_level;
+          put_level(lev8, level, v[j], next_level);
           atomicOr(&nx[wl[j]], 1ull << bit[j]);
         }
       }
@@ -858,8 +897,8 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
     const int32_t *__restrict__ hint, const int32_t *__restrict__ hint_id,
     const uint64_t *__restrict__ fh, int64_t fh_words, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
-    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words,
-    int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
+    int32_t *__restrict__ parent, int32_t *__restrict__ level, uint8_t *__restrict__ lev8,
+    int64_t words, int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
     unsigned long long *__restrict__ host, unsigned long long seq, bool check_go, BuNext bn) {
   extern __shared__ uint64_t s_fh[];
   if (check_go && !ctr[C_BUGO]) return;  // queued ahead; the last step chose top-down
@@ -874,7 +913,7 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
   const int64_t nw = ((int64_t)gridDim.x * kBuBlock) / kWave;
   BuCount c;
   bu_chunks<LANE_SCAN, R, ACCT>(FrontGlobal{(const uint32_t *)front}, s_fh, rp, ci, hint, hint_id, vis, next,
-                                parent, level, words, next_level, packed, gw, nw, s_base, s_row,
+                                parent, level, lev8, words, next_level, packed, gw, nw, s_base, s_row,
                                 s_first, s_nx, c);
   bu_flush<kBuBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
@@ -897,8 +936,8 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
     const int32_t *__restrict__ hint, const int32_t *__restrict__ hint_id,
     const uint64_t *__restrict__ fh, int64_t fh_words, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
-    int32_t *__restrict__ parent, int32_t *__restrict__ level, int64_t words,
-    int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
+    int32_t *__restrict__ parent, int32_t *__restrict__ level, uint8_t *__restrict__ lev8,
+    int64_t words, int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
     const uint32_t *__restrict__ sum, int64_t sum_words, int gs,
     unsigned long long *__restrict__ host, unsigned long long seq, BuNext bn) {
   extern __shared__ uint64_t s_dyn[];
@@ -916,16 +955,22 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
   const int64_t nw = ((int64_t)gridDim.x * kLdsBlock) / kWave;
   BuCount c;
   bu_chunks<LANE_SCAN, R, ACCT>(FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, vis,
-                                next, parent, level, words, next_level, packed, gw, nw, s_base,
+                                next, parent, level, lev8, words, next_level, packed, gw, nw, s_base,
                                 s_row, s_first, s_nx, c);
   bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
 
-// After a traversal whose parent array was pre-filled with hint targets: the
-// unreached non-isolated vertices get parent -1.
-__global__ void k_unreached(const uint64_t *__restrict__ vis, const uint64_t *__restrict__ iso,
-                            int64_t words, int32_t *__restrict__ parent) {
-  unreached_words(vis, iso, words, parent, (int64_t)gridDim.x * blockDim.x);
+// End of a traversal not ended by a top-down decision kernel: the unreached
+// non-isolated vertices get parent -1 when the parent array was pre-filled with
+// hint targets (fix), and the byte levels are widened into `level` when lev8 is
+// given (also used alone before the first level deeper than kByteLevels).
+__global__ void k_finish(const uint64_t *__restrict__ vis, const uint64_t *__restrict__ iso,
+                         int64_t words, int32_t *__restrict__ fix,
+                         const uint8_t *__restrict__ lev8, int32_t *__restrict__ level,
+                         int64_t n, bool vec) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (fix) unreached_words(vis, iso, words, fix, stride);
+  if (lev8) expand_levels(lev8, level, n, vec, stride);
 }
 
 // Frontier summary: bit i of sum = OR of front bits [i << gs, (i + 1) << gs).
@@ -1118,6 +1163,7 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
   };
   A((void **)&w->vis, W * 8);
+  A((void **)&w->lev8, ((n + 15) / 16) * 16);
   A((void **)&w->front, W * 8);
   A((void **)&w->next, W * 8);
   A((void **)&w->snap[0], W * 8);
@@ -1168,6 +1214,7 @@ struct WorkLease {
 
 BfsWork::~BfsWork() {
   if (vis) (void)hipFree(vis);
+  if (lev8) (void)hipFree(lev8);
   if (front) (void)hipFree(front);
   if (next) (void)hipFree(next);
   for (auto *p : snap)
@@ -1280,11 +1327,26 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   // reset at the end).  Compare-and-swap claims need parent -1.
   const bool prefill = use_hint && p.claim != CLAIM_CAS;
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
-                     dim3(kBlock), 0, s, root, level, parent, n,
+                     dim3(kBlock), 0, s, root, w.lev8, parent, n,
                      prefill ? g->hint_id : nullptr, w.vis, w.snap[0], w.snap[1], g->iso, W,
-                     (((uintptr_t)level | (uintptr_t)parent) & 15) == 0, w.q[0], w.qoff[0], ctr,
-                     g->row_ptr, g->nnz, g->nonisolated);
+                     ((uintptr_t)parent & 15) == 0, w.q[0], w.qoff[0], ctr, g->row_ptr, g->nnz,
+                     g->nonisolated);
   G5_LAUNCH_CHECK();
+  // Levels go to the byte array while they fit; the kernels of level lv (writing
+  // lv + 1) get sink(lv), which widens the bytes into `level` once, before the
+  // first level that does not fit, and returns nullptr from then on.
+  const bool lvec = ((uintptr_t)level & 15) == 0;
+  const int finish_grid = grid_for(std::max(n / 4, W), kBlock, ncu * 16);
+  bool widened = false;
+  auto sink = [&](int32_t lv) -> uint8_t * {
+    if (lv + 1 <= kByteLevels) return w.lev8;
+    if (!widened) {
+      hipLaunchKernelGGL(k_finish, dim3(finish_grid), dim3(kBlock), 0, s, w.vis, g->iso, W,
+                         nullptr, (const uint8_t *)w.lev8, level, n, lvec);
+      widened = true;
+    }
+    return nullptr;
+  };
 
   int cur = 0;                // queue holding the current frontier (top-down)
   bool q_from_bu = false;     // the queue was filled from a bottom-up bitmap
@@ -1327,12 +1389,14 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       g5_status st_ = rec(lv, 0);
       if (st_ != G5_OK) return st_;
     }
+    uint8_t *l8 = sink(lv);
     hipLaunchKernelGGL(k_td_decide, dim3(decide_grid), dim3(kBlock), 0, s, ctr, c, lv, from_bu,
                        rule, hpub, sq, w.snap[lv & 1], (const uint64_t *)w.vis, W,
-                       (const uint64_t *)g->iso, prefill ? parent : nullptr);
+                       (const uint64_t *)g->iso, prefill ? parent : nullptr,
+                       (const uint8_t *)l8, level, n, lvec);
 #define G5_TD(C)                                                                              \
   hipLaunchKernelGGL(k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, \
-                     c, g->rp32, g->col_idx, w.vis, w.snap[lv & 1], parent, level, w.q[nx],     \
+                     c, g->rp32, g->col_idx, w.vis, w.snap[lv & 1], parent, level, l8, w.q[nx], \
                      w.qoff[nx], lv + 1)
     if (min_parent)
       G5_TD(CLAIM_MIN);
@@ -1348,6 +1412,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   // fh_ready: fh already holds the frontier bits of the hot targets
   auto launch_bu = [&](int32_t lv, const uint64_t *f, uint64_t *nfp, bool lds, bool check,
                        unsigned long long sq, bool fh_ready) -> g5_status {
+    uint8_t *l8 = sink(lv);
     if (lds) {
       hipLaunchKernelGGL(k_zero_u64, dim3(grid_for((lds_words + 1) / 2, kBlock, ncu * 16)),
                          dim3(kBlock), 0, s, (uint64_t *)w.sum, (lds_words + 1) / 2);
@@ -1370,8 +1435,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     const int per_cu_ = resident_per_cu(fn_, kLdsBlock, dyn_);                              \
     hipLaunchKernelGGL((k_bu_step_lds<K, P, A>), dim3(ncu * per_cu_), dim3(kLdsBlock), dyn_, s, \
                        g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words, w.vis, f, nfp,     \
-                       parent, level, W, lv + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub,   \
-                       sq, bn);                                                             \
+                       parent, level, l8, W, lv + 1, ctr, packed, w.sum, lds_words, lds_gs,     \
+                       hpub, sq, bn);                                                       \
   } while (0)
 #define G5_BU(K, P, A)                                                                      \
   do {                                                                                      \
@@ -1382,8 +1447,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     const int per_cu_ = resident_per_cu(fn_, kBuBlock, dyn_);                               \
     hipLaunchKernelGGL((k_bu_step<K, P, A>), dim3(ncu * std::min(bu_bpc, per_cu_)),         \
                        dim3(kBuBlock), dyn_, s, g->rp32, g->col_idx, hint, hint_id, w.fh,      \
-                       fh_words, w.vis, f, nfp, parent, level, W, lv + 1, ctr, packed, hpub,  \
-                       sq, check, bn);                                                      \
+                       fh_words, w.vis, f, nfp, parent, level, l8, W, lv + 1, ctr, packed,    \
+                       hpub, sq, check, bn);                                                \
   } while (0)
 #define G5_BU_P(M, K, A)          \
   if (vpl == 2)                   \
@@ -1525,10 +1590,12 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         stats->discovered[i] = nnew;
         if (acct) {
           stats->edges[i] = hc[C_SCAN];
-          // parent is not written for hint hits when it was pre-filled
+          // parent is not written for hint hits when it was pre-filled; a level
+          // is one byte while levels fit the byte array
           const int64_t pw = prefill ? nnew - hc[C_HINT] : nnew;
+          const int64_t lb = i + 1 <= kByteLevels ? 1 : 4;
           stats->bytes[i] = (use_hint ? 4 : 0) * hc[C_UNVIS] + 4 * hc[C_ROWS] +
-                            4 * hc[C_SCAN] + 16 * W + 4 * nnew + 4 * pw;
+                            4 * hc[C_SCAN] + 16 * W + lb * nnew + 4 * pw;
         }
       }
       reached += nnew;
@@ -1560,9 +1627,11 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     }
   }
 #undef G5_REC
-  if (prefill && !ended_td)
-    hipLaunchKernelGGL(k_unreached, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0, s,
-                       w.vis, g->iso, W, parent);
+  // a traversal ended by a top-down decision kernel was finished by it
+  if (!ended_td && (prefill || !widened))
+    hipLaunchKernelGGL(k_finish, dim3(finish_grid), dim3(kBlock), 0, s, w.vis, g->iso, W,
+                       prefill ? parent : nullptr, widened ? nullptr : (const uint8_t *)w.lev8,
+                       level, n, lvec);
   G5_LAUNCH_CHECK();
   G5_HIP(hipStreamSynchronize(s));
   if (stats) {
@@ -1578,7 +1647,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i)
         if (stats->dir[i] == 1)
           stats->bytes[i] = 12 * stats->frontier[i] + 4 * stats->edges[i] +
-                            24 * stats->discovered[i];
+                            (i + 1 <= kByteLevels ? 21 : 24) * stats->discovered[i];
     if (timed)
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i) {
         float a = 0;

@@ -52,6 +52,7 @@ void set_error(const std::string &msg);
 struct BfsWork {
   int64_t n = 0, words = 0;
   uint64_t *vis = nullptr;    // visited bitmap (isolated vertices pre-set)
+  uint8_t *lev8 = nullptr;    // levels as bytes while they fit (0xff = not reached)
   uint64_t *front = nullptr;  // frontier bitmap (bottom-up input)
   uint64_t *next = nullptr;   // next-frontier bitmap (bottom-up output)
   uint64_t *snap[2] = {nullptr, nullptr};  // visited bitmap before each top-down
