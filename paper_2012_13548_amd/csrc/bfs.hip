@@ -654,7 +654,15 @@ __device__ __forceinline__ int select_bit(uint64_t x, uint32_t r) {
 // pre-filled with every vertex's hint target, hint_id == nullptr, and the hint
 // was the hit) and OR their bit into the chunk's next-frontier words in LDS,
 // written out with the visited words at the end: no global atomics.
-template <int LANE_SCAN, int R, bool ACCT, class Front>
+//
+// COMPACT (one vertex per lane): rounds test hints only; the vertices whose hint
+// missed and that have a row go to a ring of kRing entries per wavefront in LDS
+// (s_ring), and whenever 64 are queued (and at the chunk's end) a round scans
+// their rows with every lane busy.  On a dense frontier most hints hit, so
+// without this nearly every round waited for the row reads of a few lanes.
+constexpr uint32_t kRing = 128;
+
+template <int LANE_SCAN, int R, bool ACCT, class Front, bool COMPACT = false>
 __device__ __forceinline__ void bu_chunks(
     const Front &F, const uint64_t *fh, const uint32_t *__restrict__ rp,
     const int32_t *__restrict__ ci, const int32_t *__restrict__ hint,
@@ -662,10 +670,137 @@ __device__ __forceinline__ void bu_chunks(
     uint64_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ level,
     uint8_t *__restrict__ lev8, int64_t words, int32_t next_level, bool packed, int64_t gw,
     int64_t nw, int64_t *s_base,
-    int32_t *s_row, int32_t *s_first, unsigned long long *s_nx, BuCount &cnt) {
+    int32_t *s_row, int32_t *s_first, unsigned long long *s_nx, BuCount &cnt,
+    int32_t *s_ring = nullptr) {
   const int lane = __lane_id();
   unsigned long long *nx = s_nx + (threadIdx.x / kWave) * kWave;
   const int64_t chunks = (words + kWave - 1) / kWave;
+  if constexpr (COMPACT) {
+    static_assert(R == 1, "the compact form takes one vertex per lane");
+    int32_t *ring = s_ring + (threadIdx.x / kWave) * kRing;
+    const uint64_t lt = lanemask_lt();
+    for (int64_t c = gw; c < chunks; c += nw) {
+      const int64_t w = c * kWave + lane;
+      const uint64_t vw = (w < words) ? vis[w] : ~0ull;  // padding past n is pre-set in iso
+      const uint64_t un = ~vw;
+      const uint32_t cl = (uint32_t)__popcll(un);
+      const uint32_t incl = wave_incl_scan(cl);
+      const uint32_t total = __shfl(incl, kWave - 1, kWave);
+      const uint32_t excl = incl - cl;
+      nx[lane] = 0ull;
+      uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      // a round over `take` (<= 64) queued vertices, one per lane: row offsets,
+      // the first LANE_SCAN entries, then the wavefront-wide scan
+      auto rows = [&](uint32_t take) {
+        const bool a = (uint32_t)lane < take;
+        const int32_t vv = a ? ring[(head + (uint32_t)lane) & (kRing - 1)] : 0;
+        head += take;
+        queued -= take;
+        uint32_t b = 0, e = 0;
+        if (a) {
+          uint32_t be[2];
+          __builtin_memcpy(be, rp + vv, 8);
+          b = be[0];
+          e = be[1];
+        }
+        if (ACCT && a) cnt.nrows += 1;
+        bool found = false;
+        int32_t par = -1;
+        int32_t u[LANE_SCAN];
+        if (a && b < e) {
+          __builtin_memcpy(u, ci + b, LANE_SCAN * sizeof(int32_t));
+#pragma unroll
+          for (int t = 0; t < LANE_SCAN; ++t)
+            if (b + t >= e) u[t] = -1;
+        } else {
+#pragma unroll
+          for (int t = 0; t < LANE_SCAN; ++t) u[t] = -1;
+        }
+        uint32_t sure = 0, need = 0;
+#pragma unroll
+        for (int t = 0; t < LANE_SCAN; ++t) {
+          const int p = F.pre(u[t] < 0 ? 0 : u[t]);
+          if (u[t] >= 0) {
+            sure |= (uint32_t)(p == 1) << t;
+            need |= (uint32_t)(p == 2) << t;
+          }
+        }
+        uint32_t uw[LANE_SCAN];
+#pragma unroll
+        for (int t = 0; t < LANE_SCAN; ++t) uw[t] = ((need >> t) & 1) ? F.word(u[t]) : 0u;
+#pragma unroll
+        for (int t = 0; t < LANE_SCAN; ++t) {
+          const bool hv = ((sure >> t) & 1) || (((need >> t) & 1) && ((uw[t] >> (u[t] & 31)) & 1));
+          if (a && !found && hv) {
+            found = true;
+            par = u[t];
+            if (ACCT) cnt.nscan += (uint64_t)(t + 1);
+          }
+        }
+        uint32_t k = b;
+        if (a && !found) {
+          k = std::min<uint32_t>(b + LANE_SCAN, e);
+          if (ACCT) cnt.nscan += (uint64_t)(k - b);
+        }
+        bu_row_rest<Front, ACCT>(F, ci, packed, a, (int64_t)k, (int64_t)e, found, par, s_base,
+                                 s_row, s_first, cnt);
+        if (found) {
+          parent[vv] = par;
+          put_level(lev8, level, vv, next_level);
+          atomicOr(&nx[(vv >> 6) & (kWave - 1)], 1ull << (vv & 63));
+        }
+      };
+      for (uint32_t base = 0; base < total; base += kWave) {
+        const uint32_t idx = base + (uint32_t)lane;
+        const bool act = idx < total;
+        int pos = 0;  // last word whose exclusive prefix is <= idx
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1)
+          if (__shfl(excl, pos + st, kWave) <= idx) pos += st;
+        const uint32_t r = idx - __shfl(excl, pos, kWave);
+        const uint64_t word = __shfl(un, pos, kWave);
+        const int bit = act ? select_bit(word, r) : 0;
+        const int32_t v = (int32_t)((c * kWave + pos) * kWave + bit);
+        int32_t h = (act && hint) ? hint[v] : -1;
+        if (ACCT && act) cnt.nunvis += 1;
+        int hp = 0;
+        int32_t par = -1;
+        const bool only = h != -1 && (h & kHintOnly);
+        if (h >= 0) {
+          h &= ~kHintOnly;
+          hp = F.pre(h);
+          par = h;
+        } else if (h != -1) {
+          const uint32_t hr = (uint32_t)h & (uint32_t)(kHintOnly - 1);
+          hp = (int)((fh[hr >> 6] >> (hr & 63)) & 1);
+        }
+        const uint32_t hw = (hp == 2) ? F.word(h) : 0u;
+        const bool via = hp == 1 || (hp == 2 && ((hw >> (h & 31)) & 1));
+        if (via) {
+          if (ACCT) cnt.nhint += 1;
+          if (hint_id) parent[v] = par >= 0 ? par : hint_id[v];
+          put_level(lev8, level, v, next_level);
+          atomicOr(&nx[pos], 1ull << bit);
+        }
+        const bool miss = act && !via && !only;
+        const uint64_t mb = __ballot(miss);
+        if (miss) ring[(head + queued + (uint32_t)__popcll(mb & lt)) & (kRing - 1)] = v;
+        queued += (uint32_t)__popcll(mb);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (queued >= (uint32_t)kWave) rows(kWave);
+      }
+      while (queued > 0) rows(std::min<uint32_t>(queued, kWave));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const uint64_t m = nx[lane];
+      if (w < words) {
+        next[w] = m;
+        if (m) vis[w] = vw | m;
+      }
+      cnt.nnew += (uint64_t)__popcll(m);
+    }
+    return;
+  }
   for (int64_t c = gw; c < chunks; c += nw) {
     const int64_t w = c * kWave + lane;
     const uint64_t vw = (w < words) ? vis[w] : ~0ull;  // padding lanes past n are pre-set in iso
@@ -907,14 +1042,15 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
   __shared__ int32_t s_row[kBuBlock];
   __shared__ int32_t s_first[kBuBlock];
   __shared__ unsigned long long s_nx[kBuBlock];
+  __shared__ int32_t s_ring[(R == 1) ? kBuBlock / kWave * kRing : 1];
   for (int64_t i = threadIdx.x; i < fh_words; i += kBuBlock) s_fh[i] = fh[i];
   __syncthreads();
   const int64_t gw = ((int64_t)blockIdx.x * kBuBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kBuBlock) / kWave;
   BuCount c;
-  bu_chunks<LANE_SCAN, R, ACCT>(FrontGlobal{(const uint32_t *)front}, s_fh, rp, ci, hint, hint_id, vis, next,
-                                parent, level, lev8, words, next_level, packed, gw, nw, s_base, s_row,
-                                s_first, s_nx, c);
+  bu_chunks<LANE_SCAN, R, ACCT, FrontGlobal, R == 1>(
+      FrontGlobal{(const uint32_t *)front}, s_fh, rp, ci, hint, hint_id, vis, next, parent, level,
+      lev8, words, next_level, packed, gw, nw, s_base, s_row, s_first, s_nx, c, s_ring);
   bu_flush<kBuBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
 
