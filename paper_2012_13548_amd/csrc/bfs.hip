@@ -540,7 +540,7 @@ struct BuCount {
 template <class Front, bool ACCT>
 __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__restrict__ ci,
                                             bool packed, bool pending, int64_t k, int64_t e,
-                                            bool &found, int32_t &par, int64_t *s_base,
+                                            bool &found, int32_t &par, uint32_t *s_base,
                                             int32_t *s_row, int32_t *s_first, BuCount &cnt) {
   const int lane = __lane_id();
   if (packed) {
@@ -553,7 +553,9 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
     if (total) {
       const uint32_t pre = incl - len;
       const int wb = (threadIdx.x / kWave) * kWave;
-      s_base[wb + lane] = k - (int64_t)pre;
+      // row entry j of the window sits at s_base + j: k - pre + j lies in
+      // [0, nnz) < 2^32, so 32-bit wrap-around arithmetic gives it exactly
+      s_base[wb + lane] = (uint32_t)k - pre;
       s_first[wb + lane] = kWave;
       uint64_t done = __ballot(len == 0);
       int carry = 0;
@@ -568,7 +570,7 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
         int32_t u = -1;
         bool hit = false;
         if (j < total && !((done >> r) & 1)) {
-          u = ci[s_base[wb + r] + (int64_t)j];
+          u = ci[(uint32_t)(s_base[wb + r] + j)];
           hit = F.test(u);
         }
         if (hit) atomicMin(&s_first[wb + r], lane);
@@ -669,7 +671,7 @@ __device__ __forceinline__ void bu_chunks(
     const int32_t *__restrict__ hint_id, uint64_t *__restrict__ vis,
     uint64_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ level,
     uint8_t *__restrict__ lev8, int64_t words, int32_t next_level, bool packed, int64_t gw,
-    int64_t nw, int64_t *s_base,
+    int64_t nw, uint32_t *s_base,
     int32_t *s_row, int32_t *s_first, unsigned long long *s_nx, BuCount &cnt,
     int32_t *s_ring = nullptr) {
   const int lane = __lane_id();
@@ -1038,7 +1040,7 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
   extern __shared__ uint64_t s_fh[];
   if (check_go && !ctr[C_BUGO]) return;  // queued ahead; the last step chose top-down
   __shared__ uint64_t s[kBuBlock / kWave];
-  __shared__ int64_t s_base[kBuBlock];
+  __shared__ uint32_t s_base[kBuBlock];
   __shared__ int32_t s_row[kBuBlock];
   __shared__ int32_t s_first[kBuBlock];
   __shared__ unsigned long long s_nx[kBuBlock];
@@ -1059,7 +1061,7 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
 // hot-target words): probes of vertices whose summary bit is clear never leave
 // the compute unit.
 constexpr int kLdsBlock = 1024;
-// k_bu_step_lds's own LDS arrays (about 24 KiB), with margin
+// k_bu_step_lds's own LDS arrays (about 20 KiB), with margin
 constexpr int64_t kBuStaticLds = 28 * 1024;
 
 // At most 64 VGPRs (8 waves per SIMD, a few values spilled): with a staged
@@ -1080,7 +1082,7 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
   uint32_t *s_sum = reinterpret_cast<uint32_t *>(s_dyn);
   uint64_t *s_fh = s_dyn + (sum_words + 1) / 2;
   __shared__ uint64_t s[kLdsBlock / kWave];
-  __shared__ int64_t s_base[kLdsBlock];
+  __shared__ uint32_t s_base[kLdsBlock];
   __shared__ int32_t s_row[kLdsBlock];
   __shared__ int32_t s_first[kLdsBlock];
   __shared__ unsigned long long s_nx[kLdsBlock];
@@ -1090,9 +1092,11 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
   const int64_t gw = ((int64_t)blockIdx.x * kLdsBlock + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * kLdsBlock) / kWave;
   BuCount c;
-  bu_chunks<LANE_SCAN, R, ACCT>(FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, vis,
-                                next, parent, level, lev8, words, next_level, packed, gw, nw, s_base,
-                                s_row, s_first, s_nx, c);
+  // (compacting hint misses as k_bu_step does measured no faster here: on a
+  // sparse frontier most hints miss, so its rounds are dense already)
+  bu_chunks<LANE_SCAN, R, ACCT>(
+      FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, vis, next, parent,
+      level, lev8, words, next_level, packed, gw, nw, s_base, s_row, s_first, s_nx, c);
   bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
 
