@@ -33,6 +33,10 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kLaneRow = 32;  // rows up to this length are scanned by one lane
+// A lane's row goes in batches of kRowBatch entries: their neighbour ids, then
+// the masks they index, loaded together, so a batch costs two dependent loads
+// rather than two per entry.
+constexpr int kRowBatch = 8;
 constexpr int kStatLevels = G5_MAX_STAT_LEVELS;
 
 struct Slot {
@@ -149,7 +153,23 @@ __device__ void td_phase(const MsArgs &a, const uint64_t *front, uint64_t *next,
     }
     const int64_t d = e - b;
     if (f && d <= kLaneRow)
-      for (int64_t k = b; k < e; ++k) td_edge<PAR>(a, next, (int32_t)u, f, a.ci[k], lvl, acc);
+      for (int64_t k0 = b; k0 < e; k0 += kRowBatch) {
+        int32_t vv[kRowBatch];
+        uint64_t nw[kRowBatch], old[kRowBatch];
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) vv[t] = k0 + t < e ? a.ci[k0 + t] : -1;
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) nw[t] = vv[t] >= 0 ? f & ~a.seen[vv[t]] : 0ull;
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t)
+          old[t] = nw[t] ? atomicOr((unsigned long long *)&next[vv[t]], (unsigned long long)nw[t])
+                         : ~0ull;
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) {
+          const uint64_t won = nw[t] & ~old[t];
+          if (won) commit_atomic<PAR>(a, vv[t], won, old[t], (int32_t)u, lvl, acc);
+        }
+      }
     uint64_t rem = __ballot(f && d > kLaneRow && d <= kHubDeg);
     while (rem) {
       const int L = __ffsll((unsigned long long)rem) - 1;
@@ -206,20 +226,29 @@ __device__ void bu_phase(const MsArgs &a, const uint64_t *front, uint64_t *next,
     const uint64_t missing = a.full & ~s;
     uint64_t got = 0;
     if (act && d <= kLaneRow) {
-      for (int64_t k = b; k < e; ++k) {
-        const int32_t u = a.ci[k];
-        const uint64_t g = front[u] & missing & ~got;
-        if (g) {
-          got |= g;
-          if (PAR) {
-            uint64_t x = g;
-            while (x) {
-              const int bb = __ffsll((unsigned long long)x) - 1;
-              x &= x - 1;
-              a.parents[(int64_t)bb * a.n + v] = u;
+      // entries in row order, so the first provider of a bit is its parent; a
+      // batch past the point where every missing bit is found contributes nothing
+      for (int64_t k0 = b; k0 < e && got != missing; k0 += kRowBatch) {
+        int32_t uu[kRowBatch];
+        uint64_t fu[kRowBatch];
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) uu[t] = k0 + t < e ? a.ci[k0 + t] : -1;
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) fu[t] = uu[t] >= 0 ? front[uu[t]] : 0ull;
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) {
+          const uint64_t g = fu[t] & missing & ~got;
+          if (g) {
+            got |= g;
+            if (PAR) {
+              uint64_t x = g;
+              while (x) {
+                const int bb = __ffsll((unsigned long long)x) - 1;
+                x &= x - 1;
+                a.parents[(int64_t)bb * a.n + v] = uu[t];
+              }
             }
           }
-          if (got == missing) break;
         }
       }
     }
