@@ -113,17 +113,22 @@ typedef struct {
 /* Time each level's step with HIP events on `stream` (step_ms in the stats). */
 #define G5_FLAG_TIME_STEPS 1
 /* Count the algorithmic bytes and edges of each level (slower kernels; use in
- * an untimed run).  Bytes per level:
- *   top-down   12 per frontier vertex (queue entry, its degree/offset word, its
- *              row start) + 4 per frontier edge + 24 per discovered vertex
- *              (level, parent, queue entry, its degree and its two row offsets);
+ * an untimed run).  Levels are written as bytes during the traversal while they
+ * fit (levels 0..254) and widened into `level` once at the end; past level 254
+ * they are written as int32.  Bytes per level:
+ *   top-down   12 per frontier vertex (queue entry, its edge-index word, its
+ *              row start) + 4 per frontier edge + 21 per discovered vertex
+ *              (byte level, parent, queue entry, its edge index and its two row
+ *              offsets; 24 past level 254);
  *   bottom-up  4 per unvisited non-isolated vertex (its neighbour hint) + 4 per
  *              vertex whose hint missed (its 32-bit row offset) + 4 per row
  *              entry read up to the first frontier hit + n/4 (visited words
- *              read, next-frontier words written) + 4 per discovered vertex
- *              (level) + 4 per parent written (a hint hit writes none when the
- *              parent array was pre-filled with the hint targets).
- * Frontier-bitmap probes (one per examined neighbour) are not counted. */
+ *              read, next-frontier words written) + 1 per discovered vertex
+ *              (byte level; 4 past level 254) + 4 per parent written (a hint
+ *              hit writes none when the parent array was pre-filled with the
+ *              hint targets).
+ * Frontier-bitmap probes (one per examined neighbour) and the final widening
+ * pass are not counted. */
 #define G5_FLAG_COUNT_BYTES 2
 /* Do not test each vertex's highest-degree neighbour (built by g5_build_csr)
  * before its row in bottom-up steps. */
