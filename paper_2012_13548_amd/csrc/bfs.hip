@@ -47,7 +47,7 @@ enum Ctr : int {
   C_QLEN1 = 1,  // length of queue 1
   C_MF = 2,     // degree sum of the scanned frontier queue
   C_NNEW = 3,   // vertices found by a bottom-up step (reset after publishing)
-  C_GO = 4,     // 1: this top-down level expands (decided by the degree scan)
+  C_GO = 4,     // 1: the decided top-down level expands
   C_RDEG = 5,   // degree of the root
   C_ERR = 6,    // nonzero if a kernel met an impossible state
   C_SCAN = 7,   // row entries read by a bottom-up step (byte counting only)
@@ -62,8 +62,8 @@ enum Ctr : int {
   C_UNV = 15,   // non-isolated vertices not reached yet
   C_QP0 = 16,   // queue 0: entries << 32 | degree sum (appended to by one atomic per block)
   C_QP1 = 17,   // queue 1: the same
-  C_XP0 = 18,   // lvl + 1 when the last top-down level of even lvl expanded, else 0
-  C_XP1 = 19,   // the same for odd levels
+  C_ENDL = 18,  // lvl + 1 when level lvl's queue came out empty (the traversal ended), else 0
+  C_TICKET = 19,  // workgroups done in the kernel that fills a queue (the last one decides)
   C_NCTR = 20
 };
 
@@ -92,64 +92,16 @@ __device__ void publish(const unsigned long long *ctr, unsigned long long *host,
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Start of a traversal from `root`: byte levels = 0xff and parent = fill (the
-// hint targets) or -1, except at the root (level 0, its own parent); visited
-// bitmap = the isolated vertices and the root, its snapshots = the isolated
-// vertices; counters zeroed, then queue 0 = {root} (edge index 0, its degree in
-// the queue's counter) and the direction state of the root's level.
-__global__ void k_bfs_init(int64_t root, uint8_t *__restrict__ lev8,
-                           int32_t *__restrict__ parent, int64_t n,
-                           const int32_t *__restrict__ fill, uint64_t *__restrict__ vis,
-                           uint64_t *__restrict__ prev0, uint64_t *__restrict__ prev1,
-                           const uint64_t *__restrict__ iso, int64_t words, bool vec,
-                           int32_t *__restrict__ q0, uint32_t *__restrict__ qo0,
-                           unsigned long long *__restrict__ ctr, const int64_t *__restrict__ rp,
-                           int64_t nnz, int64_t nonisolated) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t n4 = vec ? n / 4 : 0;
-  typedef int v4i __attribute__((ext_vector_type(4)));
-  const v4i m1 = {-1, -1, -1, -1};
-  // streaming (non-temporal) accesses: the arrays are far larger than L2
-  for (int64_t i = t; i < n4; i += stride) {
-    v4i f = fill ? __builtin_nontemporal_load(reinterpret_cast<const v4i *>(fill) + i) : m1;
-    if (i == (root >> 2)) f[root & 3] = (int32_t)root;
-    __builtin_nontemporal_store(f, reinterpret_cast<v4i *>(parent) + i);
-  }
-  for (int64_t i = n4 * 4 + t; i < n; i += stride)
-    parent[i] = i == root ? (int32_t)root : (fill ? fill[i] : -1);
-  // lev8 is 16-byte aligned and padded to a multiple of 16 bytes
-  for (int64_t i = t; i < (n + 15) / 16; i += stride) {
-    v4i x = m1;
-    if (i == (root >> 4)) reinterpret_cast<uint8_t *>(&x)[root & 15] = 0;
-    __builtin_nontemporal_store(x, reinterpret_cast<v4i *>(lev8) + i);
-  }
-  const int64_t rw = root >> 6;
-  for (int64_t i = t; i < words; i += stride) {
-    const uint64_t x = iso[i];
-    vis[i] = i == rw ? x | (1ull << (root & 63)) : x;
-    prev0[i] = x;
-    prev1[i] = x;
-  }
-  if (t == 0) {
-    for (int i = 0; i < C_NCTR; ++i) ctr[i] = 0;
-    const int64_t rdeg = rp[root + 1] - rp[root];  // 64-bit offsets
-    q0[0] = (int32_t)root;
-    qo0[0] = 0;
-    ctr[C_QLEN0] = 1;
-    ctr[C_QP0] = (1ull << 32) | (unsigned long long)rdeg;
-    ctr[C_RDEG] = (unsigned long long)rdeg;
-    ctr[C_MU] = (unsigned long long)(nnz - rdeg);
-    ctr[C_UNV] = (unsigned long long)(nonisolated - (rdeg > 0 ? 1 : 0));
-  }
-}
-
 // Direction of a top-down level (the rule the host reads from the published
 // counters): queue slot qs holds its frontier Q (qlen vertices, mf edges).
 // m_u (edges of vertices no top-down level has discovered) drops by m_f except
 // at the root's level; switch to bottom-up when Q grew and m_f > m_u / alpha.
-// ctr[C_GO] = 1 lets the level's queued expansion run.  Records Q for the
-// host, clears the counters of the queue that this level fills and publishes.
+// The decision is taken where the level's queue is complete (the root's at the
+// start, otherwise by the last workgroup of the kernel that filled the queue),
+// so an expansion queued ahead needs no kernel of its own for it: it runs when
+// ctr[C_GO] = 1 (a level queued behind one that did not expand sees that
+// level's 0).  Records Q for the host, marks an empty queue (the end) in
+// C_ENDL, clears the counter of the queue this level fills and publishes.
 struct TdRule {
   int dirmode;
   double alpha;
@@ -177,13 +129,64 @@ __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool fro
   ctr[C_UNV] = (unsigned long long)unv;
   ctr[C_MF] = mf;
   ctr[C_GO] = go ? 1ull : 0ull;
+  ctr[C_ENDL] = qlen == 0 ? (unsigned long long)(lvl + 1) : 0ull;
   if (go) ctr[C_LASTNF] = (unsigned long long)qlen;
-  ctr[C_XP0 + (lvl & 1)] = go ? (unsigned long long)(lvl + 1) : 0ull;
   ctr[C_QLEN0 + qs] = (unsigned long long)qlen;
-  ctr[C_QLEN0 + (qs ^ 1)] = 0;
   ctr[C_QP0 + (qs ^ 1)] = 0;
   publish(ctr, host, seq);
 }
+
+// Start of a traversal from `root`: byte levels = 0xff and parent = fill (the
+// hint targets) or -1, except at the root (level 0, its own parent); visited
+// bitmap = the isolated vertices and the root; counters zeroed, then queue 0 =
+// {root} (edge index 0, its degree in the queue's counter), the direction
+// state, and the root level's decision (published under seq).
+__global__ void k_bfs_init(int64_t root, uint8_t *__restrict__ lev8,
+                           int32_t *__restrict__ parent, int64_t n,
+                           const int32_t *__restrict__ fill, uint64_t *__restrict__ vis,
+                           const uint64_t *__restrict__ iso, int64_t words, bool vec,
+                           int32_t *__restrict__ q0, uint32_t *__restrict__ qo0,
+                           unsigned long long *__restrict__ ctr, const int64_t *__restrict__ rp,
+                           int64_t nnz, int64_t nonisolated, TdRule rule,
+                           unsigned long long *host, unsigned long long seq) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t n4 = vec ? n / 4 : 0;
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  const v4i m1 = {-1, -1, -1, -1};
+  // streaming (non-temporal) accesses: the arrays are far larger than L2
+  for (int64_t i = t; i < n4; i += stride) {
+    v4i f = fill ? __builtin_nontemporal_load(reinterpret_cast<const v4i *>(fill) + i) : m1;
+    if (i == (root >> 2)) f[root & 3] = (int32_t)root;
+    __builtin_nontemporal_store(f, reinterpret_cast<v4i *>(parent) + i);
+  }
+  for (int64_t i = n4 * 4 + t; i < n; i += stride)
+    parent[i] = i == root ? (int32_t)root : (fill ? fill[i] : -1);
+  // lev8 is 16-byte aligned and padded to a multiple of 16 bytes
+  for (int64_t i = t; i < (n + 15) / 16; i += stride) {
+    v4i x = m1;
+    if (i == (root >> 4)) reinterpret_cast<uint8_t *>(&x)[root & 15] = 0;
+    __builtin_nontemporal_store(x, reinterpret_cast<v4i *>(lev8) + i);
+  }
+  const int64_t rw = root >> 6;
+  for (int64_t i = t; i < words; i += stride) {
+    const uint64_t x = iso[i];
+    vis[i] = i == rw ? x | (1ull << (root & 63)) : x;
+  }
+  if (t == 0) {
+    for (int i = 0; i < C_NCTR; ++i) ctr[i] = 0;
+    const int64_t rdeg = rp[root + 1] - rp[root];  // 64-bit offsets
+    q0[0] = (int32_t)root;
+    qo0[0] = 0;
+    ctr[C_QLEN0] = 1;
+    ctr[C_QP0] = (1ull << 32) | (unsigned long long)rdeg;
+    ctr[C_RDEG] = (unsigned long long)rdeg;
+    ctr[C_MU] = (unsigned long long)(nnz - rdeg);
+    ctr[C_UNV] = (unsigned long long)(nonisolated - (rdeg > 0 ? 1 : 0));
+    td_decide(ctr, 0, 0, false, rule, 1, (uint64_t)rdeg, host, seq);
+  }
+}
+
 
 // Levels are kept as bytes (lev8, 0xff = not reached) while they fit, so the
 // scattered level writes of a traversal touch a quarter of the bytes; the
@@ -239,44 +242,6 @@ __global__ void k_zero_u64(uint64_t *__restrict__ p, int64_t len) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
 }
 
-// First kernel of a top-down level: the queue's counter gives Q and m_f, thread
-// 0 takes the level's direction decision (td_decide) and publishes it, and the
-// grid snapshots the visited bitmap into `snap` before the level's expansion.
-// An empty queue skips the snapshot: either it was queued ahead behind a level
-// that did not expand, or the previous level expanded and found nothing, which
-// ends the traversal; then the grid also resets the parent of the unreached
-// non-isolated vertices to -1 when `fix` (the parent array pre-filled with
-// hint targets) is given, and widens the byte levels into `level` when lev8 is.
-__global__ __launch_bounds__(kBlock) void k_td_decide(unsigned long long *__restrict__ ctr,
-                                                      int cur, int32_t lvl, bool from_bu,
-                                                      TdRule rule,
-                                                      unsigned long long *__restrict__ host,
-                                                      unsigned long long seq,
-                                                      uint64_t *__restrict__ snap,
-                                                      const uint64_t *__restrict__ vis,
-                                                      int64_t words,
-                                                      const uint64_t *__restrict__ iso,
-                                                      int32_t *__restrict__ fix,
-                                                      const uint8_t *__restrict__ lev8,
-                                                      int32_t *__restrict__ level, int64_t n,
-                                                      bool vec) {
-  const unsigned long long qp = ctr[C_QP0 + cur];
-  const int64_t qlen = (int64_t)(qp >> 32);
-  // read before thread 0 writes this level's tag (the other parity slot)
-  const bool ended = qlen == 0 && lvl > 0 &&
-                     ctr[C_XP0 + ((lvl - 1) & 1)] == (unsigned long long)lvl;
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    td_decide(ctr, cur, lvl, from_bu, rule, qlen, qp & 0xffffffffull, host, seq);
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  if (qlen == 0) {
-    if (ended && fix) unreached_words(vis, iso, words, fix, stride);
-    if (ended && lev8) expand_levels(lev8, level, n, vec, stride);
-    return;
-  }
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride)
-    snap[i] = vis[i];
-}
-
 // Edge index of frontier entry i in the frontier's edge list (non-decreasing
 // in i; the total past the last entry).
 struct FrontOffsets {
@@ -310,8 +275,8 @@ __device__ int64_t block_search(const Off &off, int64_t len, uint32_t e) {
 }
 
 // CLAIM_MIN: parent[v] is the smallest frontier neighbour (unsigned atomic
-// min over every edge into a vertex unvisited at level start, read from the
-// snapshot taken before the expansion); the visited-bit OR still decides who
+// min over every edge into a vertex unvisited at level start: its level is
+// still unset or the one being written); the visited-bit OR still decides who
 // appends v to the next queue.
 enum Claim : int { CLAIM_OR = 0, CLAIM_CAS = 1, CLAIM_MIN = 2 };
 
@@ -326,28 +291,46 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
 // turn.  A tile's claimed vertices go to the next queue together: their
 // degrees' block prefix sum, then one atomic on the queue's packed counter
 // (entries << 32 | degree sum) gives the tile both its queue positions and
-// its entries' edge indices.
+// its entries' edge indices.  The last block to finish (by a ticket) takes the
+// next level's decision from that counter and publishes it under seq.  When
+// the level's own decision found its queue empty (the traversal ended) the
+// grid instead resets the parent of the unreached non-isolated vertices to -1
+// if `fix` (the parent array was pre-filled with hint targets) and widens the
+// byte levels into `level` when lev8 is given.
 
 template <int CLAIM>
 __global__ __launch_bounds__(kBlock) void k_td_expand(
     const int32_t *__restrict__ q, const uint32_t *__restrict__ qoff,
     unsigned long long *__restrict__ ctr, int cur,
     const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    uint64_t *vis, const uint64_t *__restrict__ prev, int32_t *parent,
-    int32_t *__restrict__ level, uint8_t *__restrict__ lev8, int32_t *__restrict__ qn,
-    uint32_t *__restrict__ qon, int32_t next_level) {
+    uint64_t *vis, int32_t *parent, int32_t *__restrict__ level, uint8_t *__restrict__ lev8,
+    int32_t *__restrict__ qn, uint32_t *__restrict__ qon, int32_t next_level, TdRule rule,
+    unsigned long long *__restrict__ host, unsigned long long seq,
+    const uint64_t *__restrict__ iso, int64_t words, bool fix, int64_t n, bool vec) {
   __shared__ uint32_t s_off[kTdTile + 1];
   __shared__ int32_t s_src[kTdTile];
   __shared__ int64_t s_base[kTdTile];
   __shared__ unsigned long long s_scan[kBlock / kWave];
   __shared__ unsigned long long s_gbase;
-  if (!ctr[C_GO]) return;
+  if (!ctr[C_GO]) {
+    if (ctr[C_ENDL] == (unsigned long long)next_level) {
+      const int64_t stride = (int64_t)gridDim.x * kBlock;
+      if (fix) unreached_words(vis, iso, words, parent, stride);
+      if (lev8) expand_levels(lev8, level, n, vec, stride);
+    }
+    return;
+  }
   const int nxt = cur ^ 1;
   unsigned long long *qn_pack = ctr + C_QP0 + nxt;
   const int64_t qlen = (int64_t)ctr[C_QLEN0 + cur];
   const uint32_t total = (uint32_t)ctr[C_MF];
+  // only the blocks that own a tile take part (and take a ticket): same-address
+  // atomics are serialised, so 1500 tickets cost ~20 us on a small level
+  const uint64_t ntiles = ((uint64_t)total + kTdTile - 1) / kTdTile;
+  const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(gridDim.x, ntiles));
+  if (blockIdx.x >= active) return;
   const FrontOffsets off{qoff, qlen, total};
-  for (uint64_t tile = blockIdx.x; tile * kTdTile < total; tile += gridDim.x) {
+  for (uint64_t tile = blockIdx.x; tile * kTdTile < total; tile += active) {
     const uint32_t e0 = (uint32_t)(tile * kTdTile);
     const uint32_t e1 = (uint32_t)std::min<uint64_t>((uint64_t)e0 + kTdTile, total);
     const int64_t i0 = block_search(off, qlen, e0);
@@ -392,7 +375,8 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
         uint64_t bit = 1ull << (v & 63);
         uint64_t *wp = vis + (v >> 6);
         if (CLAIM == CLAIM_MIN) {
-          if (!(prev[v >> 6] & bit)) {
+          const int32_t lv = lev8 ? (lev8[v] == 0xff ? -1 : (int32_t)lev8[v]) : level[v];
+          if (lv < 0 || lv == next_level) {
             atomicMin((unsigned int *)(parent + v), (unsigned int)u);
             if (!(*wp & bit)) {
               won = !(atomicOr((unsigned long long *)wp, (unsigned long long)bit) & bit);
@@ -451,35 +435,83 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
     }
     __syncthreads();  // the shared arrays are reused by the next tile
   }
+  // No fences: a device-wide one writes back and invalidates this XCD's L2.
+  // Thread 0 made the block's appends, and each one returned (its result was
+  // used) before the ticket is taken.  The last block reads the queue's counter
+  // with an atomic too (adding 0), where the appends were made, after its own
+  // ticket returned, so it sees every append; a plain or atomic load could be
+  // served by a stale copy of the line in this XCD's L2.
+  if (threadIdx.x == 0) {
+    if (atomicAdd(ctr + C_TICKET, 1ull) + 1 == active) {
+      const unsigned long long qp = atomicAdd(qn_pack, 0ull);
+      atomicExch(ctr + C_TICKET, 0ull);
+      td_decide(ctr, nxt, next_level, false, rule, (int64_t)(qp >> 32), qp & 0xffffffffull, host,
+                seq);
+    }
+  }
 }
 
-// Frontier bitmap of the last top-down level without atomics: the vertices
-// visited now but not before that level's expansion.
-// The same launch builds fh (bit r = frontier bit of hot[r], one wavefront per
-// 64 hot targets) from the same two bitmaps, so the first bottom-up step needs
-// no separate pass for it.
-__global__ __launch_bounds__(kBlock) void k_front_from_vis(
-    const uint64_t *__restrict__ vis, const uint64_t *__restrict__ prev,
-    uint64_t *__restrict__ front, int64_t words, unsigned long long *__restrict__ ctr, int64_t nf,
-    const int32_t *__restrict__ hot, int64_t num_hot, uint64_t *__restrict__ fh) {
+// Frontier bitmap of level lvl (the vertices whose level is lvl), built
+// without atomics from the byte levels: each thread reads 16 levels and four
+// neighbouring lanes combine their 16-bit pieces into one 64-bit word.  With
+// int32 levels (lev8 == nullptr, a graph deeper than the byte levels) one
+// thread builds a word.  The same launch builds fh (bit r = frontier bit of
+// hot[r], one wavefront per 64 hot targets), so the first bottom-up step needs
+// no separate pass for it, and records the frontier size for the step.
+__global__ __launch_bounds__(kBlock) void k_front_from_level(
+    const uint8_t *__restrict__ lev8, const int32_t *__restrict__ level, int64_t n,
+    int32_t lvl, uint64_t *__restrict__ front, int64_t words,
+    unsigned long long *__restrict__ ctr, int64_t nf, const int32_t *__restrict__ hot,
+    int64_t num_hot, uint64_t *__restrict__ fh) {
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_NFIN] = (unsigned long long)nf;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride)
-    front[i] = vis[i] & ~prev[i];
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = __lane_id();
-  for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) - lane; i0 < num_hot;
-       i0 += stride) {
-    const int64_t i = i0 + lane;
-    bool b = false;
-    if (i < num_hot) {
-      const int32_t t = hot[i];
-      b = ((vis[t >> 6] & ~prev[t >> 6]) >> (t & 63)) & 1;
+  auto at = [&](int32_t v) -> bool {
+    return lev8 ? lev8[v] == (uint8_t)lvl : level[v] == lvl;
+  };
+  if (lev8) {
+    // lev8 is padded with 0xff to a multiple of 16 bytes (no level is 0xff)
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const int64_t chunks = (n + 15) / 16;
+    const uint32_t pat = 0x01010101u * (uint32_t)lvl;
+    // the loop bound is rounded up to whole wavefronts so all lanes shuffle
+    const int64_t span = ((words * 4 + kWave - 1) / kWave) * kWave;
+    for (int64_t i = t; i < span; i += stride) {
+      uint32_t bits = 0;
+      if (i < chunks) {
+        const v4u x = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(lev8) + i);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // byte k of y is zero exactly where byte k of x equals lvl
+          const uint32_t y = x[j] ^ pat;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            bits |= (uint32_t)(((y >> (8 * k)) & 0xffu) == 0) << (4 * j + k);
+        }
+      }
+      uint64_t wv = (uint64_t)bits << (16 * (lane & 3));
+      wv |= __shfl_xor(wv, 1, kWave);
+      wv |= __shfl_xor(wv, 2, kWave);
+      if ((lane & 3) == 0 && (i >> 2) < words) front[i >> 2] = wv;
     }
+  } else {
+    for (int64_t w = t; w < words; w += stride) {
+      uint64_t m = 0;
+      for (int b = 0; b < kWave; ++b) {
+        const int64_t v = w * kWave + b;
+        if (v < n && level[v] == lvl) m |= 1ull << b;
+      }
+      front[w] = m;
+    }
+  }
+  for (int64_t i0 = t - lane; i0 < num_hot; i0 += stride) {
+    const int64_t i = i0 + lane;
+    const bool b = i < num_hot && at(hot[i]);
     const uint64_t m = __ballot(b);
     if (lane == 0) fh[i0 >> 6] = m;
   }
 }
-
 
 // Frontier membership for the bottom-up step: the frontier bitmap in HBM, or
 // a summary staged in LDS (bit i set when some frontier vertex lies in
@@ -1148,8 +1180,9 @@ __global__ void k_front_summary(const uint64_t *__restrict__ front, int64_t word
 // staged in LDS in vertex order, their degrees loaded in parallel, and a block
 // prefix sum of the degrees plus one atomic on the queue's packed counter
 // (entries << 32 | degree sum, zero before) places them with their edge
-// indices.  A denser round walks each thread's words serially instead.  Block
-// 0 also sets the direction state's previous frontier size.
+// indices.  A denser round walks each thread's words serially instead.  The
+// last block to finish (by a ticket) sets the direction state's previous
+// frontier size and takes level lvl's decision (published under seq).
 constexpr int kFqPer = 16;
 constexpr int64_t kFqWords = (int64_t)kBlock * kFqPer;
 constexpr uint32_t kFqCap = 2048;
@@ -1161,12 +1194,14 @@ __global__ __launch_bounds__(kBlock) void k_front_queue(const uint64_t *__restri
                                                         int32_t *__restrict__ q,
                                                         uint32_t *__restrict__ qo,
                                                         unsigned long long *__restrict__ ctr,
-                                                        int cur, int64_t last_nf) {
+                                                        int cur, int64_t last_nf, int32_t lvl,
+                                                        TdRule rule,
+                                                        unsigned long long *__restrict__ host,
+                                                        unsigned long long seq) {
   __shared__ int32_t s_v[kFqCap];
   __shared__ uint32_t s32[kBlock / kWave];
   __shared__ unsigned long long s[kBlock / kWave];
   __shared__ unsigned long long s_g;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_LASTNF] = (unsigned long long)last_nf;
   for (int64_t r0 = (int64_t)blockIdx.x * kFqWords; r0 < words;
        r0 += (int64_t)gridDim.x * kFqWords) {
     const int64_t w0 = r0 + (int64_t)threadIdx.x * kFqPer;
@@ -1257,6 +1292,15 @@ __global__ __launch_bounds__(kBlock) void k_front_queue(const uint64_t *__restri
       }
     }
   }
+  // no fences, for the reason given at the end of k_td_expand
+  if (threadIdx.x == 0) {
+    if (atomicAdd(ctr + C_TICKET, 1ull) + 1 == gridDim.x) {
+      const unsigned long long qp = atomicAdd(ctr + C_QP0 + cur, 0ull);
+      atomicExch(ctr + C_TICKET, 0ull);
+      ctr[C_LASTNF] = (unsigned long long)last_nf;
+      td_decide(ctr, cur, lvl, true, rule, (int64_t)(qp >> 32), qp & 0xffffffffull, host, seq);
+    }
+  }
 }
 
 int grid_for(int64_t items, int per_block, int cap) {
@@ -1306,8 +1350,6 @@ g5_status alloc_work(const g5_csr *g, BfsWork **out) {
   A((void **)&w->lev8, ((n + 15) / 16) * 16);
   A((void **)&w->front, W * 8);
   A((void **)&w->next, W * 8);
-  A((void **)&w->snap[0], W * 8);
-  A((void **)&w->snap[1], W * 8);
   A((void **)&w->q[0], n * 4);
   A((void **)&w->q[1], n * 4);
   A((void **)&w->qoff[0], (n + 1) * 4);
@@ -1357,8 +1399,6 @@ BfsWork::~BfsWork() {
   if (lev8) (void)hipFree(lev8);
   if (front) (void)hipFree(front);
   if (next) (void)hipFree(next);
-  for (auto *p : snap)
-    if (p) (void)hipFree(p);
   if (sum) (void)hipFree(sum);
   if (fh) (void)hipFree(fh);
   if (q[0]) (void)hipFree(q[0]);
@@ -1444,7 +1484,6 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   unsigned long long *ctr = (unsigned long long *)w.ctr;
   unsigned long long *hpub = (unsigned long long *)w.host_pub_dev;
   int64_t hc[C_NPUB] = {};  // the counters last published
-  const int decide_grid = grid_for(W, kBlock, ncu * 8);
   if (timed && w.ev.empty()) {
     w.ev.resize(2 * G5_MAX_STAT_LEVELS);
     for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
@@ -1466,11 +1505,13 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   // a bottom-up hit on the hint then writes no parent (unreached vertices are
   // reset at the end).  Compare-and-swap claims need parent -1.
   const bool prefill = use_hint && p.claim != CLAIM_CAS;
+  const TdRule rule{p.direction, alpha, gamma};
+  const unsigned long long seq0 = ++w.seq;  // the root level's decision, taken by k_bfs_init
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
                      dim3(kBlock), 0, s, root, w.lev8, parent, n,
-                     prefill ? g->hint_id : nullptr, w.vis, w.snap[0], w.snap[1], g->iso, W,
+                     prefill ? g->hint_id : nullptr, w.vis, g->iso, W,
                      ((uintptr_t)parent & 15) == 0, w.q[0], w.qoff[0], ctr, g->row_ptr, g->nnz,
-                     g->nonisolated);
+                     g->nonisolated, rule, hpub, seq0);
   G5_LAUNCH_CHECK();
   // Levels go to the byte array while they fit; the kernels of level lv (writing
   // lv + 1) get sink(lv), which widens the bytes into `level` once, before the
@@ -1502,7 +1543,6 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   if (stats) *stats = g5_bfs_stats{};
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
   const BuNext bn{p.direction, beta, n};
-  const TdRule rule{p.direction, alpha, gamma};
   const int32_t *hint = use_hint ? g->hint : nullptr;
   const int32_t *hint_id = prefill ? nullptr : g->hint_id;
   const int64_t fh_words = use_hint ? (g->num_hot + 63) / 64 : 0;
@@ -1519,25 +1559,22 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                                      kBlock, 0));
   const int td_grid = ncu * td_per_cu;
 
-  // Top-down level lv from queue slot c: the level's direction decision
-  // (published under sq) with the visited snapshot, then the expansion (runs
-  // only if the level stays top-down).  Queued ahead behind a level that did not
-  // expand, the level's queue is empty and nothing happens.
-  auto launch_td = [&](int32_t lv, int c, unsigned long long sq, bool from_bu) -> g5_status {
+  // Top-down level lv from queue slot c: the expansion, which runs only if the
+  // level's decision (already taken when the queue was completed) kept it top
+  // down, and whose last workgroup takes level lv + 1's decision (published
+  // under sq).  Queued ahead behind a level that did not expand, it does
+  // nothing, or finishes the traversal when that level's queue was empty.
+  auto launch_td = [&](int32_t lv, int c, unsigned long long sq) -> g5_status {
     const int nx = c ^ 1;
     {
       g5_status st_ = rec(lv, 0);
       if (st_ != G5_OK) return st_;
     }
     uint8_t *l8 = sink(lv);
-    hipLaunchKernelGGL(k_td_decide, dim3(decide_grid), dim3(kBlock), 0, s, ctr, c, lv, from_bu,
-                       rule, hpub, sq, w.snap[lv & 1], (const uint64_t *)w.vis, W,
-                       (const uint64_t *)g->iso, prefill ? parent : nullptr,
-                       (const uint8_t *)l8, level, n, lvec);
 #define G5_TD(C)                                                                              \
   hipLaunchKernelGGL(k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, \
-                     c, g->rp32, g->col_idx, w.vis, w.snap[lv & 1], parent, level, l8, w.q[nx], \
-                     w.qoff[nx], lv + 1)
+                     c, g->rp32, g->col_idx, w.vis, parent, level, l8, w.q[nx], w.qoff[nx],     \
+                     lv + 1, rule, hpub, sq, (const uint64_t *)g->iso, W, prefill, n, lvec)
     if (min_parent)
       G5_TD(CLAIM_MIN);
     else if (p.claim == CLAIM_CAS)
@@ -1635,18 +1672,20 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   };
 
   // Top-down levels are queued kTdAhead levels beyond the one whose decision
-  // the host waits for; td_seq[L % 4] is level L's publication sequence.  A
-  // level queued behind one that did not expand finds its queue empty and does
-  // nothing.  Queueing two levels ahead measured slower at scale 26: the
-  // device rarely waited for the host, and every switch or end ran one more
-  // empty level.  (At most kTdAhead + 1 publications are unread, fewer than
-  // kPubBufs.)
+  // the host waits for; td_seq[L % 4] is the publication sequence of level L's
+  // decision, taken by level L - 1's expansion.  A level queued behind one that
+  // did not expand does nothing.  Queueing two levels ahead measured slower at
+  // scale 26: the device rarely waited for the host, and every switch or end
+  // ran one more empty level.  (At most kTdAhead + 2 publications are unread,
+  // no more than kPubBufs.)
   constexpr int kTdAhead = 1;
+  static_assert(kTdAhead + 2 <= kPubBufs, "unread decisions would share a buffer");
   unsigned long long td_seq[4] = {0, 0, 0, 0};
   int32_t td_queued = 0;  // highest top-down level queued
-  td_seq[0] = ++w.seq;
+  td_seq[0] = seq0;
+  td_seq[1] = ++w.seq;
   {
-    g5_status st = launch_td(0, 0, td_seq[0], false);
+    g5_status st = launch_td(0, 0, td_seq[1]);
     if (st != G5_OK) return st;
   }
   while (true) {
@@ -1657,8 +1696,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       while (td_queued < lvl + kTdAhead) {
         ++td_queued;
         const unsigned long long sq = ++w.seq;
-        td_seq[td_queued & 3] = sq;
-        g5_status st = launch_td(td_queued, cur ^ ((td_queued - lvl) & 1), sq, false);
+        td_seq[(td_queued + 1) & 3] = sq;
+        g5_status st = launch_td(td_queued, cur ^ ((td_queued - lvl) & 1), sq);
         if (st != G5_OK) return st;
       }
       {
@@ -1675,16 +1714,17 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         reached += qlen;
         if (lvl - 1 < G5_MAX_STAT_LEVELS && stats) stats->discovered[lvl - 1] = qlen;
       }
-      if (qlen == 0) {  // the queued kernels do nothing
-        ended_td = true;  // this level's decision kernel reset the unreached parents
+      if (qlen == 0) {  // the traversal ended
+        ended_td = true;  // this level's queued expansion finishes it
         break;
       }
       q_from_bu = false;
       if (!hc[C_GO]) {
-        // bottom-up from here: frontier bitmap = visited now, not visited
-        // before the last expansion
-        hipLaunchKernelGGL(k_front_from_vis, dim3(grid_for(W, kBlock, ncu * 16)), dim3(kBlock), 0,
-                           s, w.vis, w.snap[(lvl + 1) & 1], front, W, ctr, qlen, g->hot,
+        // bottom-up from here: frontier bitmap = the vertices of level lvl
+        // (in `level` once the byte levels were widened)
+        hipLaunchKernelGGL(k_front_from_level, dim3(grid_for(4 * W, kBlock, ncu * 16)),
+                           dim3(kBlock), 0, s, widened ? nullptr : (const uint8_t *)w.lev8,
+                           (const int32_t *)level, n, lvl, front, W, ctr, qlen, g->hot,
                            fh_words ? g->num_hot : (int64_t)0, w.fh);
         G5_LAUNCH_CHECK();
         dir = 2;
@@ -1707,7 +1747,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                                  lds_density * (double)n;
         if (use_lds) ++lds_levels;
         bu_seq = ++w.seq;
-        // the first step after top-down: k_front_from_vis built fh
+        // the first step after top-down: k_front_from_level built fh
         g5_status st = launch_bu(lvl, front, next, use_lds, false, bu_seq, true);
         if (st != G5_OK) return st;
       }
@@ -1749,17 +1789,18 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         bu_seq = spec_seq;
         continue;
       }
-      // top-down from here: bitmap -> queue (with edge indices), the level's
-      // decision, and its kernels
+      // top-down from here: bitmap -> queue (with edge indices) and the level's
+      // decision, then its expansion
       bu_queued = false;
+      td_seq[lvl & 3] = ++w.seq;
       hipLaunchKernelGGL(k_front_queue, dim3(grid_for(W, (int)kFqWords, ncu)), dim3(kBlock), 0, s,
                          (const uint64_t *)front, W, g->rp32, w.q[cur], w.qoff[cur], ctr, cur,
-                         last_nf);
+                         last_nf, lvl, rule, hpub, td_seq[lvl & 3]);
       G5_LAUNCH_CHECK();
       td_queued = lvl;  // top-down levels queued before the bottom-up steps did nothing
-      td_seq[lvl & 3] = ++w.seq;
+      td_seq[(lvl + 1) & 3] = ++w.seq;
       {
-        g5_status st = launch_td(lvl, cur, td_seq[lvl & 3], true);
+        g5_status st = launch_td(lvl, cur, td_seq[(lvl + 1) & 3]);
         if (st != G5_OK) return st;
       }
       q_from_bu = true;
@@ -1767,7 +1808,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     }
   }
 #undef G5_REC
-  // a traversal ended by a top-down decision kernel was finished by it
+  // a traversal ended by an empty top-down queue was finished by that level's
+  // queued expansion
   if (!ended_td && (prefill || !widened))
     hipLaunchKernelGGL(k_finish, dim3(finish_grid), dim3(kBlock), 0, s, w.vis, g->iso, W,
                        prefill ? parent : nullptr, widened ? nullptr : (const uint8_t *)w.lev8,

@@ -55,8 +55,6 @@ struct BfsWork {
   uint8_t *lev8 = nullptr;    // levels as bytes while they fit (0xff = not reached)
   uint64_t *front = nullptr;  // frontier bitmap (bottom-up input)
   uint64_t *next = nullptr;   // next-frontier bitmap (bottom-up output)
-  uint64_t *snap[2] = {nullptr, nullptr};  // visited bitmap before each top-down
-                                           // expansion, by level parity
   uint32_t *sum = nullptr;    // frontier summary staged in LDS by bottom-up steps
   int64_t sum_words = 0;      // its 32-bit words
   int sum_gs = 0;             // log2 of the vertices per summary bit
