@@ -110,7 +110,9 @@ typedef struct {
                              (unvisited non-isolated vertices); 0 takes the default, < 0 disables */
 } g5_bfs_params;
 
-/* Time each level's step with HIP events on `stream` (step_ms in the stats). */
+/* Time each level's step kernel (the top-down expansion or the bottom-up step)
+ * with HIP start/stop events carried by that kernel's own dispatch on `stream`
+ * (step_ms in the stats); no extra packets are queued between kernels. */
 #define G5_FLAG_TIME_STEPS 1
 /* Count the algorithmic bytes and edges of each level (slower kernels; use in
  * an untimed run).  Levels are written as bytes during the traversal while they

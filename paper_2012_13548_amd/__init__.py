@@ -198,8 +198,8 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
     """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
 
     With ``stats=True`` also returns a dict of per-level directions, frontier
-    sizes and discoveries; ``time_steps`` adds each step's device time (HIP
-    events on the current stream) and ``count_bytes`` its algorithmic bytes.
+    sizes and discoveries; ``time_steps`` adds each step kernel's device time
+    (HIP events carried by its dispatch on the current stream) and ``count_bytes`` its algorithmic bytes.
     """
     import torch
     if parent is None:

@@ -27,6 +27,8 @@
 #include <atomic>
 #include <cstring>
 
+#include <hip/hip_ext.h>
+
 #include "g5_internal.h"
 
 namespace g5 {
@@ -1491,14 +1493,15 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   auto ev_at = [&](int lv, int k) -> hipEvent_t {
     return (timed && lv < G5_MAX_STAT_LEVELS) ? w.ev[2 * lv + k] : nullptr;
   };
-  auto rec = [&](int lv, int k) -> g5_status {
-    if (hipEvent_t e = ev_at(lv, k)) G5_HIP(hipEventRecord(e, s));
-    return G5_OK;
-  };
-#define G5_REC(lv, k)                 \
-  do {                                \
-    g5_status st_ = rec(lv, k);       \
-    if (st_ != G5_OK) return st_;     \
+  // A timed level's step kernel carries the level's start and stop events in
+  // its own dispatch (no marker packets between kernels: recorded separately,
+  // two events per level made the traversal ~6 % slower).
+#define G5_KLAUNCH(E0, E1, K, G, B, SH, S, ...)                       \
+  do {                                                                \
+    if (E0)                                                           \
+      hipExtLaunchKernelGGL(K, G, B, SH, S, E0, E1, 0, __VA_ARGS__);   \
+    else                                                              \
+      hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                 \
   } while (0)
 
   // With hints and claims by OR, parent starts as every vertex's hint target:
@@ -1566,15 +1569,12 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   // nothing, or finishes the traversal when that level's queue was empty.
   auto launch_td = [&](int32_t lv, int c, unsigned long long sq) -> g5_status {
     const int nx = c ^ 1;
-    {
-      g5_status st_ = rec(lv, 0);
-      if (st_ != G5_OK) return st_;
-    }
     uint8_t *l8 = sink(lv);
-#define G5_TD(C)                                                                              \
-  hipLaunchKernelGGL(k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, \
-                     c, g->rp32, g->col_idx, w.vis, parent, level, l8, w.q[nx], w.qoff[nx],     \
-                     lv + 1, rule, hpub, sq, (const uint64_t *)g->iso, W, prefill, n, lvec)
+    hipEvent_t t0 = ev_at(lv, 0), t1 = ev_at(lv, 1);
+#define G5_TD(C)                                                                                 \
+  G5_KLAUNCH(t0, t1, k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, c, \
+             g->rp32, g->col_idx, w.vis, parent, level, l8, w.q[nx], w.qoff[nx], lv + 1, rule,     \
+             hpub, sq, (const uint64_t *)g->iso, W, prefill, n, lvec)
     if (min_parent)
       G5_TD(CLAIM_MIN);
     else if (p.claim == CLAIM_CAS)
@@ -1583,7 +1583,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       G5_TD(CLAIM_OR);
 #undef G5_TD
     G5_LAUNCH_CHECK();
-    return rec(lv, 1);
+    return G5_OK;
   };
 
   // fh_ready: fh already holds the frontier bits of the hot targets
@@ -1599,10 +1599,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     if (fh_words && !fh_ready)
       hipLaunchKernelGGL(k_fh_build, dim3(grid_for(g->num_hot, kBlock, ncu * 8)), dim3(kBlock),
                          0, s, f, g->hot, g->num_hot, w.fh);
-    {
-      g5_status st_ = rec(lv, 0);
-      if (st_ != G5_OK) return st_;
-    }
+    hipEvent_t t0 = ev_at(lv, 0), t1 = ev_at(lv, 1);
 #define G5_BUL(K, P, A)                                                                     \
   do {                                                                                      \
     const void *fn_ = (const void *)&k_bu_step_lds<K, P, A>;                                 \
@@ -1610,10 +1607,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     g5_status st_ = lds_ready(fn_, (int64_t)dyn_);                                          \
     if (st_ != G5_OK) return st_;                                                           \
     const int per_cu_ = resident_per_cu(fn_, kLdsBlock, dyn_);                              \
-    hipLaunchKernelGGL((k_bu_step_lds<K, P, A>), dim3(ncu * per_cu_), dim3(kLdsBlock), dyn_, s, \
-                       g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words, w.vis, f, nfp,     \
-                       parent, level, l8, W, lv + 1, ctr, packed, w.sum, lds_words, lds_gs,     \
-                       hpub, sq, bn);                                                       \
+    G5_KLAUNCH(t0, t1, (k_bu_step_lds<K, P, A>), dim3(ncu * per_cu_), dim3(kLdsBlock), dyn_, s, \
+               g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words, w.vis, f, nfp, parent, level, \
+               l8, W, lv + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub, sq, bn);          \
   } while (0)
 #define G5_BU(K, P, A)                                                                      \
   do {                                                                                      \
@@ -1622,10 +1618,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     g5_status st_ = lds_ready(fn_, (int64_t)dyn_);                                          \
     if (st_ != G5_OK) return st_;                                                           \
     const int per_cu_ = resident_per_cu(fn_, kBuBlock, dyn_);                               \
-    hipLaunchKernelGGL((k_bu_step<K, P, A>), dim3(ncu * std::min(bu_bpc, per_cu_)),         \
-                       dim3(kBuBlock), dyn_, s, g->rp32, g->col_idx, hint, hint_id, w.fh,      \
-                       fh_words, w.vis, f, nfp, parent, level, l8, W, lv + 1, ctr, packed,    \
-                       hpub, sq, check, bn);                                                \
+    G5_KLAUNCH(t0, t1, (k_bu_step<K, P, A>), dim3(ncu * std::min(bu_bpc, per_cu_)),         \
+               dim3(kBuBlock), dyn_, s, g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words,   \
+               w.vis, f, nfp, parent, level, l8, W, lv + 1, ctr, packed, hpub, sq, check, bn); \
   } while (0)
 #define G5_BU_P(M, K, A)          \
   if (vpl == 2)                   \
@@ -1668,7 +1663,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
 #undef G5_BU
 #undef G5_BUL
     G5_LAUNCH_CHECK();
-    return rec(lv, 1);
+    return G5_OK;
   };
 
   // Top-down levels are queued kTdAhead levels beyond the one whose decision
@@ -1807,7 +1802,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       dir = 1;
     }
   }
-#undef G5_REC
+#undef G5_KLAUNCH
   // a traversal ended by an empty top-down queue was finished by that level's
   // queued expansion
   if (!ended_td && (prefill || !widened))
