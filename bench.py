@@ -112,9 +112,9 @@ def _per_dispatch(rows, counter, match, largest=False, min_kib=0.0):
 
 
 def is_bu_step(name):
-    """The bottom-up step kernels of timed runs (with or without the LDS-staged
-    summary; not the byte-counting variants, whose third template argument is
-    true)."""
+    """The bottom-up step kernels of the timed steps and the instrumented pass
+    (with or without the LDS-staged summary; not the byte-counting variants,
+    whose third template argument is true)."""
     import re
     m = re.search(r"k_bu_step(?:_lds)?<\d+, \d+, (true|false)", name)
     return bool(m) and m.group(1) == "false"
@@ -188,7 +188,7 @@ def summarize_trace(db, command, bench_json=None):
         out.append(f"| `{k}` | {n} | {t:.1f} | {t / n:.2f} | {100 * t / total:.1f} |")
     bu = [(t1 - t0) / 1e3 for name, t0, t1 in rows if is_bu_step(name)]
     work = [d for d in bu if d > NOOP_US]
-    out += ["", "## Bottom-up step (k_bu_step and k_bu_step_lds, timed variants)", "",
+    out += ["", "## Bottom-up step (k_bu_step and k_bu_step_lds, without byte counting)", "",
             f"* dispatches: {len(bu)}, of which {len(bu) - len(work)} are steps queued ahead "
             f"that exited at once (< {NOOP_US:.0f} us)",
             f"* working dispatches: {len(work)}, average {sum(work) / max(len(work), 1):.2f} us"]
