@@ -55,9 +55,9 @@ def source_hash(paths):
 BFS_SOURCES = ["paper_2012_13548_amd/csrc/bfs.hip", "paper_2012_13548_amd/csrc/g5_internal.h"]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source (else None)."""
+def measured_traffic(kernel, workload, field="bytes_per_launch"):
+    """HBM bytes (per launch, or the record's `field`) from committed rocprofv3
+    counter runs, if they were taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -66,7 +66,7 @@ def measured_traffic(kernel, workload):
     rec = data.get(f"{kernel}@{workload}")
     if not rec or rec.get("source_hash") != source_hash(BFS_SOURCES):
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get(field)
 
 
 COPY_PROBE_BYTES = 1 << 31  # each direction
@@ -109,6 +109,17 @@ def _per_dispatch(rows, counter, match, largest=False, min_kib=0.0):
     if largest:
         return max(per.values()), 1
     return sum(per.values()) / len(per), len(per)
+
+
+def _per_dispatch_map(rows, counter, match):
+    """{dispatch id: counter value in KiB} over dispatches of matching kernels."""
+    per = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter or not match(r.get("Kernel_Name", "")):
+            continue
+        key = int(r.get("Dispatch_Id") or r.get("Correlation_Id"))
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    return per
 
 
 def is_bu_step(name):
@@ -154,9 +165,40 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command):
         with open(path) as f:
             data = json.load(f)
     data[f"{kernel}@{workload}"] = rec
+
+    # The top-down expansion: its launches include those queued ahead that did
+    # nothing and, once per traversal, the one that finishes it (widens the
+    # byte levels into the int32 level array: it writes ~4n bytes and fetches
+    # less than it writes), which belongs to no top-down level.  Both runs
+    # execute the same program, so dispatch ids match between them; the
+    # record is the traffic of the real expansions per traversal (the bench
+    # divides it by its own count of top-down levels per traversal).
+    is_td = lambda name: "k_td_expand<" in name
+    tf = _per_dispatch_map(fr, "FETCH_SIZE", is_td)
+    tw = _per_dispatch_map(wr, "WRITE_SIZE", is_td)
+    if set(tf) != set(tw):
+        raise SystemExit("the two counter runs dispatched different top-down expansions")
+    # traversals of the workload graph: init dispatches of the largest grid (the
+    # run also warms the kernels up on a small graph)
+    grids = {int(r["Dispatch_Id"]): int(r["Grid_Size"]) for r in fr
+             if r.get("Counter_Name") == "FETCH_SIZE" and "k_bfs_init" in r.get("Kernel_Name", "")}
+    inits = sum(1 for g in grids.values() if g == max(grids.values()))
+    n = 1 << int(workload.lstrip("s"))
+    ending = {k for k in tw
+              if tw[k] * 1024 * w_factor >= 0.9 * 4 * n and tf[k] * f_factor < tw[k] * w_factor}
+    td_f = sum(v for k, v in tf.items() if k not in ending) * 1024 * f_factor
+    td_w = sum(v for k, v in tw.items() if k not in ending) * 1024 * w_factor
+    td = {"source_hash": rec["source_hash"],
+          "bytes_per_traversal": int((td_f + td_w) / inits),
+          "fetch_bytes_per_traversal": int(td_f / inits),
+          "write_bytes_per_traversal": int(td_w / inits),
+          "traversals": inits, "dispatches": len(tf), "finishing_dispatches": len(ending),
+          "command": command}
+    data[f"td_step@{workload}"] = td
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     print(json.dumps(rec))
+    print(json.dumps(td))
 
 
 def summarize_trace(db, command, bench_json=None):
@@ -305,7 +347,17 @@ def run_gpu(args):
         roofline["other_step"] = {
             "kernel": {1: "td_step", 2: "k_bu_step"}[other],
             "achieved": round(step_bytes[other] / (step_time[other] / 1e3) / 1e9, 1),
-            "time_share": round(step_time[other] / (step_time[1] + step_time[2]), 3)}
+            "time_share": round(step_time[other] / (step_time[1] + step_time[2]), 3),
+            "launches": step_launches[other],
+            "avg_launch_ms": round(step_time[other] / max(step_launches[other], 1), 4),
+            "alg_bytes_per_launch": int(step_bytes[other] / max(step_launches[other], 1))}
+        if other == 1:
+            # measured HBM bytes of the top-down expansions per traversal, spread
+            # over this pass's top-down levels (one launch each)
+            per_trav = measured_traffic("td_step", f"s{scale}", "bytes_per_traversal")
+            roofline["other_step"]["traffic"] = (
+                int(per_trav * len(roots) / step_launches[1])
+                if per_trav is not None and step_launches[1] else None)
     gpu = {"value": hmean(samples) / 1e9, "ms_per_step": wall * 1e3 / args.steps,
            "build_ms": build_ms, "nnz": csr.nnz, "roots": roots, "m_r": m_r,
            "roofline": roofline, "per_level_root0": per_level}
