@@ -103,6 +103,22 @@ def disjoint_union(*parts):
     return np.concatenate(out).reshape(-1, 2), base, offs
 
 
+def broom(path_len, leaves):
+    """A path 0 .. path_len-1 whose last vertex is the centre of a star; each
+    leaf path_len + j also holds a pendant vertex path_len + leaves + j."""
+    p, l = path_len, leaves
+    pairs = [(i, i + 1) for i in range(p - 1)] + [(p - 1, p + j) for j in range(l)] + \
+            [(p + j, p + l + j) for j in range(l)]
+    return as_edges(pairs), p + 2 * l
+
+
+def broom_dist(path_len, leaves):
+    """Levels from root 0: i on the path, path_len on a leaf, path_len + 1 on a
+    pendant vertex."""
+    return np.concatenate([np.arange(path_len), np.full(leaves, path_len),
+                           np.full(leaves, path_len + 1)]).astype(np.int32)
+
+
 def random_graph(rng, n, p):
     iu = np.triu_indices(n, 1)
     keep = rng.random(iu[0].size) < p

@@ -97,6 +97,21 @@ def test_long_path():
         c.check_root(int(perm[n // 2]), **m)
 
 
+def test_deep_switch_to_bottom_up():
+    # The frontier first grows at level 300 (a path, then a star whose 4,000
+    # leaves each hold a pendant vertex), so the switch to bottom-up comes after
+    # the byte levels were widened: its frontier bitmap is built from the int32
+    # levels, and min-id claims test the int32 level of a target.
+    e, n = G.broom(300, 4000)
+    c = Case(e, n)
+    want = G.broom_dist(300, 4000)
+    for m in (dict(), dict(claim=g5.CLAIM_CAS), dict(min_parent=True), dict(hint=False),
+              dict(lds=False), dict(direction=g5.DIR_TOPDOWN, min_parent=True)):
+        parent, level = c.check_root(0, **m)
+        assert np.array_equal(level, want), m
+        assert np.array_equal(parent[300 + 4000:], np.arange(300, 300 + 4000)), m
+
+
 @pytest.fixture(scope="module")
 def kron10():
     scale = 10

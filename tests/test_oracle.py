@@ -57,6 +57,15 @@ def test_star(leaves, r):
         assert np.all(parent[1:] == 0)
 
 
+@pytest.mark.parametrize("path_len,leaves", [(1, 3), (5, 1), (300, 40)])
+def test_broom(path_len, leaves):
+    e, n = G.broom(path_len, leaves)
+    _, parent, level = run(e, n, 0)
+    assert np.array_equal(level, G.broom_dist(path_len, leaves))
+    # a pendant's only neighbour is its leaf
+    assert np.array_equal(parent[path_len + leaves:], np.arange(path_len, path_len + leaves))
+
+
 @pytest.mark.parametrize("a,b,r", [(1, 5, 2), (4, 4, 0), (7, 3, 10), (20, 31, 311)])
 def test_grid(a, b, r):
     e, n = G.grid(a, b)
