@@ -25,6 +25,7 @@
 //             n_f < n / beta and the frontier shrinks.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstring>
 
 #include <hip/hip_ext.h>
@@ -1414,7 +1415,9 @@ BfsWork::~BfsWork() {
 
 // Waits until a kernel on `s` has published sequence number `want` to the
 // mapped host counters and copies their values to out[0, C_NPUB); falls back to
-// the stream's status so a failed launch cannot leave the host spinning.
+// the stream's status so a failed launch cannot leave the host spinning.  The
+// status is asked only after kQueryAfter of waiting (longer than any level
+// takes): asking while the stream runs can queue a marker between kernels.
 static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want, int64_t *out) {
   volatile uint64_t *h = w.host_pub + (want % kPubBufs) * kPubSlots;
   const uint64_t tag = want & 0xffff;
@@ -1423,9 +1426,13 @@ static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want, int64_
       if ((h[i] >> kPubShift) != tag) return false;
     return true;
   };
+  using clk = std::chrono::steady_clock;
+  constexpr auto kQueryAfter = std::chrono::milliseconds(2);
+  auto next_query = clk::now() + kQueryAfter;
   for (uint32_t spin = 0;; ++spin) {
     if (ready()) break;
-    if ((spin & 1023) == 1023) {
+    if ((spin & 255) == 255 && clk::now() >= next_query) {
+      next_query = clk::now() + kQueryAfter;
       hipError_t e = hipStreamQuery(s);
       if (e == hipSuccess) {
         if (ready()) break;
