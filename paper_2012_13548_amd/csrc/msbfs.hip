@@ -51,7 +51,7 @@ struct MsCtl {
   unsigned long long mu0;  // degree sum of vertices not yet seen by every root
   unsigned long long err;
   unsigned long long nlevels;
-  unsigned long long pad;
+  unsigned long long mu_lv[2];  // stepped mode: m_u at the start of level l, by parity
   int64_t frontier[kStatLevels];
   int32_t dir[kStatLevels];
 };
@@ -426,11 +426,27 @@ __global__ __launch_bounds__(kBlock) void k_ms_root_stats(MsArgs a) {
   root_stats(a, s_red);
 }
 
+// Level l takes its own direction decision from the counters the previous
+// level left (every workgroup computes the same one), so the host can queue
+// levels ahead: a level whose frontier is empty (the traversal ended earlier)
+// does nothing, and one deeper than int8 levels allow flags the error.  m_u at
+// the start of level l is kept by parity: m_u(l) = m_u(l - 1) - the degree sum
+// of vertices that level l - 1 made fully seen.
 template <bool PAR>
-__global__ __launch_bounds__(kBlock) void k_ms_level(MsArgs a, int l, int td,
-                                                     unsigned long long nf) {
+__global__ __launch_bounds__(kBlock) void k_ms_level(MsArgs a, int l) {
   __shared__ uint64_t s_red[kBlock / kWave];
-  level_body<PAR>(a, l, td != 0, nf, s_red);
+  MsCtl *ctl = a.ctl;
+  Slot *cur = &ctl->slot[l % 3];
+  const uint64_t nf = ld_agent(&cur->nf), mf = ld_agent(&cur->mf);
+  if (nf == 0) return;
+  if (l > a.max_level) {  // a vertex lies deeper than int8 can hold
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(&ctl->err, 1ull);
+    return;
+  }
+  const uint64_t mu =
+      l == 0 ? ld_agent(&ctl->mu0) : ld_agent(&ctl->mu_lv[(l - 1) & 1]) - ld_agent(&cur->dec);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->mu_lv[l & 1] = mu;
+  level_body<PAR>(a, l, choose_td(a, mf, mu), nf, s_red);
 }
 
 __global__ void k_fill_i8(int8_t *__restrict__ p, int64_t len, bool vec) {
@@ -521,8 +537,10 @@ struct BatchLease {
 };
 }  // namespace
 
-// Stepped batch: one launch per level; the host reads the level counters
-// after each launch and takes the direction decision.
+// Stepped batch: one launch per level, each taking its own direction
+// decision on the device.  The host queues levels in groups (8, then 4 at a
+// time) and reads the counters once per group instead of once per level; the
+// levels queued past the end do nothing.
 g5_status batch_stepped(const g5_csr *g, BatchWork &w, const MsArgs &a, int32_t *parents,
                         hipStream_t s, bool timed, g5_batch_stats *stats, int bpc) {
   const int blocks = g->num_cu * bpc;
@@ -530,32 +548,26 @@ g5_status batch_stepped(const g5_csr *g, BatchWork &w, const MsArgs &a, int32_t 
   if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
   hipLaunchKernelGGL(k_ms_root_stats, dim3(blocks), dim3(kBlock), 0, s, a);
   G5_LAUNCH_CHECK();
-  G5_HIP(hipMemcpyAsync(hc, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
-  G5_HIP(hipStreamSynchronize(s));
-  uint64_t mu = hc->mu0;
   bool err = false;
-  int l = 0;
-  for (;; ++l) {
-    const Slot &cur = hc->slot[l % 3];
-    const uint64_t nf = cur.nf, mf = cur.mf;
-    if (nf == 0) break;
-    const bool td = a.direction == G5_DIR_TOPDOWN ||
-                    (a.direction == G5_DIR_AUTO && (double)mf <= (double)mu / a.alpha);
-    if (parents)
-      hipLaunchKernelGGL(k_ms_level<true>, dim3(blocks), dim3(kBlock), 0, s, a, l, (int)td,
-                         (unsigned long long)nf);
-    else
-      hipLaunchKernelGGL(k_ms_level<false>, dim3(blocks), dim3(kBlock), 0, s, a, l, (int)td,
-                         (unsigned long long)nf);
+  int l = 0;  // levels queued
+  for (int group = 8;; group = 4) {
+    for (int j = 0; j < group; ++j, ++l) {
+      if (parents)
+        hipLaunchKernelGGL(k_ms_level<true>, dim3(blocks), dim3(kBlock), 0, s, a, l);
+      else
+        hipLaunchKernelGGL(k_ms_level<false>, dim3(blocks), dim3(kBlock), 0, s, a, l);
+    }
     G5_LAUNCH_CHECK();
     G5_HIP(hipMemcpyAsync(hc, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
     G5_HIP(hipStreamSynchronize(s));
-    const Slot &nxt = hc->slot[(l + 1) % 3];
-    mu -= nxt.dec;
-    if (l + 1 > a.max_level && nxt.nf != 0) {
+    if (hc->err) {
       err = true;
       break;
     }
+    // levels 0 .. nlevels-1 ran; fewer than queued means one found its frontier
+    // empty, else the frontier of the next level decides (its slot was cleared
+    // by level l - 2 and filled by level l - 1, both of which ran)
+    if ((int)hc->nlevels < l || hc->slot[l % 3].nf == 0) break;
   }
   if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
   G5_HIP(hipStreamSynchronize(s));
