@@ -1135,7 +1135,7 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
   bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
 
-// End of a traversal not ended by a top-down decision kernel: the unreached
+// End of a traversal not finished by a top-down expansion: the unreached
 // non-isolated vertices get parent -1 when the parent array was pre-filled with
 // hint targets (fix), and the byte levels are widened into `level` when lev8 is
 // given (also used alone before the first level deeper than kByteLevels).
