@@ -55,10 +55,12 @@ def source_hash(paths):
 BFS_SOURCES = ["paper_2012_13548_amd/csrc/bfs.hip", "paper_2012_13548_amd/csrc/g5_internal.h"]
 
 
-def measured_traffic(kernel, workload, field="bytes_per_launch"):
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel, workload, field="bytes_per_launch", path=TRAFFIC_PATH):
     """HBM bytes (per launch, or the record's `field`) from committed rocprofv3
     counter runs, if they were taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -138,7 +140,7 @@ NOOP_KIB = 1024.0
 NOOP_US = 10.0
 
 
-def reduce_pmc(fetch_dir, write_dir, kernel, workload, command):
+def reduce_pmc(fetch_dir, write_dir, kernel, workload, command, path=TRAFFIC_PATH):
     """Calibrated HBM bytes per launch of `kernel` from a FETCH_SIZE run and a
     WRITE_SIZE run; each counter is scaled by what it reads for the copy probe
     (known bytes).  Stored in profiles/traffic.json with the kernel source hash,
@@ -159,7 +161,6 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command):
            "write_bytes_per_launch": int(k_w * 1024 * w_factor),
            "fetch_factor": round(f_factor, 4), "write_factor": round(w_factor, 4),
            "launches": [nf, nw], "command": command}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     data = {}
     if os.path.exists(path):
         with open(path) as f:
