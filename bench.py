@@ -196,10 +196,29 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command, path=TRAFFIC_PAT
           "traversals": inits, "dispatches": len(tf), "finishing_dispatches": len(ending),
           "command": command}
     data[f"td_step@{workload}"] = td
+
+    # Per level: the run's last traversal of the workload graph is a plain one
+    # from the benchmark's first root.  Its step kernels in dispatch order are
+    # its levels, leaving out the steps queued ahead that exited at once (they
+    # write nothing) and the dispatch that finishes the traversal.
+    last = max(k for k, g in grids.items() if g == max(grids.values()))
+    names = {int(r["Dispatch_Id"]): r.get("Kernel_Name", "") for r in fr}
+    fa = _per_dispatch_map(fr, "FETCH_SIZE", lambda name: True)
+    wa = _per_dispatch_map(wr, "WRITE_SIZE", lambda name: True)
+    levels = []
+    for k in sorted(d for d in fa if d > last):
+        name = names[k]
+        if not (is_td(name) or is_bu_step(name)) or wa.get(k, 0.0) <= 0 or k in ending:
+            continue
+        levels.append({"dir": "TD" if is_td(name) else "BU",
+                       "bytes": int(fa[k] * 1024 * f_factor + wa[k] * 1024 * w_factor)})
+    data[f"root0_levels@{workload}"] = {"source_hash": rec["source_hash"], "levels": levels,
+                                        "command": command}
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     print(json.dumps(rec))
     print(json.dumps(td))
+    print(json.dumps(levels))
 
 
 def summarize_trace(db, command, bench_json=None):
@@ -330,6 +349,12 @@ def run_gpu(args):
                   "alg_bytes": acct[0]["bytes"][lv],
                   "ms": round(stats[0]["step_ms"][lv], 4)}
                  for lv in range(min(stats[0]["nlevels"], len(stats[0]["dir"])))]
+    # measured HBM bytes per level of the first root, from the counter runs
+    lv_bytes = measured_traffic("root0_levels", f"s{scale}", "levels")
+    if lv_bytes and [x["dir"] for x in lv_bytes] == [p["dir"] for p in per_level]:
+        for p, x in zip(per_level, lv_bytes):
+            p["hbm_bytes"] = x["bytes"]
+            p["hbm_gbs"] = round(x["bytes"] / (p["ms"] / 1e3) / 1e9, 1) if p["ms"] else None
     log(f"instrumented pass done: {step_launches[1]} top-down and {step_launches[2]} "
         f"bottom-up step kernels timed")
 

@@ -1,6 +1,7 @@
 """Host logic of the benchmark's measurement tools, on synthetic inputs: the
 rocprofv3 counter reduction (calibration by the copy probe, the dispatches it
-keeps and drops, traversal counting), the source-hash gate on the stored
+keeps and drops, traversal counting, the per-level split of the last
+traversal), the source-hash gate on the stored
 record, and the kernel-trace summary."""
 import csv
 import json
@@ -68,6 +69,12 @@ def test_reduce_pmc(tmp_path):
     assert bench.measured_traffic("td_step", "s10", "bytes_per_traversal", path=out) == \
         td["bytes_per_traversal"]
     assert bench.measured_traffic("k_bu_step", "s26", path=out) is None
+    # the last workload traversal's levels: working step dispatches in order, without
+    # the queued-ahead step (writes nothing), the byte-counting variant and the finish
+    levels = bench.measured_traffic("root0_levels", "s10", "levels", path=out)
+    assert [x["dir"] for x in levels] == ["BU", "BU", "TD", "TD"]
+    assert [x["bytes"] for x in levels] == [(2 * 2000 + 1500) * KIB, (2 * 4000 + 2500) * KIB,
+                                            (2 * 100 + 50) * KIB, (2 * 300 + 70) * KIB]
 
 
 def test_traffic_gated_by_source_hash(tmp_path):
