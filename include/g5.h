@@ -185,10 +185,14 @@ typedef struct {
 g5_status g5_bfs_ex(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
                     void *stream, const g5_bfs_params *params, g5_bfs_stats *stats);
 
-/* Batched BFS from k roots in one persistent launch (multi-source BFS: each
- * vertex carries a 64-bit mask whose bit b stands for roots[b]; one pass over
- * the graph per level serves every root; levels stay synchronous through a
- * grid-wide barrier, Section 2.3.2).
+/* Batched BFS from k roots (multi-source BFS: each vertex carries a 64-bit
+ * mask whose bit b stands for roots[b]; one pass over the graph per level
+ * serves every root).  Levels stay synchronous as in Section 2.3.2: by default
+ * each level is one plain launch (the kernel boundary is the level barrier)
+ * that takes its own direction decision on the device, and the host reads the
+ * level counters once per group of queued levels; G5_FLAG_PERSISTENT in
+ * g5_bfs_batch_ex runs every level in one cooperative launch with a grid-wide
+ * barrier instead.  Returns once the work on `stream` is complete.
  *   roots    host, int64 [k], each in [0, n); duplicates allowed.
  *   k        1 .. 64.
  *   parents  device, int32 [k][n] (row b for roots[b]), or NULL to skip parents.
@@ -216,8 +220,9 @@ typedef struct {
   int32_t nlevels;                         /* levels processed */
   int32_t dir[G5_MAX_STAT_LEVELS];         /* 1 top-down, 2 bottom-up */
   int64_t frontier[G5_MAX_STAT_LEVELS];    /* vertices with a nonzero frontier mask */
-  double launch_ms;                        /* device time of the persistent launch (TIME_STEPS) */
-  int32_t grid_blocks;                     /* workgroups of the persistent launch */
+  double launch_ms;                        /* device time of the traversal: root statistics and
+                                              every level (TIME_STEPS) */
+  int32_t grid_blocks;                     /* workgroups per launch */
   int32_t pad;
   double alpha;                            /* switch threshold used */
   int32_t reserved[6];
