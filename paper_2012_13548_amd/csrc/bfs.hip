@@ -151,7 +151,7 @@ __global__ void k_bfs_init(int64_t root, uint8_t *__restrict__ lev8,
                            int32_t *__restrict__ q0, uint32_t *__restrict__ qo0,
                            unsigned long long *__restrict__ ctr, const int64_t *__restrict__ rp,
                            int64_t nnz, int64_t nonisolated, TdRule rule,
-                           unsigned long long *host, unsigned long long seq) {
+                           unsigned long long *host, unsigned long long seq, bool fill_lev8) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t n4 = vec ? n / 4 : 0;
@@ -165,11 +165,19 @@ __global__ void k_bfs_init(int64_t root, uint8_t *__restrict__ lev8,
   }
   for (int64_t i = n4 * 4 + t; i < n; i += stride)
     parent[i] = i == root ? (int32_t)root : (fill ? fill[i] : -1);
-  // lev8 is 16-byte aligned and padded to a multiple of 16 bytes
-  for (int64_t i = t; i < (n + 15) / 16; i += stride) {
-    v4i x = m1;
-    if (i == (root >> 4)) reinterpret_cast<uint8_t *>(&x)[root & 15] = 0;
-    __builtin_nontemporal_store(x, reinterpret_cast<v4i *>(lev8) + i);
+  // A byte level is read only where the visited bitmap says the vertex was
+  // reached in this traversal (stale bytes elsewhere are never used), so only
+  // the root's byte is written; min-id claims test the bytes of vertices not
+  // reached yet, and get 0xff everywhere (fill_lev8; lev8 is 16-byte aligned
+  // and padded to a multiple of 16 bytes).
+  if (fill_lev8) {
+    for (int64_t i = t; i < (n + 15) / 16; i += stride) {
+      v4i x = m1;
+      if (i == (root >> 4)) reinterpret_cast<uint8_t *>(&x)[root & 15] = 0;
+      __builtin_nontemporal_store(x, reinterpret_cast<v4i *>(lev8) + i);
+    }
+  } else if (t == 0) {
+    lev8[root] = 0;
   }
   const int64_t rw = root >> 6;
   for (int64_t i = t; i < words; i += stride) {
@@ -191,7 +199,7 @@ __global__ void k_bfs_init(int64_t root, uint8_t *__restrict__ lev8,
 }
 
 
-// Levels are kept as bytes (lev8, 0xff = not reached) while they fit, so the
+// Levels are kept as bytes (lev8, valid where the vertex was reached) while they fit, so the
 // scattered level writes of a traversal touch a quarter of the bytes; the
 // int32 output is written once, by a streaming pass at the end (or, on a graph
 // deeper than kByteLevels, before the first level that would not fit, after
@@ -206,24 +214,36 @@ __device__ __forceinline__ void put_level(uint8_t *lev8, int32_t *level, int32_t
     level[v] = lvl;
 }
 
-// level = lev8 widened (0xff -> -1), 4 vertices per thread, grid-stride.
+// Bit v: vertex v was reached in this traversal (visited and not isolated;
+// the isolated bitmap also covers the padding past n), or is the root.
+__device__ __forceinline__ uint64_t reached_word(const uint64_t *__restrict__ vis,
+                                                 const uint64_t *__restrict__ iso, int64_t w,
+                                                 int64_t root) {
+  uint64_t m = vis[w] & ~iso[w];
+  if ((root >> 6) == w) m |= 1ull << (root & 63);
+  return m;
+}
+
+// level = lev8 widened where the vertex was reached, -1 elsewhere; 4 vertices
+// per thread, grid-stride.
 __device__ __forceinline__ void expand_levels(const uint8_t *__restrict__ lev8,
                                               int32_t *__restrict__ level, int64_t n, bool vec,
-                                              int64_t stride) {
+                                              int64_t stride, const uint64_t *__restrict__ vis,
+                                              const uint64_t *__restrict__ iso, int64_t root) {
   typedef int v4i __attribute__((ext_vector_type(4)));
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n4 = vec ? n / 4 : 0;
   for (int64_t i = t; i < n4; i += stride) {
     const uint32_t x = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(lev8) + i);
+    const int64_t v0 = 4 * i;
+    const uint32_t r4 = (uint32_t)(reached_word(vis, iso, v0 >> 6, root) >> (v0 & 63)) & 0xfu;
     v4i o;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t b = (x >> (8 * j)) & 0xffu;
-      o[j] = b == 0xffu ? -1 : (int)b;
-    }
+    for (int j = 0; j < 4; ++j) o[j] = ((r4 >> j) & 1) ? (int)((x >> (8 * j)) & 0xffu) : -1;
     __builtin_nontemporal_store(o, reinterpret_cast<v4i *>(level) + i);
   }
-  for (int64_t i = n4 * 4 + t; i < n; i += stride) level[i] = lev8[i] == 0xff ? -1 : lev8[i];
+  for (int64_t i = n4 * 4 + t; i < n; i += stride)
+    level[i] = ((reached_word(vis, iso, i >> 6, root) >> (i & 63)) & 1) ? (int32_t)lev8[i] : -1;
 }
 
 // parent = -1 for the non-isolated vertices not visited (grid-stride over words).
@@ -309,7 +329,8 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
     uint64_t *vis, int32_t *parent, int32_t *__restrict__ level, uint8_t *__restrict__ lev8,
     int32_t *__restrict__ qn, uint32_t *__restrict__ qon, int32_t next_level, TdRule rule,
     unsigned long long *__restrict__ host, unsigned long long seq,
-    const uint64_t *__restrict__ iso, int64_t words, bool fix, int64_t n, bool vec) {
+    const uint64_t *__restrict__ iso, int64_t words, bool fix, int64_t n, bool vec,
+    int64_t root) {
   __shared__ uint32_t s_off[kTdTile + 1];
   __shared__ int32_t s_src[kTdTile];
   __shared__ int64_t s_base[kTdTile];
@@ -319,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
     if (ctr[C_ENDL] == (unsigned long long)next_level) {
       const int64_t stride = (int64_t)gridDim.x * kBlock;
       if (fix) unreached_words(vis, iso, words, parent, stride);
-      if (lev8) expand_levels(lev8, level, n, vec, stride);
+      if (lev8) expand_levels(lev8, level, n, vec, stride, vis, iso, root);
     }
     return;
   }
@@ -378,6 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
         uint64_t bit = 1ull << (v & 63);
         uint64_t *wp = vis + (v >> 6);
         if (CLAIM == CLAIM_MIN) {
+          // (min-id mode fills the byte levels with 0xff at the start)
           const int32_t lv = lev8 ? (lev8[v] == 0xff ? -1 : (int32_t)lev8[v]) : level[v];
           if (lv < 0 || lv == next_level) {
             atomicMin((unsigned int *)(parent + v), (unsigned int)u);
@@ -465,16 +487,20 @@ __global__ __launch_bounds__(kBlock) void k_front_from_level(
     const uint8_t *__restrict__ lev8, const int32_t *__restrict__ level, int64_t n,
     int32_t lvl, uint64_t *__restrict__ front, int64_t words,
     unsigned long long *__restrict__ ctr, int64_t nf, const int32_t *__restrict__ hot,
-    int64_t num_hot, uint64_t *__restrict__ fh) {
+    int64_t num_hot, uint64_t *__restrict__ fh, const uint64_t *__restrict__ vis,
+    const uint64_t *__restrict__ iso, int64_t root) {
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_NFIN] = (unsigned long long)nf;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = __lane_id();
+  // a byte level counts only where the vertex was reached in this traversal
   auto at = [&](int32_t v) -> bool {
-    return lev8 ? lev8[v] == (uint8_t)lvl : level[v] == lvl;
+    return lev8 ? lev8[v] == (uint8_t)lvl && ((reached_word(vis, iso, v >> 6, root) >> (v & 63)) & 1)
+                : level[v] == lvl;
   };
   if (lev8) {
-    // lev8 is padded with 0xff to a multiple of 16 bytes (no level is 0xff)
+    // lev8 is padded to a multiple of 16 bytes; the padding past n is masked
+    // like every vertex not reached
     typedef uint32_t v4u __attribute__((ext_vector_type(4)));
     const int64_t chunks = (n + 15) / 16;
     const uint32_t pat = 0x01010101u * (uint32_t)lvl;
@@ -496,7 +522,8 @@ __global__ __launch_bounds__(kBlock) void k_front_from_level(
       uint64_t wv = (uint64_t)bits << (16 * (lane & 3));
       wv |= __shfl_xor(wv, 1, kWave);
       wv |= __shfl_xor(wv, 2, kWave);
-      if ((lane & 3) == 0 && (i >> 2) < words) front[i >> 2] = wv;
+      if ((lane & 3) == 0 && (i >> 2) < words)
+        front[i >> 2] = wv & reached_word(vis, iso, i >> 2, root);
     }
   } else {
     for (int64_t w = t; w < words; w += stride) {
@@ -1142,10 +1169,10 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
 __global__ void k_finish(const uint64_t *__restrict__ vis, const uint64_t *__restrict__ iso,
                          int64_t words, int32_t *__restrict__ fix,
                          const uint8_t *__restrict__ lev8, int32_t *__restrict__ level,
-                         int64_t n, bool vec) {
+                         int64_t n, bool vec, int64_t root) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (fix) unreached_words(vis, iso, words, fix, stride);
-  if (lev8) expand_levels(lev8, level, n, vec, stride);
+  if (lev8) expand_levels(lev8, level, n, vec, stride, vis, iso, root);
 }
 
 // Frontier summary: bit i of sum = OR of front bits [i << gs, (i + 1) << gs).
@@ -1521,7 +1548,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                      dim3(kBlock), 0, s, root, w.lev8, parent, n,
                      prefill ? g->hint_id : nullptr, w.vis, g->iso, W,
                      ((uintptr_t)parent & 15) == 0, w.q[0], w.qoff[0], ctr, g->row_ptr, g->nnz,
-                     g->nonisolated, rule, hpub, seq0);
+                     g->nonisolated, rule, hpub, seq0, min_parent);
   G5_LAUNCH_CHECK();
   // Levels go to the byte array while they fit; the kernels of level lv (writing
   // lv + 1) get sink(lv), which widens the bytes into `level` once, before the
@@ -1533,7 +1560,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     if (lv + 1 <= kByteLevels) return w.lev8;
     if (!widened) {
       hipLaunchKernelGGL(k_finish, dim3(finish_grid), dim3(kBlock), 0, s, w.vis, g->iso, W,
-                         nullptr, (const uint8_t *)w.lev8, level, n, lvec);
+                         nullptr, (const uint8_t *)w.lev8, level, n, lvec, root);
       widened = true;
     }
     return nullptr;
@@ -1581,7 +1608,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
 #define G5_TD(C)                                                                                 \
   G5_KLAUNCH(t0, t1, k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, c, \
              g->rp32, g->col_idx, w.vis, parent, level, l8, w.q[nx], w.qoff[nx], lv + 1, rule,     \
-             hpub, sq, (const uint64_t *)g->iso, W, prefill, n, lvec)
+             hpub, sq, (const uint64_t *)g->iso, W, prefill, n, lvec, root)
     if (min_parent)
       G5_TD(CLAIM_MIN);
     else if (p.claim == CLAIM_CAS)
@@ -1727,7 +1754,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         hipLaunchKernelGGL(k_front_from_level, dim3(grid_for(4 * W, kBlock, ncu * 16)),
                            dim3(kBlock), 0, s, widened ? nullptr : (const uint8_t *)w.lev8,
                            (const int32_t *)level, n, lvl, front, W, ctr, qlen, g->hot,
-                           fh_words ? g->num_hot : (int64_t)0, w.fh);
+                           fh_words ? g->num_hot : (int64_t)0, w.fh, (const uint64_t *)w.vis,
+                           (const uint64_t *)g->iso, root);
         G5_LAUNCH_CHECK();
         dir = 2;
         nf_prev = qlen;
@@ -1815,7 +1843,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   if (!ended_td && (prefill || !widened))
     hipLaunchKernelGGL(k_finish, dim3(finish_grid), dim3(kBlock), 0, s, w.vis, g->iso, W,
                        prefill ? parent : nullptr, widened ? nullptr : (const uint8_t *)w.lev8,
-                       level, n, lvec);
+                       level, n, lvec, root);
   G5_LAUNCH_CHECK();
   G5_HIP(hipStreamSynchronize(s));
   if (stats) {
