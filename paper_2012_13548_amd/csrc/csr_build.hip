@@ -119,6 +119,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
   __shared__ uint64_t base[kRadix];
   __shared__ uint32_t wh[4][kRadix];
   __shared__ uint32_t ttot[kRadix];
+  __shared__ uint32_t doff[kRadix];        // where each digit's run starts in the tile
+  __shared__ uint64_t s_keys[kSortTile];   // the tile's keys in digit order
+  __shared__ uint32_t s_scan[kSortBlock / kWave];
   const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
   base[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
   const uint64_t lt = lanemask_lt();
@@ -158,16 +161,29 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         s += c;
       }
       ttot[tid] = s;
+      uint32_t total;
+      doff[tid] = block_excl_scan<kSortBlock, uint32_t>(s, s_scan, total);
     }
-    __syncthreads();
+    __syncthreads();  // doff, wh and ttot complete
+    // Stage the tile in LDS in digit order (stable: within a digit, keys keep
+    // their input order), then write each digit's run out contiguously, so a
+    // wavefront's stores cover few lines instead of one line per lane.
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       uint64_t idx = tbase + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
       if (idx < nkeys) {
         uint32_t d = (uint32_t)(key[j] >> shift) & 0xFF;
-        uint64_t pos = base[d] + wh[w][d] + rank[j];
-        if (pos < nkeys) kout[pos] = key[j];
+        const uint32_t lp = doff[d] + wh[w][d] + rank[j];
+        if (lp < (uint32_t)kSortTile) s_keys[lp] = key[j];
       }
+    }
+    __syncthreads();
+    const uint32_t tile_n = (uint32_t)std::min<uint64_t>(kSortTile, nkeys - tbase);
+    for (uint32_t i = tid; i < tile_n; i += kSortBlock) {
+      const uint64_t k = s_keys[i];
+      const uint32_t d = (uint32_t)(k >> shift) & 0xFF;
+      const uint64_t pos = base[d] + (i - doff[d]);
+      if (pos < nkeys) kout[pos] = k;
     }
     __syncthreads();
     base[tid] += ttot[tid];
