@@ -198,15 +198,16 @@ __device__ __forceinline__ bool is_head(const uint64_t *keys, uint64_t i, uint64
   return k != sent && (i == 0 || keys[i - 1] != k);
 }
 
-// Distinct keys per compaction tile (thread t owns 16 consecutive keys).
+// Distinct keys per compaction tile of kCompactTile keys (only the count, so
+// the threads take the tile's keys strided by the block: coalesced loads).
 __global__ __launch_bounds__(kCompactBlock) void k_heads_count(const uint64_t *__restrict__ keys,
                                                                uint64_t nkeys, uint64_t sent,
                                                                uint32_t *__restrict__ bsum) {
   __shared__ uint32_t s[kCompactBlock / kWave];
-  uint64_t b = (uint64_t)blockIdx.x * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
+  const uint64_t b = (uint64_t)blockIdx.x * kCompactTile + threadIdx.x;
   uint32_t c = 0;
   for (int j = 0; j < kCompactItems; ++j) {
-    uint64_t i = b + j;
+    uint64_t i = b + (uint64_t)j * kCompactBlock;
     if (i < nkeys && is_head(keys, i, sent)) ++c;
   }
   uint32_t tot = block_sum<kCompactBlock, uint32_t>(c, s);
@@ -218,11 +219,22 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
     const uint64_t *__restrict__ boff, int32_t *__restrict__ col_idx,
     int64_t *__restrict__ row_ptr) {
   __shared__ uint32_t s[kCompactBlock / kWave];
-  uint64_t b = (uint64_t)blockIdx.x * kCompactTile + (uint64_t)threadIdx.x * kCompactItems;
+  // The tile (and the key before it) staged in LDS by coalesced loads: thread t
+  // then takes its 16 consecutive keys from there (the compaction keeps key
+  // order, so a thread's keys must be consecutive).  Past the end: sentinels.
+  __shared__ uint64_t s_k[kCompactTile + 1];
+  const uint64_t t0 = (uint64_t)blockIdx.x * kCompactTile;
+  for (int x = threadIdx.x; x <= kCompactTile; x += kCompactBlock) {
+    const uint64_t i = t0 + (uint64_t)x;  // key i - 1 goes to s_k[x]
+    s_k[x] = (i == 0 || i - 1 >= nkeys) ? sent : keys[i - 1];
+  }
+  __syncthreads();
+  const int x0 = threadIdx.x * kCompactItems + 1;  // s_k index of this thread's first key
+  uint64_t b = t0 + (uint64_t)threadIdx.x * kCompactItems;
   uint32_t c = 0;
   for (int j = 0; j < kCompactItems; ++j) {
-    uint64_t i = b + j;
-    if (i < nkeys && is_head(keys, i, sent)) ++c;
+    const uint64_t k = s_k[x0 + j];
+    if (b + j < nkeys && k != sent && s_k[x0 + j - 1] != k) ++c;
   }
   uint32_t tot;
   uint64_t pos = boff[blockIdx.x] + block_excl_scan<kCompactBlock, uint32_t>(c, s, tot);
@@ -230,8 +242,8 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
   for (int j = 0; j < kCompactItems; ++j) {
     uint64_t i = b + j;
     if (i >= nkeys) break;
-    uint64_t k = keys[i];
-    uint64_t prev = i ? keys[i - 1] : sent;
+    uint64_t k = s_k[x0 + j];
+    uint64_t prev = s_k[x0 + j - 1];  // the sentinel before key 0
     int64_t up = i ? (int64_t)(prev >> sb) : -1;
     if (k != sent) {
       if (i == 0 || prev != k) {
