@@ -324,31 +324,6 @@ __device__ void bu_phase(const MsArgs &a, const uint64_t *front, uint64_t *next,
   }
 }
 
-// Counters of the root frontier (level 0) into slot 0 and mu0.
-__device__ void root_stats(const MsArgs &a, uint64_t *s_red) {
-  MsCtl *ctl = a.ctl;
-  const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t gthreads = (int64_t)gridDim.x * kBlock;
-  uint64_t nf = 0, mf = 0, mu = 0;
-  for (int64_t v = gtid; v < a.n; v += gthreads) {
-    const uint64_t f = a.buf0[v], s = a.seen[v];
-    const int64_t d = a.rp[v + 1] - a.rp[v];
-    if (f) {
-      nf += 1;
-      mf += (uint64_t)d;
-    }
-    if (s != a.full) mu += (uint64_t)d;
-  }
-  nf = block_sum<kBlock, uint64_t>(nf, s_red);
-  mf = block_sum<kBlock, uint64_t>(mf, s_red);
-  mu = block_sum<kBlock, uint64_t>(mu, s_red);
-  if (threadIdx.x == 0) {
-    atomicAdd(&ctl->slot[0].nf, (unsigned long long)nf);
-    atomicAdd(&ctl->slot[0].mf, (unsigned long long)mf);
-    atomicAdd(&ctl->mu0, (unsigned long long)mu);
-  }
-}
-
 // One level l: expands buffer l%3 into (l+1)%3 top-down or bottom-up, clears
 // (l+2)%3, and adds the next frontier's counters into slot (l+1)%3.
 template <bool PAR>
@@ -401,9 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_msbfs(MsArgs a) {
   __shared__ uint64_t s_red[kBlock / kWave];
   MsCtl *ctl = a.ctl;
   const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  root_stats(a, s_red);
-  grid.sync();
-  uint64_t mu = ld_agent(&ctl->mu0);
+  uint64_t mu = ld_agent(&ctl->mu0);  // the seeding kernel left the root level's counters
   for (int l = 0;; ++l) {
     Slot *cur = &ctl->slot[l % 3], *nxt = &ctl->slot[(l + 1) % 3];
     const uint64_t nf = ld_agent(&cur->nf), mf = ld_agent(&cur->mf);
@@ -421,10 +394,6 @@ __global__ __launch_bounds__(kBlock) void k_msbfs(MsArgs a) {
 
 // Stepped mode: the same level as a plain launch (the kernel boundary is the
 // level barrier), so batches can share the device with other work.
-__global__ __launch_bounds__(kBlock) void k_ms_root_stats(MsArgs a) {
-  __shared__ uint64_t s_red[kBlock / kWave];
-  root_stats(a, s_red);
-}
 
 // Level l takes its own direction decision from the counters the previous
 // level left (every workgroup computes the same one), so the host can queue
@@ -472,8 +441,14 @@ __global__ void k_zero_words(uint64_t *__restrict__ p, int64_t len) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0;
 }
 
+// Seeds the roots (seen and frontier bits, level 0, parent = itself) and the
+// root level's counters in the zeroed ctl: n_f = the distinct roots, m_f their
+// degree sum, and m_u (degree sum of the vertices not yet seen by every root)
+// = nnz minus the degree of a vertex every root has seen, which happens only
+// when all roots are one vertex.  One thread per root.
 __global__ void k_ms_seed(const int64_t *__restrict__ roots, int k, int64_t n, uint64_t *seen,
-                          uint64_t *front, int8_t *levels, int32_t *parents) {
+                          uint64_t *front, int8_t *levels, int32_t *parents,
+                          const int64_t *__restrict__ rp, MsCtl *ctl) {
   int b = threadIdx.x;
   if (b >= k) return;
   int64_t v = roots[b];
@@ -481,6 +456,26 @@ __global__ void k_ms_seed(const int64_t *__restrict__ roots, int k, int64_t n, u
   atomicOr((unsigned long long *)&front[v], 1ull << b);
   levels[(int64_t)b * n + v] = 0;
   if (parents) parents[(int64_t)b * n + v] = (int32_t)v;
+  const int64_t d = rp[v + 1] - rp[v];
+  bool first = true;  // the first of equal roots counts the vertex
+  for (int c = 0; c < b; ++c)
+    if (roots[c] == v) {
+      first = false;
+      break;
+    }
+  if (first) {
+    atomicAdd(&ctl->slot[0].nf, 1ull);
+    atomicAdd(&ctl->slot[0].mf, (unsigned long long)d);
+  }
+  if (b == 0) {
+    bool all = true;
+    for (int c = 1; c < k; ++c)
+      if (roots[c] != v) {
+        all = false;
+        break;
+      }
+    ctl->mu0 = (unsigned long long)(rp[n] - (all ? d : 0));
+  }
 }
 
 int grid_for(int64_t items, int per_block, int cap) {
@@ -546,8 +541,6 @@ g5_status batch_stepped(const g5_csr *g, BatchWork &w, const MsArgs &a, int32_t 
   const int blocks = g->num_cu * bpc;
   MsCtl *hc = (MsCtl *)w.host_ctl;
   if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
-  hipLaunchKernelGGL(k_ms_root_stats, dim3(blocks), dim3(kBlock), 0, s, a);
-  G5_LAUNCH_CHECK();
   bool err = false;
   int l = 0;  // levels queued
   for (int group = 8;; group = 4) {
@@ -624,12 +617,13 @@ g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)k * n / 4, 256, fg)), dim3(256), 0, s,
                        parents, (int64_t)k * n, ((uintptr_t)parents & 15) == 0);
   hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, w.seen, n);
-  for (auto *b : w.buf)
-    hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, b, n);
+  // buf[2] is cleared by level 0 before level 1 fills it
+  for (int i = 0; i < 2; ++i)
+    hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, w.buf[i], n);
   hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (uint64_t *)w.ctl,
                      (int64_t)(sizeof(MsCtl) / 8));
   hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, w.roots, k, n, w.seen, w.buf[0], levels,
-                     parents);
+                     parents, g->row_ptr, (MsCtl *)w.ctl);
   G5_LAUNCH_CHECK();
 
   MsArgs a;
