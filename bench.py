@@ -241,7 +241,7 @@ def summarize_trace(db, command, bench_json=None):
         a[1] += (t1 - t0) / 1e3
     total = sum(a[1] for a in agg.values())
     out = ["# Kernel trace: scale-26 single-root BFS benchmark", "",
-           "Command (from the repository root on the GPU box):", "", "```", command, "```", "",
+           "Command (from the repository root):", "", "```", command, "```", "",
            "Durations are rocprofv3 kernel-trace dispatch times (microseconds), over the",
            "whole command (graph generation and CSR build, accounting pass, warm-up and",
            "timed steps, and any batch run or probe it includes).", "",
@@ -390,6 +390,49 @@ def run_gpu(args):
     return gpu, csr, parent, level
 
 
+def run_alg3_curve(args):
+    """The host experiment's speedup curve: the paper's parallel level-synchronous
+    BFS (OpenMP threads, libg5alg3.so) on a Kronecker graph built on the GPU and
+    copied to the host, over thread counts up to this host's share (at most 16),
+    a few roots each; one root's levels are checked against the GPU's."""
+    import numpy as np
+    import torch
+    import kronecker as K
+    import paper_2012_13548_amd as g5
+    from paper_2012_13548_amd import alg3
+    scale, n = args.alg3_scale, 1 << args.alg3_scale
+    dev = torch.device("cuda:0")
+    edges = K.edges_device(scale, args.edgefactor, device=dev)
+    csr = g5.build_csr(edges, n)
+    roots = K.select_roots(K.nonisolated_device(edges, n).cpu().numpy(), args.alg3_roots,
+                           K.root_seed(scale))
+    del edges
+    _, gpu_level = g5.bfs(csr, roots[0])
+    gpu_level = gpu_level.cpu().numpy()
+    rp_t, ci_t = csr.arrays()
+    rp, ci = rp_t.cpu().numpy(), ci_t.cpu().numpy()
+    deg = np.diff(rp)
+    cores = len(os.sched_getaffinity(0))
+    threads = [t for t in (1, 2, 4, 8, 16) if t <= min(cores, 16)]
+    rows, equal = [], True
+    for t in threads:
+        secs, teps = [], []
+        for i, r in enumerate(roots):
+            _, level, sec = alg3.bfs(rp, ci, r, t)
+            if i == 0:
+                equal = equal and bool(np.array_equal(level, gpu_level))
+            secs.append(sec)
+            teps.append((int(deg[level >= 0].sum()) // 2) / sec)
+        rows.append({"threads": t, "mean_s": round(float(np.mean(secs)), 5),
+                     "hmean_gteps": round(hmean(teps) / 1e9, 4)})
+        log(f"alg3 threads {t}: {rows[-1]}")
+    for row in rows:
+        row["speedup"] = round(rows[0]["mean_s"] / row["mean_s"], 2)
+    print(json.dumps({"alg3_curve": {"scale": scale, "edgefactor": args.edgefactor,
+                                     "roots": len(roots), "host_threads": cores,
+                                     "levels_equal_gpu": equal, "rows": rows}}))
+
+
 def run_batch(args):
     """64 roots at scale 22: one batched launch vs 64 sequential single-root runs."""
     import torch
@@ -502,7 +545,15 @@ def main():
     ap.add_argument("--summarize-trace", nargs="+", metavar=("DB", "BENCH_JSON"),
                     help="print a markdown summary of a rocprofv3 kernel-trace database")
     ap.add_argument("--trace-command", default="", help="command recorded with --summarize-trace")
+    ap.add_argument("--alg3-curve", action="store_true",
+                    help="time the host experiment (the paper's parallel level-synchronous BFS "
+                         "with OpenMP) over thread counts, print one JSON line and exit")
+    ap.add_argument("--alg3-scale", type=int, default=20)
+    ap.add_argument("--alg3-roots", type=int, default=4)
     args = ap.parse_args()
+    if args.alg3_curve:
+        run_alg3_curve(args)
+        return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace[0], args.trace_command,
                         args.summarize_trace[1] if len(args.summarize_trace) > 1 else None)

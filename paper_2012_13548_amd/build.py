@@ -1,4 +1,6 @@
-"""Build step for libg5.so: every HIP source of csrc/ compiled for gfx950.
+"""Build step for libg5.so: every HIP source of csrc/ compiled for gfx950; and
+libg5alg3.so, the host experiment (the paper's parallel level-synchronous BFS
+with OpenMP, for its thread-count speedup curve), compiled with gcc.
 
 Run ``python -m paper_2012_13548_amd.build`` or call :func:`build`.
 """
@@ -11,6 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["api.cpp", "csr_build.hip", "bfs.hip", "msbfs.hip"]
 LIB = os.path.join(HERE, "libg5.so")
+ALG3_LIB = os.path.join(HERE, "libg5alg3.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -40,8 +43,12 @@ def build(verbose=False, jobs=8):
     subprocess.run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs,
                    check=True)
     os.replace(LIB + ".tmp", LIB)
+    subprocess.run(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+                    "-I", os.path.join(ROOT, "include"), "-o", ALG3_LIB + ".tmp",
+                    os.path.join(CSRC, "alg3_host.c")], check=True)
+    os.replace(ALG3_LIB + ".tmp", ALG3_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, ALG3_LIB)
 
 
 if __name__ == "__main__":

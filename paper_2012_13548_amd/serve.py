@@ -11,7 +11,7 @@ The executor does the traversal: :class:`GpuExecutor` calls g5_bfs_batch in
 stepped mode (one plain launch per level, safe next to other streams) or g5_bfs
 for a lone request; tests drive the scheduler with a CPU executor.
 
-CLI (on the GPU machine): ``python -m paper_2012_13548_amd.serve --scales 16 18 20
+CLI (on a machine with the GPU): ``python -m paper_2012_13548_amd.serve --scales 16 18 20
 22 23 --requests 10000`` prints one JSON line with p50/p99 latency and
 aggregate TEPS under a Poisson arrival stream.
 """
