@@ -105,7 +105,11 @@ typedef struct {
   int32_t bu_vertices_per_lane; /* bottom-up: unvisited vertices a lane works on at once: 1 or 2 */
   int32_t td_blocks_per_cu; /* top-down expansion grid: workgroups per compute unit (1..256);
                                0 = those that fit at once, at most 6 */
-  int32_t reserved[2];
+  int32_t heavy_kedges;   /* a growing top-down level whose frontier has more than this many
+                             thousand edges claims without reading the claimed vertices' row
+                             offsets, and the next level goes bottom-up; 0 takes the default
+                             (nnz / 512 edges), < 0 disables.  Only with G5_DIR_AUTO. */
+  int32_t reserved;
   double gamma;           /* also top-down -> bottom-up when the frontier grew and m_f > gamma *
                              (unvisited non-isolated vertices); 0 takes the default, < 0 disables */
 } g5_bfs_params;

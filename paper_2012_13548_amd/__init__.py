@@ -48,7 +48,8 @@ class BfsParams(ctypes.Structure):
                 ("lds_density", ctypes.c_double), ("claim", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("bu_blocks_per_cu", ctypes.c_int32),
                 ("lds_kb", ctypes.c_int32), ("bu_vertices_per_lane", ctypes.c_int32),
-                ("td_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+                ("td_blocks_per_cu", ctypes.c_int32), ("heavy_kedges", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
                 ("gamma", ctypes.c_double)]
 
 
@@ -173,8 +174,10 @@ def build_csr(edges, n):
 
 
 def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None, lds_kb=None,
-            lds_density=None, vertices_per_lane=None, td_blocks_per_cu=None, gamma=None):
+            lds_density=None, vertices_per_lane=None, td_blocks_per_cu=None, gamma=None,
+            heavy_kedges=None):
     p = BfsParams()
+    p.heavy_kedges = heavy_kedges or 0
     p.bu_vertices_per_lane = vertices_per_lane or 0
     p.td_blocks_per_cu = td_blocks_per_cu or 0
     p.gamma = gamma or 0.0
@@ -193,7 +196,7 @@ def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None,
 def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta=None,
         lane_scan=None, claim=CLAIM_OR, hint=True, packed=None, min_parent=False, lds=True,
         blocks_per_cu=None, lds_kb=None, lds_density=None, vertices_per_lane=None,
-        td_blocks_per_cu=None, gamma=None, stats=False,
+        td_blocks_per_cu=None, gamma=None, heavy_kedges=None, stats=False,
         time_steps=False, count_bytes=False):
     """Kernel 2: (parent, level) int32 device tensors of length n from ``root``.
 
@@ -214,7 +217,7 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
              | {None: 0, True: FLAG_PACKED, False: FLAG_ROWLOOP}[packed]
              | (FLAG_MIN_PARENT if min_parent else 0) | (0 if lds else FLAG_NO_LDS))
     p = _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu, lds_kb,
-                lds_density, vertices_per_lane, td_blocks_per_cu, gamma)
+                lds_density, vertices_per_lane, td_blocks_per_cu, gamma, heavy_kedges)
     want = stats or time_steps or count_bytes
     st = BfsStats()
     _check(lib.g5_bfs_ex(csr.handle, int(root), parent.data_ptr(), level.data_ptr(),

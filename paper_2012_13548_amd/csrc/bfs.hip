@@ -67,7 +67,8 @@ enum Ctr : int {
   C_QP1 = 17,   // queue 1: the same
   C_ENDL = 18,  // lvl + 1 when level lvl's queue came out empty (the traversal ended), else 0
   C_TICKET = 19,  // workgroups done in the kernel that fills a queue (the last one decides)
-  C_NCTR = 20
+  C_HEAVY = 20,   // 1: the decided top-down level is heavy (its winners read no row offsets)
+  C_NCTR = 21
 };
 
 // Copies the counters to host memory.  Each 8-byte slot carries the low 16
@@ -109,11 +110,18 @@ struct TdRule {
   int dirmode;
   double alpha;
   double gamma;  // > 0: also switch when m_f > gamma * unvisited non-isolated vertices
+  // > 0: a growing top-down level with m_f above this many edges is heavy: its
+  // expansion skips the row-offset read of every vertex it claims (one random
+  // line each), so the next queue has no edge offsets or degree sum, and the
+  // next level goes bottom-up, which uses neither (the conversion builds its
+  // frontier from the byte levels)
+  uint64_t heavy_edges;
 };
 
 __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool from_bu,
                           const TdRule &rule, int64_t qlen, uint64_t mf,
-                          unsigned long long *host, unsigned long long seq) {
+                          unsigned long long *host, unsigned long long seq,
+                          bool after_heavy = false) {
   auto ld = [&](int i) {
     return (int64_t)__hip_atomic_load(ctr + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
@@ -122,12 +130,17 @@ __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool fro
   int64_t unv = ld(C_UNV);
   if (lvl > 0 && !from_bu) unv -= qlen;  // this frontier was found by a top-down level
   const bool growing = qlen > ld(C_LASTNF);
+  // after a heavy level mf is unknown (0) and the level goes bottom-up
   const bool to_bu =
-      rule.dirmode == G5_DIR_BOTTOMUP ||
+      rule.dirmode == G5_DIR_BOTTOMUP || after_heavy ||
       (rule.dirmode == G5_DIR_AUTO && growing &&
        ((double)mf > (double)mu / rule.alpha ||
         (rule.gamma > 0 && (double)mf > rule.gamma * (double)unv)));
   const bool go = qlen > 0 && !to_bu;
+  ctr[C_HEAVY] = (go && growing && rule.dirmode == G5_DIR_AUTO && rule.heavy_edges > 0 &&
+                  mf > rule.heavy_edges)
+                     ? 1ull
+                     : 0ull;
   ctr[C_MU] = (unsigned long long)mu;
   ctr[C_UNV] = (unsigned long long)unv;
   ctr[C_MF] = mf;
@@ -348,6 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
   unsigned long long *qn_pack = ctr + C_QP0 + nxt;
   const int64_t qlen = (int64_t)ctr[C_QLEN0 + cur];
   const uint32_t total = (uint32_t)ctr[C_MF];
+  const bool heavy = ctr[C_HEAVY] != 0;  // claimed vertices read no row offsets
   // only the blocks that own a tile take part (and take a ticket): same-address
   // atomics are serialised, so 1500 tickets cost ~20 us on a small level
   const uint64_t ntiles = ((uint64_t)total + kTdTile - 1) / kTdTile;
@@ -423,9 +437,11 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
       wdeg[j] = 0;
       if (won) {
         wmask |= 1u << j;
-        uint32_t be[2];
-        __builtin_memcpy(be, rp + v, 8);
-        wdeg[j] = be[1] - be[0];
+        if (!heavy) {
+          uint32_t be[2];
+          __builtin_memcpy(be, rp + v, 8);
+          wdeg[j] = be[1] - be[0];
+        }
       }
     }
     // the tile's winners in thread order: one block scan of (count << 32 | degree
@@ -471,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
       const unsigned long long qp = atomicAdd(qn_pack, 0ull);
       atomicExch(ctr + C_TICKET, 0ull);
       td_decide(ctr, nxt, next_level, false, rule, (int64_t)(qp >> 32), qp & 0xffffffffull, host,
-                seq);
+                seq, heavy);
     }
   }
 }
@@ -1542,7 +1558,10 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   // a bottom-up hit on the hint then writes no parent (unreached vertices are
   // reset at the end).  Compare-and-swap claims need parent -1.
   const bool prefill = use_hint && p.claim != CLAIM_CAS;
-  const TdRule rule{p.direction, alpha, gamma};
+  const uint64_t heavy_edges =
+      p.heavy_kedges > 0 ? (uint64_t)p.heavy_kedges * 1000
+                         : (p.heavy_kedges < 0 ? 0 : (uint64_t)g->nnz / 512);
+  const TdRule rule{p.direction, alpha, gamma, heavy_edges};
   const unsigned long long seq0 = ++w.seq;  // the root level's decision, taken by k_bfs_init
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
                      dim3(kBlock), 0, s, root, w.lev8, parent, n,
@@ -1578,6 +1597,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   unsigned long long bu_seq = 0;
   uint64_t *front = w.front, *next = w.next;
   if (stats) *stats = g5_bfs_stats{};
+  bool heavy_lv[G5_MAX_STAT_LEVELS] = {};  // top-down levels that read no row offsets
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
   const BuNext bn{p.direction, beta, n};
   const int32_t *hint = use_hint ? g->hint : nullptr;
@@ -1766,6 +1786,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         stats->dir[i] = 1;
         stats->frontier[i] = qlen;
         stats->edges[i] = mf;
+        // the device's heavy rule (the frontier grew past the last top-down one)
+        heavy_lv[i] = p.direction == G5_DIR_AUTO && heavy_edges > 0 &&
+                      (uint64_t)mf > heavy_edges && qlen > last_nf;
       }
       cur = nxt;
       last_nf = qlen;
@@ -1859,7 +1882,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i)
         if (stats->dir[i] == 1)
           stats->bytes[i] = 12 * stats->frontier[i] + 4 * stats->edges[i] +
-                            (i + 1 <= kByteLevels ? 21 : 24) * stats->discovered[i];
+                            ((i + 1 <= kByteLevels ? 21 : 24) - (heavy_lv[i] ? 8 : 0)) *
+                                stats->discovered[i];
     if (timed)
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i) {
         float a = 0;

@@ -145,6 +145,18 @@ def test_expansion_grid_variants(kron16, td_blocks_per_cu, direction):
         c.check_root(r, direction=direction, td_blocks_per_cu=td_blocks_per_cu)
 
 
+@pytest.mark.parametrize("heavy_kedges", [-1, 1, 0])
+def test_heavy_levels(kron16, heavy_kedges):
+    # heavy top-down levels claim without reading the claimed vertices' row
+    # offsets and send the next level bottom-up: off, on almost every growing
+    # level (1,000 edges), and the default threshold
+    c, roots = kron16
+    for r in roots:
+        c.check_root(r, heavy_kedges=heavy_kedges)
+        c.check_root(r, heavy_kedges=heavy_kedges, claim=g5.CLAIM_CAS)
+        c.check_root(r, heavy_kedges=heavy_kedges, min_parent=True)
+
+
 @pytest.fixture(scope="module")
 def kron16():
     scale = 16
