@@ -107,8 +107,9 @@ typedef struct {
                                0 = those that fit at once, at most 6 */
   int32_t heavy_kedges;   /* a growing top-down level whose frontier has more than this many
                              thousand edges claims without reading the claimed vertices' row
-                             offsets, and the next level goes bottom-up; 0 takes the default
-                             (nnz / 512 edges), < 0 disables.  Only with G5_DIR_AUTO. */
+                             offsets or writing its queue (only the count), and the next level
+                             goes bottom-up; 0 takes the default (nnz / 2048 edges), < 0
+                             disables.  Only with G5_DIR_AUTO. */
   int32_t reserved;
   double gamma;           /* also top-down -> bottom-up when the frontier grew and m_f > gamma *
                              (unvisited non-isolated vertices); 0 takes the default, < 0 disables */

@@ -112,8 +112,8 @@ struct TdRule {
   double gamma;  // > 0: also switch when m_f > gamma * unvisited non-isolated vertices
   // > 0: a growing top-down level with m_f above this many edges is heavy: its
   // expansion skips the row-offset read of every vertex it claims (one random
-  // line each), so the next queue has no edge offsets or degree sum, and the
-  // next level goes bottom-up, which uses neither (the conversion builds its
+  // line each) and writes no queue entries (only their count), and the next
+  // level goes bottom-up, which uses neither (the conversion builds its
   // frontier from the byte levels)
   uint64_t heavy_edges;
 };
@@ -452,7 +452,12 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
     unsigned long long tot;
     const unsigned long long ex = block_excl_scan<kBlock, unsigned long long>(mine, s_scan, tot);
     const uint32_t cnt = (uint32_t)(tot >> 32);  // block-uniform
-    if (cnt) {
+    if (cnt && heavy) {
+      // the next level goes bottom-up and never reads this queue: only its
+      // length.  The result is kept so the add has returned before this block's
+      // ticket (the last block reads the counter after every ticket).
+      if (threadIdx.x == 0) s_gbase = atomicAdd(qn_pack, tot);
+    } else if (cnt) {
       // every thread has left the edge loop (the scan synchronised): stage the
       // entries at their tile positions in s_src (vertex) and s_off (edge
       // index from the tile's first), then write them out coalesced
@@ -477,11 +482,11 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
     __syncthreads();  // the shared arrays are reused by the next tile
   }
   // No fences: a device-wide one writes back and invalidates this XCD's L2.
-  // Thread 0 made the block's appends, and each one returned (its result was
-  // used) before the ticket is taken.  The last block reads the queue's counter
-  // with an atomic too (adding 0), where the appends were made, after its own
-  // ticket returned, so it sees every append; a plain or atomic load could be
-  // served by a stale copy of the line in this XCD's L2.
+  // Thread 0 made the block's appends, each a returning device-scope atomic
+  // waited for before the ticket is taken.  The last block reads the queue's
+  // counter with a device-scope atomic (an add of 0, which the compiler emits
+  // as a device-coherent load) issued after its own ticket returned, so it
+  // sees every append.
   if (threadIdx.x == 0) {
     if (atomicAdd(ctr + C_TICKET, 1ull) + 1 == active) {
       const unsigned long long qp = atomicAdd(qn_pack, 0ull);
@@ -1560,7 +1565,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   const bool prefill = use_hint && p.claim != CLAIM_CAS;
   const uint64_t heavy_edges =
       p.heavy_kedges > 0 ? (uint64_t)p.heavy_kedges * 1000
-                         : (p.heavy_kedges < 0 ? 0 : (uint64_t)g->nnz / 512);
+                         : (p.heavy_kedges < 0 ? 0 : (uint64_t)g->nnz / 2048);
   const TdRule rule{p.direction, alpha, gamma, heavy_edges};
   const unsigned long long seq0 = ++w.seq;  // the root level's decision, taken by k_bfs_init
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
@@ -1597,7 +1602,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   unsigned long long bu_seq = 0;
   uint64_t *front = w.front, *next = w.next;
   if (stats) *stats = g5_bfs_stats{};
-  bool heavy_lv[G5_MAX_STAT_LEVELS] = {};  // top-down levels that read no row offsets
+  bool heavy_lv[G5_MAX_STAT_LEVELS] = {};  // top-down levels without row offsets or queue
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
   const BuNext bn{p.direction, beta, n};
   const int32_t *hint = use_hint ? g->hint : nullptr;
@@ -1882,7 +1887,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i)
         if (stats->dir[i] == 1)
           stats->bytes[i] = 12 * stats->frontier[i] + 4 * stats->edges[i] +
-                            ((i + 1 <= kByteLevels ? 21 : 24) - (heavy_lv[i] ? 8 : 0)) *
+                            ((i + 1 <= kByteLevels ? 21 : 24) - (heavy_lv[i] ? 16 : 0)) *
                                 stats->discovered[i];
     if (timed)
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i) {
