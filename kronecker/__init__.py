@@ -40,6 +40,9 @@ def _load_host():
         lib.kron_nonisolated_host.argtypes = [ctypes.c_void_p, ctypes.c_int64,
                                               ctypes.c_int64, ctypes.c_void_p]
         lib.kron_nonisolated_host.restype = ctypes.c_int
+        lib.kron_weights_host.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_void_p]
+        lib.kron_weights_host.restype = ctypes.c_int
         lib.kron_splitmix64_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.kron_splitmix64_at.restype = ctypes.c_uint64
         _host = lib
@@ -61,6 +64,9 @@ def _load_dev():
                                                 ctypes.c_int64, ctypes.c_void_p,
                                                 ctypes.c_void_p, ctypes.c_void_p]
         lib.kron_nonisolated_device.restype = ctypes.c_int
+        lib.kron_weights_device.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_void_p]
+        lib.kron_weights_device.restype = ctypes.c_int
         _dev = lib
     return _dev
 
@@ -119,6 +125,32 @@ def edges_device(scale, edgefactor=16, seed=None, relabel=True, device="cuda"):
                                        stream)
     if rc != 0:
         raise RuntimeError(f"kron_edges_device failed ({rc})")
+    return out
+
+
+def weights_host(scale, edgefactor=16, seed=None, start=0, stop=None):
+    """Integer weights in [1, 255] of tuples [start, stop) as a uint8 numpy
+    array (the weight row of the paper's 3 x #E tuple matrix)."""
+    if seed is None:
+        seed = graph_seed(scale)
+    m = num_tuples(scale, edgefactor)
+    stop = m if stop is None else stop
+    out = np.empty(stop - start, dtype=np.uint8)
+    if _load_host().kron_weights_host(seed, start, stop, out.ctypes.data) != 0:
+        raise ValueError("bad tuple range")
+    return out
+
+
+def weights_device(scale, edgefactor=16, seed=None, device="cuda"):
+    """The same weights as :func:`weights_host`, generated straight into HBM."""
+    import torch
+    if seed is None:
+        seed = graph_seed(scale)
+    m = num_tuples(scale, edgefactor)
+    out = torch.empty(m, dtype=torch.uint8, device=device)
+    stream = torch.cuda.current_stream(out.device).cuda_stream
+    if _load_dev().kron_weights_device(seed, m, out.data_ptr(), stream) != 0:
+        raise RuntimeError("kron_weights_device failed")
     return out
 
 

@@ -35,6 +35,10 @@
  * scale-bit integers, so the composition is a permutation.  Its six constants
  * are splitmix64_at(perm_base, 0 .. 5) with perm_base = splitmix64_at(seed, 1)
  * (multipliers forced odd).
+ *
+ * Weights (the third row of the paper's 3 x #E tuple matrix, Section 2.1):
+ * tuple i carries the integer weight 1 + (splitmix64_at(weight_base, i) mod
+ * 255), in [1, 255], with weight_base = splitmix64_at(seed, 3).
  */
 #ifndef KRON_CORE_H
 #define KRON_CORE_H
@@ -114,5 +118,12 @@ KRON_FN void kron_raw_tuple(const kron_params *p, uint64_t i, uint64_t *row,
   *row = r0;
   *col = c0;
 }
+
+/* Weight of tuple i (see above). */
+KRON_FN uint8_t kron_weight(uint64_t weight_base, uint64_t i) {
+  return (uint8_t)(1 + splitmix64_at(weight_base, i) % 255);
+}
+
+KRON_FN uint64_t kron_weight_base(uint64_t seed) { return splitmix64_at(seed, 3); }
 
 #endif

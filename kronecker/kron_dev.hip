@@ -39,6 +39,12 @@ __global__ void kron_nonisolated_kernel(const int64_t *__restrict__ edges, int64
   }
 }
 
+__global__ void kron_weights_kernel(uint64_t base, int64_t m, uint8_t *__restrict__ out) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    out[i] = kron_weight(base, (uint64_t)i);
+}
+
 static int grid_for(int64_t m) {
   int64_t g = (m + 255) / 256;
   if (g > 65536) g = 65536;
@@ -57,6 +63,15 @@ int kron_edges_device(int scale, uint64_t seed, int relabel, int64_t m, int64_t 
   kron_params p = kron_make_params(scale, seed);
   hipLaunchKernelGGL(kron_edges_kernel, dim3(grid_for(m)), dim3(256), 0,
                      (hipStream_t)stream, p, relabel, m, out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// Writes the weights of tuples [0, m) of (seed) to the device buffer out[m].
+int kron_weights_device(uint64_t seed, int64_t m, uint8_t *out, void *stream) {
+  if (m < 0 || (m > 0 && !out)) return -1;
+  if (m == 0) return 0;
+  hipLaunchKernelGGL(kron_weights_kernel, dim3(grid_for(m)), dim3(256), 0, (hipStream_t)stream,
+                     kron_weight_base(seed), m, out);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

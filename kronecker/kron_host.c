@@ -59,4 +59,13 @@ int kron_nonisolated_host(const int64_t *edges, int64_t m, int64_t n,
   return bad ? -1 : 0;
 }
 
+/* Weights of tuples [i0, i1) of (seed): out[i - i0] in [1, 255]. */
+int kron_weights_host(uint64_t seed, int64_t i0, int64_t i1, uint8_t *out) {
+  if (i0 < 0 || i1 < i0) return -1;
+  const uint64_t base = kron_weight_base(seed);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = i0; i < i1; ++i) out[i - i0] = kron_weight(base, (uint64_t)i);
+  return 0;
+}
+
 uint64_t kron_splitmix64_at(uint64_t state, uint64_t c) { return splitmix64_at(state, c); }

@@ -11,11 +11,17 @@ Python bindings (numpy in, numpy out) for ``oracle.c``:
   visited marked at discovery; parent[root] = root; -1 for unreached.
 * :func:`bfs_batch` -- the single-root BFS per root, levels cast to int8.
 * :func:`components`, :func:`validate`, :func:`validate_edges` -- independent
-  checks of a BFS result (union-find reached set, tree edges, level rules).
+  checks of a BFS result (union-find reached set, tree edges, level rules);
+  :func:`check_parents` -- the parent rules alone, for levels already compared
+  bit-exactly with :func:`bfs`.
 * :func:`teps_edges` -- m_r, the distinct undirected edges of the root's
   component (traversed edges for TEPS, Section 4.3).
 * :func:`min_parents` -- the deterministic parent choice: the smallest-id
   neighbour one level up.
+* :func:`build_csr_w`, :func:`sssp`, :func:`check_sssp`, :func:`min_prev` --
+  Kernel 3 (Section 2.4, "Sequential SSSP"): the weighted CSR (smallest weight
+  of repeated tuples), Dijkstra's distances and predecessors, an independent
+  validator, and the deterministic predecessor choice.
 """
 import ctypes
 import os
@@ -57,6 +63,16 @@ def _load():
         lib.orc_validate.restype = ctypes.c_int
         lib.orc_validate_edges.argtypes = [P, I64, I64, I64, P, P]
         lib.orc_validate_edges.restype = ctypes.c_int
+        lib.orc_build_csr_w.argtypes = [P, P, I64, I64, P, P, P]
+        lib.orc_build_csr_w.restype = I64
+        lib.orc_sssp.argtypes = [P, P, P, I64, I64, P, P]
+        lib.orc_sssp.restype = I64
+        lib.orc_check_sssp.argtypes = [P, P, P, I64, I64, P, P]
+        lib.orc_check_sssp.restype = ctypes.c_int
+        lib.orc_min_prev.argtypes = [P, P, P, I64, I64, P, P]
+        lib.orc_min_prev.restype = ctypes.c_int
+        lib.orc_check_parents.argtypes = [P, P, I64, I64, P, P]
+        lib.orc_check_parents.restype = ctypes.c_int
         lib.orc_teps_edges.argtypes = [P, I64, P]
         lib.orc_teps_edges.restype = I64
         lib.orc_min_parents.argtypes = [P, P, I64, I64, P, P]
@@ -171,6 +187,16 @@ def validate_edges(edges, n, root, parent, level):
                                       parent.ctypes.data, level.ctypes.data)
 
 
+def check_parents(csr, root, parent, level):
+    """Parent rules of validate() for a level array known to be exact; 0 or a
+    rule number.  Parallel over vertices, so it suits full-size graphs."""
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    level = np.ascontiguousarray(level, dtype=np.int32)
+    ci = csr.col_idx if csr.col_idx.size else np.zeros(1, np.int32)
+    return _load().orc_check_parents(csr.row_ptr.ctypes.data, ci.ctypes.data, csr.n, int(root),
+                                     parent.ctypes.data, level.ctypes.data)
+
+
 def teps_edges(csr, level):
     level = np.ascontiguousarray(level, dtype=np.int32)
     return int(_load().orc_teps_edges(csr.row_ptr.ctypes.data, csr.n, level.ctypes.data))
@@ -186,3 +212,93 @@ def min_parents(csr, root, level):
     if rc != 0:
         raise ValueError("a reached vertex has no neighbour one level up")
     return parent
+
+
+INF32 = 0xFFFFFFFF
+
+SSSP_RULES = {
+    0: "valid",
+    1: "dist[src] != 0 or prev[src] != src",
+    2: "value out of range, or infinity and prev = -1 disagree",
+    3: "prev[v] is not a neighbour of v",
+    4: "dist[v] != dist[prev[v]] + w(prev[v], v)",
+    5: "an edge can shorten a distance (or joins reached and unreached)",
+    6: "prev pointers of a reached vertex do not lead back to the source",
+}
+
+
+class CsrW(Csr):
+    """Weighted oracle CSR: row_ptr, col_idx and weights uint8[nnz]."""
+
+    def __init__(self, row_ptr, col_idx, weights):
+        super().__init__(row_ptr, col_idx)
+        self.weights = weights
+
+    def row_weights(self, v):
+        return self.weights[self.row_ptr[v]:self.row_ptr[v + 1]]
+
+
+def build_csr_w(edges, weights, n):
+    e = _edges(edges)
+    w = np.ascontiguousarray(weights, dtype=np.uint8)
+    if w.shape[0] != e.shape[0]:
+        raise ValueError("one weight per tuple")
+    m = e.shape[0]
+    rp = np.empty(n + 1, dtype=np.int64)
+    ci = np.empty(max(2 * m, 1), dtype=np.int32)
+    wt = np.empty(max(2 * m, 1), dtype=np.uint8)
+    nnz = _load().orc_build_csr_w(e.ctypes.data, w.ctypes.data, m, n, rp.ctypes.data,
+                                  ci.ctypes.data, wt.ctypes.data)
+    if nnz < 0:
+        raise ValueError(f"orc_build_csr_w failed ({nnz})")
+    return CsrW(rp, ci[:nnz].copy(), wt[:nnz].copy())
+
+
+def _wargs(csr):
+    ci = csr.col_idx if csr.col_idx.size else np.zeros(1, np.int32)
+    wt = csr.weights if csr.weights.size else np.zeros(1, np.uint8)
+    return csr.row_ptr.ctypes.data, ci.ctypes.data, wt.ctypes.data, ci, wt
+
+
+def sssp(csr, src):
+    """(dist uint32[n], prev int32[n]) by Dijkstra; INF32 / -1 when unreached."""
+    rp, ci, wt, _k1, _k2 = _wargs(csr)
+    dist = np.empty(csr.n, dtype=np.uint32)
+    prev = np.empty(csr.n, dtype=np.int32)
+    r = _load().orc_sssp(rp, ci, wt, csr.n, int(src), dist.ctypes.data, prev.ctypes.data)
+    if r < 0:
+        raise ValueError(f"orc_sssp failed ({r}) for source {src}")
+    return dist, prev
+
+
+def sssp_timed(csr, src):
+    """sssp() plus the wall time of the Dijkstra call alone (seconds)."""
+    rp, ci, wt, _k1, _k2 = _wargs(csr)
+    dist = np.empty(csr.n, dtype=np.uint32)
+    prev = np.empty(csr.n, dtype=np.int32)
+    lib = _load()
+    t0 = time.perf_counter()
+    r = lib.orc_sssp(rp, ci, wt, csr.n, int(src), dist.ctypes.data, prev.ctypes.data)
+    t1 = time.perf_counter()
+    if r < 0:
+        raise ValueError(f"orc_sssp failed ({r}) for source {src}")
+    return dist, prev, t1 - t0
+
+
+def check_sssp(csr, src, dist, prev):
+    """0 if (dist, prev) is an exact shortest-path result from src, else a rule."""
+    rp, ci, wt, _k1, _k2 = _wargs(csr)
+    dist = np.ascontiguousarray(dist, dtype=np.uint32)
+    prev = np.ascontiguousarray(prev, dtype=np.int32)
+    return _load().orc_check_sssp(rp, ci, wt, csr.n, int(src), dist.ctypes.data,
+                                  prev.ctypes.data)
+
+
+def min_prev(csr, src, dist):
+    """prev[v] = smallest-id neighbour u with dist[u] + w(u, v) = dist[v]."""
+    rp, ci, wt, _k1, _k2 = _wargs(csr)
+    dist = np.ascontiguousarray(dist, dtype=np.uint32)
+    prev = np.empty(csr.n, dtype=np.int32)
+    if _load().orc_min_prev(rp, ci, wt, csr.n, int(src), dist.ctypes.data, prev.ctypes.data):
+        raise ValueError("a reached vertex has no tight neighbour")
+    return prev

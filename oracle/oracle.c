@@ -291,6 +291,40 @@ int orc_validate_edges(const int64_t *edges, int64_t m, int64_t n, int64_t root,
   return bad;
 }
 
+/* Parent check for a level array already known to be exact (compared with
+ * orc_bfs's levels beforehand): parent[root] = root, level[root] = 0, and for
+ * every other v either parent[v] = level[v] = -1 (unreached) or parent[v] is a
+ * neighbour of v (binary search in its ascending row) one level closer to the
+ * root, with no other vertex at level 0.  With exact levels these are the
+ * rules of orc_validate that concern the parent array; the rules about the
+ * reached set and edge spans hold because the levels are the hop distances.
+ * One parallel pass over the vertices.  Returns 0 or the rule number of
+ * orc_validate (1, 2, 3, 4 or 7); when several rules are broken, the largest
+ * number found. */
+int orc_check_parents(const int64_t *rp, const int32_t *ci, int64_t n, int64_t root,
+                      const int32_t *parent, const int32_t *level) {
+  if (root < 0 || root >= n) return 2;
+  if (parent[root] != root || level[root] != 0) return 1;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(max : bad)
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t p = parent[v], l = level[v];
+    int r = 0;
+    if (p < -1 || p >= n || l < -1 || (p == -1) != (l == -1))
+      r = 2;
+    else if (l >= 0 && v != root) {
+      if (l == 0)
+        r = 7;
+      else if (!row_has(ci, rp[v], rp[v + 1], p))
+        r = 3;
+      else if (level[p] != l - 1)
+        r = 4;
+    }
+    if (r > bad) bad = r;
+  }
+  return bad;
+}
+
 /* Edges traversed from a root, for TEPS: the number of distinct undirected
  * non-loop edges in the root's component, (1/2) * sum of deg(v) over reached
  * v. */
@@ -320,6 +354,282 @@ int orc_min_parents(const int64_t *rp, const int32_t *ci, int64_t n, int64_t roo
         break;
       }
     if (parent[v] < 0) bad = 1;
+  }
+  return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Kernel 3 (Section 2.4, Algorithm "Sequential SSSP"): shortest paths from
+ * one source over the weighted graph.  The tuple list carries a weight per
+ * tuple (Section 2.1: the generator's 3 x #E matrix of start, end and weight
+ * columns).  Readings: weights are integers (0..255 here, so sums and ties
+ * are exact); the graph is undirected, so each non-loop tuple gives both
+ * directions with its weight; of repeated tuples joining the same two
+ * vertices only the smallest weight can lie on a shortest path, so the CSR
+ * keeps that one; self-loops are dropped; dist[v] = infinity (UINT32_MAX)
+ * and prev[v] = -1 for unreached v; prev[source] = source, as for the BFS
+ * parent array (the printed algorithm leaves it at -1).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t v;
+  uint8_t w;
+} orc_vw;
+
+static int cmp_vw(const void *a, const void *b) {
+  const orc_vw *x = (const orc_vw *)a, *y = (const orc_vw *)b;
+  if (x->v != y->v) return (x->v > y->v) - (x->v < y->v);
+  return (x->w > y->w) - (x->w < y->w);
+}
+
+/* Weighted Kernel 1.  edges [m][2], weights [m]; rp int64[n+1], ci int32 and
+ * wt uint8 buffers with room for 2*m entries (outputs, packed to nnz).  Row v
+ * holds v's distinct neighbours ascending, each with the smallest weight of
+ * the tuples joining them.  Returns nnz, or -1 / -2 / -3 as orc_build_csr. */
+int64_t orc_build_csr_w(const int64_t *edges, const uint8_t *weights, int64_t m, int64_t n,
+                        int64_t *rp, int32_t *ci, uint8_t *wt) {
+  if (n < 1 || n > 2147483647LL || m < 0) return -2;
+  for (int64_t i = 0; i < 2 * m; ++i)
+    if (edges[i] < 0 || edges[i] >= n) return -1;
+  int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  orc_vw *tmp = (orc_vw *)malloc((size_t)(2 * m + 1) * sizeof(orc_vw));
+  if (!cnt || !tmp) {
+    free(cnt);
+    free(tmp);
+    return -3;
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    int64_t u = edges[2 * i], v = edges[2 * i + 1];
+    if (u == v) continue;
+    cnt[u + 1]++;
+    cnt[v + 1]++;
+  }
+  for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+  for (int64_t v = 0; v <= n; ++v) rp[v] = cnt[v];
+  for (int64_t i = 0; i < m; ++i) {
+    int64_t u = edges[2 * i], v = edges[2 * i + 1];
+    if (u == v) continue;
+    tmp[cnt[u]].v = (int32_t)v;
+    tmp[cnt[u]++].w = weights[i];
+    tmp[cnt[v]].v = (int32_t)u;
+    tmp[cnt[v]++].w = weights[i];
+  }
+  /* sort each row by (neighbour, weight); the first of each neighbour's run
+   * carries the smallest weight */
+  int64_t w = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t b = rp[v], e = rp[v + 1];
+    if (e - b > 1) qsort(tmp + b, (size_t)(e - b), sizeof(orc_vw), cmp_vw);
+    rp[v] = w;
+    for (int64_t k = b; k < e; ++k)
+      if (k == b || tmp[k].v != tmp[k - 1].v) {
+        ci[w] = tmp[k].v;
+        wt[w] = tmp[k].w;
+        ++w;
+      }
+  }
+  rp[n] = w;
+  free(cnt);
+  free(tmp);
+  return w;
+}
+
+/* Binary min-heap of (distance, vertex) with lazy deletion: the "vertex in Q
+ * with min dist" selection of the algorithm. */
+typedef struct {
+  uint64_t d;
+  int32_t v;
+} orc_hn;
+
+static void heap_push(orc_hn *h, int64_t *len, uint64_t d, int32_t v) {
+  int64_t i = (*len)++;
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (h[p].d <= d) break;
+    h[i] = h[p];
+    i = p;
+  }
+  h[i].d = d;
+  h[i].v = v;
+}
+
+static orc_hn heap_pop(orc_hn *h, int64_t *len) {
+  orc_hn top = h[0], last = h[--(*len)];
+  int64_t i = 0;
+  for (;;) {
+    int64_t c = 2 * i + 1;
+    if (c >= *len) break;
+    if (c + 1 < *len && h[c + 1].d < h[c].d) ++c;
+    if (h[c].d >= last.d) break;
+    h[i] = h[c];
+    i = c;
+  }
+  if (*len > 0) h[i] = last;
+  return top;
+}
+
+/* Dijkstra from src (Algorithm "Sequential SSSP"): dist starts at infinity
+ * and prev at -1 everywhere, dist[src] = 0; repeatedly take the unsettled
+ * vertex of smallest dist and relax every unsettled neighbour, setting
+ * dist[v] = dist[u] + w(u, v) and prev[v] = u when that is smaller.
+ * dist uint32 [n] (UINT32_MAX = unreached), prev int32 [n]; prev[src] = src.
+ * Returns the number of reached vertices, -1 for a bad source, -3 if memory
+ * runs out, -4 if a distance exceeds UINT32_MAX - 1. */
+int64_t orc_sssp(const int64_t *rp, const int32_t *ci, const uint8_t *wt, int64_t n, int64_t src,
+                 uint32_t *dist, int32_t *prev) {
+  if (src < 0 || src >= n) return -1;
+  uint64_t *d = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+  uint8_t *done = (uint8_t *)calloc((size_t)n, 1);
+  orc_hn *h = (orc_hn *)malloc((size_t)(rp[n] + 1) * sizeof(orc_hn));
+  if (!d || !done || !h) {
+    free(d);
+    free(done);
+    free(h);
+    return -3;
+  }
+  const uint64_t INF = ~0ull;
+  for (int64_t v = 0; v < n; ++v) {
+    d[v] = INF;
+    prev[v] = -1;
+  }
+  d[src] = 0;
+  prev[src] = (int32_t)src;
+  int64_t len = 0, reached = 0;
+  heap_push(h, &len, 0, (int32_t)src);
+  while (len > 0) {
+    orc_hn t = heap_pop(h, &len);
+    int32_t u = t.v;
+    if (done[u] || t.d != d[u]) continue; /* a stale entry */
+    done[u] = 1;
+    ++reached;
+    for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
+      int32_t v = ci[k];
+      if (done[v]) continue;
+      uint64_t alt = d[u] + wt[k];
+      if (alt < d[v]) {
+        d[v] = alt;
+        prev[v] = u;
+        heap_push(h, &len, alt, v);
+      }
+    }
+  }
+  int64_t rc = reached;
+  for (int64_t v = 0; v < n; ++v) {
+    if (d[v] != INF && d[v] >= 0xffffffffull) rc = -4;
+    dist[v] = d[v] == INF ? 0xffffffffu : (uint32_t)d[v];
+  }
+  free(d);
+  free(done);
+  free(h);
+  return rc;
+}
+
+/* Weight of the edge (u, v) in u's ascending row, or -1 if there is none. */
+static int row_weight(const int32_t *ci, const uint8_t *wt, int64_t b, int64_t e, int32_t x) {
+  while (b < e) {
+    int64_t mid = b + (e - b) / 2;
+    if (ci[mid] == x) return wt[mid];
+    if (ci[mid] < x)
+      b = mid + 1;
+    else
+      e = mid;
+  }
+  return -1;
+}
+
+/* Validation of an SSSP result (dist, prev) from src, independent of the
+ * Dijkstra above.  Returns 0 if valid, else the first rule broken:
+ *   1  dist[src] != 0 or prev[src] != src
+ *   2  dist is infinity exactly where prev is -1 fails, or a value out of range
+ *   3  prev[v] is not a neighbour of v
+ *   4  dist[v] != dist[prev[v]] + w(prev[v], v)
+ *   5  an edge (u, v) with dist[v] > dist[u] + w(u, v) (or one end unreached)
+ *   6  the prev pointers of some reached vertex do not lead back to src
+ * Rule 5 makes dist a lower bound of every path length and rules 3, 4, 6 give
+ * each reached v a path of length dist[v] from src, so dist is exactly the
+ * shortest-path distance and prev a shortest-path tree. */
+int orc_check_sssp(const int64_t *rp, const int32_t *ci, const uint8_t *wt, int64_t n, int64_t src,
+                   const uint32_t *dist, const int32_t *prev) {
+  const uint32_t INF = 0xffffffffu;
+  if (src < 0 || src >= n) return 2;
+  if (dist[src] != 0 || prev[src] != src) return 1;
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t p = prev[v];
+    if (p < -1 || p >= n) return 2;
+    if ((p == -1) != (dist[v] == INF)) return 2;
+    if (p < 0 || v == src) continue;
+    int w = row_weight(ci, wt, rp[v], rp[v + 1], p);
+    if (w < 0) return 3;
+    if (dist[p] == INF || (uint64_t)dist[v] != (uint64_t)dist[p] + (uint64_t)w) return 4;
+  }
+  for (int64_t u = 0; u < n; ++u)
+    for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
+      int32_t v = ci[k];
+      if ((dist[u] == INF) != (dist[v] == INF)) return 5;
+      if (dist[u] != INF && (uint64_t)dist[v] > (uint64_t)dist[u] + wt[k]) return 5;
+    }
+  /* children lists of the prev tree, then a walk from src over them */
+  int64_t *cs = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  int32_t *kids = (int32_t *)malloc((size_t)n * sizeof(int32_t) + 4);
+  int32_t *stack = (int32_t *)malloc((size_t)n * sizeof(int32_t) + 4);
+  uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+  if (!cs || !kids || !stack || !seen) {
+    free(cs);
+    free(kids);
+    free(stack);
+    free(seen);
+    return -3;
+  }
+  for (int64_t v = 0; v < n; ++v)
+    if (prev[v] >= 0 && v != src) cs[prev[v] + 1]++;
+  for (int64_t v = 0; v < n; ++v) cs[v + 1] += cs[v];
+  for (int64_t v = 0; v < n; ++v)
+    if (prev[v] >= 0 && v != src) kids[cs[prev[v]]++] = (int32_t)v;
+  for (int64_t v = n; v > 0; --v) cs[v] = cs[v - 1];
+  cs[0] = 0;
+  int64_t top = 0;
+  stack[top++] = (int32_t)src;
+  seen[src] = 1;
+  while (top > 0) {
+    int32_t u = stack[--top];
+    for (int64_t k = cs[u]; k < cs[u + 1]; ++k)
+      if (!seen[kids[k]]) {
+        seen[kids[k]] = 1;
+        stack[top++] = kids[k];
+      }
+  }
+  int bad = 0;
+  for (int64_t v = 0; v < n; ++v)
+    if (prev[v] >= 0 && !seen[v]) bad = 6;
+  free(cs);
+  free(kids);
+  free(stack);
+  free(seen);
+  return bad;
+}
+
+/* Deterministic predecessors from a distance array: prev[src] = src; for a
+ * reached v != src, the smallest-id neighbour u with
+ * dist[u] + w(u, v) = dist[v]; -1 if v is unreached.  Returns 0, or -1 if
+ * some reached v has no such neighbour. */
+int orc_min_prev(const int64_t *rp, const int32_t *ci, const uint8_t *wt, int64_t n, int64_t src,
+                 const uint32_t *dist, int32_t *prev) {
+  int bad = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    prev[v] = -1;
+    if (dist[v] == 0xffffffffu) continue;
+    if (v == src) {
+      prev[v] = (int32_t)v;
+      continue;
+    }
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+      int32_t u = ci[k];
+      if (dist[u] != 0xffffffffu && (uint64_t)dist[u] + wt[k] == (uint64_t)dist[v]) {
+        prev[v] = u; /* rows are ascending: the first match is the smallest id */
+        break;
+      }
+    }
+    if (prev[v] < 0) bad = 1;
   }
   return bad ? -1 : 0;
 }

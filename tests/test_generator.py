@@ -111,3 +111,22 @@ def test_select_roots():
     assert roots == K.select_roots(mask, 64, K.root_seed(scale))
     with pytest.raises(ValueError):
         K.select_roots(np.zeros(8, np.uint8), 1, 1)
+
+
+def test_weights_definition_range_and_frequencies():
+    # weight of tuple i = 1 + (splitmix64_at(splitmix64_at(seed, 3), i) mod 255)
+    scale = 12
+    w = K.weights_host(scale)
+    assert w.dtype == np.uint8 and w.shape == (K.num_tuples(scale),)
+    base = K.splitmix64_at(K.graph_seed(scale), 3)
+    for i in (0, 1, 2, 1000, len(w) - 1):
+        assert int(w[i]) == 1 + K.splitmix64_at(base, i) % 255
+    assert w.min() >= 1 and w.max() <= 255
+    # a window of the list equals the same tuples of the whole list
+    assert np.array_equal(K.weights_host(scale, start=100, stop=900), w[100:900])
+    # every value 1..255 within 5 sigma of uniform
+    cnt = np.bincount(w, minlength=256)[1:]
+    exp = len(w) / 255
+    assert np.all(np.abs(cnt - exp) < 5 * np.sqrt(exp))
+    # another seed gives other weights
+    assert not np.array_equal(K.weights_host(scale, seed=7)[:64], w[:64])

@@ -120,3 +120,48 @@ def test_shortcut_levels_rejected():
     parent = np.array([0, 0, 1, 2, 3, 4, 5, 6], np.int32)
     assert O.validate(csr, 0, parent, level, label) == 6
     assert O.validate_edges(e, n, 0, parent, level) == 6
+
+
+# check_parents: the parent rules alone, for level arrays already compared with
+# the oracle's.  Each parent mutation above is rejected with the same rule as
+# the full CSR validator, and random parent mutations agree with it on
+# accept/reject.
+
+def test_check_parents_valid(case):
+    _, _, csr, root, parent, level, _ = case
+    assert O.check_parents(csr, root, parent, level) == 0
+    assert O.check_parents(csr, root, O.min_parents(csr, root, level), level) == 0
+
+
+def test_check_parents_rules(case):
+    e, n, csr, root, parent, level, label = case
+    p = parent.copy()
+    p[root] = pick(level, 1)
+    assert O.check_parents(csr, root, p, level) == 1
+    v = pick(level, 3)
+    adj = set(csr.row(v).tolist())
+    p = parent.copy()
+    p[v] = [u for u in np.flatnonzero(level == 2) if u not in adj][0]
+    assert O.check_parents(csr, root, p, level) == 3
+    v = next(v for v in np.flatnonzero(level == 2) if any(level[u] == 2 for u in csr.row(v)))
+    p = parent.copy()
+    p[v] = next(u for u in csr.row(v) if level[u] == 2)
+    assert O.check_parents(csr, root, p, level) == 4
+    p = parent.copy()
+    p[int(np.flatnonzero(level < 0)[0])] = 0
+    assert O.check_parents(csr, root, p, level) == 2
+    p = parent.copy()
+    p[pick(level, 2)] = -1
+    assert O.check_parents(csr, root, p, level) == 2
+
+
+def test_check_parents_agrees_with_validate(case):
+    _, n, csr, root, parent, level, label = case
+    rng = np.random.default_rng(5)
+    reached = np.flatnonzero((level > 0))
+    for _ in range(300):
+        p = parent.copy()
+        v = int(rng.choice(reached))
+        p[v] = int(rng.choice(csr.row(v))) if rng.random() < 0.7 else int(rng.integers(0, n))
+        full = O.validate(csr, root, p, level, label)
+        assert (O.check_parents(csr, root, p, level) == 0) == (full == 0), (v, p[v], full)
