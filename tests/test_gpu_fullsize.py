@@ -1,14 +1,21 @@
 """Full-size parity at the benchmark's configuration (Kronecker scale 26, edge
-factor 16, the benchmark's roots and default launch parameters).
+factor 16, the benchmark's 64 roots and default launch parameters), and the
+batched configuration (scale 22, 64 roots in one batch).
 
-The oracle cannot afford everything at this size inside a test, so:
   * CSR: 2,000 sampled rows recomputed from the tuple list, bit-exact;
-  * BFS: the tuple-list validator (levels are exactly hop distances and
-    parents a BFS tree; proof in oracle.c) for 4 roots, and the oracle's own
-    queue BFS, bit-exact on levels, for the first root;
-  * batch: 64 roots at scale 22 (the batched configuration), every row equal
-    to single-root levels, 8 rows bit-exact against the oracle.
+  * BFS: for every one of the 64 roots, the GPU's levels equal the oracle's
+    queue BFS bit-exactly and its parent array passes the parent rules; the
+    roots whose traversal takes a heavy top-down level are named from the
+    direction log and must be among them; two roots (the first, and the first
+    heavy one) also pass the tuple-list validator, which needs no CSR;
+  * batch: all 64 rows bit-exact against the oracle, parents checked.
+
+The oracle runs several roots at once from a thread pool (the C calls release
+the interpreter lock).
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -18,6 +25,25 @@ import oracle as O
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 SCALE = 26
+GROUP = 16  # roots per test: 64 roots in four tests
+
+
+def _workers(cap=16):
+    try:
+        return max(1, min(cap, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(cap, os.cpu_count() or 1))
+
+
+def _heavy_levels(info, nnz):
+    """Levels the device ran as heavy top-down levels: top-down, frontier grew,
+    more than nnz/2048 frontier edges (the library's default rule)."""
+    out = []
+    for i, d in enumerate(info["dir"]):
+        grew = i > 0 and info["frontier"][i] > info["frontier"][i - 1]
+        if d == 1 and grew and info["edges"][i] > nnz // 2048:
+            out.append(i)
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -25,6 +51,7 @@ def big():
     import torch
     import paper_2012_13548_amd as g5
     n = 1 << SCALE
+    print(f"[fullsize] scale {SCALE}: device tuples, CSR", flush=True)
     dev_edges = K.edges_device(SCALE)
     csr = g5.build_csr(dev_edges, n)
     mask = K.nonisolated_device(dev_edges, n).cpu().numpy()
@@ -36,7 +63,16 @@ def big():
     torch.cuda.empty_cache()
     host = K.edges_host(SCALE)
     assert np.array_equal(sample_dev, host[idx])
-    return {"n": n, "csr": csr, "roots": roots, "edges": host}
+    print("[fullsize] oracle CSR", flush=True)
+    ocsr = O.build_csr(host, n)
+    heavy = {}
+    for r in roots:
+        _, _, info = g5.bfs(csr, r, stats=True)
+        lv = _heavy_levels(info, csr.nnz)
+        if lv:
+            heavy[r] = lv
+    print(f"[fullsize] {len(heavy)} of 64 roots run heavy top-down levels", flush=True)
+    return {"n": n, "csr": csr, "roots": roots, "edges": host, "ocsr": ocsr, "heavy": heavy}
 
 
 def test_csr_sampled_rows(big):
@@ -56,6 +92,7 @@ def test_csr_sampled_rows(big):
     rp, ci = csr.arrays()
     rp_h = rp.cpu().numpy()
     assert rp_h[0] == 0 and rp_h[-1] == csr.nnz and np.all(np.diff(rp_h) >= 0)
+    assert np.array_equal(rp_h, big["ocsr"].row_ptr)
     for v in rows:
         expect = key[(key >= v * n) & (key < (v + 1) * n)] - v * n
         got = ci[int(rp_h[v]):int(rp_h[v + 1])].cpu().numpy()
@@ -64,22 +101,43 @@ def test_csr_sampled_rows(big):
     torch.cuda.empty_cache()
 
 
+def test_heavy_roots_present(big):
+    # the heavy top-down path is exercised at full size (and all 64 roots,
+    # these included, are compared with the oracle below)
+    assert len(big["heavy"]) >= 1, "no root of the benchmark runs a heavy top-down level"
+
+
+@pytest.mark.parametrize("group", range(64 // GROUP))
+def test_bfs_levels_equal_oracle(big, group):
+    import paper_2012_13548_amd as g5
+    roots = big["roots"][group * GROUP:(group + 1) * GROUP]
+    gpu = []
+    for r in roots:
+        parent, level = g5.bfs(big["csr"], r)
+        gpu.append((parent.cpu().numpy(), level.cpu().numpy()))
+        del parent, level
+    print(f"[fullsize] group {group}: oracle BFS of {len(roots)} roots", flush=True)
+    with ThreadPoolExecutor(_workers()) as ex:
+        olevels = list(ex.map(lambda r: O.bfs(big["ocsr"], r)[1], roots))
+    for r, (parent, level), olevel in zip(roots, gpu, olevels):
+        bad = np.flatnonzero(level != olevel)
+        tag = f"root {r}{' (heavy levels %s)' % big['heavy'][r] if r in big['heavy'] else ''}"
+        assert bad.size == 0, (f"{tag}: {bad.size} levels differ, first at {bad[:5]}: "
+                               f"gpu {level[bad[:5]]} oracle {olevel[bad[:5]]}")
+        rule = O.check_parents(big["ocsr"], r, parent, level)
+        assert rule == 0, f"{tag}: parent array invalid ({O.RULES[rule]})"
+
+
 def test_bfs_validated_from_tuples(big):
     import paper_2012_13548_amd as g5
-    for r in big["roots"][:4]:
+    picks = [big["roots"][0]]
+    if big["heavy"]:
+        picks.append(next(iter(big["heavy"])))
+    for r in picks:
         parent, level = g5.bfs(big["csr"], r)
         rule = O.validate_edges(big["edges"], big["n"], r, parent.cpu().numpy(),
                                 level.cpu().numpy())
         assert rule == 0, f"root {r}: {O.RULES[rule]}"
-
-
-def test_bfs_levels_equal_oracle(big):
-    import paper_2012_13548_amd as g5
-    r = big["roots"][0]
-    _, level = g5.bfs(big["csr"], r)
-    ocsr = O.build_csr(big["edges"], big["n"])
-    _, olevel = O.bfs(ocsr, r)
-    assert np.array_equal(level.cpu().numpy(), olevel)
 
 
 def test_batch_scale22_64_roots():
@@ -91,13 +149,12 @@ def test_batch_scale22_64_roots():
     csr = g5.build_csr(torch.from_numpy(e).cuda(), n)
     roots = K.select_roots(K.nonisolated_host(e, n), 64, K.root_seed(scale))
     parents, levels = g5.bfs_batch(csr, roots)
-    for b, r in enumerate(roots):
-        _, single = g5.bfs(csr, r)
-        assert torch.equal(levels[b].to(torch.int32), single), b
-    ocsr = O.build_csr(e, n)
-    label = O.components(e, n)
     lv, pa = levels.cpu().numpy(), parents.cpu().numpy()
-    for b in range(0, 64, 8):
-        _, olevel = O.bfs(ocsr, roots[b])
-        assert np.array_equal(lv[b].astype(np.int32), olevel)
-        assert O.validate(ocsr, roots[b], pa[b], olevel, label) == 0
+    ocsr = O.build_csr(e, n)
+    with ThreadPoolExecutor(_workers()) as ex:
+        olevels = list(ex.map(lambda r: O.bfs(ocsr, r)[1], roots))
+    for b, (r, olevel) in enumerate(zip(roots, olevels)):
+        bad = np.flatnonzero(lv[b].astype(np.int32) != olevel)
+        assert bad.size == 0, f"row {b} root {r}: {bad.size} levels differ, first {bad[:5]}"
+        rule = O.check_parents(ocsr, r, pa[b], olevel)
+        assert rule == 0, f"row {b} root {r}: parents invalid ({O.RULES[rule]})"
