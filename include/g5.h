@@ -60,6 +60,24 @@ g5_status g5_build_csr(const int64_t *edges, int64_t m, int64_t n_vertices, void
 g5_status g5_csr_info(const g5_csr *g, int64_t *n, int64_t *nnz, const int64_t **row_ptr,
                       const int32_t **col_idx);
 
+/* Kernel 1 for Kernel 3 (Sections 2.1, 2.2 and 2.4): the undirected CSR of
+ * a weighted tuple list (the generator's 3 x #E matrix of start, end and
+ * weight).  As g5_build_csr, plus
+ *   weights  device, uint8 [m]: the integer weight (0..255) of each tuple,
+ *            borrowed for the call (may be NULL only when m = 0).
+ * Every non-loop tuple gives both directions with its weight; of repeated
+ * tuples joining the same two vertices the CSR keeps the smallest weight
+ * (the only one a shortest path can use).  Weights are stored beside col_idx
+ * (g5_csr_copy_weights).  Needs n <= 2^28 (a sort key holds two vertex ids
+ * and the weight).  The graph also serves g5_bfs.  Errors as g5_build_csr. */
+g5_status g5_build_csr_w(const int64_t *edges, const uint8_t *weights, int64_t m,
+                         int64_t n_vertices, void *stream, g5_csr **out);
+
+/* Copies the weights of a graph built by g5_build_csr_w (uint8 [nnz], aligned
+ * with col_idx) into a caller buffer (device or host memory).  G5_EINVAL if
+ * the graph has no weights. */
+g5_status g5_csr_copy_weights(const g5_csr *g, uint8_t *weights, void *stream);
+
 /* Copies the CSR arrays into caller buffers (device or host memory):
  * row_ptr int64 [n+1], col_idx int32 [nnz]; either may be NULL. */
 g5_status g5_csr_copy(const g5_csr *g, int64_t *row_ptr, int32_t *col_idx, void *stream);
@@ -163,6 +181,12 @@ typedef struct {
  * grid barrier per level (same results).  It waits at the barriers for all of
  * its workgroups, so it should own the device. */
 #define G5_FLAG_PERSISTENT 512
+/* g5_bfs_batch_ex: the level loop runs as replays of one instantiated HIP
+ * graph of 8 level kernels (each takes the level's direction decision on the
+ * device and does nothing past the end), built once per workspace from kernel
+ * nodes only; the host reads the level counters after each replay.  Same
+ * results. */
+#define G5_FLAG_GRAPH 1024
 
 #define G5_MAX_STAT_LEVELS 64
 
@@ -182,7 +206,9 @@ typedef struct {
   int32_t bu_lane_scan, bu_blocks_per_cu;   /* bottom-up shape used */
   int32_t lds_levels;                       /* bottom-up levels that staged the frontier in LDS */
   int32_t lds_shift;                        /* log2 vertices per staged bit (0: exact bitmap) */
-  int64_t reserved[5];
+  int64_t lds_mask;                         /* bit i (i < 64): level i's bottom-up step staged the
+                                               frontier in LDS */
+  int64_t reserved[4];
 } g5_bfs_stats;
 
 /* g5_bfs with explicit parameters (NULL = defaults) and optional statistics
@@ -238,6 +264,66 @@ typedef struct {
 g5_status g5_bfs_batch_ex(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
                           int8_t *levels, void *stream, const g5_batch_params *params,
                           g5_batch_stats *stats);
+
+/* Kernel 3 (Section 2.4): single-source shortest paths from `src` over a
+ * graph built by g5_build_csr_w, by parallel delta-stepping (the direction
+ * named in Section 4.1; buckets of width delta, relaxations by atomic
+ * minimum, one queue per round).
+ *   dist  device, uint32 [n]: the shortest-path distance from src, or
+ *         0xFFFFFFFF (infinity) where v is not in src's component.
+ *   prev  device, int32 [n]: prev[src] = src; for another reached v, the
+ *         smallest-id neighbour u with dist[u] + w(u, v) = dist[v] (a
+ *         shortest-path tree, the same on every run); -1 where unreached.
+ * Errors: G5_EINVAL (src outside [0, n), NULL pointer, a graph without
+ * weights), G5_ERANGE (a distance above 2^32 - 2), G5_ENOMEM, G5_EDEVICE. */
+g5_status g5_sssp(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, void *stream);
+
+typedef struct {
+  uint32_t delta;   /* bucket width (0 = the default, 32) */
+  int32_t flags;    /* G5_FLAG_TIME_STEPS: time the call on the device (ms) */
+  int32_t reserved[6];
+} g5_sssp_params;
+
+typedef struct {
+  int64_t rounds;   /* relaxation rounds (one launch each, plus hub pieces) */
+  int64_t scans;    /* scans of the far set */
+  int64_t buckets;  /* thresholds used */
+  int64_t relaxed;  /* queue entries relaxed (a vertex counts once per round it is in) */
+  int64_t delta;    /* bucket width used */
+  double ms;        /* device time of the call (G5_FLAG_TIME_STEPS) */
+  int64_t reserved[4];
+} g5_sssp_stats;
+
+/* g5_sssp with explicit parameters (NULL = defaults) and statistics (NULL =
+ * none).  Same results and errors. */
+g5_status g5_sssp_ex(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, void *stream,
+                     const g5_sssp_params *params, g5_sssp_stats *stats);
+
+/* Measurement (not part of a traversal): the work that level `lvl` of a
+ * finished traversal had to do, computed from its level array alone.  The
+ * level array is unique (hop distances), so the counts do not depend on how
+ * the traversal ran; they define the algorithmic bytes of a step:
+ *   top-down   (Section 2.3.2, the parallel loops over the frontier and each
+ *              frontier vertex's neighbours) 4 per queue entry + 16 per row's
+ *              two 64-bit offsets + 4 per row entry, over Q, and 12 per
+ *              claimed vertex (level, parent, next-queue entry):
+ *              20 |Q| + 4 m_f + 12 claimed;
+ *   bottom-up  16 row offsets + 4 per row entry read in row order up to and
+ *              including the first frontier neighbour, over the unvisited
+ *              vertices of degree >= 1, + n/8 (visited bitmap read) + n/8
+ *              (next-frontier bitmap written) + 8 per claimed vertex:
+ *              16 U + 4 S + n/4 + 8 claimed.
+ *   level   device, int32 [n]: the level array of a traversal of g.
+ *   lvl     the level whose step is counted (its frontier is level lvl).
+ *   out     host, int64 [5]: |Q| (vertices at level lvl), m_f (their degree
+ *           sum), claimed (vertices at level lvl + 1), U (vertices of degree
+ *           >= 1 at a level above lvl or unreached), S (over those, row
+ *           entries up to and including the first one at level lvl, or the
+ *           whole row).
+ * Allocates a small device buffer per call; returns when the counts are on
+ * the host.  Errors: G5_EINVAL (NULL pointer, lvl < 0), G5_ENOMEM, G5_EDEVICE. */
+g5_status g5_level_work(const g5_csr *g, const int32_t *level, int32_t lvl, int64_t *out,
+                        void *stream);
 
 /* Message for the last non-OK status returned on the calling host thread. */
 const char *g5_last_error(void);

@@ -9,11 +9,14 @@ import fails if it is missing.
 * :func:`build_csr` -- Kernel 1 of the paper (Section 2.2): undirected CSR.
 * :func:`bfs` -- Kernel 2 (Section 2.3): parent and level arrays from a root.
 * :func:`bfs_batch` -- up to 64 roots in one launch.
+* :func:`build_csr_w`, :func:`sssp` -- Kernel 3 (Section 2.4): weighted CSR
+  and single-source shortest paths by delta-stepping.
 """
 import ctypes
 import os
 
-__all__ = ["G5Error", "Csr", "build_csr", "bfs", "bfs_batch", "LIB_PATH", "lib",
+__all__ = ["G5Error", "Csr", "build_csr", "build_csr_w", "bfs", "bfs_batch", "sssp",
+           "level_work", "LIB_PATH", "lib",
            "DIR_AUTO", "DIR_TOPDOWN", "DIR_BOTTOMUP", "CLAIM_OR", "CLAIM_CAS"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +43,7 @@ lib = ctypes.CDLL(LIB_PATH)
 
 FLAG_TIME_STEPS, FLAG_COUNT_BYTES, FLAG_NO_HINT, FLAG_STEPPED, FLAG_PACKED = 1, 2, 4, 8, 16
 FLAG_MIN_PARENT, FLAG_NO_LDS, FLAG_ROWLOOP, FLAG_PERSISTENT = 32, 64, 128, 512
+FLAG_GRAPH = 1024
 
 
 class BfsParams(ctypes.Structure):
@@ -64,7 +68,7 @@ class BfsStats(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("bu_lane_scan", ctypes.c_int32), ("bu_blocks_per_cu", ctypes.c_int32),
                 ("lds_levels", ctypes.c_int32), ("lds_shift", ctypes.c_int32),
-                ("reserved", ctypes.c_int64 * 5)]
+                ("lds_mask", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
 
 
 class BatchParams(ctypes.Structure):
@@ -101,6 +105,31 @@ lib.g5_bfs_batch.restype = ctypes.c_int
 lib.g5_bfs_batch_ex.argtypes = [_P, ctypes.POINTER(_I64), ctypes.c_int32, _P, _P, _P,
                                 ctypes.POINTER(BatchParams), ctypes.POINTER(BatchStats)]
 lib.g5_bfs_batch_ex.restype = ctypes.c_int
+lib.g5_build_csr_w.argtypes = [_P, _P, _I64, _I64, _P, _PP]
+lib.g5_build_csr_w.restype = ctypes.c_int
+lib.g5_csr_copy_weights.argtypes = [_P, _P, _P]
+lib.g5_csr_copy_weights.restype = ctypes.c_int
+
+
+class SsspParams(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_uint32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class SsspStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("scans", ctypes.c_int64),
+                ("buckets", ctypes.c_int64), ("relaxed", ctypes.c_int64),
+                ("delta", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("reserved", ctypes.c_int64 * 4)]
+
+
+lib.g5_sssp.argtypes = [_P, _I64, _P, _P, _P]
+lib.g5_sssp.restype = ctypes.c_int
+lib.g5_sssp_ex.argtypes = [_P, _I64, _P, _P, _P, ctypes.POINTER(SsspParams),
+                           ctypes.POINTER(SsspStats)]
+lib.g5_sssp_ex.restype = ctypes.c_int
+lib.g5_level_work.argtypes = [_P, _P, ctypes.c_int32, ctypes.POINTER(_I64), _P]
+lib.g5_level_work.restype = ctypes.c_int
 lib.g5_last_error.argtypes = []
 lib.g5_last_error.restype = ctypes.c_char_p
 
@@ -146,6 +175,15 @@ class Csr:
                "g5_csr_copy")
         return rp, ci[:self.nnz]
 
+    def weights(self):
+        """Copy of the edge weights (uint8 [nnz], aligned with col_idx) of a
+        graph built by :func:`build_csr_w`, as a device tensor."""
+        import torch
+        w = torch.empty(max(self.nnz, 1), dtype=torch.uint8, device=self.device)
+        _check(lib.g5_csr_copy_weights(self._h, w.data_ptr(), _stream(self.device)),
+               "g5_csr_copy_weights")
+        return w[:self.nnz]
+
     def free(self):
         if self._h and self._h.value:
             lib.g5_csr_free(self._h)
@@ -171,6 +209,52 @@ def build_csr(edges, n):
     _check(lib.g5_build_csr(ptr, edges.shape[0], int(n), _stream(edges.device),
                             ctypes.byref(out)), "g5_build_csr")
     return Csr(out.value, edges.device)
+
+
+def build_csr_w(edges, weights, n):
+    """Kernel 1 with weights: CSR of a device int64 [m, 2] tuple tensor and a
+    device uint8 [m] weight tensor (smallest weight of repeated tuples)."""
+    import torch
+    if edges.dtype != torch.int64 or edges.dim() != 2 or edges.shape[1] != 2:
+        raise ValueError("edges must be an int64 tensor of shape [m, 2]")
+    if weights.dtype != torch.uint8 or weights.dim() != 1 or weights.shape[0] != edges.shape[0]:
+        raise ValueError("weights must be a uint8 tensor of shape [m]")
+    if not edges.is_cuda or not weights.is_cuda:
+        raise ValueError("edges and weights must be device tensors")
+    edges, weights = edges.contiguous(), weights.contiguous()
+    out = ctypes.c_void_p()
+    pe = edges.data_ptr() if edges.shape[0] else None
+    pw = weights.data_ptr() if edges.shape[0] else None
+    _check(lib.g5_build_csr_w(pe, pw, edges.shape[0], int(n), _stream(edges.device),
+                              ctypes.byref(out)), "g5_build_csr_w")
+    return Csr(out.value, edges.device)
+
+
+def sssp(csr, src, dist=None, prev=None, delta=None, stats=False, time_call=False):
+    """Kernel 3: (dist uint32-as-int32 tensor, prev int32 tensor) from ``src``
+    on a graph built by :func:`build_csr_w`.  dist holds uint32 values (0xFFFFFFFF
+    = unreached) in an int32 tensor (torch has no uint32 arithmetic); view it
+    with ``.cpu().numpy().view(numpy.uint32)``."""
+    import torch
+    if dist is None:
+        dist = torch.empty(csr.n, dtype=torch.int32, device=csr.device)
+    if prev is None:
+        prev = torch.empty(csr.n, dtype=torch.int32, device=csr.device)
+    for t in (dist, prev):
+        if t.dtype != torch.int32 or t.numel() < csr.n or not t.is_contiguous():
+            raise ValueError("dist and prev must be contiguous 32-bit tensors of length n")
+    p = SsspParams()
+    p.delta = int(delta or 0)
+    p.flags = FLAG_TIME_STEPS if time_call else 0
+    st = SsspStats()
+    want = stats or time_call
+    _check(lib.g5_sssp_ex(csr.handle, int(src), dist.data_ptr(), prev.data_ptr(),
+                          _stream(csr.device), ctypes.byref(p), ctypes.byref(st) if want else None),
+           "g5_sssp")
+    if not want:
+        return dist, prev
+    info = {k: getattr(st, k) for k in ("rounds", "scans", "buckets", "relaxed", "delta", "ms")}
+    return dist, prev, info
 
 
 def _params(direction, alpha, beta, lane_scan, claim, flags, blocks_per_cu=None, lds_kb=None,
@@ -228,7 +312,8 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
     nl = min(st.nlevels, MAX_STAT_LEVELS)
     info = {"nlevels": st.nlevels, "reached": st.reached, "alpha": st.alpha, "beta": st.beta,
             "lane_scan": st.bu_lane_scan, "blocks_per_cu": st.bu_blocks_per_cu,
-            "lds_levels": st.lds_levels, "lds_shift": st.lds_shift}
+            "lds_levels": st.lds_levels, "lds_shift": st.lds_shift,
+            "lds_mask": st.lds_mask & ((1 << 64) - 1)}
     for k in ("dir", "frontier", "discovered", "edges", "bytes", "step_ms"):
         info[k] = list(getattr(st, k)[:nl])
     return parent, level, info
@@ -236,10 +321,11 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
 
 def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=DIR_AUTO,
               alpha=None, blocks_per_cu=None, stepped=True, persistent=False, stats=False,
-              time_launch=False):
+              time_launch=False, graph=False):
     """Batched BFS from 1..64 roots, one plain launch per level (these may
     overlap other streams' work); ``persistent=True``: every level in one
-    cooperative launch.  ``stepped`` is accepted for older callers.
+    cooperative launch; ``graph=True``: the level loop as replays of one HIP
+    graph of 8 level kernels.  ``stepped`` is accepted for older callers.
 
     Returns (parents int32 [k, n] or None, levels int8 [k, n]) and, with
     ``stats=True``, a dict of per-level directions and frontier sizes.
@@ -259,7 +345,7 @@ def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=
     p.direction = direction
     p.alpha = alpha or 0.0
     p.flags = ((FLAG_TIME_STEPS if time_launch else 0) | (FLAG_STEPPED if stepped else 0)
-               | (FLAG_PERSISTENT if persistent else 0))
+               | (FLAG_PERSISTENT if persistent else 0) | (FLAG_GRAPH if graph else 0))
     p.blocks_per_cu = blocks_per_cu or 0
     st = BatchStats()
     want = stats or time_launch
@@ -273,3 +359,16 @@ def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=
     info = {"nlevels": st.nlevels, "dir": list(st.dir[:nl]), "frontier": list(st.frontier[:nl]),
             "launch_ms": st.launch_ms, "grid_blocks": st.grid_blocks, "alpha": st.alpha}
     return out + (info,)
+
+
+def level_work(csr, level, lvl):
+    """Work counts of level ``lvl`` of a finished traversal (measurement):
+    dict with q, mf, claimed, unvisited, scanned (see g5_level_work)."""
+    import torch
+    if level.dtype != torch.int32 or level.numel() < csr.n or not level.is_contiguous():
+        raise ValueError("level must be a contiguous int32 tensor of length n")
+    out = (_I64 * 5)()
+    _check(lib.g5_level_work(csr.handle, level.data_ptr(), int(lvl), out, _stream(csr.device)),
+           "g5_level_work")
+    return dict(zip(("q", "mf", "claimed", "unvisited", "scanned"), list(out)))
+

@@ -40,11 +40,41 @@ g5_status g5_build_csr(const int64_t *edges, int64_t m, int64_t n_vertices, void
   }
   *out = nullptr;
   try {
-    return g5::build_csr_impl(edges, m, n_vertices, (hipStream_t)stream, out);
+    return g5::build_csr_impl(edges, nullptr, false, m, n_vertices, (hipStream_t)stream, out);
   } catch (const std::bad_alloc &) {
     set_error("g5_build_csr: host allocation failed");
     return G5_ENOMEM;
   }
+}
+
+g5_status g5_build_csr_w(const int64_t *edges, const uint8_t *weights, int64_t m,
+                         int64_t n_vertices, void *stream, g5_csr **out) {
+  if (!out) {
+    set_error("g5_build_csr_w: out is NULL");
+    return G5_EINVAL;
+  }
+  *out = nullptr;
+  try {
+    return g5::build_csr_impl(edges, weights, true, m, n_vertices, (hipStream_t)stream, out);
+  } catch (const std::bad_alloc &) {
+    set_error("g5_build_csr_w: host allocation failed");
+    return G5_ENOMEM;
+  }
+}
+
+g5_status g5_csr_copy_weights(const g5_csr *g, uint8_t *weights, void *stream) {
+  if (!g || !weights) {
+    set_error("g5_csr_copy_weights: graph and weights must be non-NULL");
+    return G5_EINVAL;
+  }
+  if (!g->wt) {
+    set_error("g5_csr_copy_weights: the graph has no weights (built by g5_build_csr)");
+    return G5_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (g->nnz) G5_HIP(hipMemcpyAsync(weights, g->wt, g->nnz, hipMemcpyDefault, s));
+  G5_HIP(hipStreamSynchronize(s));
+  return G5_OK;
 }
 
 g5_status g5_csr_info(const g5_csr *g, int64_t *n, int64_t *nnz, const int64_t **row_ptr,
@@ -78,8 +108,10 @@ void g5_csr_free(g5_csr *g) {
   if (!g) return;
   for (auto *w : g->bfs_pool) delete w;
   for (auto *w : g->batch_pool) delete w;
+  for (auto *w : g->sssp_pool) delete w;
   if (g->row_ptr) (void)hipFree(g->row_ptr);
   if (g->col_idx) (void)hipFree(g->col_idx);
+  if (g->wt) (void)hipFree(g->wt);
   if (g->iso) (void)hipFree(g->iso);
   if (g->hint) (void)hipFree(g->hint);
   if (g->hot) (void)hipFree(g->hot);
@@ -163,6 +195,45 @@ g5_status g5_bfs_batch_ex(const g5_csr *g, const int64_t *roots, int32_t k, int3
 g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t *parents,
                        int8_t *levels, void *stream) {
   return g5_bfs_batch_ex(g, roots, k, parents, levels, stream, nullptr, nullptr);
+}
+
+g5_status g5_sssp_ex(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, void *stream,
+                     const g5_sssp_params *params, g5_sssp_stats *stats) {
+  if (!g || !dist || !prev) {
+    set_error("g5_sssp: graph, dist and prev must be non-NULL");
+    return G5_EINVAL;
+  }
+  if (src < 0 || src >= g->n) {
+    set_error("g5_sssp: source " + std::to_string(src) + " outside [0, " + std::to_string(g->n) +
+              ")");
+    return G5_EINVAL;
+  }
+  g5_sssp_params p;
+  std::memset(&p, 0, sizeof(p));
+  if (params) p = *params;
+  try {
+    return g5::sssp_impl(g, src, dist, prev, (hipStream_t)stream, p, stats);
+  } catch (const std::bad_alloc &) {
+    set_error("g5_sssp: host allocation failed");
+    return G5_ENOMEM;
+  }
+}
+
+g5_status g5_sssp(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, void *stream) {
+  return g5_sssp_ex(g, src, dist, prev, stream, nullptr, nullptr);
+}
+
+g5_status g5_level_work(const g5_csr *g, const int32_t *level, int32_t lvl, int64_t *out,
+                        void *stream) {
+  if (!g || !level || !out) {
+    set_error("g5_level_work: graph, level and out must be non-NULL");
+    return G5_EINVAL;
+  }
+  if (lvl < 0) {
+    set_error("g5_level_work: lvl must be >= 0");
+    return G5_EINVAL;
+  }
+  return g5::level_work_impl(g, level, lvl, out, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -40,8 +40,12 @@ constexpr int kCompactBlock = 256;
 constexpr int kCompactItems = 16;
 constexpr int kCompactTile = kCompactBlock * kCompactItems;  // 4096 keys
 
-__global__ __launch_bounds__(256) void k_pack(const int64_t *__restrict__ edges, int64_t m,
-                                              int64_t n, int sb, uint64_t sent,
+// With weights (wb = 8) a key is (u << (sb + 8) | v << 8 | w): the sort then
+// orders each run of one (u, v) by weight, and the compaction keeps its first
+// key, i.e. the smallest weight of repeated tuples.  Without weights wb = 0.
+__global__ __launch_bounds__(256) void k_pack(const int64_t *__restrict__ edges,
+                                              const uint8_t *__restrict__ wts, int64_t m,
+                                              int64_t n, int sb, int wb, uint64_t sent,
                                               uint64_t *__restrict__ keys,
                                               uint32_t *__restrict__ err) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -52,8 +56,9 @@ __global__ __launch_bounds__(256) void k_pack(const int64_t *__restrict__ edges,
     if (t.x < 0 || t.x >= n || t.y < 0 || t.y >= n) {
       bad = true;
     } else if (t.x != t.y) {
-      k0 = ((uint64_t)t.x << sb) | (uint64_t)t.y;
-      k1 = ((uint64_t)t.y << sb) | (uint64_t)t.x;
+      const uint64_t w = wts ? (uint64_t)wts[i] : 0;
+      k0 = ((uint64_t)t.x << (sb + wb)) | ((uint64_t)t.y << wb) | w;
+      k1 = ((uint64_t)t.y << (sb + wb)) | ((uint64_t)t.x << wb) | w;
     }
     ulonglong2 o;
     o.x = k0;
@@ -193,31 +198,33 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
 
 __global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
 
-__device__ __forceinline__ bool is_head(const uint64_t *keys, uint64_t i, uint64_t sent) {
+// Key i opens a run of one (u, v) (the weight bits below wb are ignored).
+__device__ __forceinline__ bool is_head(const uint64_t *keys, uint64_t i, uint64_t sent, int wb) {
   uint64_t k = keys[i];
-  return k != sent && (i == 0 || keys[i - 1] != k);
+  return k != sent && (i == 0 || (keys[i - 1] >> wb) != (k >> wb));
 }
 
 // Distinct keys per compaction tile of kCompactTile keys (only the count, so
 // the threads take the tile's keys strided by the block: coalesced loads).
 __global__ __launch_bounds__(kCompactBlock) void k_heads_count(const uint64_t *__restrict__ keys,
                                                                uint64_t nkeys, uint64_t sent,
+                                                               int wb,
                                                                uint32_t *__restrict__ bsum) {
   __shared__ uint32_t s[kCompactBlock / kWave];
   const uint64_t b = (uint64_t)blockIdx.x * kCompactTile + threadIdx.x;
   uint32_t c = 0;
   for (int j = 0; j < kCompactItems; ++j) {
     uint64_t i = b + (uint64_t)j * kCompactBlock;
-    if (i < nkeys && is_head(keys, i, sent)) ++c;
+    if (i < nkeys && is_head(keys, i, sent, wb)) ++c;
   }
   uint32_t tot = block_sum<kCompactBlock, uint32_t>(c, s);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(kCompactBlock) void k_compact(
-    const uint64_t *__restrict__ keys, uint64_t nkeys, uint64_t sent, int sb, int64_t n,
+    const uint64_t *__restrict__ keys, uint64_t nkeys, uint64_t sent, int sb, int wb, int64_t n,
     const uint64_t *__restrict__ boff, int32_t *__restrict__ col_idx,
-    int64_t *__restrict__ row_ptr) {
+    int64_t *__restrict__ row_ptr, uint8_t *__restrict__ wt) {
   __shared__ uint32_t s[kCompactBlock / kWave];
   // The tile (and the key before it) staged in LDS by coalesced loads: thread t
   // then takes its 16 consecutive keys from there (the compaction keeps key
@@ -234,7 +241,7 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
   uint32_t c = 0;
   for (int j = 0; j < kCompactItems; ++j) {
     const uint64_t k = s_k[x0 + j];
-    if (b + j < nkeys && k != sent && s_k[x0 + j - 1] != k) ++c;
+    if (b + j < nkeys && k != sent && (s_k[x0 + j - 1] >> wb) != (k >> wb)) ++c;
   }
   uint32_t tot;
   uint64_t pos = boff[blockIdx.x] + block_excl_scan<kCompactBlock, uint32_t>(c, s, tot);
@@ -244,11 +251,12 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
     if (i >= nkeys) break;
     uint64_t k = s_k[x0 + j];
     uint64_t prev = s_k[x0 + j - 1];  // the sentinel before key 0
-    int64_t up = i ? (int64_t)(prev >> sb) : -1;
+    int64_t up = i ? (int64_t)(prev >> (sb + wb)) : -1;
     if (k != sent) {
-      if (i == 0 || prev != k) {
-        col_idx[pos] = (int32_t)(k & vmask);
-        int64_t u = std::min<int64_t>((int64_t)(k >> sb), n - 1);
+      if (i == 0 || (prev >> wb) != (k >> wb)) {
+        col_idx[pos] = (int32_t)((k >> wb) & vmask);
+        if (wt) wt[pos] = (uint8_t)(k & 0xffu);
+        int64_t u = std::min<int64_t>((int64_t)(k >> (sb + wb)), n - 1);
         for (int64_t r = up + 1; r <= u; ++r) row_ptr[r] = (int64_t)pos;
         ++pos;
       }
@@ -436,11 +444,12 @@ struct DevBuf {
 
 }  // namespace
 
-g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t s,
-                         g5_csr **out) {
+g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weighted, int64_t m,
+                         int64_t n, hipStream_t s, g5_csr **out) {
   *out = nullptr;
-  if (m < 0 || n < 1 || n > 2147483647LL || (m > 0 && !edges)) {
-    set_error("g5_build_csr: need m >= 0, 1 <= n <= 2^31-1 and a non-NULL edge list");
+  if (m < 0 || n < 1 || n > 2147483647LL || (m > 0 && !edges) || (weighted && m > 0 && !weights)) {
+    set_error("g5_build_csr: need m >= 0, 1 <= n <= 2^31-1 and a non-NULL edge list (and weight "
+              "list)");
     return G5_EINVAL;
   }
   int dev = 0, ncu = 256;
@@ -449,7 +458,12 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
 
   int sb = 1;
   while ((1ll << sb) < n) ++sb;
-  const int key_bits = 2 * sb;
+  const int wb = weighted ? 8 : 0;
+  if (2 * sb + wb > 64) {
+    set_error("g5_build_csr_w: weighted graphs need n <= 2^28");
+    return G5_EINVAL;
+  }
+  const int key_bits = 2 * sb + wb;
   const uint64_t sent = (key_bits >= 64) ? ~0ull : ((1ull << key_bits) - 1);
   const uint64_t nkeys = 2ull * (uint64_t)m;
 
@@ -464,8 +478,9 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
   uint64_t *keys = (uint64_t *)ka.p, *alt = (uint64_t *)kb.p;
 
   if (m > 0) {
-    hipLaunchKernelGGL(k_pack, dim3(grid_cap(m, 256, ncu * 64)), dim3(256), 0, s, edges, m, n,
-                       sb, sent, keys, err);
+    hipLaunchKernelGGL(k_pack, dim3(grid_cap(m, 256, ncu * 64)), dim3(256), 0, s, edges,
+                       weighted ? weights : nullptr,
+                       m, n, sb, wb, sent, keys, err);
     G5_LAUNCH_CHECK();
     // radix sort
     int64_t tiles = (int64_t)((nkeys + kSortTile - 1) / kSortTile);
@@ -493,7 +508,7 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
   G5_HIP(hipMalloc(&cb.p, cblocks * sizeof(uint32_t)));
   G5_HIP(hipMalloc(&cbo.p, cblocks * sizeof(uint64_t)));
   hipLaunchKernelGGL(k_heads_count, dim3(cblocks), dim3(kCompactBlock), 0, s, keys, ntot, sent,
-                     (uint32_t *)cb.p);
+                     wb, (uint32_t *)cb.p);
   hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(kScanBlock), 0, s, (const uint32_t *)cb.p,
                      (uint64_t *)cbo.p, cblocks, nnz_dev);
   G5_LAUNCH_CHECK();
@@ -548,8 +563,12 @@ g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t
     return fail(e, "memset");
   if ((e = hipMalloc(&g->iso, g->words * sizeof(uint64_t))) != hipSuccess)
     return fail(e, "iso");
+  if (weighted) {
+    if ((e = hipMalloc(&g->wt, nnz + kColPad)) != hipSuccess) return fail(e, "weights");
+    if ((e = hipMemsetAsync(g->wt + nnz, 0, kColPad, s)) != hipSuccess) return fail(e, "memset");
+  }
   hipLaunchKernelGGL(k_compact, dim3(cblocks), dim3(kCompactBlock), 0, s, keys, ntot, sent, sb,
-                     n, (const uint64_t *)cbo.p, g->col_idx, g->row_ptr);
+                     wb, n, (const uint64_t *)cbo.p, g->col_idx, g->row_ptr, g->wt);
   hipLaunchKernelGGL(k_iso, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
                      n, g->words, g->iso, noniso_dev);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");

@@ -77,9 +77,21 @@ struct BatchWork {
   uint64_t *buf[3] = {nullptr, nullptr, nullptr};  // frontier masks, rotated per level
   void *ctl = nullptr;                 // level counters (MsCtl in msbfs.hip)
   void *host_ctl = nullptr;            // pinned mirror
-  int64_t *roots = nullptr;            // device copy of the roots
   hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // level-loop graph (without / with parents)
+  int gblocks[2] = {0, 0};             // the grid each was built for
   ~BatchWork();
+};
+
+// Device state of one shortest-path computation (sssp.hip); reused across calls.
+struct SsspWork {
+  uint64_t *pend = nullptr;   // far set: vertices improved at or above the threshold
+  uint32_t *stamp = nullptr;  // per vertex: the stamp of the last queue it joined
+  int32_t *q[2] = {nullptr, nullptr};  // current and next queue
+  uint64_t *ctr = nullptr;    // device counters (SCtr in sssp.hip)
+  uint32_t epoch = 0;         // last queue stamp handed out (only grows)
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~SsspWork();
 };
 
 // Defaults picked per graph from the autotuned table (tuned_table.inc).
@@ -109,6 +121,7 @@ struct g5_csr {
   int64_t nonisolated = 0;     // vertices of degree >= 1
   int64_t *row_ptr = nullptr;  // device [n+1]
   int32_t *col_idx = nullptr;  // device [nnz]
+  uint8_t *wt = nullptr;       // device [nnz]: edge weights (weighted graphs only)
   uint64_t *iso = nullptr;     // device [words]: bit set = degree 0 (or padding)
   uint32_t *rp32 = nullptr;    // device [n+1]: row_ptr as 32-bit offsets
   int32_t *hint = nullptr;     // device [n]: highest-degree neighbour, -1 if none, or
@@ -125,6 +138,7 @@ struct g5_csr {
   mutable std::mutex mu;
   mutable std::vector<g5::BfsWork *> bfs_pool;
   mutable std::vector<g5::BatchWork *> batch_pool;
+  mutable std::vector<g5::SsspWork *> sssp_pool;
 };
 
 namespace g5 {
@@ -186,12 +200,23 @@ __device__ __forceinline__ T block_sum(T x, T *s) {
 }
 
 // ---------------------------------------------------------------- host entry points
-g5_status build_csr_impl(const int64_t *edges, int64_t m, int64_t n, hipStream_t s,
-                         g5_csr **out);
+g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weighted, int64_t m,
+                         int64_t n, hipStream_t s, g5_csr **out);
 g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *level,
                    hipStream_t s, const g5_bfs_params &p, g5_bfs_stats *stats);
 g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *parents,
                          int8_t *levels, hipStream_t s, const g5_batch_params &p,
                          g5_batch_stats *stats);
+// A stepped batch (default parameters, no statistics) on a workspace the
+// caller provides: masks = device uint64 [4n] (seen and three frontier
+// buffers), ctl = device memory of batch_ctl_bytes() bytes.  Every part that
+// must start at zero is cleared by the call; nothing is allocated.
+size_t batch_ctl_bytes();
+g5_status batch_in_workspace(const g5_csr *g, uint64_t *masks, void *ctl, const int64_t *roots,
+                             int k, int32_t *parents, int8_t *levels, hipStream_t s);
+g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, hipStream_t s,
+                    const g5_sssp_params &p, g5_sssp_stats *stats);
+g5_status level_work_impl(const g5_csr *g, const int32_t *level, int32_t lvl, int64_t *out,
+                          hipStream_t s);
 
 }  // namespace g5

@@ -18,7 +18,8 @@ def declared_symbols():
 def test_header_declares_the_boundary():
     syms = declared_symbols()
     for s in ["g5_build_csr", "g5_csr_info", "g5_csr_copy", "g5_csr_free", "g5_bfs",
-              "g5_bfs_ex", "g5_bfs_batch", "g5_last_error"]:
+              "g5_bfs_ex", "g5_bfs_batch", "g5_last_error", "g5_build_csr_w", "g5_sssp",
+              "g5_sssp_ex", "g5_csr_copy_weights", "g5_level_work"]:
         assert s in syms
 
 
@@ -37,6 +38,9 @@ def test_null_arguments_rejected_without_device():
     assert lib.g5_csr_info(None, None, None, None, None) == g5.G5_EINVAL
     assert lib.g5_bfs_batch(None, None, 1, None, None, None) == g5.G5_EINVAL
     assert lib.g5_build_csr(None, 0, 4, None, None) == g5.G5_EINVAL
+    assert lib.g5_sssp(None, 0, None, None, None) == g5.G5_EINVAL
+    assert lib.g5_build_csr_w(None, None, 0, 4, None, None) == g5.G5_EINVAL
+    assert lib.g5_level_work(None, None, 0, None, None) == g5.G5_EINVAL
     lib.g5_csr_free(None)
 
 
@@ -51,12 +55,14 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     import paper_2012_13548_amd as g5
     src = tmp_path / "sizes.c"
-    src.write_text('#include <stdio.h>\n#include "g5.h"\nint main(void){printf("%zu %zu %zu %zu",'
+    src.write_text('#include <stdio.h>\n#include "g5.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu",'
                    ' sizeof(g5_bfs_params), sizeof(g5_bfs_stats), sizeof(g5_batch_params),'
-                   ' sizeof(g5_batch_stats));return 0;}\n')
+                   ' sizeof(g5_batch_stats), sizeof(g5_sssp_params), sizeof(g5_sssp_stats));'
+                   'return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
                    check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     assert [int(x) for x in out] == [ctypes.sizeof(g5.BfsParams), ctypes.sizeof(g5.BfsStats),
-                                     ctypes.sizeof(g5.BatchParams), ctypes.sizeof(g5.BatchStats)]
+                                     ctypes.sizeof(g5.BatchParams), ctypes.sizeof(g5.BatchStats),
+                                     ctypes.sizeof(g5.SsspParams), ctypes.sizeof(g5.SsspStats)]
