@@ -23,6 +23,7 @@
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "g5_internal.h"
 
@@ -46,15 +47,7 @@ struct Slot {
   unsigned long long pad;
 };
 
-struct MsCtl {
-  Slot slot[3];
-  unsigned long long mu0;  // degree sum of vertices not yet seen by every root
-  unsigned long long err;
-  unsigned long long nlevels;
-  unsigned long long mu_lv[2];  // stepped mode: m_u at the start of level l, by parity
-  int64_t frontier[kStatLevels];
-  int32_t dir[kStatLevels];
-};
+struct MsCtl;
 
 struct MsArgs {
   const int64_t *rp;
@@ -69,10 +62,30 @@ struct MsArgs {
   const uint64_t *hub_off;
   int64_t num_hubs;
   int64_t hub_chunks;
+  const int32_t *hint;  // per vertex: its highest-degree neighbour (-1: none), from Kernel 1
   MsCtl *ctl;
   double alpha;
   int direction;
   int max_level;
+};
+
+struct MsCtl {
+  Slot slot[3];
+  unsigned long long mu0;  // degree sum of vertices not yet seen by every root
+  unsigned long long err;
+  unsigned long long nlevels;
+  unsigned long long mu_lv[2];  // stepped mode: m_u at the start of level l, by parity
+  unsigned long long lbase;     // graph replays: the first level of the next replay
+  unsigned long long pad;
+  MsArgs args;                  // graph replays: the arguments of this batch
+  int64_t frontier[kStatLevels];
+  int32_t dir[kStatLevels];
+};
+
+// The roots of a batch, passed by value to the seeding kernel (no copy of
+// them to device memory is needed).
+struct Roots64 {
+  int64_t r[64];
 };
 
 __device__ __forceinline__ unsigned long long ld_agent(unsigned long long *p) {
@@ -225,7 +238,23 @@ __device__ void bu_phase(const MsArgs &a, const uint64_t *front, uint64_t *next,
     if (__ballot(act) == 0) continue;
     const uint64_t missing = a.full & ~s;
     uint64_t got = 0;
-    if (act && d <= kLaneRow) {
+    // the highest-degree neighbour first: a hub in many roots' frontiers often
+    // provides every missing bit at once, and the row is not read
+    if (act && a.hint) {
+      const int32_t h = a.hint[v];
+      if (h >= 0) {
+        got = front[h] & missing;
+        if (PAR) {
+          uint64_t x = got;
+          while (x) {
+            const int bb = __ffsll((unsigned long long)x) - 1;
+            x &= x - 1;
+            a.parents[(int64_t)bb * a.n + v] = h;
+          }
+        }
+      }
+    }
+    if (act && d <= kLaneRow && got != missing) {
       // entries in row order, so the first provider of a bit is its parent; a
       // batch past the point where every missing bit is found contributes nothing
       for (int64_t k0 = b; k0 < e && got != missing; k0 += kRowBatch) {
@@ -252,14 +281,14 @@ __device__ void bu_phase(const MsArgs &a, const uint64_t *front, uint64_t *next,
         }
       }
     }
-    uint64_t rem = __ballot(act && d > kLaneRow);
+    uint64_t rem = __ballot(act && d > kLaneRow && got != missing);
     while (rem) {
       const int L = __ffsll((unsigned long long)rem) - 1;
       rem &= rem - 1;
       const int64_t kb = __shfl(b, L, kWave), ke = __shfl(e, L, kWave);
       const uint64_t mL = __shfl(missing, L, kWave);
       const int64_t vL = w * kWave + L;
-      uint64_t gotL = 0;
+      uint64_t gotL = __shfl(got, L, kWave);  // the hint's bits
       for (int64_t c = kb; c < ke; c += kWave) {
         const int64_t k = c + lane;
         int32_t u = -1;
@@ -418,6 +447,33 @@ __global__ __launch_bounds__(kBlock) void k_ms_level(MsArgs a, int l) {
   level_body<PAR>(a, l, choose_td(a, mf, mu), nf, s_red);
 }
 
+// Graph replays: the same level as k_ms_level, with the arguments and the
+// level number read from ctl (level = ctl->lbase + j), so one instantiated
+// graph of kGraphLevels level nodes and a final k_ms_advance serves every
+// group of levels of every batch that uses this workspace.
+template <bool PAR>
+__global__ __launch_bounds__(kBlock) void k_ms_level_g(MsCtl *ctl, int j) {
+  const MsArgs a = ctl->args;
+  const int l = (int)ld_agent(&ctl->lbase) + j;
+  __shared__ uint64_t s_red[kBlock / kWave];
+  Slot *cur = &ctl->slot[l % 3];
+  const uint64_t nf = ld_agent(&cur->nf), mf = ld_agent(&cur->mf);
+  if (nf == 0) return;
+  if (l > a.max_level) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(&ctl->err, 1ull);
+    return;
+  }
+  const uint64_t mu =
+      l == 0 ? ld_agent(&ctl->mu0) : ld_agent(&ctl->mu_lv[(l - 1) & 1]) - ld_agent(&cur->dec);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->mu_lv[l & 1] = mu;
+  level_body<PAR>(a, l, choose_td(a, mf, mu), nf, s_red);
+}
+
+// Moves the level base of graph replays on by the levels one replay runs.
+__global__ void k_ms_advance(MsCtl *ctl, int levels) {
+  if (threadIdx.x == 0) ctl->lbase += (unsigned long long)levels;
+}
+
 __global__ void k_fill_i8(int8_t *__restrict__ p, int64_t len, bool vec) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -446,10 +502,15 @@ __global__ void k_zero_words(uint64_t *__restrict__ p, int64_t len) {
 // degree sum, and m_u (degree sum of the vertices not yet seen by every root)
 // = nnz minus the degree of a vertex every root has seen, which happens only
 // when all roots are one vertex.  One thread per root.
-__global__ void k_ms_seed(const int64_t *__restrict__ roots, int k, int64_t n, uint64_t *seen,
-                          uint64_t *front, int8_t *levels, int32_t *parents,
-                          const int64_t *__restrict__ rp, MsCtl *ctl) {
+__global__ void k_ms_seed(Roots64 roots_v, int k, int64_t n, uint64_t *seen, uint64_t *front,
+                          int8_t *levels, int32_t *parents, const int64_t *__restrict__ rp,
+                          MsCtl *ctl, MsArgs args) {
+  const int64_t *roots = roots_v.r;
   int b = threadIdx.x;
+  if (b == 0) {
+    ctl->args = args;
+    ctl->lbase = 0;
+  }
   if (b >= k) return;
   int64_t v = roots[b];
   atomicOr((unsigned long long *)&seen[v], 1ull << b);
@@ -488,12 +549,13 @@ int grid_for(int64_t items, int per_block, int cap) {
 }  // namespace
 
 BatchWork::~BatchWork() {
+  for (auto &x : gexec)
+    if (x) (void)hipGraphExecDestroy(x);
   if (seen) (void)hipFree(seen);
   for (auto *b : buf)
     if (b) (void)hipFree(b);
   if (ctl) (void)hipFree(ctl);
   if (host_ctl) (void)hipHostFree(host_ctl);
-  if (roots) (void)hipFree(roots);
   for (auto &e : ev)
     if (e) (void)hipEventDestroy(e);
 }
@@ -509,7 +571,6 @@ g5_status alloc_batch(const g5_csr *g, BatchWork **out) {
   A((void **)&w->seen, g->n * 8);
   for (auto &b : w->buf) A((void **)&b, g->n * 8);
   A(&w->ctl, sizeof(MsCtl));
-  A((void **)&w->roots, 64 * sizeof(int64_t));
   if (e == hipSuccess) e = hipHostMalloc(&w->host_ctl, sizeof(MsCtl), hipHostMallocDefault);
   if (e != hipSuccess) {
     set_error(std::string("g5_bfs_batch workspace: ") + hipGetErrorString(e));
@@ -530,40 +591,78 @@ struct BatchLease {
     }
   }
 };
-}  // namespace
 
-// Stepped batch: one launch per level, each taking its own direction
-// decision on the device.  The host queues levels in groups (8, then 4 at a
-// time) and reads the counters once per group instead of once per level; the
-// levels queued past the end do nothing.
-g5_status batch_stepped(const g5_csr *g, BatchWork &w, const MsArgs &a, int32_t *parents,
-                        hipStream_t s, bool timed, g5_batch_stats *stats, int bpc) {
-  const int blocks = g->num_cu * bpc;
-  MsCtl *hc = (MsCtl *)w.host_ctl;
-  if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
-  bool err = false;
-  int l = 0;  // levels queued
-  for (int group = 8;; group = 4) {
-    for (int j = 0; j < group; ++j, ++l) {
-      if (parents)
-        hipLaunchKernelGGL(k_ms_level<true>, dim3(blocks), dim3(kBlock), 0, s, a, l);
-      else
-        hipLaunchKernelGGL(k_ms_level<false>, dim3(blocks), dim3(kBlock), 0, s, a, l);
-    }
-    G5_LAUNCH_CHECK();
-    G5_HIP(hipMemcpyAsync(hc, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
-    G5_HIP(hipStreamSynchronize(s));
-    if (hc->err) {
-      err = true;
-      break;
-    }
-    // levels 0 .. nlevels-1 ran; fewer than queued means one found its frontier
-    // empty, else the frontier of the next level decides (its slot was cleared
-    // by level l - 2 and filled by level l - 1, both of which ran)
-    if ((int)hc->nlevels < l || hc->slot[l % 3].nf == 0) break;
-  }
-  if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
+// Device workspace of one batch (a pooled BatchWork, or the library's fixed
+// scratch array) and the host buffer the level counters are read into.
+struct BatchSpace {
+  uint64_t *seen;
+  uint64_t *buf[3];
+  MsCtl *ctl;
+  MsCtl *host_ctl;
+  hipEvent_t ev[2];
+};
+
+// Output fills, zeroed masks and counters, the roots seeded; fills `a`.
+g5_status batch_start(const g5_csr *g, const BatchSpace &ws, const int64_t *roots, int k,
+                      int32_t *parents, int8_t *levels, hipStream_t s, const g5_batch_params &p,
+                      MsArgs &a) {
+  const int64_t n = g->n;
+  const int fg = g->num_cu * 16;
+  hipLaunchKernelGGL(k_fill_i8, dim3(grid_for((int64_t)k * n / 16, 256, fg)), dim3(256), 0, s,
+                     levels, (int64_t)k * n, ((uintptr_t)levels & 15) == 0);
+  if (parents)
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)k * n / 4, 256, fg)), dim3(256), 0, s,
+                       parents, (int64_t)k * n, ((uintptr_t)parents & 15) == 0);
+  hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, ws.seen, n);
+  // buf[2] is cleared by level 0 before level 1 fills it
+  for (int i = 0; i < 2; ++i)
+    hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, ws.buf[i], n);
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (uint64_t *)ws.ctl,
+                     (int64_t)(sizeof(MsCtl) / 8));
+  a.rp = g->row_ptr;
+  a.ci = g->col_idx;
+  a.n = n;
+  a.full = (k == 64) ? ~0ull : ((1ull << k) - 1);
+  a.seen = ws.seen;
+  a.buf0 = ws.buf[0];
+  a.buf1 = ws.buf[1];
+  a.buf2 = ws.buf[2];
+  a.levels = levels;
+  a.parents = parents;
+  a.hub_list = g->hub_list;
+  a.hub_off = g->hub_off;
+  a.num_hubs = g->num_hubs;
+  a.hub_chunks = g->hub_chunks;
+  a.hint = (p.flags & G5_FLAG_NO_HINT) ? nullptr : g->hint_id;
+  a.ctl = ws.ctl;
+  a.alpha = p.alpha > 0 ? p.alpha : g->tune.batch_alpha;
+  a.direction = p.direction;
+  a.max_level = 127;
+  Roots64 rv{};
+  for (int i = 0; i < k; ++i) rv.r[i] = roots[i];
+  hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, rv, k, n, ws.seen, ws.buf[0], levels,
+                     parents, g->row_ptr, ws.ctl, a);
+  G5_LAUNCH_CHECK();
+  return G5_OK;
+}
+
+g5_status read_ctl(const BatchSpace &ws, hipStream_t s) {
+  G5_HIP(hipMemcpyAsync(ws.host_ctl, ws.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
   G5_HIP(hipStreamSynchronize(s));
+  return G5_OK;
+}
+
+// After `queued` levels ran (or exited at once past the end): done when fewer
+// levels ran than were queued (one found its frontier empty), or the frontier
+// of the next level is empty (its slot was cleared by level queued - 2 and
+// filled by level queued - 1, both of which ran).
+bool batch_done(const MsCtl *hc, int queued) {
+  return (int)hc->nlevels < queued || hc->slot[queued % 3].nf == 0;
+}
+
+g5_status batch_finish(const BatchSpace &ws, const MsArgs &a, int blocks, bool timed,
+                       g5_batch_stats *stats) {
+  const MsCtl *hc = ws.host_ctl;
   if (stats) {
     *stats = g5_batch_stats{};
     stats->nlevels = (int32_t)hc->nlevels;
@@ -575,16 +674,153 @@ g5_status batch_stepped(const g5_csr *g, BatchWork &w, const MsArgs &a, int32_t 
     stats->alpha = a.alpha;
     if (timed) {
       float ms = 0;
-      G5_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));
+      G5_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]));
       stats->launch_ms = ms;
     }
   }
-  if (err) {
+  if (hc->err) {
     set_error("g5_bfs_batch: a level exceeds 127 (int8 levels); use g5_bfs for this root set");
     return G5_ERANGE;
   }
   return G5_OK;
 }
+
+// Stepped batch: one launch per level, each taking its own direction
+// decision on the device.  The host queues levels in groups (8, then 4 at a
+// time) and reads the counters once per group instead of once per level; the
+// levels queued past the end do nothing.
+g5_status batch_stepped(const g5_csr *g, const BatchSpace &ws, const MsArgs &a, hipStream_t s,
+                        bool timed, g5_batch_stats *stats, int bpc) {
+  const int blocks = g->num_cu * bpc;
+  if (timed) G5_HIP(hipEventRecord(ws.ev[0], s));
+  int l = 0;  // levels queued
+  for (int group = 8;; group = 4) {
+    for (int j = 0; j < group; ++j, ++l) {
+      if (a.parents)
+        hipLaunchKernelGGL(k_ms_level<true>, dim3(blocks), dim3(kBlock), 0, s, a, l);
+      else
+        hipLaunchKernelGGL(k_ms_level<false>, dim3(blocks), dim3(kBlock), 0, s, a, l);
+    }
+    G5_LAUNCH_CHECK();
+    g5_status st = read_ctl(ws, s);
+    if (st != G5_OK) return st;
+    if (ws.host_ctl->err || batch_done(ws.host_ctl, l)) break;
+  }
+  if (timed) {
+    G5_HIP(hipEventRecord(ws.ev[1], s));
+    G5_HIP(hipStreamSynchronize(s));
+  }
+  return batch_finish(ws, a, blocks, timed, stats);
+}
+
+// The graph of one replay: kGraphLevels level kernels (k_ms_level_g, level =
+// ctl->lbase + j) and k_ms_advance, in a chain of kernel nodes (no memset or
+// copy nodes).  Built once per workspace, parents mode and grid; the batch's
+// arguments travel in ctl (written by the seeding kernel).
+constexpr int kGraphLevels = 8;
+
+g5_status graph_exec(BatchWork &w, bool par, int blocks, hipGraphExec_t *out) {
+  const int i = par ? 1 : 0;
+  if (w.gexec[i] && w.gblocks[i] == blocks) {
+    *out = w.gexec[i];
+    return G5_OK;
+  }
+  if (w.gexec[i]) {
+    G5_HIP(hipGraphExecDestroy(w.gexec[i]));
+    w.gexec[i] = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  G5_HIP(hipGraphCreate(&graph, 0));
+  MsCtl *ctl = (MsCtl *)w.ctl;
+  hipGraphNode_t prev = nullptr;
+  int js[kGraphLevels];
+  hipError_t e = hipSuccess;
+  for (int j = 0; j <= kGraphLevels && e == hipSuccess; ++j) {
+    hipKernelNodeParams kp{};
+    void *args_level[2];
+    void *args_adv[2];
+    int adv = kGraphLevels;
+    if (j < kGraphLevels) {
+      js[j] = j;
+      args_level[0] = &ctl;
+      args_level[1] = &js[j];
+      kp.func = par ? (void *)&k_ms_level_g<true> : (void *)&k_ms_level_g<false>;
+      kp.gridDim = dim3(blocks);
+      kp.blockDim = dim3(kBlock);
+      kp.kernelParams = args_level;
+    } else {
+      args_adv[0] = &ctl;
+      args_adv[1] = &adv;
+      kp.func = (void *)&k_ms_advance;
+      kp.gridDim = dim3(1);
+      kp.blockDim = dim3(64);
+      kp.kernelParams = args_adv;
+    }
+    kp.sharedMemBytes = 0;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    set_error(std::string("g5_bfs_batch: graph: ") + hipGetErrorString(e));
+    return G5_EDEVICE;
+  }
+  w.gexec[i] = exec;
+  w.gblocks[i] = blocks;
+  *out = exec;
+  return G5_OK;
+}
+
+// Graph batch: the level loop as replays of one instantiated graph of
+// kGraphLevels levels; the host reads the counters after each replay.
+g5_status batch_graph(const g5_csr *g, BatchWork &w, const BatchSpace &ws, const MsArgs &a,
+                      hipStream_t s, bool timed, g5_batch_stats *stats, int bpc) {
+  const int blocks = g->num_cu * bpc;
+  hipGraphExec_t exec = nullptr;
+  {
+    g5_status st = graph_exec(w, a.parents != nullptr, blocks, &exec);
+    if (st != G5_OK) return st;
+  }
+  if (timed) G5_HIP(hipEventRecord(ws.ev[0], s));
+  for (int l = kGraphLevels;; l += kGraphLevels) {
+    G5_HIP(hipGraphLaunch(exec, s));
+    g5_status st = read_ctl(ws, s);
+    if (st != G5_OK) return st;
+    if (ws.host_ctl->err || batch_done(ws.host_ctl, l)) break;
+  }
+  if (timed) {
+    G5_HIP(hipEventRecord(ws.ev[1], s));
+    G5_HIP(hipStreamSynchronize(s));
+  }
+  return batch_finish(ws, a, blocks, timed, stats);
+}
+
+// Every level in one cooperative launch.
+g5_status batch_persistent(const g5_csr *g, const BatchSpace &ws, MsArgs a, hipStream_t s,
+                           bool timed, g5_batch_stats *stats, int bpc) {
+  const void *fn = a.parents ? reinterpret_cast<const void *>(&k_msbfs<true>)
+                             : reinterpret_cast<const void *>(&k_msbfs<false>);
+  int per_cu = 0;
+  G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0));
+  if (per_cu < 1) {
+    set_error("g5_bfs_batch: the persistent kernel does not fit on a compute unit");
+    return G5_EDEVICE;
+  }
+  const int blocks = g->num_cu * std::min(per_cu, bpc);
+  void *args[] = {&a};
+  if (timed) G5_HIP(hipEventRecord(ws.ev[0], s));
+  G5_HIP(hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kBlock), args, 0, s));
+  if (timed) G5_HIP(hipEventRecord(ws.ev[1], s));
+  g5_status st = read_ctl(ws, s);
+  if (st != G5_OK) return st;
+  return batch_finish(ws, a, blocks, timed, stats);
+}
+
+}  // namespace
 
 g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *parents,
                          int8_t *levels, hipStream_t s, const g5_batch_params &p,
@@ -602,90 +838,39 @@ g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *
     if (st != G5_OK) return st;
   }
   BatchWork &w = *lease.w;
-  const int64_t n = g->n;
-  const int ncu = g->num_cu;
   const bool timed = stats && (p.flags & G5_FLAG_TIME_STEPS);
   if (timed && !w.ev[0]) {
     for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
   }
-
-  G5_HIP(hipMemcpyAsync(w.roots, roots, k * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  const int fg = ncu * 16;
-  hipLaunchKernelGGL(k_fill_i8, dim3(grid_for((int64_t)k * n / 16, 256, fg)), dim3(256), 0, s,
-                     levels, (int64_t)k * n, ((uintptr_t)levels & 15) == 0);
-  if (parents)
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)k * n / 4, 256, fg)), dim3(256), 0, s,
-                       parents, (int64_t)k * n, ((uintptr_t)parents & 15) == 0);
-  hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, w.seen, n);
-  // buf[2] is cleared by level 0 before level 1 fills it
-  for (int i = 0; i < 2; ++i)
-    hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 256, fg)), dim3(256), 0, s, w.buf[i], n);
-  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (uint64_t *)w.ctl,
-                     (int64_t)(sizeof(MsCtl) / 8));
-  hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, w.roots, k, n, w.seen, w.buf[0], levels,
-                     parents, g->row_ptr, (MsCtl *)w.ctl);
-  G5_LAUNCH_CHECK();
-
+  const BatchSpace ws{w.seen, {w.buf[0], w.buf[1], w.buf[2]}, (MsCtl *)w.ctl,
+                      (MsCtl *)w.host_ctl, {w.ev[0], w.ev[1]}};
   MsArgs a;
-  a.rp = g->row_ptr;
-  a.ci = g->col_idx;
-  a.n = n;
-  a.full = (k == 64) ? ~0ull : ((1ull << k) - 1);
-  a.seen = w.seen;
-  a.buf0 = w.buf[0];
-  a.buf1 = w.buf[1];
-  a.buf2 = w.buf[2];
-  a.levels = levels;
-  a.parents = parents;
-  a.hub_list = g->hub_list;
-  a.hub_off = g->hub_off;
-  a.num_hubs = g->num_hubs;
-  a.hub_chunks = g->hub_chunks;
-  a.ctl = (MsCtl *)w.ctl;
-  a.alpha = p.alpha > 0 ? p.alpha : g->tune.batch_alpha;
-  a.direction = p.direction;
-  a.max_level = 127;
-
+  {
+    g5_status st = batch_start(g, ws, roots, k, parents, levels, s, p, a);
+    if (st != G5_OK) return st;
+  }
   const int bpc = p.blocks_per_cu > 0 ? p.blocks_per_cu : g->tune.batch_blocks_per_cu;
-  if (!(p.flags & G5_FLAG_PERSISTENT))
-    return batch_stepped(g, w, a, parents, s, timed, stats, bpc);
+  if (p.flags & G5_FLAG_PERSISTENT) return batch_persistent(g, ws, a, s, timed, stats, bpc);
+  if (p.flags & G5_FLAG_GRAPH) return batch_graph(g, w, ws, a, s, timed, stats, bpc);
+  return batch_stepped(g, ws, a, s, timed, stats, bpc);
+}
 
-  const void *fn = parents ? reinterpret_cast<const void *>(&k_msbfs<true>)
-                           : reinterpret_cast<const void *>(&k_msbfs<false>);
-  int per_cu = 0;
-  G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0));
-  if (per_cu < 1) {
-    set_error("g5_bfs_batch: the persistent kernel does not fit on a compute unit");
-    return G5_EDEVICE;
+size_t batch_ctl_bytes() { return sizeof(MsCtl); }
+
+g5_status batch_in_workspace(const g5_csr *g, uint64_t *masks, void *ctl, const int64_t *roots,
+                             int k, int32_t *parents, int8_t *levels, hipStream_t s) {
+  const int64_t n = g->n;
+  MsCtl host{};  // the counters are read into this host buffer
+  const BatchSpace ws{masks, {masks + n, masks + 2 * n, masks + 3 * n}, (MsCtl *)ctl, &host,
+                      {nullptr, nullptr}};
+  g5_batch_params p;
+  std::memset(&p, 0, sizeof(p));
+  MsArgs a;
+  {
+    g5_status st = batch_start(g, ws, roots, k, parents, levels, s, p, a);
+    if (st != G5_OK) return st;
   }
-  const int blocks = ncu * std::min(per_cu, bpc);
-  void *args[] = {&a};
-  if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
-  G5_HIP(hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kBlock), args, 0, s));
-  if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
-  G5_HIP(hipMemcpyAsync(w.host_ctl, w.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
-  G5_HIP(hipStreamSynchronize(s));
-  const MsCtl *hc = (const MsCtl *)w.host_ctl;
-  if (stats) {
-    *stats = g5_batch_stats{};
-    stats->nlevels = (int32_t)hc->nlevels;
-    for (int i = 0; i < std::min<int>((int)hc->nlevels, kStatLevels); ++i) {
-      stats->dir[i] = hc->dir[i];
-      stats->frontier[i] = hc->frontier[i];
-    }
-    stats->grid_blocks = blocks;
-    stats->alpha = a.alpha;
-    if (timed) {
-      float ms = 0;
-      G5_HIP(hipEventElapsedTime(&ms, w.ev[0], w.ev[1]));
-      stats->launch_ms = ms;
-    }
-  }
-  if (hc->err) {
-    set_error("g5_bfs_batch: a level exceeds 127 (int8 levels); use g5_bfs for this root set");
-    return G5_ERANGE;
-  }
-  return G5_OK;
+  return batch_stepped(g, ws, a, s, false, nullptr, g->tune.batch_blocks_per_cu);
 }
 
 }  // namespace g5

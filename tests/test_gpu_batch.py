@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import kronecker as K
+import oracle as O
 import paper_2012_13548_amd as g5
 from tests import graphs as G
 from tests.gpu_util import Case, check_batch
@@ -12,9 +13,10 @@ pytestmark = pytest.mark.gpu
 
 MODES = [dict(), dict(direction=g5.DIR_TOPDOWN), dict(direction=g5.DIR_BOTTOMUP),
          dict(alpha=1e-3), dict(alpha=1e6), dict(parents=False), dict(persistent=True),
-         dict(persistent=True, parents=False, direction=g5.DIR_BOTTOMUP)]
+         dict(persistent=True, parents=False, direction=g5.DIR_BOTTOMUP), dict(graph=True),
+         dict(graph=True, parents=False, direction=g5.DIR_TOPDOWN)]
 MODE_IDS = ["auto", "td", "bu", "auto-bu-early", "auto-td-long", "levels-only", "persistent",
-            "persistent-bu-levels"]
+            "persistent-bu-levels", "graph", "graph-td-levels"]
 
 
 @pytest.fixture(params=range(len(MODES)), ids=MODE_IDS)
@@ -77,10 +79,13 @@ def test_depth_limit():
     c = Case(e, n)
     _, lv, _ = check_batch(c, [127])
     assert lv.max() == 127
+    # the graph path: 128 levels are 16 replays of its 8-level graph
+    _, lv, info = check_batch(c, [127, 127], graph=True)
+    assert lv.max() == 127 and info["nlevels"] == 128
     for roots in ([126], [0, 127]):
-        for persistent in (False, True):
+        for mode in (dict(), dict(persistent=True), dict(graph=True)):
             with pytest.raises(g5.G5Error) as ei:
-                g5.bfs_batch(c.csr, roots, persistent=persistent)
+                g5.bfs_batch(c.csr, roots, **mode)
             assert ei.value.status == g5.G5_ERANGE
     e, n = G.path(256)
     c = Case(e, n)
@@ -123,3 +128,23 @@ def test_repeat_stable(kron12):
         if ref is None:
             ref = lv
         assert np.array_equal(lv, ref)
+
+
+def test_graph_replays_between_eager_work(kron12):
+    # one instantiated graph serves batches with different roots, k and output
+    # buffers; eager launches and synchronisations run between the replays,
+    # and every result equals the stepped (eager) launch's
+    import torch
+    c, roots = kron12
+    for i, k in enumerate([64, 5, 64, 1, 33]):
+        rs = roots[i:i + k] if i + k <= len(roots) else roots[:k]
+        pe, le = g5.bfs_batch(c.csr, rs)
+        torch.cuda.synchronize()
+        pg, lg = g5.bfs_batch(c.csr, rs, graph=True)
+        assert torch.equal(lg, le), (i, k)
+        _, lo = g5.bfs_batch(c.csr, rs, parents=False, graph=True)
+        assert torch.equal(lo, le), (i, k)
+        pg, lg = pg.cpu().numpy(), lg.cpu().numpy()
+        for b, r in enumerate(rs):
+            rule = O.validate(c.ocsr, r, pg[b], lg[b].astype(np.int32), c.label)
+            assert rule == 0, (i, k, b)
