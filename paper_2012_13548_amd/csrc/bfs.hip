@@ -58,16 +58,16 @@ enum Ctr : int {
   C_ROWS = 9,   // those that read their row offsets (hint missed; byte counting only)
   C_HINT = 10,  // vertices found by their hint (byte counting only)
   C_BUGO = 11,  // 1: the next level is bottom-up too (decided by the last bottom-up step)
-  C_NPUB = 12,  // slots copied to the host
-  C_MU = 12,    // m_u: edges of the vertices no top-down level has discovered yet
-  C_LASTNF = 13,  // frontier size of the previous level
-  C_NFIN = 14,  // input frontier size of the next bottom-up step
-  C_UNV = 15,   // non-isolated vertices not reached yet
-  C_QP0 = 16,   // queue 0: entries << 32 | degree sum (appended to by one atomic per block)
-  C_QP1 = 17,   // queue 1: the same
-  C_ENDL = 18,  // lvl + 1 when level lvl's queue came out empty (the traversal ended), else 0
-  C_TICKET = 19,  // workgroups done in the kernel that fills a queue (the last one decides)
-  C_HEAVY = 20,   // 1: the decided top-down level is heavy (its winners read no row offsets)
+  C_HEAVY = 12,  // 1: the decided top-down level is heavy (see TdRule)
+  C_NPUB = 13,  // slots copied to the host
+  C_MU = 13,    // m_u: edges of the vertices no top-down level has discovered yet
+  C_LASTNF = 14,  // frontier size of the previous level
+  C_NFIN = 15,  // input frontier size of the next bottom-up step
+  C_UNV = 16,   // non-isolated vertices not reached yet
+  C_QP0 = 17,   // queue 0: entries << 32 | degree sum (appended to by one atomic per block)
+  C_QP1 = 18,   // queue 1: the same
+  C_ENDL = 19,  // lvl + 1 when level lvl's queue came out empty (the traversal ended), else 0
+  C_TICKET = 20,  // workgroups done in the kernel that fills a queue (the last one decides)
   C_NCTR = 21
 };
 
@@ -114,7 +114,8 @@ struct TdRule {
   // expansion skips the row-offset read of every vertex it claims (one random
   // line each) and writes no queue entries (only their count), and the next
   // level goes bottom-up, which uses neither (the conversion builds its
-  // frontier from the byte levels)
+  // frontier from the byte levels).  Only before any bottom-up level, with
+  // claims by OR over a pre-filled parent array.
   uint64_t heavy_edges;
 };
 
@@ -361,7 +362,8 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
   unsigned long long *qn_pack = ctr + C_QP0 + nxt;
   const int64_t qlen = (int64_t)ctr[C_QLEN0 + cur];
   const uint32_t total = (uint32_t)ctr[C_MF];
-  const bool heavy = ctr[C_HEAVY] != 0;  // claimed vertices read no row offsets
+  // heavy: winners read no row offsets and get no queue entry (only counted)
+  const bool heavy = ctr[C_HEAVY] != 0;
   // only the blocks that own a tile take part (and take a ticket): same-address
   // atomics are serialised, so 1500 tickets cost ~20 us on a small level
   const uint64_t ntiles = ((uint64_t)total + kTdTile - 1) / kTdTile;
@@ -1476,6 +1478,7 @@ static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want, int64_
   };
   using clk = std::chrono::steady_clock;
   constexpr auto kQueryAfter = std::chrono::milliseconds(2);
+  constexpr auto kIdleGrace = std::chrono::milliseconds(100);
   auto next_query = clk::now() + kQueryAfter;
   for (uint32_t spin = 0;; ++spin) {
     if (ready()) break;
@@ -1483,6 +1486,13 @@ static g5_status wait_published(BfsWork &w, hipStream_t s, uint64_t want, int64_
       next_query = clk::now() + kQueryAfter;
       hipError_t e = hipStreamQuery(s);
       if (e == hipSuccess) {
+        // The stream is idle.  The publishing stores are plain system-scope
+        // stores to host memory, not ordered with the completion signal the
+        // query reads, so they may still be in flight: give them a bounded
+        // grace period before reporting a level that never published.
+        const auto give_up = clk::now() + kIdleGrace;
+        while (!ready() && clk::now() < give_up) {
+        }
         if (ready()) break;
         set_error("g5_bfs: a level finished without publishing its counters");
         return G5_EDEVICE;
@@ -1563,10 +1573,20 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   // a bottom-up hit on the hint then writes no parent (unreached vertices are
   // reset at the end).  Compare-and-swap claims need parent -1.
   const bool prefill = use_hint && p.claim != CLAIM_CAS;
+  // heavy top-down levels need claims by OR over the pre-filled parents
   const uint64_t heavy_edges =
-      p.heavy_kedges > 0 ? (uint64_t)p.heavy_kedges * 1000
-                         : (p.heavy_kedges < 0 ? 0 : (uint64_t)g->nnz / 2048);
+      (!prefill || min_parent || p.direction != G5_DIR_AUTO)
+          ? 0
+          : (p.heavy_kedges > 0 ? (uint64_t)p.heavy_kedges * 1000
+                                : (p.heavy_kedges < 0 ? 0 : (uint64_t)g->nnz / 2048));
   const TdRule rule{p.direction, alpha, gamma, heavy_edges};
+  const TdRule rule_light{p.direction, alpha, gamma, 0};
+  bool bu_seen = false;  // a bottom-up level ran: no later level is heavy
+  // the rule of the kernel that decides level L (heavy only before any
+  // bottom-up level and while the byte levels hold L)
+  auto rule_for = [&](int32_t L) -> TdRule {
+    return (bu_seen || L >= kByteLevels) ? rule_light : rule;
+  };
   const unsigned long long seq0 = ++w.seq;  // the root level's decision, taken by k_bfs_init
   hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(std::max(n / 4, W), kBlock, ncu * 16)),
                      dim3(kBlock), 0, s, root, w.lev8, parent, n,
@@ -1602,7 +1622,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   unsigned long long bu_seq = 0;
   uint64_t *front = w.front, *next = w.next;
   if (stats) *stats = g5_bfs_stats{};
-  bool heavy_lv[G5_MAX_STAT_LEVELS] = {};  // top-down levels without row offsets or queue
+  bool heavy_lv[G5_MAX_STAT_LEVELS] = {};  // heavy top-down levels (statistics)
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
   const BuNext bn{p.direction, beta, n};
   const int32_t *hint = use_hint ? g->hint : nullptr;
@@ -1632,8 +1652,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     hipEvent_t t0 = ev_at(lv, 0), t1 = ev_at(lv, 1);
 #define G5_TD(C)                                                                                 \
   G5_KLAUNCH(t0, t1, k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, c, \
-             g->rp32, g->col_idx, w.vis, parent, level, l8, w.q[nx], w.qoff[nx], lv + 1, rule,     \
-             hpub, sq, (const uint64_t *)g->iso, W, prefill, n, lvec, root)
+             g->rp32, g->col_idx, w.vis, parent, level, l8, w.q[nx], w.qoff[nx], lv + 1,          \
+             rule_for(lv + 1), hpub, sq, (const uint64_t *)g->iso, W, prefill, n, lvec, root)
     if (min_parent)
       G5_TD(CLAIM_MIN);
     else if (p.claim == CLAIM_CAS)
@@ -1759,7 +1779,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         if (st != G5_OK) return st;
       }
       if (hc[C_ERR]) {
-        set_error("g5_bfs: top-down tile met more frontier rows than edges");
+        set_error(hc[C_ERR] & 1 ? "g5_bfs: top-down tile met more frontier rows than edges"
+                                : "g5_bfs: a vertex found by a heavy level has no neighbour "
+                                  "one level up");
         return G5_EDEVICE;
       }
       const int64_t qlen = hc[C_QLEN0 + cur];
@@ -1783,6 +1805,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
                            (const uint64_t *)g->iso, root);
         G5_LAUNCH_CHECK();
         dir = 2;
+        bu_seen = true;
         nf_prev = qlen;
         continue;  // this level runs bottom-up
       }
@@ -1791,9 +1814,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         stats->dir[i] = 1;
         stats->frontier[i] = qlen;
         stats->edges[i] = mf;
-        // the device's heavy rule (the frontier grew past the last top-down one)
-        heavy_lv[i] = p.direction == G5_DIR_AUTO && heavy_edges > 0 &&
-                      (uint64_t)mf > heavy_edges && qlen > last_nf;
+        heavy_lv[i] = hc[C_HEAVY] != 0;  // the device's flag for this level
       }
       cur = nxt;
       last_nf = qlen;
@@ -1803,7 +1824,10 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         const bool use_lds = w.sum && !(p.flags & G5_FLAG_NO_LDS) &&
                              (double)nf_prev * (double)(1ll << std::min(lds_gs, 62)) <
                                  lds_density * (double)n;
-        if (use_lds) ++lds_levels;
+        if (use_lds) {
+          ++lds_levels;
+          if (stats && lvl < 64) stats->lds_mask |= (int64_t)(1ull << lvl);
+        }
         bu_seq = ++w.seq;
         // the first step after top-down: k_front_from_level built fh
         g5_status st = launch_bu(lvl, front, next, use_lds, false, bu_seq, true);
@@ -1819,6 +1843,10 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       {
         g5_status st = wait_published(w, s, bu_seq, hc);
         if (st != G5_OK) return st;
+      }
+      if (hc[C_ERR]) {
+        set_error("g5_bfs: a vertex found by a heavy level has no neighbour one level up");
+        return G5_EDEVICE;
       }
       const int64_t nnew = hc[C_NNEW];
       if (slot() >= 0) {
@@ -1853,7 +1881,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
       td_seq[lvl & 3] = ++w.seq;
       hipLaunchKernelGGL(k_front_queue, dim3(grid_for(W, (int)kFqWords, ncu)), dim3(kBlock), 0, s,
                          (const uint64_t *)front, W, g->rp32, w.q[cur], w.qoff[cur], ctr, cur,
-                         last_nf, lvl, rule, hpub, td_seq[lvl & 3]);
+                         last_nf, lvl, rule_for(lvl), hpub, td_seq[lvl & 3]);
       G5_LAUNCH_CHECK();
       td_queued = lvl;  // top-down levels queued before the bottom-up steps did nothing
       td_seq[(lvl + 1) & 3] = ++w.seq;
