@@ -296,12 +296,16 @@ def run_gpu(args):
     parent = torch.empty(n, dtype=torch.int32, device=dev)
     level = torch.empty(n, dtype=torch.int32, device=dev)
 
-    # untimed accounting pass: traversed edges m_r and algorithmic bytes per step
-    m_r, acct = [], []
+    # Untimed accounting pass: traversed edges m_r, the library's own byte
+    # count per level (count_bytes), and the work counts of every level from
+    # the finished level array (g5_level_work), which give the algorithmic
+    # bytes of each step by the definition in include/g5.h.
+    m_r, acct, work = [], [], []
     for r in roots:
         _, _, st = g5.bfs(csr, r, parent, level, count_bytes=True)
         m_r.append(int(deg[level >= 0].sum().item()) // 2)
         acct.append(st)
+        work.append([g5.level_work(csr, level, lv) for lv in range(st["nlevels"])])
     del deg
     log(f"accounting done: m_r of root 0 = {m_r[0]}, levels {acct[0]['nlevels']}, "
         f"dirs {acct[0]['dir']}")
@@ -314,8 +318,7 @@ def run_gpu(args):
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in roots]
-    samples, step_time = [], {1: 0.0, 2: 0.0}
-    step_bytes, step_launches = {1: 0, 2: 0}, {1: 0, 2: 0}
+    samples = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for step in range(args.steps):
@@ -336,58 +339,95 @@ def run_gpu(args):
     # dispatches slow the whole traversal by ~6 %.
     stats = [g5.bfs(csr, r, parent, level, time_steps=True)[2] for r in roots]
     torch.cuda.synchronize()
-    for st, ac in zip(stats, acct):
-        for lv in range(min(st["nlevels"], len(st["dir"]))):
-            d = st["dir"][lv]
-            step_time[d] += st["step_ms"][lv]
-            step_launches[d] += 1
-            if lv < len(ac["bytes"]) and ac["dir"][lv] == d:
-                step_bytes[d] += ac["bytes"][lv]
-    per_level = [{"level": lv, "dir": "TD" if stats[0]["dir"][lv] == 1 else "BU",
-                  "frontier": stats[0]["frontier"][lv],
-                  "discovered": stats[0]["discovered"][lv],
-                  "alg_bytes": acct[0]["bytes"][lv],
-                  "ms": round(stats[0]["step_ms"][lv], 4)}
-                 for lv in range(min(stats[0]["nlevels"], len(stats[0]["dir"])))]
+    steps = step_table(stats, acct, work, n)
+    log(f"instrumented pass done: {len(steps)} step kernels timed")
+    roofline, per_kernel = roofline_of(steps, scale)
+    per_level = [{k: v for k, v in st.items() if k != "root"} for st in steps
+                 if st["root"] == 0]
     # measured HBM bytes per level of the first root, from the counter runs
     lv_bytes = measured_traffic("root0_levels", f"s{scale}", "levels")
     if lv_bytes and [x["dir"] for x in lv_bytes] == [p["dir"] for p in per_level]:
         for p, x in zip(per_level, lv_bytes):
             p["hbm_bytes"] = x["bytes"]
             p["hbm_gbs"] = round(x["bytes"] / (p["ms"] / 1e3) / 1e9, 1) if p["ms"] else None
-    log(f"instrumented pass done: {step_launches[1]} top-down and {step_launches[2]} "
-        f"bottom-up step kernels timed")
-
-    dom = max(step_time, key=lambda d: step_time[d])
-    name = {1: "td_step", 2: "k_bu_step"}[dom]
-    achieved = step_bytes[dom] / (step_time[dom] / 1e3) / 1e9 if step_time[dom] else 0.0
-    traffic = measured_traffic(name, f"s{scale}")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": name,
-                "launches": step_launches[dom],
-                "avg_launch_ms": round(step_time[dom] / max(step_launches[dom], 1), 4),
-                "alg_bytes_per_launch": int(step_bytes[dom] / max(step_launches[dom], 1))}
-    other = 3 - dom
-    if step_time[other]:
-        roofline["other_step"] = {
-            "kernel": {1: "td_step", 2: "k_bu_step"}[other],
-            "achieved": round(step_bytes[other] / (step_time[other] / 1e3) / 1e9, 1),
-            "time_share": round(step_time[other] / (step_time[1] + step_time[2]), 3),
-            "launches": step_launches[other],
-            "avg_launch_ms": round(step_time[other] / max(step_launches[other], 1), 4),
-            "alg_bytes_per_launch": int(step_bytes[other] / max(step_launches[other], 1))}
-        if other == 1:
-            # measured HBM bytes of the top-down expansions per traversal, spread
-            # over this pass's top-down levels (one launch each)
-            per_trav = measured_traffic("td_step", f"s{scale}", "bytes_per_traversal")
-            roofline["other_step"]["traffic"] = (
-                int(per_trav * len(roots) / step_launches[1])
-                if per_trav is not None and step_launches[1] else None)
     gpu = {"value": hmean(samples) / 1e9, "ms_per_step": wall * 1e3 / args.steps,
            "build_ms": build_ms, "nnz": csr.nnz, "roots": roots, "m_r": m_r,
-           "roofline": roofline, "per_level_root0": per_level}
+           "roofline": roofline, "steps": per_kernel, "per_level_root0": per_level}
     return gpu, csr, parent, level
+
+
+def step_bytes(direction, w, n):
+    """Algorithmic bytes of one step from its level's work counts (g5_level_work):
+    top-down 20|Q| + 4 m_f + 12 claimed; bottom-up 16 U + 4 S + n/4 + 8 claimed."""
+    if direction == 1:
+        return 20 * w["q"] + 4 * w["mf"] + 12 * w["claimed"]
+    return 16 * w["unvisited"] + 4 * w["scanned"] + n // 4 + 8 * w["claimed"]
+
+
+def step_table(stats, acct, work, n):
+    """One row per (root, level): its step kernel, device time (instrumented
+    pass), algorithmic bytes, the library's own byte count, and its share of
+    the traversal's edge work (top-down: frontier edges; bottom-up: row entries
+    read up to the first frontier neighbour)."""
+    rows = []
+    for ri, (st, ac, wk) in enumerate(zip(stats, acct, work)):
+        nl = min(st["nlevels"], len(st["dir"]), len(wk))
+        edge = [wk[lv]["mf"] if st["dir"][lv] == 1 else wk[lv]["scanned"] for lv in range(nl)]
+        total = max(sum(edge), 1)
+        for lv in range(nl):
+            d = st["dir"][lv]
+            kernel = ("k_td_expand" if d == 1 else
+                      "k_bu_step_lds" if (st["lds_mask"] >> lv) & 1 else "k_bu_step")
+            b = step_bytes(d, wk[lv], n)
+            ms = st["step_ms"][lv]
+            rows.append({"root": ri, "level": lv, "dir": "TD" if d == 1 else "BU",
+                         "kernel": kernel, "frontier": st["frontier"][lv],
+                         "discovered": st["discovered"][lv], "edge_work": edge[lv],
+                         "edge_share": round(edge[lv] / total, 4), "ms": round(ms, 4),
+                         "alg_bytes": b,
+                         "lib_bytes": ac["bytes"][lv] if ac["dir"][lv] == d else None,
+                         "frac": round(b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if ms else None})
+    return rows
+
+
+def roofline_of(steps, scale):
+    """The dominant step kernel (largest total device time) against the HBM
+    peak, with every step kernel's totals beside it, over all steps and over
+    the steps that carry at least 1 % of their traversal's edge work."""
+    agg = {}
+    for st in steps:
+        for key in ("all", "ge1pct"):
+            if key == "ge1pct" and st["edge_share"] < 0.01:
+                continue
+            a = agg.setdefault(st["kernel"], {}).setdefault(
+                key, {"launches": 0, "ms": 0.0, "alg_bytes": 0, "lib_bytes": 0})
+            a["launches"] += 1
+            a["ms"] += st["ms"]
+            a["alg_bytes"] += st["alg_bytes"]
+            a["lib_bytes"] += st["lib_bytes"] or 0
+    per_kernel = {}
+    for k, d in agg.items():
+        per_kernel[k] = {}
+        for key, a in d.items():
+            gbs = a["alg_bytes"] / (a["ms"] / 1e3) / 1e9 if a["ms"] else 0.0
+            lgbs = a["lib_bytes"] / (a["ms"] / 1e3) / 1e9 if a["ms"] else 0.0
+            per_kernel[k][key] = {"launches": a["launches"], "ms": round(a["ms"], 3),
+                                  "alg_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                  "lib_gbs": round(lgbs, 1),
+                                  "lib_frac": round(lgbs / HBM_PEAK_GBS, 4)}
+    dom = max(agg, key=lambda k: agg[k]["all"]["ms"])
+    a = agg[dom]["all"]
+    achieved = a["alg_bytes"] / (a["ms"] / 1e3) / 1e9
+    total_ms = sum(x["all"]["ms"] for x in agg.values())
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, f"s{scale}"), "kernel": dom,
+                "launches": a["launches"], "avg_launch_ms": round(a["ms"] / a["launches"], 4),
+                "alg_bytes_per_launch": int(a["alg_bytes"] / a["launches"]),
+                "time_share": round(a["ms"] / total_ms, 3),
+                "lib_bytes_per_launch": int(a["lib_bytes"] / a["launches"]),
+                "lib_frac": round(a["lib_bytes"] / (a["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return roofline, per_kernel
 
 
 def run_alg3_curve(args):
@@ -462,7 +502,7 @@ def run_batch(args):
         return None
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 3
-    seq, bat = [], []
+    seq, bat, bat_lv = [], [], []
     for _ in range(reps):
         torch.cuda.synchronize()
         e0.record()
@@ -476,18 +516,108 @@ def run_batch(args):
         e1.record()
         torch.cuda.synchronize()
         bat.append(e0.elapsed_time(e1) / 1e3)
+        e0.record()
+        g5.bfs_batch(csr, roots, parents=False, levels=levels)
+        e1.record()
+        torch.cuda.synchronize()
+        bat_lv.append(e0.elapsed_time(e1) / 1e3)
     total = sum(m_r)
-    t_seq, t_bat = min(seq), min(bat)
+    t_seq, t_bat, t_lv = min(seq), min(bat), min(bat_lv)
     return {"scale": scale, "roots": 64, "with_parents": True,
             "sequential_gteps": round(total / t_seq / 1e9, 3),
             "batched_gteps": round(total / t_bat / 1e9, 3),
             "ratio": round(t_seq / t_bat, 3), "sequential_ms": round(t_seq * 1e3, 3),
-            "batched_ms": round(t_bat * 1e3, 3)}
+            "batched_ms": round(t_bat * 1e3, 3),
+            "levels_only": {"batched_ms": round(t_lv * 1e3, 3),
+                            "batched_gteps": round(total / t_lv / 1e9, 3),
+                            "ratio": round(t_seq / t_lv, 3)}}
 
 
-def run_cpu(args, gpu_levels):
-    """Oracle timed on the host cores: queue BFS from the first roots of the same
-    graph, on the oracle's own CSR built from the host generator."""
+def run_sssp(args):
+    """Kernel 3 (SSSP by delta-stepping) on a weighted Kronecker graph: per
+    root, device time of g5_sssp (events around the call) and m_r, the
+    distinct edges of the root's component; harmonic mean of m_r / t over the
+    roots.  The first root's distances are checked against the oracle's
+    Dijkstra when --sssp-oracle is given."""
+    import numpy as np
+    import torch
+    import kronecker as K
+    import paper_2012_13548_amd as g5
+    dev = torch.device("cuda:0")
+    scale, n = args.sssp_scale, 1 << args.sssp_scale
+    edges = K.edges_device(scale, args.edgefactor, device=dev)
+    weights = K.weights_device(scale, args.edgefactor, device=dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    csr = g5.build_csr_w(edges, weights, n)
+    e1.record()
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    roots = K.select_roots(K.nonisolated_device(edges, n).cpu().numpy(), args.sssp_roots,
+                           K.root_seed(scale))
+    del edges, weights
+    rp, _ = csr.arrays()
+    deg = rp[1:] - rp[:-1]
+    dist = torch.empty(n, dtype=torch.int32, device=dev)
+    prev = torch.empty(n, dtype=torch.int32, device=dev)
+    m_r, infos = [], []
+    for r in roots:
+        _, _, info = g5.sssp(csr, r, dist, prev, delta=args.sssp_delta, stats=True)
+        m_r.append(int(deg[dist != -1].sum().item()) // 2)
+        infos.append(info)
+    times = []
+    for i, r in enumerate(roots):
+        e0.record()
+        g5.sssp(csr, r, dist, prev, delta=args.sssp_delta)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    teps = [m / t for m, t in zip(m_r, times)]
+    out = {"scale": scale, "roots": len(roots), "weights": "integers 1..255 per tuple",
+           "delta": infos[0]["delta"], "hmean_gteps": round(hmean(teps) / 1e9, 3),
+           "mean_ms": round(1e3 * sum(times) / len(times), 3), "csr_build_ms": round(build_ms, 2),
+           "mean_rounds": round(sum(i["rounds"] for i in infos) / len(infos), 1),
+           "mean_buckets": round(sum(i["buckets"] for i in infos) / len(infos), 1)}
+    if args.sssp_oracle:
+        import oracle as O
+        eh, wh = K.edges_host(scale, args.edgefactor), K.weights_host(scale, args.edgefactor)
+        ocsr = O.build_csr_w(eh, wh, n)
+        del eh, wh
+        g5.sssp(csr, roots[0], dist, prev, delta=args.sssp_delta)
+        od, _, dt = O.sssp_timed(ocsr, roots[0])
+        out["oracle_root0_s"] = round(dt, 3)
+        out["oracle_root0_gteps"] = round(m_r[0] / dt / 1e9, 5)
+        out["dist_equal_oracle"] = bool(np.array_equal(dist.cpu().numpy().view(np.uint32), od))
+    return out
+
+
+def host_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def run_cpu(args, roots, gpu_level_of):
+    """The oracle timed on this host's cores: its single-threaded queue BFS from
+    every root of the same graph, on its own CSR built from the host generator
+    (build untimed), roots spread over P worker threads (P = this host's share
+    of cores, capped by what fits in memory; each call holds its queue, level
+    and parent arrays).  Each root's oracle levels are compared with the GPU's
+    (gpu_level_of(root) -> numpy int32 levels)."""
+    from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import kronecker as K
     import oracle as O
@@ -497,32 +627,44 @@ def run_cpu(args, gpu_levels):
     log("cpu baseline: oracle CSR")
     ocsr = O.build_csr(edges, n)
     del edges
-    roots = gpu_levels["roots"][:args.cpu_roots]
-    teps, secs, equal = [], [], True
-    for i, r in enumerate(roots):
-        _, lev, dt = O.bfs_timed(ocsr, r)
-        mr = O.teps_edges(ocsr, lev)
-        teps.append(mr / dt)
-        secs.append(dt)
-        if i == 0 and gpu_levels.get("level0") is not None:
-            equal = bool(np.array_equal(lev, gpu_levels["level0"]))
-        log(f"cpu baseline: root {r}: {dt:.2f} s, {mr / dt / 1e6:.1f} MTEPS")
-    cpu_model = ""
+    roots = roots[:args.cpu_roots]
+    per_root = 12 * n  # queue, level and parent arrays of one oracle call
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    cpu_model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return {"value": round(hmean(teps) / 1e9, 5), "unit": "GTEPS", "cores": 1,
+        import psutil
+        avail = psutil.virtual_memory().available
+    except ImportError:
+        avail = 64 << 30
+    P = max(1, min(host_threads(), args.cpu_threads or 10 ** 6, len(roots),
+                   int(0.6 * avail // per_root)))
+    log(f"cpu baseline: {len(roots)} roots on {P} threads")
+
+    def one(r):
+        _, lev, dt = O.bfs_timed(ocsr, r)
+        return lev, dt
+
+    secs, teps, mrs, equal = [], [], [], 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(P) as ex:
+        for r, (lev, dt) in zip(roots, ex.map(one, roots)):
+            mr = O.teps_edges(ocsr, lev)
+            secs.append(dt)
+            mrs.append(mr)
+            teps.append(mr / dt)
+            equal += int(np.array_equal(lev, gpu_level_of(r)))
+            log(f"cpu baseline: root {r}: {dt:.2f} s, {mr / dt / 1e6:.1f} MTEPS")
+    wall = time.perf_counter() - t0
+    return {"value": round(hmean(teps) / 1e9, 5), "unit": "GTEPS", "cores": P,
             "kind": "oracle",
-            "sample": f"single-threaded oracle queue BFS from {len(roots)} of the 64 roots of "
-                      f"the same scale-{scale} graph ({sum(secs):.1f} s of BFS; oracle's own CSR "
-                      f"from the host generator, build untimed)",
-            "host_cpu": cpu_model, "host_threads": os.cpu_count(),
-            "levels_equal_gpu": equal}
+            "sample": f"single-threaded oracle queue BFS from each of {len(roots)} roots of the "
+                      f"same scale-{scale} graph, {P} at a time on {P} host threads "
+                      f"({sum(secs):.1f} s of BFS in {wall:.1f} s wall); value = harmonic mean "
+                      f"of per-root TEPS (one core per root); oracle's own CSR from the host "
+                      f"generator, build untimed",
+            "per_root_s": [round(x, 3) for x in secs],
+            "wall_s": round(wall, 2),
+            "aggregate_gteps": round(sum(mrs) / wall / 1e9, 5),
+            "host_cpu": cpu_model(), "host_threads": host_threads(),
+            "levels_equal_gpu": f"{equal}/{len(roots)}"}
 
 
 def main():
@@ -534,8 +676,17 @@ def main():
     ap.add_argument("--edgefactor", type=int, default=16)
     ap.add_argument("--roots", type=int, default=64)
     ap.add_argument("--batch-scale", type=int, default=22)
-    ap.add_argument("--cpu-roots", type=int, default=1)
+    ap.add_argument("--cpu-roots", type=int, default=64,
+                    help="roots of the CPU oracle baseline (default: all 64)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle worker threads (default: this host's share of cores)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sssp", action="store_true")
+    ap.add_argument("--sssp-scale", type=int, default=22)
+    ap.add_argument("--sssp-roots", type=int, default=16)
+    ap.add_argument("--sssp-delta", type=int, default=0)
+    ap.add_argument("--sssp-oracle", action="store_true",
+                    help="check the first SSSP root against the oracle's Dijkstra (slow)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run the counter-calibration copy kernel first")
@@ -573,17 +724,21 @@ def main():
     gpu, csr, parent, level = run_gpu(args)
     import torch
     import paper_2012_13548_amd as g5
-    g5.bfs(csr, gpu["roots"][0], parent, level)
-    level0 = level.cpu().numpy()
-    del csr, parent, level
-    torch.cuda.empty_cache()
     batch = None if args.no_batch else run_batch(args)
     if batch:
         log(f"batch: ratio {batch['ratio']} ({batch['batched_gteps']} vs "
             f"{batch['sequential_gteps']} GTEPS)")
+    sssp = None if args.no_sssp else run_sssp(args)
+    if sssp:
+        log(f"sssp: {sssp}")
     cpu = None
     if not args.no_cpu:
-        cpu = run_cpu(args, {"roots": gpu["roots"], "level0": level0})
+        def gpu_level_of(r):
+            g5.bfs(csr, r, parent, level)
+            return level.cpu().numpy()
+        cpu = run_cpu(args, gpu["roots"], gpu_level_of)
+    del csr, parent, level
+    torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
@@ -609,6 +764,8 @@ def main():
         "cpu_baseline": cpu,
         "csr_build_ms": round(gpu["build_ms"], 2),
         "batch": batch,
+        "sssp": sssp,
+        "step_kernels": gpu["steps"],
         "per_level_root0": gpu["per_level_root0"],
     }
     print(json.dumps(out), flush=True)
