@@ -51,9 +51,12 @@ class Server:
 
     executor must provide ``graphs`` (name -> vertex count), ``footprint(graph,
     k)`` (device bytes one launch of k roots needs while it runs) and
-    ``run(graph, roots, worker) -> (parents [k][n] or None, levels [k][n],
-    m_r list or None)``; ``run`` raises :class:`RangeExceeded` when a batched
-    level does not fit.
+    ``run(graph, roots, worker) -> (parents [k][n] or None, levels [k][n])``,
+    returning once the results are complete; ``run`` raises
+    :class:`RangeExceeded` when a batched level does not fit.  An optional
+    ``edges(graph, level_rows, worker) -> list`` gives each request's traversed
+    edges m_r; it is called after the request's completion time is taken, so
+    the bookkeeping is not part of its latency.
     """
 
     def __init__(self, executor, hbm_budget, workers=4, max_batch=MAX_BATCH,
@@ -174,12 +177,21 @@ class Server:
             for r in reqs:
                 r.t_start = t0
                 r.batch_size = len(reqs)
+            rows = None
             try:
-                self._run(g, reqs, wid)
+                rows = self._run(g, reqs, wid)
             except Exception as e:  # noqa: BLE001 - reported per request
                 for r in reqs:
                     r.error = f"{type(e).__name__}: {e}"
             t1 = self.clock()
+            # TEPS bookkeeping after the completion time: not part of latency
+            if rows is not None and hasattr(self.ex, "edges"):
+                try:
+                    for r, mr in zip(reqs, self.ex.edges(g, [lv for _, lv in rows], wid)):
+                        r.m_r = mr
+                except Exception as e:  # noqa: BLE001 - reported per request
+                    for r in reqs:
+                        r.error = f"{type(e).__name__}: {e}"
             with self.cv:
                 for r in reqs:
                     r.t_done = t1
@@ -189,20 +201,21 @@ class Server:
                 self.cv.notify_all()
 
     def _run(self, g, reqs, wid):
+        """Runs the launch; returns one (parent, level) row per request."""
         roots = [r.root for r in reqs]
         try:
-            parents, levels, m_r = self.ex.run(g, roots, wid)
-            rows = [(None if parents is None else parents[i], levels[i],
-                     None if m_r is None else m_r[i]) for i in range(len(reqs))]
+            parents, levels = self.ex.run(g, roots, wid)
+            rows = [(None if parents is None else parents[i], levels[i])
+                    for i in range(len(reqs))]
         except RangeExceeded:
             rows = []
             for root in roots:
-                p, lv, mr = self.ex.run(g, [root], wid, single=True)
-                rows.append((None if p is None else p[0], lv[0], None if mr is None else mr[0]))
-        for r, (p, lv, mr) in zip(reqs, rows):
-            r.m_r = mr
+                p, lv = self.ex.run(g, [root], wid, single=True)
+                rows.append((None if p is None else p[0], lv[0]))
+        for r, (p, lv) in zip(reqs, rows):
             if self.keep:
                 r.parent, r.level = p, lv
+        return rows
 
     # ------------------------------------------------------------ statistics
     def summary(self, t_first=None, t_last=None):
@@ -264,14 +277,23 @@ class GpuExecutor:
                     if e.status == g5.G5_ERANGE:
                         raise RangeExceeded(str(e)) from e
                     raise
-            m_r = None
-            if graph in self.deg:
-                deg = self.deg[graph]
-                zero = torch.zeros((), dtype=deg.dtype, device=deg.device)
-                m_r = [int(torch.where(levels[i] >= 0, deg, zero).sum().item()) // 2
-                       for i in range(levels.shape[0])]
             self.streams[wid].synchronize()
-        return parents, levels, m_r
+        return parents, levels
+
+    def edges(self, graph, level_rows, wid):
+        """m_r of each level row: half the degree sum of its reached vertices,
+        reduced on the device in groups of rows and read back once."""
+        torch = self.torch
+        if graph not in self.deg:
+            return [None] * len(level_rows)
+        deg = self.deg[graph]
+        with torch.cuda.stream(self.streams[wid]):
+            sums = []
+            for i in range(0, len(level_rows), 8):
+                lv = torch.stack(level_rows[i:i + 8])
+                sums.append(((lv >= 0).to(deg.dtype) * deg[None, :]).sum(dim=1))
+            out = (torch.cat(sums) // 2).tolist()
+        return out
 
 
 def poisson_run(server, graphs, roots_of, rate, count, seed=3000, t_limit=None):

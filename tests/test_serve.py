@@ -41,10 +41,13 @@ class OracleExecutor:
             if (self.range_limit is not None and len(roots) > 1
                     and levels.max() > self.range_limit):
                 raise RangeExceeded("level too deep for a batch")
-            return parents, levels, [O.teps_edges(c, lv) for lv in levels]
+            return parents, levels
         finally:
             with self.lock:
                 self.active -= 1
+
+    def edges(self, g, level_rows, wid):
+        return [O.teps_edges(self.ocsr[g], lv) for lv in level_rows]
 
 
 @pytest.fixture(scope="module")
