@@ -299,6 +299,23 @@ typedef struct {
 g5_status g5_sssp_ex(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, void *stream,
                      const g5_sssp_params *params, g5_sssp_stats *stats);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The same
+ * traversal as g5_bfs_batch (one launch per level, default parameters) with
+ * its workspace (the seen and frontier masks, 32 bytes per vertex, and the
+ * level counters) in a fixed device array inside the library instead of
+ * memory it allocates: 32 * G5_NOALLOC_MAX_N bytes + 4 KiB on each GPU the
+ * library runs on, held until the process ends.  The call allocates nothing;
+ * it reads the level counters back with a device-to-host copy into a host
+ * stack buffer.  Calls on one GPU share the array, so calls that overlap on
+ * one GPU race (serialise them); each call clears what must start at zero.
+ * Arguments, results and errors as g5_bfs_batch, plus G5_EINVAL when the
+ * graph has more than G5_NOALLOC_MAX_N vertices or its device is not the
+ * current device. */
+#define G5_NOALLOC_MAX_N (1 << 20)
+g5_status g5_bfs_batch_noalloc(const g5_csr *g, const int64_t *roots, int32_t k,
+                               int32_t *parents, int8_t *levels, void *stream);
+
 /* Measurement (not part of a traversal): the work that level `lvl` of a
  * finished traversal had to do, computed from its level array alone.  The
  * level array is unique (hop distances), so the counts do not depend on how

@@ -105,6 +105,9 @@ lib.g5_bfs_batch.restype = ctypes.c_int
 lib.g5_bfs_batch_ex.argtypes = [_P, ctypes.POINTER(_I64), ctypes.c_int32, _P, _P, _P,
                                 ctypes.POINTER(BatchParams), ctypes.POINTER(BatchStats)]
 lib.g5_bfs_batch_ex.restype = ctypes.c_int
+lib.g5_bfs_batch_noalloc.argtypes = [_P, ctypes.POINTER(_I64), ctypes.c_int32, _P, _P, _P]
+lib.g5_bfs_batch_noalloc.restype = ctypes.c_int
+NOALLOC_MAX_N = 1 << 20
 lib.g5_build_csr_w.argtypes = [_P, _P, _I64, _I64, _P, _PP]
 lib.g5_build_csr_w.restype = ctypes.c_int
 lib.g5_csr_copy_weights.argtypes = [_P, _P, _P]
@@ -372,3 +375,22 @@ def level_work(csr, level, lvl):
            "g5_level_work")
     return dict(zip(("q", "mf", "claimed", "unvisited", "scanned"), list(out)))
 
+
+def bfs_batch_noalloc(csr, roots, parents=True, levels=None, parent_out=None):
+    """g5_bfs_batch_noalloc: the batched traversal on the library's fixed
+    workspace (graphs of at most NOALLOC_MAX_N vertices); the output tensors
+    are the caller's.  Returns (parents or None, levels)."""
+    import torch
+    k = len(roots)
+    arr = (_I64 * max(k, 1))(*[int(r) for r in roots])
+    if levels is None:
+        levels = torch.empty((k, csr.n), dtype=torch.int8, device=csr.device)
+    if parents and parent_out is None:
+        parent_out = torch.empty((k, csr.n), dtype=torch.int32, device=csr.device)
+    for t, dt in ((levels, torch.int8), (parent_out if parents else None, torch.int32)):
+        if t is not None and (t.dtype != dt or t.numel() < k * csr.n or not t.is_contiguous()):
+            raise ValueError("levels must be contiguous int8 [k, n] and parents int32 [k, n]")
+    pp = parent_out.data_ptr() if parents else None
+    _check(lib.g5_bfs_batch_noalloc(csr.handle, arr, k, pp, levels.data_ptr(),
+                                    _stream(csr.device)), "g5_bfs_batch_noalloc")
+    return (parent_out if parents else None), levels

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.cpp", "csr_build.hip", "bfs.hip", "msbfs.hip", "work.hip", "sssp.hip"]
+SOURCES = ["api.cpp", "csr_build.hip", "bfs.hip", "msbfs.hip", "work.hip", "noalloc.hip", "sssp.hip"]
 LIB = os.path.join(HERE, "libg5.so")
 ALG3_LIB = os.path.join(HERE, "libg5alg3.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

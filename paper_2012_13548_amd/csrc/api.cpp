@@ -197,6 +197,24 @@ g5_status g5_bfs_batch(const g5_csr *g, const int64_t *roots, int32_t k, int32_t
   return g5_bfs_batch_ex(g, roots, k, parents, levels, stream, nullptr, nullptr);
 }
 
+g5_status g5_bfs_batch_noalloc(const g5_csr *g, const int64_t *roots, int32_t k,
+                               int32_t *parents, int8_t *levels, void *stream) {
+  if (!g || !roots || !levels) {
+    set_error("g5_bfs_batch_noalloc: graph, roots and levels must be non-NULL");
+    return G5_EINVAL;
+  }
+  if (k < 1 || k > 64) {
+    set_error("g5_bfs_batch_noalloc: k must be in [1, 64]");
+    return G5_EINVAL;
+  }
+  for (int i = 0; i < k; ++i)
+    if (roots[i] < 0 || roots[i] >= g->n) {
+      set_error("g5_bfs_batch_noalloc: root " + std::to_string(roots[i]) + " outside [0, n)");
+      return G5_EINVAL;
+    }
+  return g5::bfs_batch_noalloc_impl(g, roots, k, parents, levels, (hipStream_t)stream);
+}
+
 g5_status g5_sssp_ex(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, void *stream,
                      const g5_sssp_params *params, g5_sssp_stats *stats) {
   if (!g || !dist || !prev) {

@@ -214,6 +214,8 @@ g5_status bfs_batch_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *
 size_t batch_ctl_bytes();
 g5_status batch_in_workspace(const g5_csr *g, uint64_t *masks, void *ctl, const int64_t *roots,
                              int k, int32_t *parents, int8_t *levels, hipStream_t s);
+g5_status bfs_batch_noalloc_impl(const g5_csr *g, const int64_t *roots, int k, int32_t *parents,
+                                 int8_t *levels, hipStream_t s);
 g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, hipStream_t s,
                     const g5_sssp_params &p, g5_sssp_stats *stats);
 g5_status level_work_impl(const g5_csr *g, const int32_t *level, int32_t lvl, int64_t *out,
