@@ -124,13 +124,19 @@ def _per_dispatch_map(rows, counter, match):
     return per
 
 
-def is_bu_step(name):
-    """The bottom-up step kernels of the timed steps and the instrumented pass
-    (with or without the LDS-staged summary; not the byte-counting variants,
-    whose third template argument is true)."""
+def step_kernel_of(name):
+    """The step kernel a dispatch belongs to (k_bu_step, k_bu_step_lds or
+    k_td_expand), or None; the byte-counting variants of the bottom-up steps
+    (third template argument true) belong to none."""
     import re
-    m = re.search(r"k_bu_step(?:_lds)?<\d+, \d+, (true|false)", name)
-    return bool(m) and m.group(1) == "false"
+    m = re.search(r"k_bu_step(_lds)?<\d+, \d+, (true|false)", name)
+    if m:
+        return None if m.group(2) == "true" else ("k_bu_step_lds" if m.group(1) else "k_bu_step")
+    return "k_td_expand" if "k_td_expand<" in name else None
+
+
+def is_bu_step(name):
+    return step_kernel_of(name) in ("k_bu_step", "k_bu_step_lds")
 
 
 # A bottom-up step queued ahead of the host's decision exits at once when the
@@ -138,34 +144,70 @@ def is_bu_step(name):
 # reads and writes the visited and next-frontier words).
 NOOP_KIB = 1024.0
 NOOP_US = 10.0
+# request-size split of the reads that leave L2 (FETCH_SIZE is derived from
+# these: 128 B per TCC_BUBBLE, 32 B per TCC_EA0_RDREQ_32B, 64 B for the rest)
+SPLIT_COUNTERS = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum")
 
 
-def reduce_pmc(fetch_dir, write_dir, kernel, workload, command, path=TRAFFIC_PATH):
-    """Calibrated HBM bytes per launch of `kernel` from a FETCH_SIZE run and a
-    WRITE_SIZE run; each counter is scaled by what it reads for the copy probe
-    (known bytes).  Stored in profiles/traffic.json with the kernel source hash,
-    so the bench reports it only while the kernel is unchanged."""
+def reduce_pmc(fetch_dir, write_dir, split_dir, workload, command, path=TRAFFIC_PATH):
+    """HBM bytes per working launch of each bottom-up step kernel (and per
+    traversal of the top-down expansions) from a FETCH_SIZE run, a WRITE_SIZE
+    run and a run of the read-request counters split by size.  Each of
+    FETCH_SIZE and WRITE_SIZE is scaled by what it reads for the copy probe
+    (known bytes); the raw counter values and the request split are kept
+    beside.  Stored in profiles/traffic.json with the kernel source hash, so
+    the bench reports them only while the kernels are unchanged."""
     # the copy probe: torch's elementwise add over 2 GiB, the largest such dispatch
     is_copy = lambda name: "elementwise_kernel" in name and "_add<long>" in name
-    assert kernel == "k_bu_step", "counters are reduced for the bottom-up step"
     fr, wr = _pmc_rows(fetch_dir), _pmc_rows(write_dir)
+    sr = _pmc_rows(split_dir) if split_dir else []
     copy_f, _ = _per_dispatch(fr, "FETCH_SIZE", is_copy, largest=True)
     copy_w, _ = _per_dispatch(wr, "WRITE_SIZE", is_copy, largest=True)
-    k_f, nf = _per_dispatch(fr, "FETCH_SIZE", is_bu_step, min_kib=NOOP_KIB)
-    k_w, nw = _per_dispatch(wr, "WRITE_SIZE", is_bu_step, min_kib=NOOP_KIB)
     f_factor = COPY_PROBE_BYTES / (copy_f * 1024)
     w_factor = COPY_PROBE_BYTES / (copy_w * 1024)
-    rec = {"source_hash": source_hash(BFS_SOURCES),
-           "bytes_per_launch": int(k_f * 1024 * f_factor + k_w * 1024 * w_factor),
-           "fetch_bytes_per_launch": int(k_f * 1024 * f_factor),
-           "write_bytes_per_launch": int(k_w * 1024 * w_factor),
-           "fetch_factor": round(f_factor, 4), "write_factor": round(w_factor, 4),
-           "launches": [nf, nw], "command": command}
+    h = source_hash(BFS_SOURCES)
     data = {}
     if os.path.exists(path):
         with open(path) as f:
             data = json.load(f)
-    data[f"{kernel}@{workload}"] = rec
+
+    def split_of(match, keys=None):
+        out = {}
+        for c in SPLIT_COUNTERS:
+            per = _per_dispatch_map(sr, c, match)
+            if keys is not None:
+                per = {k: v for k, v in per.items() if k in keys}
+            out[c] = int(sum(per.values()) / max(len(per), 1)) if per else None
+        if sr and copy_split:
+            out["copy_probe"] = copy_split
+        return out
+
+    copy_split = {}
+    if sr:
+        for c in SPLIT_COUNTERS:
+            per = _per_dispatch_map(sr, c, is_copy)
+            copy_split[c] = int(max(per.values())) if per else None
+    recs = []
+    for kernel in ("k_bu_step", "k_bu_step_lds"):
+        match = (lambda k: (lambda name: step_kernel_of(name) == k))(kernel)
+        fm = {k: v for k, v in _per_dispatch_map(fr, "FETCH_SIZE", match).items() if v > NOOP_KIB}
+        wm = _per_dispatch_map(wr, "WRITE_SIZE", match)
+        wm = {k: v for k, v in wm.items() if k in fm}
+        if not fm:
+            continue
+        kf = sum(fm.values()) / len(fm)
+        kw = sum(wm.values()) / max(len(wm), 1)
+        rec = {"source_hash": h,
+               "bytes_per_launch": int(kf * 1024 * f_factor + kw * 1024 * w_factor),
+               "fetch_bytes_per_launch": int(kf * 1024 * f_factor),
+               "write_bytes_per_launch": int(kw * 1024 * w_factor),
+               "raw_bytes_per_launch": int((kf + kw) * 1024),
+               "fetch_factor": round(f_factor, 4), "write_factor": round(w_factor, 4),
+               "launches": [len(fm), len(wm)],
+               "read_requests_per_launch": split_of(match, set(fm)) if sr else None,
+               "command": command}
+        data[f"{kernel}@{workload}"] = rec
+        recs.append((kernel, rec))
 
     # The top-down expansion: its launches include those queued ahead that did
     # nothing and, once per traversal, the one that finishes it (widens the
@@ -174,7 +216,7 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command, path=TRAFFIC_PAT
     # execute the same program, so dispatch ids match between them; the
     # record is the traffic of the real expansions per traversal (the bench
     # divides it by its own count of top-down levels per traversal).
-    is_td = lambda name: "k_td_expand<" in name
+    is_td = lambda name: step_kernel_of(name) == "k_td_expand"
     tf = _per_dispatch_map(fr, "FETCH_SIZE", is_td)
     tw = _per_dispatch_map(wr, "WRITE_SIZE", is_td)
     if set(tf) != set(tw):
@@ -189,13 +231,16 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command, path=TRAFFIC_PAT
               if tw[k] * 1024 * w_factor >= 0.9 * 4 * n and tf[k] * f_factor < tw[k] * w_factor}
     td_f = sum(v for k, v in tf.items() if k not in ending) * 1024 * f_factor
     td_w = sum(v for k, v in tw.items() if k not in ending) * 1024 * w_factor
-    td = {"source_hash": rec["source_hash"],
+    td_raw = (sum(v for k, v in tf.items() if k not in ending)
+              + sum(v for k, v in tw.items() if k not in ending)) * 1024
+    td = {"source_hash": h,
           "bytes_per_traversal": int((td_f + td_w) / inits),
           "fetch_bytes_per_traversal": int(td_f / inits),
           "write_bytes_per_traversal": int(td_w / inits),
+          "raw_bytes_per_traversal": int(td_raw / inits),
           "traversals": inits, "dispatches": len(tf), "finishing_dispatches": len(ending),
           "command": command}
-    data[f"td_step@{workload}"] = td
+    data[f"k_td_expand@{workload}"] = td
 
     # Per level: the run's last traversal of the workload graph is a plain one
     # from the benchmark's first root.  Its step kernels in dispatch order are
@@ -211,19 +256,22 @@ def reduce_pmc(fetch_dir, write_dir, kernel, workload, command, path=TRAFFIC_PAT
         if not (is_td(name) or is_bu_step(name)) or wa.get(k, 0.0) <= 0 or k in ending:
             continue
         levels.append({"dir": "TD" if is_td(name) else "BU",
-                       "bytes": int(fa[k] * 1024 * f_factor + wa[k] * 1024 * w_factor)})
-    data[f"root0_levels@{workload}"] = {"source_hash": rec["source_hash"], "levels": levels,
-                                        "command": command}
+                       "bytes": int(fa[k] * 1024 * f_factor + wa[k] * 1024 * w_factor),
+                       "raw_bytes": int((fa[k] + wa[k]) * 1024)})
+    data[f"root0_levels@{workload}"] = {"source_hash": h, "levels": levels, "command": command}
+    data.pop("k_bu_step_all@" + workload, None)
+    data.pop("td_step@" + workload, None)
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
-    print(json.dumps(rec))
+    for kernel, rec in recs:
+        print(kernel, json.dumps(rec))
     print(json.dumps(td))
     print(json.dumps(levels))
 
 
 def summarize_trace(db, command, bench_json=None):
     """Markdown summary of a rocprofv3 kernel trace (its SQLite database): the
-    busiest kernels, and the bottom-up step's average over working launches,
+    busiest kernels, and each step kernel's average over working launches,
     which is what the bench's avg_launch_ms measures with HIP events."""
     import re
     import sqlite3
@@ -248,18 +296,29 @@ def summarize_trace(db, command, bench_json=None):
            "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
     for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:24]:
         out.append(f"| `{k}` | {n} | {t:.1f} | {t / n:.2f} | {100 * t / total:.1f} |")
-    bu = [(t1 - t0) / 1e3 for name, t0, t1 in rows if is_bu_step(name)]
-    work = [d for d in bu if d > NOOP_US]
-    out += ["", "## Bottom-up step (k_bu_step and k_bu_step_lds, without byte counting)", "",
-            f"* dispatches: {len(bu)}, of which {len(bu) - len(work)} are steps queued ahead "
-            f"that exited at once (< {NOOP_US:.0f} us)",
-            f"* working dispatches: {len(work)}, average {sum(work) / max(len(work), 1):.2f} us"]
+    bench = None
     if bench_json:
         with open(bench_json) as f:
             line = [l for l in f if l.startswith("{")][-1]
-        r = json.loads(line)["roofline"]
-        out.append(f"* the same run's bench line: kernel {r['kernel']}, {r['launches']} timed "
-                   f"launches, avg_launch_ms {r['avg_launch_ms']} (HIP events)")
+        bench = json.loads(line)
+    for kernel in ("k_bu_step", "k_bu_step_lds"):
+        d = [(t1 - t0) / 1e3 for name, t0, t1 in rows if step_kernel_of(name) == kernel]
+        work = [x for x in d if x > NOOP_US]
+        out += ["", f"## {kernel} (timed variant, without byte counting)", "",
+                f"* dispatches: {len(d)}, of which {len(d) - len(work)} are steps queued ahead "
+                f"that exited at once (< {NOOP_US:.0f} us)",
+                f"* working dispatches: {len(work)}, average {sum(work) / max(len(work), 1):.2f} us"]
+        if bench:
+            r = bench["roofline"]
+            if r.get("kernel") == kernel:
+                out.append(f"* the same run's bench line: dominant kernel {kernel}, "
+                           f"{r['launches']} instrumented launches, avg_launch_ms "
+                           f"{r['avg_launch_ms']} (HIP events)")
+            elif kernel in bench.get("step_kernels", {}):
+                a = bench["step_kernels"][kernel]["all"]
+                out.append(f"* the same run's bench line: {a['launches']} instrumented launches, "
+                           f"{a['ms']} ms in all, avg {a['ms'] / max(a['launches'], 1):.4f} ms "
+                           f"(HIP events)")
     print("\n".join(out))
 
 
@@ -422,6 +481,8 @@ def roofline_of(steps, scale):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom, f"s{scale}"), "kernel": dom,
+                "traffic_raw": measured_traffic(dom, f"s{scale}", "raw_bytes_per_launch"),
+                "read_requests": measured_traffic(dom, f"s{scale}", "read_requests_per_launch"),
                 "launches": a["launches"], "avg_launch_ms": round(a["ms"] / a["launches"], 4),
                 "alg_bytes_per_launch": int(a["alg_bytes"] / a["launches"]),
                 "time_share": round(a["ms"] / total_ms, 3),
@@ -502,7 +563,8 @@ def run_batch(args):
         return None
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 3
-    seq, bat, bat_lv = [], [], []
+    seq, bat, bat_lv, bat_g = [], [], [], []
+    g5.bfs_batch(csr, roots, levels=levels, parent_out=parents, graph=True)  # instantiate
     for _ in range(reps):
         torch.cuda.synchronize()
         e0.record()
@@ -521,6 +583,11 @@ def run_batch(args):
         e1.record()
         torch.cuda.synchronize()
         bat_lv.append(e0.elapsed_time(e1) / 1e3)
+        e0.record()
+        g5.bfs_batch(csr, roots, levels=levels, parent_out=parents, graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        bat_g.append(e0.elapsed_time(e1) / 1e3)
     total = sum(m_r)
     t_seq, t_bat, t_lv = min(seq), min(bat), min(bat_lv)
     return {"scale": scale, "roots": 64, "with_parents": True,
@@ -530,7 +597,9 @@ def run_batch(args):
             "batched_ms": round(t_bat * 1e3, 3),
             "levels_only": {"batched_ms": round(t_lv * 1e3, 3),
                             "batched_gteps": round(total / t_lv / 1e9, 3),
-                            "ratio": round(t_seq / t_lv, 3)}}
+                            "ratio": round(t_seq / t_lv, 3)},
+            "graph_replays": {"batched_ms": round(min(bat_g) * 1e3, 3),
+                              "ratio": round(t_seq / min(bat_g), 3)}}
 
 
 def run_sssp(args):
@@ -690,8 +759,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run the counter-calibration copy kernel first")
-    ap.add_argument("--reduce-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--reduce-pmc", nargs="+", metavar="DIR",
+                    help="write profiles/traffic.json from rocprofv3 --pmc runs (FETCH_SIZE dir, "
+                         "WRITE_SIZE dir, optionally the request-split dir) and exit")
     ap.add_argument("--pmc-command", default="", help="command recorded with --reduce-pmc")
     ap.add_argument("--summarize-trace", nargs="+", metavar=("DB", "BENCH_JSON"),
                     help="print a markdown summary of a rocprofv3 kernel-trace database")
@@ -710,7 +780,8 @@ def main():
                         args.summarize_trace[1] if len(args.summarize_trace) > 1 else None)
         return
     if args.reduce_pmc:
-        reduce_pmc(args.reduce_pmc[0], args.reduce_pmc[1], "k_bu_step", f"s{args.scale}",
+        reduce_pmc(args.reduce_pmc[0], args.reduce_pmc[1],
+                   args.reduce_pmc[2] if len(args.reduce_pmc) > 2 else None, f"s{args.scale}",
                    args.pmc_command)
         return
     if args.gpus != 1:

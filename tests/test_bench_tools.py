@@ -48,17 +48,38 @@ def test_reduce_pmc(tmp_path):
              (2, INIT, 1 << 20, [10]), (3, INIT, 1 << 20, [10]), (4, INIT, 256, [1]),
              (5, BU, 99, [1500]), (6, BU, 99, [2500]), (7, BU, 99, [0]), (8, BU_ACCT, 99, [9e6]),
              (9, TD, 99, [50]), (10, TD, 99, [70]), (11, TD, 99, [4])]  # 11 finishes a traversal
+    fetch += [(12, BU_LDS, 99, [8000])]
+    write += [(12, BU_LDS, 99, [3000])]
+    split = [(1, COPY, 8, [100]), (5, BU, 99, [40]), (6, BU, 99, [60]), (7, BU, 99, [1]),
+             (12, BU_LDS, 99, [70])]
     write_run(str(tmp_path / "f"), "FETCH_SIZE", fetch)
     write_run(str(tmp_path / "w"), "WRITE_SIZE", write)
+    for c in bench.SPLIT_COUNTERS:
+        write_run(str(tmp_path / "s" / c), c, split)
+    # the three split counters in one run directory
+    rows = []
+    for c in bench.SPLIT_COUNTERS:
+        rows += list(csv.reader(open(str(tmp_path / "s" / c / "host" /
+                                         "run_counter_collection.csv"))))[1:]
+    os.makedirs(str(tmp_path / "sp" / "host"))
+    with open(str(tmp_path / "sp" / "host" / "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(HEAD)
+        w.writerows(rows)
     out = str(tmp_path / "traffic.json")
-    bench.reduce_pmc(str(tmp_path / "f"), str(tmp_path / "w"), "k_bu_step", "s10", "cmd", path=out)
+    bench.reduce_pmc(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "sp"), "s10", "cmd",
+                     path=out)
     data = json.load(open(out))
-    bu, td = data["k_bu_step@s10"], data["td_step@s10"]
+    bu, td, lds = data["k_bu_step@s10"], data["k_td_expand@s10"], data["k_bu_step_lds@s10"]
     assert bu["fetch_factor"] == 2.0 and bu["write_factor"] == 1.0
     # working bottom-up dispatches only: (2000 + 4000) / 2 KiB fetched, x2; (1500 + 2500) / 2 written
     assert bu["fetch_bytes_per_launch"] == 6000 * KIB
     assert bu["write_bytes_per_launch"] == 2000 * KIB
     assert bu["bytes_per_launch"] == 8000 * KIB and bu["launches"] == [2, 2]
+    assert bu["raw_bytes_per_launch"] == (3000 + 2000) * KIB
+    assert bu["read_requests_per_launch"]["TCC_EA0_RDREQ_sum"] == 50  # (40 + 60) / 2
+    assert bu["read_requests_per_launch"]["copy_probe"]["TCC_EA0_RDREQ_sum"] == 100
+    assert lds["bytes_per_launch"] == (2 * 8000 + 3000) * KIB and lds["launches"] == [1, 1]
     # two traversals of the workload graph (the small-grid init is a warm-up); the
     # finishing dispatch (writes >= 4n bytes, fetches less) is left out
     assert td["traversals"] == 2 and td["finishing_dispatches"] == 1 and td["dispatches"] == 3
@@ -66,15 +87,16 @@ def test_reduce_pmc(tmp_path):
     assert td["write_bytes_per_traversal"] == (50 + 70) * KIB // 2
     assert td["source_hash"] == bench.source_hash(bench.BFS_SOURCES)
     assert bench.measured_traffic("k_bu_step", "s10", path=out) == 8000 * KIB
-    assert bench.measured_traffic("td_step", "s10", "bytes_per_traversal", path=out) == \
+    assert bench.measured_traffic("k_td_expand", "s10", "bytes_per_traversal", path=out) == \
         td["bytes_per_traversal"]
     assert bench.measured_traffic("k_bu_step", "s26", path=out) is None
     # the last workload traversal's levels: working step dispatches in order, without
     # the queued-ahead step (writes nothing), the byte-counting variant and the finish
     levels = bench.measured_traffic("root0_levels", "s10", "levels", path=out)
-    assert [x["dir"] for x in levels] == ["BU", "BU", "TD", "TD"]
+    assert [x["dir"] for x in levels] == ["BU", "BU", "TD", "TD", "BU"]
     assert [x["bytes"] for x in levels] == [(2 * 2000 + 1500) * KIB, (2 * 4000 + 2500) * KIB,
-                                            (2 * 100 + 50) * KIB, (2 * 300 + 70) * KIB]
+                                            (2 * 100 + 50) * KIB, (2 * 300 + 70) * KIB,
+                                            (2 * 8000 + 3000) * KIB]
 
 
 def test_traffic_gated_by_source_hash(tmp_path):
@@ -98,13 +120,16 @@ def test_summarize_trace(tmp_path, capsys):
     c.executemany("insert into kernels values (?, ?, ?)", rows)
     c.commit()
     c.close()
-    line = {"roofline": {"kernel": "k_bu_step", "launches": 3, "avg_launch_ms": 0.2}}
+    line = {"roofline": {"kernel": "k_bu_step", "launches": 3, "avg_launch_ms": 0.2},
+            "step_kernels": {"k_bu_step_lds": {"all": {"launches": 1, "ms": 0.3}}}}
     bj = str(tmp_path / "bench.json")
     open(bj, "w").write("progress\n" + json.dumps(line) + "\n")
     bench.summarize_trace(db, "the command", bj)
     md = capsys.readouterr().out
     assert "the command" in md
-    assert "* dispatches: 4, of which 1 are steps queued ahead" in md
-    assert "* working dispatches: 3, average 200.00 us" in md
+    assert "* dispatches: 3, of which 1 are steps queued ahead" in md
+    assert "* working dispatches: 2, average 150.00 us" in md
+    assert "* working dispatches: 1, average 300.00 us" in md
     assert "avg_launch_ms 0.2" in md
     assert "| `k_bu_step<8, 1, false>` | 3 | 303.0 | 101.00 |" in md
+    assert "## k_bu_step_lds" in md and "1 instrumented launches, 0.3 ms" in md
