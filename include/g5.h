@@ -208,7 +208,8 @@ typedef struct {
   int32_t lds_shift;                        /* log2 vertices per staged bit (0: exact bitmap) */
   int64_t lds_mask;                         /* bit i (i < 64): level i's bottom-up step staged the
                                                frontier in LDS */
-  int64_t reserved[4];
+  int64_t heavy_mask;                       /* bit i (i < 64): level i was a heavy top-down level */
+  int64_t reserved[3];
 } g5_bfs_stats;
 
 /* g5_bfs with explicit parameters (NULL = defaults) and optional statistics
@@ -291,7 +292,8 @@ typedef struct {
   int64_t relaxed;  /* queue entries relaxed (a vertex counts once per round it is in) */
   int64_t delta;    /* bucket width used */
   double ms;        /* device time of the call (G5_FLAG_TIME_STEPS) */
-  int64_t reserved[4];
+  int64_t edges;    /* edges relaxed (the rows of the relaxed queue entries) */
+  int64_t reserved[3];
 } g5_sssp_stats;
 
 /* g5_sssp with explicit parameters (NULL = defaults) and statistics (NULL =

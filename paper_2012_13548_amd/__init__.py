@@ -68,7 +68,8 @@ class BfsStats(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("bu_lane_scan", ctypes.c_int32), ("bu_blocks_per_cu", ctypes.c_int32),
                 ("lds_levels", ctypes.c_int32), ("lds_shift", ctypes.c_int32),
-                ("lds_mask", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
+                ("lds_mask", ctypes.c_int64), ("heavy_mask", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 3)]
 
 
 class BatchParams(ctypes.Structure):
@@ -123,7 +124,7 @@ class SsspStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("scans", ctypes.c_int64),
                 ("buckets", ctypes.c_int64), ("relaxed", ctypes.c_int64),
                 ("delta", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("reserved", ctypes.c_int64 * 4)]
+                ("edges", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
 
 
 lib.g5_sssp.argtypes = [_P, _I64, _P, _P, _P]
@@ -256,7 +257,8 @@ def sssp(csr, src, dist=None, prev=None, delta=None, stats=False, time_call=Fals
            "g5_sssp")
     if not want:
         return dist, prev
-    info = {k: getattr(st, k) for k in ("rounds", "scans", "buckets", "relaxed", "delta", "ms")}
+    info = {k: getattr(st, k) for k in ("rounds", "scans", "buckets", "relaxed", "edges", "delta",
+                                        "ms")}
     return dist, prev, info
 
 
@@ -316,7 +318,8 @@ def bfs(csr, root, parent=None, level=None, direction=DIR_AUTO, alpha=None, beta
     info = {"nlevels": st.nlevels, "reached": st.reached, "alpha": st.alpha, "beta": st.beta,
             "lane_scan": st.bu_lane_scan, "blocks_per_cu": st.bu_blocks_per_cu,
             "lds_levels": st.lds_levels, "lds_shift": st.lds_shift,
-            "lds_mask": st.lds_mask & ((1 << 64) - 1)}
+            "lds_mask": st.lds_mask & ((1 << 64) - 1),
+            "heavy_mask": st.heavy_mask & ((1 << 64) - 1)}
     for k in ("dir", "frontier", "discovered", "edges", "bytes", "step_ms"):
         info[k] = list(getattr(st, k)[:nl])
     return parent, level, info

@@ -1815,6 +1815,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
         stats->frontier[i] = qlen;
         stats->edges[i] = mf;
         heavy_lv[i] = hc[C_HEAVY] != 0;  // the device's flag for this level
+        if (heavy_lv[i] && i < 64) stats->heavy_mask |= (int64_t)(1ull << i);
       }
       cur = nxt;
       last_nf = qlen;

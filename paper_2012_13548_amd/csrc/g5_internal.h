@@ -88,6 +88,7 @@ struct SsspWork {
   uint64_t *pend = nullptr;   // far set: vertices improved at or above the threshold
   uint32_t *stamp = nullptr;  // per vertex: the stamp of the last queue it joined
   int32_t *q[2] = {nullptr, nullptr};  // current and next queue
+  uint32_t *qo[2] = {nullptr, nullptr}; // per entry: its first edge in the queue's edge list
   uint64_t *ctr = nullptr;    // device counters (SCtr in sssp.hip)
   uint32_t epoch = 0;         // last queue stamp handed out (only grows)
   hipEvent_t ev[2] = {nullptr, nullptr};

@@ -16,8 +16,11 @@
 //   predecessors  one pass at the end: prev[v] = the smallest-id neighbour u
 //                 with dist[u] + w(u, v) = dist[v] (so prev is deterministic)
 //
-// Rows longer than kHubDeg are relaxed in kHubChunk-edge pieces spread over
-// all wavefronts (the hub list of Kernel 1); the main loop skips them.
+// Relaxations are edge-balanced: every queue entry carries the index of its
+// first edge in the queue's edge list (assigned when it was appended, from one
+// packed atomic per wavefront), and each workgroup takes 1,024-edge tiles of
+// that list in turn, so hub rows are split across workgroups and short rows
+// are packed together.
 #include <algorithm>
 
 #include "g5_internal.h"
@@ -26,33 +29,59 @@ namespace g5 {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kLaneRow = 32;  // rows up to this length are relaxed by one lane
+constexpr int kItems = 4;
+constexpr int kTile = kBlock * kItems;  // edges per relaxation tile
 constexpr uint32_t kInf = 0xffffffffu;
 // Bucket width when the caller gives none: weights lie in [1, 255] for the
-// seeded graphs, with tens of edges per vertex.
+// seeded graphs, with tens of edges per vertex (a sweep at scale 22 over
+// 4..2^20: 16 and 32 within 4 %, 8 and 64 10-20 % slower).
 constexpr uint32_t kDefaultDelta = 32;
 
 enum SCtr : int {
-  S_QLEN0 = 0,  // length of queue 0
-  S_QLEN1 = 1,  // length of queue 1
+  S_QP0 = 0,    // queue 0: entries << 32 | edges (appended to by one atomic per wavefront)
+  S_QP1 = 1,    // queue 1: the same
   S_PEND = 2,   // pending vertices left after a scan
   S_MIN = 3,    // smallest distance among them (kInf if none)
-  S_ERR = 4,    // a distance exceeded kInf - 1
+  S_ERR = 4,    // 1: a distance exceeded kInf - 1; 2: a reached vertex without a tight edge
   S_RELAX = 5,  // queue entries relaxed (statistics)
-  S_N = 8
+  S_EDGES = 6,  // edges relaxed (statistics)
+  S_DONE = 7,   // 1: no queue and no pending vertex left (read by the host)
+  S_ROUNDS = 8,   // relaxation steps (statistics)
+  S_SCANS = 9,    // scan steps (statistics)
+  S_BUCKETS = 10, // thresholds used (statistics)
+  S_EPOCH = 11,   // last queue stamp handed out (read back by the host)
+  S_TICK0 = 12,   // step tickets, by step parity (S_TICK0 + (j & 1))
+  S_ST0 = 16,     // step state, by step parity: S_ST0 + (j & 1) * kStSlots + ST_*
+  S_N = 32
 };
+// Per-step state.  Step j reads the slots of parity j & 1, which only step
+// j - 1 (finished before j starts) and step j + 1 (which starts after j ends)
+// write, so a workgroup of step j that starts late still sees its step's state.
+enum StSlot : int { ST_QP = 0, ST_CUR = 1, ST_T = 2, ST_EP = 3, ST_DONE = 4 };
+constexpr int kStSlots = 8;
 
-// Pushes v (one lane each) onto a queue: one atomic per wavefront.
-__device__ __forceinline__ void push_wave(bool want, int32_t v, int32_t *q,
-                                          unsigned long long *len) {
+// Appends v (one lane each) to a queue with its first-edge index: a wave
+// prefix sum of the degrees and one atomic on the queue's packed counter
+// (entries << 32 | edges) per wavefront.  Called by every lane of the wave.
+__device__ __forceinline__ void push_wave(bool want, int32_t v, const int64_t *__restrict__ rp,
+                                          int32_t *__restrict__ q, uint32_t *__restrict__ qo,
+                                          unsigned long long *pack) {
   const uint64_t m = __ballot(want);
   if (!m) return;
   const int lane = __lane_id();
+  const uint32_t deg = want ? (uint32_t)(rp[v + 1] - rp[v]) : 0u;
+  const uint32_t inc = wave_incl_scan(deg);
+  const uint32_t tot = __shfl(inc, kWave - 1, kWave);
   const int leader = __ffsll((unsigned long long)m) - 1;
   unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(len, (unsigned long long)__popcll(m));
+  if (lane == leader)
+    base = atomicAdd(pack, ((unsigned long long)__popcll(m) << 32) | (unsigned long long)tot);
   base = __shfl(base, leader, kWave);
-  if (want) q[base + __popcll(m & lanemask_lt())] = v;
+  if (want) {
+    const uint64_t pos = (base >> 32) + (uint64_t)__popcll(m & lanemask_lt());
+    q[pos] = v;
+    qo[pos] = (uint32_t)base + inc - deg;
+  }
 }
 
 struct RelaxArgs {
@@ -62,7 +91,8 @@ struct RelaxArgs {
   uint32_t *dist;
   uint64_t *pend;
   uint32_t *stamp;
-  int32_t *qn;
+  int32_t *qn;   // next queue
+  uint32_t *qon; // its first-edge indices
   unsigned long long *ctr;
   int nxt;
   uint64_t T;
@@ -90,7 +120,8 @@ __device__ __forceinline__ bool relax(const RelaxArgs &a, uint32_t du, int32_t v
 // {src} with the stamp of the first queue; counters zeroed.
 __global__ void k_sssp_init(uint32_t *__restrict__ dist, int64_t n, int64_t src,
                             uint64_t *__restrict__ pend, int64_t words, int32_t *__restrict__ q0,
-                            uint32_t *__restrict__ stamp, uint32_t epoch,
+                            uint32_t *__restrict__ qo0, const int64_t *__restrict__ rp,
+                            uint32_t *__restrict__ stamp, uint32_t epoch, uint64_t delta,
                             unsigned long long *__restrict__ ctr) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -98,116 +129,124 @@ __global__ void k_sssp_init(uint32_t *__restrict__ dist, int64_t n, int64_t src,
   for (int64_t i = t; i < words; i += stride) pend[i] = 0;
   if (t == 0) {
     for (int i = 0; i < S_N; ++i) ctr[i] = 0;
-    ctr[S_QLEN0] = 1;
+    unsigned long long *st = ctr + S_ST0;  // step 0's state: queue 0 = {src}
+    st[ST_QP] = (1ull << 32) | (unsigned long long)(rp[src + 1] - rp[src]);
+    st[ST_CUR] = 0;
+    st[ST_T] = delta;
+    st[ST_EP] = epoch + 1;
     ctr[S_MIN] = kInf;
+    ctr[S_BUCKETS] = 1;
+    ctr[S_EPOCH] = epoch + 1;
     q0[0] = (int32_t)src;
+    qo0[0] = 0;
     stamp[src] = epoch;
   }
 }
 
-// One relaxation round over queue `cur` (its length in ctr); fills queue nxt.
-__global__ __launch_bounds__(kBlock) void k_sssp_relax(const int32_t *__restrict__ q, int cur,
-                                                       RelaxArgs a) {
-  const int lane = __lane_id();
-  const int64_t qlen = (int64_t)a.ctr[S_QLEN0 + cur];
-  const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
-  unsigned long long *nlen = a.ctr + S_QLEN0 + a.nxt;
-  for (int64_t base = gw * kWave; base < qlen; base += nw * kWave) {
-    const int64_t i = base + lane;
-    int32_t u = -1;
-    int64_t b = 0, e = 0;
-    uint32_t du = kInf;
-    if (i < qlen) {
-      u = q[i];
-      b = a.rp[u];
-      e = a.rp[u + 1];
-      du = a.dist[u];
-      // u is relaxed now: it leaves the far set if it was there
-      const uint64_t bit = 1ull << (u & 63);
-      if (a.pend[u >> 6] & bit) atomicAnd((unsigned long long *)(a.pend + (u >> 6)), ~bit);
-    }
-    const int64_t d = e - b;
-    // short rows: one lane each; the queue pushes stay wave-uniform
-    int64_t k = b;
-    const bool mine = u >= 0 && d <= kLaneRow;
-    while (__ballot(mine && k < e)) {
-      bool push = false;
-      int32_t v = 0;
-      if (mine && k < e) {
-        v = a.ci[k];
-        push = relax(a, du, v, a.wt[k]);
-        ++k;
-      }
-      push_wave(push, v, a.qn, nlen);
-    }
-    // longer rows (not hubs): the whole wavefront, one row at a time
-    uint64_t rem = __ballot(u >= 0 && d > kLaneRow && d <= kHubDeg);
-    while (rem) {
-      const int L = __ffsll((unsigned long long)rem) - 1;
-      rem &= rem - 1;
-      const int64_t kb = __shfl(b, L, kWave), ke = __shfl(e, L, kWave);
-      const uint32_t dL = __shfl(du, L, kWave);
-      for (int64_t c = kb; c < ke; c += kWave) {
-        const int64_t kk = c + lane;
-        bool push = false;
-        int32_t v = 0;
-        if (kk < ke) {
-          v = a.ci[kk];
-          push = relax(a, dL, v, a.wt[kk]);
-        }
-        push_wave(push, v, a.qn, nlen);
-      }
-    }
+// Edge index of queue entry i in the queue's edge list (non-decreasing in i;
+// the total past the last entry).
+struct QueueOffsets {
+  const uint32_t *qo;
+  int64_t qlen;
+  uint32_t total;
+  __device__ __forceinline__ uint32_t operator()(int64_t i) const {
+    return i >= qlen ? total : qo[i];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.ctr + S_RELAX, (unsigned long long)qlen);
+};
+
+// Largest i in [0, len) with off(i) <= e (off non-decreasing, off(0) = 0 <= e):
+// a kBlock-way search, one probe per thread per round.
+template <class Off>
+__device__ int64_t tile_search(const Off &off, int64_t len, uint32_t e) {
+  int64_t lo = 0, hi = len;
+  while (true) {
+    const int64_t span = hi - lo;
+    if (span <= kBlock) {
+      const int64_t p = lo + threadIdx.x;
+      const int c = __syncthreads_count(p < hi && off(p) <= e);
+      return lo + c - 1;
+    }
+    const int64_t p = lo + (span * (int64_t)threadIdx.x) / kBlock;
+    const int c = __syncthreads_count(off(p) <= e);
+    const int64_t nlo = lo + (span * (int64_t)(c - 1)) / kBlock;
+    const int64_t nhi = (c < kBlock) ? lo + (span * (int64_t)c) / kBlock : hi;
+    lo = nlo;
+    hi = nhi;
+  }
 }
 
-// Hub rows of the current queue (stamp = cur_epoch) in kHubChunk-edge pieces.
-__global__ __launch_bounds__(kBlock) void k_sssp_relax_hubs(const int32_t *__restrict__ hub_list,
-                                                            const uint64_t *__restrict__ hub_off,
-                                                            int64_t num_hubs, int64_t chunks,
-                                                            uint32_t cur_epoch, RelaxArgs a) {
-  const int lane = __lane_id();
-  const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * kBlock) / kWave;
-  unsigned long long *nlen = a.ctr + S_QLEN0 + a.nxt;
-  for (int64_t c = gw; c < chunks; c += nw) {
-    int64_t lo = 0, hi = num_hubs;  // hub owning chunk c: largest i with hub_off[i] <= c
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (hub_off[mid] <= (uint64_t)c)
-        lo = mid;
-      else
-        hi = mid;
+// One relaxation round over a queue (qlen entries, total edges): every queue
+// vertex leaves the far set, then 1,024-edge tiles of the queue's edge list
+// are relaxed by workgroups 0 .. active - 1 in turn; improved vertices below T
+// fill queue nxt.
+__device__ void relax_round(const int32_t *__restrict__ q, const uint32_t *__restrict__ qo,
+                            int64_t qlen, uint32_t total, uint32_t active, const RelaxArgs &a) {
+  __shared__ uint32_t s_off[kTile + 1];
+  __shared__ int64_t s_base[kTile];
+  __shared__ uint32_t s_du[kTile];
+  unsigned long long *npack = a.ctr + S_QP0 + a.nxt;
+  // the queue's vertices are relaxed now: they leave the far set (no relaxation
+  // of this round can put them back, their distances lie below T)
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < qlen;
+       i += (int64_t)active * kBlock) {
+    const int32_t u = q[i];
+    const uint64_t bit = 1ull << (u & 63);
+    if (a.pend[u >> 6] & bit) atomicAnd((unsigned long long *)(a.pend + (u >> 6)), ~bit);
+  }
+  const QueueOffsets off{qo, qlen, total};
+  for (uint64_t tile = blockIdx.x; tile * kTile < total; tile += active) {
+    const uint32_t e0 = (uint32_t)(tile * kTile);
+    const uint32_t e1 = (uint32_t)std::min<uint64_t>((uint64_t)e0 + kTile, total);
+    const int64_t i0 = tile_search(off, qlen, e0);
+    const int64_t i1 = tile_search(off, qlen, e1 - 1);
+    const int S = (int)(i1 - i0 + 1);
+    if (S > kTile) {  // only degree-0 entries could do this, and none are queued
+      if (threadIdx.x == 0) atomicOr(a.ctr + S_ERR, 4ull);
+      break;
     }
-    const int32_t h = hub_list[lo];
-    if (a.stamp[h] != cur_epoch) continue;
-    const uint32_t dh = a.dist[h];
-    const int64_t kb = a.rp[h] + (int64_t)((uint64_t)c - hub_off[lo]) * kHubChunk;
-    const int64_t ke = std::min<int64_t>(kb + kHubChunk, a.rp[h + 1]);
-    for (int64_t k0 = kb; k0 < ke; k0 += kWave) {
-      const int64_t k = k0 + lane;
+    for (int k = threadIdx.x; k < S; k += kBlock) {
+      const uint32_t o = off(i0 + k);
+      const int32_t u = q[i0 + k];
+      s_off[k] = o;
+      s_base[k] = a.rp[u] - (int64_t)o;
+      s_du[k] = a.dist[u];
+    }
+    if (threadIdx.x == 0) s_off[S] = off(i1 + 1);
+    __syncthreads();
+    int klo = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t e = e0 + j * kBlock + threadIdx.x;
       bool push = false;
       int32_t v = 0;
-      if (k < ke) {
+      if (e < e1) {
+        int lo = klo, hi = S;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_off[mid] <= e)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        klo = lo;
+        const int64_t k = s_base[lo] + (int64_t)e;
         v = a.ci[k];
-        push = relax(a, dh, v, a.wt[k]);
+        push = relax(a, s_du[lo], v, a.wt[k]);
       }
-      push_wave(push, v, a.qn, nlen);
+      push_wave(push, v, a.rp, a.qn, a.qon, npack);
     }
+    __syncthreads();  // the shared arrays are reused by the next tile
   }
 }
 
 // Pending vertices with dist < T leave the far set for queue nxt (stamp =
 // epoch); the rest are counted and their smallest distance taken.
-__global__ __launch_bounds__(kBlock) void k_sssp_scan(const uint32_t *__restrict__ dist,
-                                                      uint64_t *__restrict__ pend, int64_t words,
-                                                      uint64_t T, int32_t *__restrict__ qn,
-                                                      int nxt, uint32_t *__restrict__ stamp,
-                                                      uint32_t epoch,
-                                                      unsigned long long *__restrict__ ctr) {
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
+__device__ void scan_pending(const uint32_t *__restrict__ dist, const int64_t *__restrict__ rp,
+                             uint64_t *__restrict__ pend, int64_t words, uint64_t T,
+                             int32_t *__restrict__ qn, uint32_t *__restrict__ qon, int nxt,
+                             uint32_t *__restrict__ stamp, uint32_t epoch,
+                             unsigned long long *__restrict__ ctr, uint32_t active) {
+  const int64_t stride = (int64_t)active * kBlock;
   const int64_t span = ((words + kWave - 1) / kWave) * kWave;  // whole wavefronts
   unsigned long long left = 0;
   uint32_t dmin = kInf;
@@ -233,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_sssp_scan(const uint32_t *__restrict
           dmin = std::min(dmin, dv);
         }
       }
-      push_wave(push, v, qn, ctr + S_QLEN0 + nxt);
+      push_wave(push, v, rp, qn, qon, ctr + S_QP0 + nxt);
     }
     if (take) pend[w] = m & ~take;
   }
@@ -244,6 +283,86 @@ __global__ __launch_bounds__(kBlock) void k_sssp_scan(const uint32_t *__restrict
   for (int d = kWave / 2; d >= 1; d >>= 1) bm = std::min(bm, (uint32_t)__shfl_xor(bm, d, kWave));
   if (threadIdx.x == 0 && tl) atomicAdd(ctr + S_PEND, tl);
   if (__lane_id() == 0 && bm != kInf) atomicMin(ctr + S_MIN, (unsigned long long)bm);
+}
+
+// Step j of the traversal; the host queues steps in groups without waiting.
+// It relaxes its queue if that holds entries, else it scans the far set below
+// the threshold; its last workgroup (a ticket) writes step j + 1's state:
+// the queues flip, the threshold moves to the end of the bucket of the
+// smallest pending distance after a scan found nothing below it, or the end
+// is marked.  Steps queued past the end do nothing.
+__global__ __launch_bounds__(kBlock) void k_sssp_step(RelaxArgs a, int64_t j, int32_t *q0,
+                                                      int32_t *q1, uint32_t *qo0, uint32_t *qo1,
+                                                      int64_t words, uint64_t delta) {
+  __shared__ int s_last;
+  unsigned long long *ctr = a.ctr;
+  unsigned long long *st = ctr + S_ST0 + (int)(j & 1) * kStSlots;
+  if (st[ST_DONE]) return;
+  const unsigned long long qp = st[ST_QP];
+  const int cur = (int)st[ST_CUR];
+  const int nxt = cur ^ 1;
+  const int64_t qlen = (int64_t)(qp >> 32);
+  const uint32_t total = (uint32_t)qp;
+  a.T = st[ST_T];
+  a.epoch = (uint32_t)st[ST_EP];
+  a.nxt = nxt;
+  a.qn = nxt ? q1 : q0;
+  a.qon = nxt ? qo1 : qo0;
+  // workgroups with work take part (and a ticket): same-address atomics serialise
+  const uint64_t need =
+      qlen > 0 ? std::max<uint64_t>(((uint64_t)total + kTile - 1) / kTile,
+                                    ((uint64_t)qlen + kBlock - 1) / kBlock)
+               : ((uint64_t)words + kBlock - 1) / kBlock;
+  const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(gridDim.x, need));
+  if (blockIdx.x >= active) return;
+  if (qlen > 0)
+    relax_round(cur ? q1 : q0, cur ? qo1 : qo0, qlen, total, active, a);
+  else
+    scan_pending(a.dist, a.rp, a.pend, words, a.T, a.qn, a.qon, nxt, a.stamp, a.epoch, ctr,
+                 active);
+  unsigned long long *tick = ctr + S_TICK0 + (int)(j & 1);
+  if (threadIdx.x == 0) s_last = atomicAdd(tick, 1ull) + 1 == active;
+  __syncthreads();
+  if (!s_last || threadIdx.x != 0) return;
+  // every workgroup's pushes and counts returned before its ticket
+  const unsigned long long np = atomicAdd(ctr + S_QP0 + nxt, 0ull);
+  unsigned long long *ns = ctr + S_ST0 + (int)((j + 1) & 1) * kStSlots;
+  unsigned long long T = a.T, done = 0;
+  if (qlen > 0) {
+    ctr[S_ROUNDS] += 1;
+    ctr[S_RELAX] += (unsigned long long)qlen;
+    ctr[S_EDGES] += (unsigned long long)total;
+  } else {
+    ctr[S_SCANS] += 1;
+    if ((np >> 32) == 0) {
+      // nothing below T: done without pending vertices, else the next scan
+      // uses the end of the bucket of the smallest pending distance
+      const unsigned long long left = atomicAdd(ctr + S_PEND, 0ull);
+      const unsigned long long mn = atomicAdd(ctr + S_MIN, 0ull);
+      if (left == 0) {
+        done = 1;
+      } else {
+        T = (mn / delta + 1) * delta;
+        ctr[S_BUCKETS] += 1;
+      }
+    }
+    atomicExch(ctr + S_PEND, 0ull);
+    atomicExch(ctr + S_MIN, (unsigned long long)kInf);
+  }
+  ns[ST_QP] = np;
+  ns[ST_CUR] = (unsigned long long)nxt;
+  ns[ST_T] = T;
+  ns[ST_EP] = (unsigned long long)a.epoch + 1;
+  ns[ST_DONE] = done;
+  ctr[S_EPOCH] = (unsigned long long)a.epoch + 1;
+  if (done) {
+    // both parities: every later step finds the end, whichever state it reads
+    // (every workgroup of this step has passed its check of st already)
+    st[ST_DONE] = 1;
+    ctr[S_DONE] = 1;
+  }
+  atomicExch(ctr + S_QP0 + cur, 0ull);  // the consumed queue is step j + 1's output
+  atomicExch(tick, 0ull);
 }
 
 // prev[v] = src for the source, -1 where dist is infinite, else the
@@ -269,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_sssp_prev(const int64_t *__restrict_
       }
     }
     int32_t p = (v < n && dv != kInf && v == src) ? (int32_t)src : -1;
-    const bool lane_row = e - b <= kLaneRow;
+    const bool lane_row = e - b <= kWave;
     if (lane_row)
       for (int64_t k = b; k < e; ++k) {
         const uint32_t du = dist[ci[k]];
@@ -305,18 +424,6 @@ __global__ __launch_bounds__(kBlock) void k_sssp_prev(const int64_t *__restrict_
   }
 }
 
-// Clears the next queue's length (and, before a scan, the pending count and
-// minimum).
-__global__ void k_reset_ctr(unsigned long long *ctr, int nxt, bool scan) {
-  if (threadIdx.x == 0) {
-    ctr[S_QLEN0 + nxt] = 0;
-    if (scan) {
-      ctr[S_PEND] = 0;
-      ctr[S_MIN] = kInf;
-    }
-  }
-}
-
 __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t len, uint32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = v;
@@ -334,6 +441,8 @@ SsspWork::~SsspWork() {
   if (stamp) (void)hipFree(stamp);
   for (auto *p : q)
     if (p) (void)hipFree(p);
+  for (auto *p : qo)
+    if (p) (void)hipFree(p);
   if (ctr) (void)hipFree(ctr);
   if (ev[0]) (void)hipEventDestroy(ev[0]);
   if (ev[1]) (void)hipEventDestroy(ev[1]);
@@ -350,6 +459,8 @@ g5_status alloc_sssp(const g5_csr *g, SsspWork **out) {
   A((void **)&w->stamp, g->n * 4);
   A((void **)&w->q[0], g->n * 4);
   A((void **)&w->q[1], g->n * 4);
+  A((void **)&w->qo[0], g->n * 4);
+  A((void **)&w->qo[1], g->n * 4);
   A((void **)&w->ctr, S_N * 8);
   if (e == hipSuccess) e = hipMemset(w->stamp, 0, g->n * 4);
   if (e != hipSuccess) {
@@ -412,15 +523,10 @@ g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev,
   if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
   uint32_t ep = ++w.epoch;
   hipLaunchKernelGGL(k_sssp_init, dim3(grid_blocks(std::max(n, W), 256, ncu * 16)), dim3(256), 0,
-                     s, dist, n, src, w.pend, W, w.q[0], w.stamp, ep, ctr);
+                     s, dist, n, src, w.pend, W, w.q[0], w.qo[0], g->row_ptr, w.stamp, ep, delta,
+                     ctr);
   G5_LAUNCH_CHECK();
-  uint64_t T = delta;
-  int cur = 0;
-  int64_t rounds = 0, scans = 0, buckets = 1;
-  unsigned long long hc[S_N] = {};
-  unsigned long long qlen = 1;
-  bool last_scan = false;
-  RelaxArgs a;
+  RelaxArgs a{};
   a.rp = g->row_ptr;
   a.ci = g->col_idx;
   a.wt = g->wt;
@@ -428,67 +534,41 @@ g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev,
   a.pend = w.pend;
   a.stamp = w.stamp;
   a.ctr = ctr;
-  while (true) {
-    const int nxt = cur ^ 1;
-    if (qlen > 0) {
-      // relax the current queue into the other one
-      a.qn = w.q[nxt];
-      a.nxt = nxt;
-      a.T = T;
-      const uint32_t cur_ep = ep;
-      a.epoch = ep = ++w.epoch;
-      hipLaunchKernelGGL(k_reset_ctr, dim3(1), dim3(64), 0, s, ctr, nxt, false);
-      hipLaunchKernelGGL(k_sssp_relax, dim3(grid_blocks((int64_t)qlen, kBlock, grid)),
-                         dim3(kBlock), 0, s, (const int32_t *)w.q[cur], cur, a);
-      if (g->hub_chunks > 0)
-        hipLaunchKernelGGL(k_sssp_relax_hubs,
-                           dim3(grid_blocks(g->hub_chunks, kBlock / kWave, grid)), dim3(kBlock),
-                           0, s, (const int32_t *)g->hub_list, (const uint64_t *)g->hub_off,
-                           g->num_hubs, g->hub_chunks, cur_ep, a);
-      G5_LAUNCH_CHECK();
-      ++rounds;
-      last_scan = false;
-    } else {
-      // the queue ran dry: pending vertices below T form the next one
-      ep = ++w.epoch;
-      hipLaunchKernelGGL(k_reset_ctr, dim3(1), dim3(64), 0, s, ctr, nxt, true);
-      hipLaunchKernelGGL(k_sssp_scan, dim3(grid_blocks(W, kBlock, ncu * 16)), dim3(kBlock), 0, s,
-                         (const uint32_t *)dist, w.pend, W, T, w.q[nxt], nxt, w.stamp, ep, ctr);
-      G5_LAUNCH_CHECK();
-      ++scans;
-      last_scan = true;
-    }
-    cur = nxt;
+  // steps are queued in groups; the host reads the counters once per group
+  unsigned long long hc[S_N] = {};
+  int64_t steps = 0;
+  for (int group = 8;; group = 16) {
+    for (int i = 0; i < group; ++i, ++steps)
+      hipLaunchKernelGGL(k_sssp_step, dim3(grid), dim3(kBlock), 0, s, a, steps, w.q[0], w.q[1],
+                         w.qo[0], w.qo[1], W, delta);
+    G5_LAUNCH_CHECK();
     G5_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
     G5_HIP(hipStreamSynchronize(s));
     if (hc[S_ERR]) {
-      set_error("g5_sssp: a distance exceeds 2^32 - 2");
-      return G5_ERANGE;
+      set_error(hc[S_ERR] & 1 ? "g5_sssp: a distance exceeds 2^32 - 2"
+                              : "g5_sssp: a relaxation tile met more queue entries than edges");
+      return (hc[S_ERR] & 1) ? G5_ERANGE : G5_EDEVICE;
     }
-    qlen = hc[S_QLEN0 + cur];
-    if (qlen > 0 || !last_scan) continue;
-    // a scan found nothing below T: done without pending vertices, else T
-    // moves to the end of the bucket of the smallest pending distance
-    if (hc[S_PEND] == 0) break;
-    T = (hc[S_MIN] / delta + 1) * delta;
-    ++buckets;
+    if (hc[S_DONE]) break;
   }
+  w.epoch = (uint32_t)hc[S_EPOCH];
   hipLaunchKernelGGL(k_sssp_prev, dim3(grid_blocks(n, kBlock, ncu * 16)), dim3(kBlock), 0, s,
                      g->row_ptr, g->col_idx, g->wt, (const uint32_t *)dist, n, src, prev, ctr);
   G5_LAUNCH_CHECK();
   if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
   G5_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
   G5_HIP(hipStreamSynchronize(s));
-  if (hc[S_ERR]) {
+  if (hc[S_ERR] & 2) {
     set_error("g5_sssp: a reached vertex has no tight neighbour (inconsistent distances)");
     return G5_EDEVICE;
   }
   if (stats) {
     *stats = g5_sssp_stats{};
-    stats->rounds = rounds;
-    stats->scans = scans;
-    stats->buckets = buckets;
+    stats->rounds = (int64_t)hc[S_ROUNDS];
+    stats->scans = (int64_t)hc[S_SCANS];
+    stats->buckets = (int64_t)hc[S_BUCKETS];
     stats->relaxed = (int64_t)hc[S_RELAX];
+    stats->edges = (int64_t)hc[S_EDGES];
     stats->delta = (int64_t)delta;
     if (timed) {
       float ms = 0;

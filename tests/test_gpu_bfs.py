@@ -157,6 +157,22 @@ def test_heavy_levels(kron16, heavy_kedges):
         c.check_root(r, heavy_kedges=heavy_kedges, min_parent=True)
 
 
+def test_heavy_hub_star():
+    # a star of 200,000 leaves (plus a few leaf-leaf edges) from a leaf with a
+    # leaf neighbour: level 1 is the hub and that neighbour (a growing
+    # frontier), level 2 claims every other leaf in one heavy top-down level
+    # (alpha and gamma keep it top-down); from a plain leaf it is not heavy
+    e, n = G.star(200_000)
+    extra = np.array([[1, 2], [3, 4], [5, 6]])
+    c = Case(np.concatenate([e, extra]), n)
+    for r in (1, 4, 5, 7, n - 1):
+        _, _, st = g5.bfs(c.csr, r, stats=True, heavy_kedges=1, alpha=1e-3, gamma=-1)
+        # from a leaf with a leaf neighbour level 1 is heavy; from a plain leaf the
+        # hub alone is level 1 (not a growing frontier) and level 2 goes bottom-up
+        assert st["heavy_mask"] == (0b10 if r <= 6 else 0), (r, st["dir"], st["heavy_mask"])
+        c.check_root(r, heavy_kedges=1, alpha=1e-3, gamma=-1)
+
+
 @pytest.fixture(scope="module")
 def kron16():
     scale = 16
