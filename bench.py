@@ -86,6 +86,31 @@ def copy_probe():
     torch.cuda.empty_cache()
 
 
+GATHER_ELEMS = 1 << 29   # int64 source: 4 GiB
+GATHER_PICKS = 1 << 24   # random reads
+
+
+def gather_probe():
+    """A random gather of known footprint: 2^24 int64 elements picked at
+    seeded random positions of a 4 GiB array (torch.take), for calibrating the
+    read counters on small random requests.  Prints the distinct 64-byte lines
+    it touches and the bytes of its index and output streams."""
+    import torch
+    src = torch.zeros(GATHER_ELEMS, dtype=torch.int64, device="cuda:0")
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(5)
+    idx = torch.randint(0, GATHER_ELEMS, (GATHER_PICKS,), generator=gen, device="cuda:0")
+    torch.cuda.synchronize()
+    out = torch.take(src, idx)
+    torch.cuda.synchronize()
+    lines = int(torch.unique(idx // 8).numel())
+    log(json.dumps({"gather_probe": {"distinct_lines": lines, "line_bytes": 64,
+                                     "index_bytes": GATHER_PICKS * 8,
+                                     "out_bytes": GATHER_PICKS * 8}}))
+    del src, idx, out
+    torch.cuda.empty_cache()
+
+
 def _pmc_rows(d):
     import csv
     import glob
@@ -261,12 +286,37 @@ def reduce_pmc(fetch_dir, write_dir, split_dir, workload, command, path=TRAFFIC_
     data[f"root0_levels@{workload}"] = {"source_hash": h, "levels": levels, "command": command}
     data.pop("k_bu_step_all@" + workload, None)
     data.pop("td_step@" + workload, None)
+    if sr:
+        g = gather_calibration(fr, sr, copy_split)
+        if g:
+            data["gather_probe"] = dict(g, command=command)
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
     for kernel, rec in recs:
         print(kernel, json.dumps(rec))
     print(json.dumps(td))
     print(json.dumps(levels))
+
+
+def gather_calibration(fr, sr, copy_split):
+    """Read requests of the random-gather probe (when the counter runs include
+    it): the copy probe gives the bytes one request moves on a stream; the
+    gather's requests beyond those of its index stream, per random pick, show
+    whether scattered 8-byte reads cost one such request each."""
+    is_take = lambda name: "index_elementwise_kernel" in name
+    req = _per_dispatch_map(sr, "TCC_EA0_RDREQ_sum", is_take)
+    fetch = _per_dispatch_map(fr, "FETCH_SIZE", is_take)
+    copy_req = copy_split.get("TCC_EA0_RDREQ_sum")
+    if not req or not copy_req:
+        return None
+    r = max(req.values())
+    per_req = COPY_PROBE_BYTES / copy_req
+    index_req = GATHER_PICKS * 8 / per_req
+    return {"picks": GATHER_PICKS, "read_requests": int(r),
+            "stream_bytes_per_request": round(per_req, 2),
+            "index_requests": int(index_req),
+            "requests_per_pick": round((r - index_req) / GATHER_PICKS, 4),
+            "fetch_size_kib": round(max(fetch.values()), 1) if fetch else None}
 
 
 def summarize_trace(db, command, bench_json=None):
@@ -364,7 +414,9 @@ def run_gpu(args):
         _, _, st = g5.bfs(csr, r, parent, level, count_bytes=True)
         m_r.append(int(deg[level >= 0].sum().item()) // 2)
         acct.append(st)
-        work.append([g5.level_work(csr, level, lv) for lv in range(st["nlevels"])])
+        work.append([g5.level_work(csr, level, lv, bottom_up=st["dir"][lv] == 2)
+                     if lv < len(st["dir"]) else g5.level_work(csr, level, lv)
+                     for lv in range(st["nlevels"])])
     del deg
     log(f"accounting done: m_r of root 0 = {m_r[0]}, levels {acct[0]['nlevels']}, "
         f"dirs {acct[0]['dir']}")
@@ -759,6 +811,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run the counter-calibration copy kernel first")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="run the random-gather calibration kernel first")
     ap.add_argument("--reduce-pmc", nargs="+", metavar="DIR",
                     help="write profiles/traffic.json from rocprofv3 --pmc runs (FETCH_SIZE dir, "
                          "WRITE_SIZE dir, optionally the request-split dir) and exit")
@@ -792,6 +846,8 @@ def main():
 
     if args.copy_probe:
         copy_probe()
+    if args.gather_probe:
+        gather_probe()
     gpu, csr, parent, level = run_gpu(args)
     import torch
     import paper_2012_13548_amd as g5

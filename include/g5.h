@@ -334,6 +334,8 @@ g5_status g5_bfs_batch_noalloc(const g5_csr *g, const int64_t *roots, int32_t k,
  *              16 U + 4 S + n/4 + 8 claimed.
  *   level   device, int32 [n]: the level array of a traversal of g.
  *   lvl     the level whose step is counted (its frontier is level lvl).
+ *   bottom_up  nonzero: also count U and S (a row scan per unvisited vertex);
+ *           zero: out[3] = out[4] = 0 (a top-down step needs neither).
  *   out     host, int64 [5]: |Q| (vertices at level lvl), m_f (their degree
  *           sum), claimed (vertices at level lvl + 1), U (vertices of degree
  *           >= 1 at a level above lvl or unreached), S (over those, row
@@ -341,8 +343,8 @@ g5_status g5_bfs_batch_noalloc(const g5_csr *g, const int64_t *roots, int32_t k,
  *           whole row).
  * Allocates a small device buffer per call; returns when the counts are on
  * the host.  Errors: G5_EINVAL (NULL pointer, lvl < 0), G5_ENOMEM, G5_EDEVICE. */
-g5_status g5_level_work(const g5_csr *g, const int32_t *level, int32_t lvl, int64_t *out,
-                        void *stream);
+g5_status g5_level_work(const g5_csr *g, const int32_t *level, int32_t lvl, int32_t bottom_up,
+                        int64_t *out, void *stream);
 
 /* Message for the last non-OK status returned on the calling host thread. */
 const char *g5_last_error(void);

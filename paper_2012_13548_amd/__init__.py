@@ -132,7 +132,7 @@ lib.g5_sssp.restype = ctypes.c_int
 lib.g5_sssp_ex.argtypes = [_P, _I64, _P, _P, _P, ctypes.POINTER(SsspParams),
                            ctypes.POINTER(SsspStats)]
 lib.g5_sssp_ex.restype = ctypes.c_int
-lib.g5_level_work.argtypes = [_P, _P, ctypes.c_int32, ctypes.POINTER(_I64), _P]
+lib.g5_level_work.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_I64), _P]
 lib.g5_level_work.restype = ctypes.c_int
 lib.g5_last_error.argtypes = []
 lib.g5_last_error.restype = ctypes.c_char_p
@@ -367,15 +367,16 @@ def bfs_batch(csr, roots, parents=True, levels=None, parent_out=None, direction=
     return out + (info,)
 
 
-def level_work(csr, level, lvl):
+def level_work(csr, level, lvl, bottom_up=True):
     """Work counts of level ``lvl`` of a finished traversal (measurement):
-    dict with q, mf, claimed, unvisited, scanned (see g5_level_work)."""
+    dict with q, mf, claimed, unvisited, scanned (see g5_level_work); the last
+    two only with ``bottom_up``."""
     import torch
     if level.dtype != torch.int32 or level.numel() < csr.n or not level.is_contiguous():
         raise ValueError("level must be a contiguous int32 tensor of length n")
     out = (_I64 * 5)()
-    _check(lib.g5_level_work(csr.handle, level.data_ptr(), int(lvl), out, _stream(csr.device)),
-           "g5_level_work")
+    _check(lib.g5_level_work(csr.handle, level.data_ptr(), int(lvl), int(bool(bottom_up)), out,
+                             _stream(csr.device)), "g5_level_work")
     return dict(zip(("q", "mf", "claimed", "unvisited", "scanned"), list(out)))
 
 

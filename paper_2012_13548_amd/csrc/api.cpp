@@ -241,8 +241,8 @@ g5_status g5_sssp(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, v
   return g5_sssp_ex(g, src, dist, prev, stream, nullptr, nullptr);
 }
 
-g5_status g5_level_work(const g5_csr *g, const int32_t *level, int32_t lvl, int64_t *out,
-                        void *stream) {
+g5_status g5_level_work(const g5_csr *g, const int32_t *level, int32_t lvl, int32_t bottom_up,
+                        int64_t *out, void *stream) {
   if (!g || !level || !out) {
     set_error("g5_level_work: graph, level and out must be non-NULL");
     return G5_EINVAL;
@@ -251,7 +251,7 @@ g5_status g5_level_work(const g5_csr *g, const int32_t *level, int32_t lvl, int6
     set_error("g5_level_work: lvl must be >= 0");
     return G5_EINVAL;
   }
-  return g5::level_work_impl(g, level, lvl, out, (hipStream_t)stream);
+  return g5::level_work_impl(g, level, lvl, bottom_up != 0, out, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -219,7 +219,7 @@ g5_status bfs_batch_noalloc_impl(const g5_csr *g, const int64_t *roots, int k, i
                                  int8_t *levels, hipStream_t s);
 g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, hipStream_t s,
                     const g5_sssp_params &p, g5_sssp_stats *stats);
-g5_status level_work_impl(const g5_csr *g, const int32_t *level, int32_t lvl, int64_t *out,
-                          hipStream_t s);
+g5_status level_work_impl(const g5_csr *g, const int32_t *level, int32_t lvl, bool bottom_up,
+                          int64_t *out, hipStream_t s);
 
 }  // namespace g5

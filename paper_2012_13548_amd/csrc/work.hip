@@ -23,7 +23,7 @@ enum WorkOut : int { W_Q = 0, W_MF = 1, W_CLAIMED = 2, W_UNVIS = 3, W_SCANNED = 
 
 __global__ __launch_bounds__(kWorkBlock) void k_level_work(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ level, int64_t n, int32_t lvl,
+    const int32_t *__restrict__ level, int64_t n, int32_t lvl, bool bottom_up,
     unsigned long long *__restrict__ out) {
   __shared__ unsigned long long s_red[kWorkBlock / kWave];
   const int lane = __lane_id();
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kWorkBlock) void k_level_work(
       mf += (unsigned long long)d;
     }
     if (v < n && lv == lvl + 1) ++claimed;
-    const bool cand = v < n && d > 0 && (lv == -1 || lv > lvl);
+    const bool cand = bottom_up && v < n && d > 0 && (lv == -1 || lv > lvl);
     if (cand) ++unvis;
     // short rows: this lane alone
     if (cand && d <= kWave) {
@@ -86,8 +86,8 @@ __global__ void k_work_zero(unsigned long long *out) {
 
 }  // namespace
 
-g5_status level_work_impl(const g5_csr *g, const int32_t *level, int32_t lvl, int64_t *out,
-                          hipStream_t s) {
+g5_status level_work_impl(const g5_csr *g, const int32_t *level, int32_t lvl, bool bottom_up,
+                          int64_t *out, hipStream_t s) {
   unsigned long long *d = nullptr;
   G5_HIP(hipMalloc((void **)&d, W_N * sizeof(unsigned long long)));
   hipLaunchKernelGGL(k_work_zero, dim3(1), dim3(64), 0, s, d);
@@ -95,7 +95,7 @@ g5_status level_work_impl(const g5_csr *g, const int32_t *level, int32_t lvl, in
                                            (int64_t)g->num_cu * 16);
   hipLaunchKernelGGL(k_level_work, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(kWorkBlock),
                      0, s, (const int64_t *)g->row_ptr, (const int32_t *)g->col_idx, level, g->n,
-                     lvl, d);
+                     lvl, bottom_up, d);
   hipError_t e = hipGetLastError();
   unsigned long long h[W_N] = {};
   if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s);

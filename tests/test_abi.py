@@ -40,7 +40,7 @@ def test_null_arguments_rejected_without_device():
     assert lib.g5_build_csr(None, 0, 4, None, None) == g5.G5_EINVAL
     assert lib.g5_sssp(None, 0, None, None, None) == g5.G5_EINVAL
     assert lib.g5_build_csr_w(None, None, 0, 4, None, None) == g5.G5_EINVAL
-    assert lib.g5_level_work(None, None, 0, None, None) == g5.G5_EINVAL
+    assert lib.g5_level_work(None, None, 0, 1, None, None) == g5.G5_EINVAL
     lib.g5_csr_free(None)
 
 
