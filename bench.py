@@ -709,7 +709,10 @@ def run_sssp(args):
         od, _, dt = O.sssp_timed(ocsr, roots[0])
         out["oracle_root0_s"] = round(dt, 3)
         out["oracle_root0_gteps"] = round(m_r[0] / dt / 1e9, 5)
-        out["dist_equal_oracle"] = bool(np.array_equal(dist.cpu().numpy().view(np.uint32), od))
+        gd = dist.cpu().numpy().view(np.uint32)
+        out["dist_equal_oracle"] = bool(np.array_equal(gd, od))
+        out["prev_equal_oracle"] = bool(np.array_equal(prev.cpu().numpy(),
+                                                       O.min_prev(ocsr, roots[0], od)))
     return out
 
 

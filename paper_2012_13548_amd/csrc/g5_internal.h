@@ -86,6 +86,7 @@ struct BatchWork {
 // Device state of one shortest-path computation (sssp.hip); reused across calls.
 struct SsspWork {
   uint64_t *pend = nullptr;   // far set: vertices improved at or above the threshold
+  unsigned long long *dp = nullptr;  // per vertex: distance << 32 | predecessor
   uint32_t *stamp = nullptr;  // per vertex: the stamp of the last queue it joined
   int32_t *q[2] = {nullptr, nullptr};  // current and next queue
   uint32_t *qo[2] = {nullptr, nullptr}; // per entry: its first edge in the queue's edge list

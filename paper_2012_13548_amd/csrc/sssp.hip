@@ -7,14 +7,19 @@
 //   threshold T   vertices with dist < T form the current buckets; T advances
 //                 by delta once nothing below it is left to relax
 //   relax         every vertex of the current queue relaxes all its edges:
-//                 nd = dist[u] + w, atomic minimum into dist[v]; an improved v
-//                 goes to the next queue if nd < T (once per queue, by a stamp
-//                 per vertex), else its "pending" bit is set (the far set)
+//                 nd = dist[u] + w; a 64-bit atomic minimum of (nd << 32 | u)
+//                 into v's word keeps its distance and, among the relaxations
+//                 that reach it, the smallest-id predecessor; a v whose
+//                 distance improved goes to the next queue if nd < T (once per
+//                 queue, by a stamp per vertex), else its "pending" bit is set
+//                 (the far set)
 //   scan          when the queue runs dry: pending vertices with dist < T
 //                 form the next queue; with none, T jumps to the bucket of the
 //                 smallest pending distance; with no pending vertex, done
-//   predecessors  one pass at the end: prev[v] = the smallest-id neighbour u
-//                 with dist[u] + w(u, v) = dist[v] (so prev is deterministic)
+//   predecessors  every neighbour u on a shortest path to v relaxes v with
+//                 its final distance at some round, so the packed minimum ends
+//                 as (dist[v], the smallest such u): prev is deterministic; one
+//                 streaming pass writes dist and prev
 //
 // Relaxations are edge-balanced: every queue entry carries the index of its
 // first edge in the queue's edge list (assigned when it was appended, from one
@@ -42,7 +47,7 @@ enum SCtr : int {
   S_QP1 = 1,    // queue 1: the same
   S_PEND = 2,   // pending vertices left after a scan
   S_MIN = 3,    // smallest distance among them (kInf if none)
-  S_ERR = 4,    // 1: a distance exceeded kInf - 1; 2: a reached vertex without a tight edge
+  S_ERR = 4,    // 1: a distance exceeded kInf - 1; 4: a tile met more entries than edges
   S_RELAX = 5,  // queue entries relaxed (statistics)
   S_EDGES = 6,  // edges relaxed (statistics)
   S_DONE = 7,   // 1: no queue and no pending vertex left (read by the host)
@@ -88,7 +93,7 @@ struct RelaxArgs {
   const int64_t *rp;
   const int32_t *ci;
   const uint8_t *wt;
-  uint32_t *dist;
+  unsigned long long *dp;  // per vertex: dist << 32 | predecessor
   uint64_t *pend;
   uint32_t *stamp;
   int32_t *qn;   // next queue
@@ -100,32 +105,38 @@ struct RelaxArgs {
 };
 
 // Relaxes edge (u, v) of weight w from distance du; returns true when v must
-// join the next queue (improved below T and not yet in it).
-__device__ __forceinline__ bool relax(const RelaxArgs &a, uint32_t du, int32_t v, uint32_t w) {
+// join the next queue (its distance improved below T and it is not yet in it).
+// A relaxation that reaches v's distance with a smaller-id u only updates the
+// predecessor.
+__device__ __forceinline__ bool relax(const RelaxArgs &a, uint32_t du, int32_t u, int32_t v,
+                                      uint32_t w) {
   const uint64_t nd = (uint64_t)du + w;
-  if (nd >= (uint64_t)a.dist[v]) return false;
   if (nd >= (uint64_t)kInf) {
     atomicOr(a.ctr + S_ERR, 1ull);
     return false;
   }
-  const uint32_t old = atomicMin(a.dist + v, (uint32_t)nd);
-  if (nd >= old) return false;
+  const unsigned long long cand = (nd << 32) | (uint32_t)u;
+  if (cand >= a.dp[v]) return false;
+  const unsigned long long old = atomicMin(a.dp + v, cand);
+  if (nd >= (old >> 32)) return false;  // not closer (at most a smaller predecessor)
   if (nd < a.T) return atomicExch(a.stamp + v, a.epoch) != a.epoch;
   const uint64_t bit = 1ull << (v & 63);
   if (!(a.pend[v >> 6] & bit)) atomicOr((unsigned long long *)(a.pend + (v >> 6)), bit);
   return false;
 }
 
-// Start: dist = infinity except the source (0); no pending vertex; queue 0 =
-// {src} with the stamp of the first queue; counters zeroed.
-__global__ void k_sssp_init(uint32_t *__restrict__ dist, int64_t n, int64_t src,
+// Start: distance infinity (and no predecessor) except the source (0, itself);
+// no pending vertex; queue 0 = {src} with the stamp of the first queue;
+// counters zeroed.
+__global__ void k_sssp_init(unsigned long long *__restrict__ dp, int64_t n, int64_t src,
                             uint64_t *__restrict__ pend, int64_t words, int32_t *__restrict__ q0,
                             uint32_t *__restrict__ qo0, const int64_t *__restrict__ rp,
                             uint32_t *__restrict__ stamp, uint32_t epoch, uint64_t delta,
                             unsigned long long *__restrict__ ctr) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = t; i < n; i += stride) dist[i] = i == src ? 0u : kInf;
+  for (int64_t i = t; i < n; i += stride)
+    dp[i] = i == src ? (unsigned long long)src : ((unsigned long long)kInf << 32) | 0xffffffffull;
   for (int64_t i = t; i < words; i += stride) pend[i] = 0;
   if (t == 0) {
     for (int i = 0; i < S_N; ++i) ctr[i] = 0;
@@ -184,6 +195,7 @@ __device__ void relax_round(const int32_t *__restrict__ q, const uint32_t *__res
   __shared__ uint32_t s_off[kTile + 1];
   __shared__ int64_t s_base[kTile];
   __shared__ uint32_t s_du[kTile];
+  __shared__ int32_t s_u[kTile];
   unsigned long long *npack = a.ctr + S_QP0 + a.nxt;
   // the queue's vertices are relaxed now: they leave the far set (no relaxation
   // of this round can put them back, their distances lie below T)
@@ -209,7 +221,8 @@ __device__ void relax_round(const int32_t *__restrict__ q, const uint32_t *__res
       const int32_t u = q[i0 + k];
       s_off[k] = o;
       s_base[k] = a.rp[u] - (int64_t)o;
-      s_du[k] = a.dist[u];
+      s_du[k] = (uint32_t)(a.dp[u] >> 32);
+      s_u[k] = u;
     }
     if (threadIdx.x == 0) s_off[S] = off(i1 + 1);
     __syncthreads();
@@ -231,7 +244,7 @@ __device__ void relax_round(const int32_t *__restrict__ q, const uint32_t *__res
         klo = lo;
         const int64_t k = s_base[lo] + (int64_t)e;
         v = a.ci[k];
-        push = relax(a, s_du[lo], v, a.wt[k]);
+        push = relax(a, s_du[lo], s_u[lo], v, a.wt[k]);
       }
       push_wave(push, v, a.rp, a.qn, a.qon, npack);
     }
@@ -241,7 +254,8 @@ __device__ void relax_round(const int32_t *__restrict__ q, const uint32_t *__res
 
 // Pending vertices with dist < T leave the far set for queue nxt (stamp =
 // epoch); the rest are counted and their smallest distance taken.
-__device__ void scan_pending(const uint32_t *__restrict__ dist, const int64_t *__restrict__ rp,
+__device__ void scan_pending(const unsigned long long *__restrict__ dp,
+                             const int64_t *__restrict__ rp,
                              uint64_t *__restrict__ pend, int64_t words, uint64_t T,
                              int32_t *__restrict__ qn, uint32_t *__restrict__ qon, int nxt,
                              uint32_t *__restrict__ stamp, uint32_t epoch,
@@ -262,7 +276,7 @@ __device__ void scan_pending(const uint32_t *__restrict__ dist, const int64_t *_
         const int b = __ffsll((unsigned long long)rest) - 1;
         rest &= rest - 1;
         v = (int32_t)(w * kWave + b);
-        const uint32_t dv = dist[v];
+        const uint32_t dv = (uint32_t)(dp[v] >> 32);
         if ((uint64_t)dv < T) {
           take |= 1ull << b;
           stamp[v] = epoch;
@@ -318,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_sssp_step(RelaxArgs a, int64_t j, in
   if (qlen > 0)
     relax_round(cur ? q1 : q0, cur ? qo1 : qo0, qlen, total, active, a);
   else
-    scan_pending(a.dist, a.rp, a.pend, words, a.T, a.qn, a.qon, nxt, a.stamp, a.epoch, ctr,
+    scan_pending(a.dp, a.rp, a.pend, words, a.T, a.qn, a.qon, nxt, a.stamp, a.epoch, ctr,
                  active);
   unsigned long long *tick = ctr + S_TICK0 + (int)(j & 1);
   if (threadIdx.x == 0) s_last = atomicAdd(tick, 1ull) + 1 == active;
@@ -365,62 +379,16 @@ __global__ __launch_bounds__(kBlock) void k_sssp_step(RelaxArgs a, int64_t j, in
   atomicExch(tick, 0ull);
 }
 
-// prev[v] = src for the source, -1 where dist is infinite, else the
-// smallest-id neighbour u with dist[u] + w(u, v) = dist[v] (rows ascending:
-// the first such entry).
-__global__ __launch_bounds__(kBlock) void k_sssp_prev(const int64_t *__restrict__ rp,
-                                                      const int32_t *__restrict__ ci,
-                                                      const uint8_t *__restrict__ wt,
-                                                      const uint32_t *__restrict__ dist, int64_t n,
-                                                      int64_t src, int32_t *__restrict__ prev,
-                                                      unsigned long long *__restrict__ ctr) {
-  const int lane = __lane_id();
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const int64_t span = ((n + kWave - 1) / kWave) * kWave;
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < span; v += stride) {
-    uint32_t dv = kInf;
-    int64_t b = 0, e = 0;
-    if (v < n) {
-      dv = dist[v];
-      if (dv != kInf && v != src) {
-        b = rp[v];
-        e = rp[v + 1];
-      }
-    }
-    int32_t p = (v < n && dv != kInf && v == src) ? (int32_t)src : -1;
-    const bool lane_row = e - b <= kWave;
-    if (lane_row)
-      for (int64_t k = b; k < e; ++k) {
-        const uint32_t du = dist[ci[k]];
-        if (du != kInf && (uint64_t)du + wt[k] == (uint64_t)dv) {
-          p = ci[k];
-          break;
-        }
-      }
-    uint64_t rem = __ballot(!lane_row);
-    while (rem) {
-      const int L = __ffsll((unsigned long long)rem) - 1;
-      rem &= rem - 1;
-      const int64_t kb = __shfl(b, L, kWave), ke = __shfl(e, L, kWave);
-      const uint32_t dL = __shfl(dv, L, kWave);
-      int32_t found = -1;
-      for (int64_t c = kb; c < ke && found < 0; c += kWave) {
-        const int64_t k = c + lane;
-        bool hit = false;
-        if (k < ke) {
-          const uint32_t du = dist[ci[k]];
-          hit = du != kInf && (uint64_t)du + wt[k] == (uint64_t)dL;
-        }
-        const uint64_t m = __ballot(hit);
-        if (m) found = __shfl(ci[std::min<int64_t>(c + __ffsll((unsigned long long)m) - 1, ke - 1)],
-                              0, kWave);
-      }
-      if (lane == L) p = found;
-    }
-    if (v < n) {
-      if (dv != kInf && p < 0) atomicOr(ctr + S_ERR, 2ull);  // no tight neighbour
-      prev[v] = p;
-    }
+// dist[v] and prev[v] from v's packed word: infinity and -1 where unreached,
+// the source its own predecessor.
+__global__ void k_sssp_unpack(const unsigned long long *__restrict__ dp, int64_t n, int64_t src,
+                              uint32_t *__restrict__ dist, int32_t *__restrict__ prev) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const unsigned long long x = dp[v];
+    const uint32_t d = (uint32_t)(x >> 32);
+    dist[v] = d;
+    prev[v] = d == kInf ? -1 : (v == src ? (int32_t)src : (int32_t)(uint32_t)x);
   }
 }
 
@@ -438,6 +406,7 @@ int grid_blocks(int64_t items, int per_block, int cap) {
 
 SsspWork::~SsspWork() {
   if (pend) (void)hipFree(pend);
+  if (dp) (void)hipFree(dp);
   if (stamp) (void)hipFree(stamp);
   for (auto *p : q)
     if (p) (void)hipFree(p);
@@ -456,6 +425,7 @@ g5_status alloc_sssp(const g5_csr *g, SsspWork **out) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
   };
   A((void **)&w->pend, g->words * 8);
+  A((void **)&w->dp, g->n * 8);
   A((void **)&w->stamp, g->n * 4);
   A((void **)&w->q[0], g->n * 4);
   A((void **)&w->q[1], g->n * 4);
@@ -523,14 +493,14 @@ g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev,
   if (timed) G5_HIP(hipEventRecord(w.ev[0], s));
   uint32_t ep = ++w.epoch;
   hipLaunchKernelGGL(k_sssp_init, dim3(grid_blocks(std::max(n, W), 256, ncu * 16)), dim3(256), 0,
-                     s, dist, n, src, w.pend, W, w.q[0], w.qo[0], g->row_ptr, w.stamp, ep, delta,
+                     s, w.dp, n, src, w.pend, W, w.q[0], w.qo[0], g->row_ptr, w.stamp, ep, delta,
                      ctr);
   G5_LAUNCH_CHECK();
   RelaxArgs a{};
   a.rp = g->row_ptr;
   a.ci = g->col_idx;
   a.wt = g->wt;
-  a.dist = dist;
+  a.dp = w.dp;
   a.pend = w.pend;
   a.stamp = w.stamp;
   a.ctr = ctr;
@@ -552,16 +522,11 @@ g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev,
     if (hc[S_DONE]) break;
   }
   w.epoch = (uint32_t)hc[S_EPOCH];
-  hipLaunchKernelGGL(k_sssp_prev, dim3(grid_blocks(n, kBlock, ncu * 16)), dim3(kBlock), 0, s,
-                     g->row_ptr, g->col_idx, g->wt, (const uint32_t *)dist, n, src, prev, ctr);
+  hipLaunchKernelGGL(k_sssp_unpack, dim3(grid_blocks(n, 256, ncu * 16)), dim3(256), 0, s,
+                     (const unsigned long long *)w.dp, n, src, dist, prev);
   G5_LAUNCH_CHECK();
   if (timed) G5_HIP(hipEventRecord(w.ev[1], s));
-  G5_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
   G5_HIP(hipStreamSynchronize(s));
-  if (hc[S_ERR] & 2) {
-    set_error("g5_sssp: a reached vertex has no tight neighbour (inconsistent distances)");
-    return G5_EDEVICE;
-  }
   if (stats) {
     *stats = g5_sssp_stats{};
     stats->rounds = (int64_t)hc[S_ROUNDS];
