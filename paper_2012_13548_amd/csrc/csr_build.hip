@@ -13,8 +13,8 @@
 //   hubs      list of rows longer than kHubDeg and their kHubChunk-edge pieces
 //             (the batched traversal splits these rows across wavefronts)
 //   rp32      32-bit copy of row_ptr for the traversal (nnz < 2^32 is required)
-//   hint      for each vertex, its highest-degree neighbour (among the first
-//             kHintScan of its row; smallest id on ties): the bottom-up step
+//   hint      for each vertex, its highest-degree neighbour (over its whole
+//             row; smallest id on ties): the bottom-up step
 //             tests it before reading the row (hint_id keeps the ids); bit 30
 //             marks a target that is the vertex's only neighbour (no row to read)
 //   hot       the hint targets named by the most vertices (at most kHotMax of
@@ -29,12 +29,15 @@
 namespace g5 {
 namespace {
 
+// A scatter tile of 7,168 keys puts ~28 keys (224 bytes) of each digit side
+// by side, so its runs cover whole lines; two such workgroups fit a compute
+// unit (measured at 2^31 random 52-bit keys, per pass: 2,048-key tiles
+// 14.6 ms, 4,096 12.6 ms, 7,168 11.1 ms).
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kSortBlock * kSortItems;  // 2048 keys
-constexpr int kWaveKeys = kWave * kSortItems;       // 512 keys per wavefront
+constexpr int kSortItems = 28;
+constexpr int kSortTile = kSortBlock * kSortItems;  // 7,168 keys
+constexpr int kWaveKeys = kWave * kSortItems;       // 1,792 keys per wavefront
 constexpr int kRadix = 256;
-constexpr int kMaxSortBlocks = 2048;
 constexpr int kScanBlock = 1024;
 constexpr int kCompactBlock = 256;
 constexpr int kCompactItems = 16;
@@ -115,9 +118,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_u32(const uint32_t *__restr
 }
 
 // Stable scatter of one 8-bit digit.  Wavefront w of a tile owns keys
-// [w*512, (w+1)*512) in 8 steps of 64; a key's rank inside its wavefront is
-// the count of equal digits in earlier steps (LDS counter) plus earlier lanes
-// of its step (match mask from 8 ballots).
+// [w*kWaveKeys, (w+1)*kWaveKeys) in kSortItems steps of 64; a key's rank
+// inside its wavefront is the count of equal digits in earlier steps (LDS
+// counter) plus earlier lanes of its step (match mask from 8 ballots).  The
+// next tile's keys are loaded while the current one is ranked and written.
 __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     const uint64_t *__restrict__ kin, uint64_t *__restrict__ kout, uint64_t nkeys, int shift,
     int64_t tiles_per_block, int nblocks, const uint64_t *__restrict__ offs) {
@@ -131,6 +135,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
   base[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
   const uint64_t lt = lanemask_lt();
   int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+  uint64_t next[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const uint64_t idx = (uint64_t)t0 * kSortTile + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
+    next[j] = idx < nkeys ? kin[idx] : 0;
+  }
   for (int64_t t = t0; t < t0 + tiles_per_block; ++t) {
     uint64_t tbase = (uint64_t)t * kSortTile;
     if (tbase >= nkeys) break;
@@ -138,10 +148,19 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     uint64_t key[kSortItems];
     uint32_t rank[kSortItems];
 #pragma unroll
+    for (int j = 0; j < kSortItems; ++j) key[j] = next[j];
+    if (t + 1 < t0 + tiles_per_block) {
+#pragma unroll
+      for (int j = 0; j < kSortItems; ++j) {
+        const uint64_t idx = tbase + kSortTile + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
+        next[j] = idx < nkeys ? kin[idx] : 0;
+      }
+    }
+#pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       uint64_t idx = tbase + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
       bool valid = idx < nkeys;
-      uint64_t k = valid ? kin[idx] : 0;
+      uint64_t k = key[j];
       uint32_t d = (uint32_t)(k >> shift) & 0xFF;
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -154,7 +173,6 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
       if (valid && lane == leader) old = atomicAdd(&wh[w][d], (uint32_t)__popcll(peers));
       old = __shfl(old, leader, kWave);
       rank[j] = old + (uint32_t)__popcll(peers & lt);
-      key[j] = k;
     }
     __syncthreads();
     {
@@ -304,17 +322,27 @@ __global__ void k_hub_chunks(const int64_t *__restrict__ rp, const int32_t *__re
   }
 }
 
-constexpr int kHintScan = 1024;
 
-__device__ __forceinline__ uint64_t hint_key(const int64_t *rp, int32_t u) {
+// deg16[v] = min(degree, 0xffff): the degrees the hint scan compares, in an
+// array small enough to stay cached (2 bytes per vertex instead of the two
+// 8-byte row offsets); the few saturated ones are read exactly from rp.
+__global__ void k_deg16(const int64_t *__restrict__ rp, int64_t n, uint16_t *__restrict__ d16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    d16[v] = (uint16_t)std::min<int64_t>(rp[v + 1] - rp[v], 0xffff);
+}
+
+__device__ __forceinline__ uint64_t hint_key(const int64_t *rp, const uint16_t *d16, int32_t u) {
   // larger degree first, then smaller id
-  uint64_t d = (uint64_t)(rp[u + 1] - rp[u]);
+  uint64_t d = d16[u];
+  if (d == 0xffff) d = (uint64_t)(rp[u + 1] - rp[u]);
   return (d << 32) | (uint64_t)(0x7fffffffu - (uint32_t)u);
 }
 
 // hint_id[v] = the target (or -1); hint[v] = the same with kHintOnly set when
 // it is v's only neighbour (only used while n <= 2^30, so ids leave bit 30 free).
 __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
+                                              const uint16_t *__restrict__ d16,
                                               const int32_t *__restrict__ ci, int64_t n,
                                               int64_t words, int32_t *__restrict__ hint,
                                               int32_t *__restrict__ hint_id) {
@@ -330,20 +358,22 @@ __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
     }
     uint64_t best = 0;
     if (e - b <= kWave)
-      for (int64_t k = b; k < e; ++k) best = std::max(best, hint_key(rp, ci[k]));
-    uint64_t rem = __ballot(e - b > kWave);
+      for (int64_t k = b; k < e; ++k) best = std::max(best, hint_key(rp, d16, ci[k]));
+    // rows of up to kHubDeg entries: the wavefront, 64 entries per step; hub
+    // rows are left to k_hint_hubs
+    uint64_t rem = __ballot(e - b > kWave && e - b <= kHubDeg);
     while (rem) {
       const int L = __ffsll((unsigned long long)rem) - 1;
       rem &= rem - 1;
       const int64_t kb = __shfl(b, L, kWave);
-      const int64_t ke = std::min<int64_t>(__shfl(e, L, kWave), kb + kHintScan);
+      const int64_t ke = __shfl(e, L, kWave);
       uint64_t m = 0;
-      for (int64_t k = kb + lane; k < ke; k += kWave) m = std::max(m, hint_key(rp, ci[k]));
+      for (int64_t k = kb + lane; k < ke; k += kWave) m = std::max(m, hint_key(rp, d16, ci[k]));
 #pragma unroll
       for (int d = kWave / 2; d >= 1; d >>= 1) m = std::max(m, (uint64_t)__shfl_xor(m, d, kWave));
       if (lane == L) best = m;
     }
-    if (v < n) {
+    if (v < n && e - b <= kHubDeg) {
       const int32_t t = best ? (int32_t)(0x7fffffffu - (uint32_t)(best & 0xffffffffu)) : -1;
       hint_id[v] = t;
       hint[v] = (t >= 0 && e - b == 1 && n <= (1ll << 30)) ? (t | kHintOnly) : t;
@@ -351,16 +381,74 @@ __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
   }
 }
 
+// Hub rows (longer than kHubDeg) in kHubChunk-edge pieces, one wavefront per
+// piece: the piece's best key goes to best[h] by a 64-bit atomic maximum.
+// off[h] = the first piece of hub h (off[nh] = pieces in all).
+__global__ __launch_bounds__(256) void k_hint_hubs(const int64_t *__restrict__ rp,
+                                                   const uint16_t *__restrict__ d16,
+                                                   const int32_t *__restrict__ ci,
+                                                   const int32_t *__restrict__ hubs,
+                                                   const uint64_t *__restrict__ off, int64_t nh,
+                                                   unsigned long long *__restrict__ best) {
+  const int lane = __lane_id();
+  const int64_t pieces = (int64_t)off[nh];
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; c < pieces; c += nw) {
+    // the hub of piece c: the last h with off[h] <= c
+    int64_t lo = 0, hi = nh;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)off[mid] <= c) lo = mid; else hi = mid;
+    }
+    const int32_t v = hubs[lo];
+    const int64_t kb = rp[v] + (c - (int64_t)off[lo]) * kHubChunk;
+    const int64_t ke = std::min<int64_t>(kb + kHubChunk, rp[v + 1]);
+    uint64_t m = 0;
+    for (int64_t k = kb + lane; k < ke; k += kWave) m = std::max(m, hint_key(rp, d16, ci[k]));
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) m = std::max(m, (uint64_t)__shfl_xor(m, d, kWave));
+    if (lane == 0 && m) atomicMax(best + lo, (unsigned long long)m);
+  }
+}
+
+// The hubs' hints from their best keys (a hub has more than one neighbour, so
+// never kHintOnly).
+__global__ void k_hint_hubs_write(const int32_t *__restrict__ hubs, int64_t nh,
+                                  const unsigned long long *__restrict__ best,
+                                  int32_t *__restrict__ hint, int32_t *__restrict__ hint_id) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < nh) {
+    const uint64_t b = best[h];
+    const int32_t t = b ? (int32_t)(0x7fffffffu - (uint32_t)(b & 0xffffffffu)) : -1;
+    hint_id[hubs[h]] = t;
+    hint[hubs[h]] = t;
+  }
+}
+
 constexpr int kHotBins = 1024;
 constexpr int kHotTile = 4096;  // vertices per workgroup when numbering hot targets
 
-// cnt[t] = number of vertices whose hint is t
+// cnt[t] = number of vertices whose hint is t.  Most vertices name one of a
+// few hubs, so the lanes of a wavefront that name the same target are counted
+// together (one atomic per distinct target per wavefront).
 __global__ void k_hint_count(const int32_t *__restrict__ hint, int64_t n,
                              uint32_t *__restrict__ cnt) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    const int32_t h = hint[v];
-    if (h >= 0) atomicAdd(cnt + (h & ~kHintOnly), 1u);
+  const int lane = __lane_id();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;  // a multiple of kWave
+  const int64_t span = ((n + kWave - 1) / kWave) * kWave;    // every lane runs each round
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < span; v += stride) {
+    const int32_t h = v < n ? hint[v] : -1;
+    const int32_t t = h >= 0 ? (h & ~kHintOnly) : -1;
+    bool todo = t >= 0;
+    uint64_t m;
+    while ((m = __ballot(todo)) != 0) {
+      const int L = __ffsll((unsigned long long)m) - 1;
+      const int32_t tl = __shfl(t, L, kWave);
+      const bool same = todo && t == tl;
+      const uint64_t grp = __ballot(same);
+      if (lane == L) atomicAdd(cnt + tl, (uint32_t)__popcll(grp));
+      if (same) todo = false;
+    }
   }
 }
 
@@ -483,8 +571,12 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
                        m, n, sb, wb, sent, keys, err);
     G5_LAUNCH_CHECK();
     // radix sort
+    // one resident wave of workgroups, each over a contiguous run of tiles
+    int per_cu = 0;
+    G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_radix_downsweep, kSortBlock, 0));
+    const int64_t max_blocks = (int64_t)ncu * std::max(per_cu, 1);
     int64_t tiles = (int64_t)((nkeys + kSortTile - 1) / kSortTile);
-    int64_t tpb = (tiles + kMaxSortBlocks - 1) / kMaxSortBlocks;
+    int64_t tpb = (tiles + max_blocks - 1) / max_blocks;
     int nb = (int)((tiles + tpb - 1) / tpb);
     G5_HIP(hipMalloc(&counts.p, (size_t)kRadix * nb * sizeof(uint32_t)));
     G5_HIP(hipMalloc(&offs.p, (size_t)kRadix * nb * sizeof(uint64_t)));
@@ -580,11 +672,62 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
   if ((e = hipMalloc(&g->rp32, (n + 1) * sizeof(uint32_t))) != hipSuccess) return fail(e, "rp32");
   hipLaunchKernelGGL(k_rp32, dim3(grid_cap(n + 1, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr,
                      n + 1, g->rp32);
+  // hub list (order does not matter) and its chunk prefix
+  const int64_t max_hubs = (int64_t)(nnz / kHubDeg) + 1;
+  if ((e = hipMalloc(&g->hub_list, max_hubs * sizeof(int32_t))) != hipSuccess)
+    return fail(e, "hub list");
+  if ((e = hipMemsetAsync(noniso_dev, 0, 8, s)) != hipSuccess) return fail(e, "memset");
+  hipLaunchKernelGGL(k_find_hubs, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+                     n, g->hub_list, noniso_dev);
+  unsigned long long nh = 0;
+  if ((e = hipMemcpyAsync(&nh, noniso_dev, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+  g->num_hubs = (int64_t)nh;
+  std::vector<uint64_t> off(nh + 1, 0);
+  if ((e = hipMalloc(&g->hub_off, (nh + 1) * sizeof(uint64_t))) != hipSuccess)
+    return fail(e, "hub offsets");
+  if (nh) {
+    hipLaunchKernelGGL(k_hub_chunks, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s,
+                       g->row_ptr, g->hub_list, (int64_t)nh, g->hub_off);
+    if ((e = hipMemcpyAsync(off.data() + 1, g->hub_off, nh * 8, hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return fail(e, "copy");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+    for (size_t i = 1; i <= nh; ++i) off[i] += off[i - 1];
+  }
+  g->hub_chunks = (int64_t)off[nh];
+  if ((e = hipMemcpyAsync(g->hub_off, off.data(), (nh + 1) * 8, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return fail(e, "copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   if ((e = hipMalloc(&g->hint, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
   if ((e = hipMalloc(&g->hint_id, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
-  hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
-                     g->col_idx, n, g->words, g->hint, g->hint_id);
-  if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+  {
+    DevBuf d16;
+    if ((e = d16.alloc(n * sizeof(uint16_t))) != hipSuccess) return fail(e, "degrees");
+    hipLaunchKernelGGL(k_deg16, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr, n,
+                       (uint16_t *)d16.p);
+    hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+                       (const uint16_t *)d16.p, g->col_idx, n, g->words, g->hint, g->hint_id);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+    if (g->num_hubs > 0) {
+      DevBuf best;
+      const int64_t nh = g->num_hubs;
+      if ((e = best.alloc(nh * sizeof(unsigned long long))) != hipSuccess) return fail(e, "hints");
+      if ((e = hipMemsetAsync(best.p, 0, nh * sizeof(unsigned long long), s)) != hipSuccess)
+        return fail(e, "memset");
+      hipLaunchKernelGGL(k_hint_hubs, dim3(grid_cap(g->hub_chunks, 4, ncu * 16)), dim3(256), 0, s,
+                         g->row_ptr, (const uint16_t *)d16.p, g->col_idx, g->hub_list,
+                         (const uint64_t *)g->hub_off, nh, (unsigned long long *)best.p);
+      hipLaunchKernelGGL(k_hint_hubs_write, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s,
+                         g->hub_list, nh, (const unsigned long long *)best.p, g->hint, g->hint_id);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+    }
+    // d16 is freed on return from this scope: the stream must be done with it
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+  }
   {
     // hot hint targets: the most-named ones, at most kHotMax, numbered in vertex order
     const int64_t nb = (n + kHotTile - 1) / kHotTile;
@@ -632,35 +775,6 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   }
 
-  // hub list (order does not matter) and its chunk prefix
-  const int64_t max_hubs = (int64_t)(nnz / kHubDeg) + 1;
-  if ((e = hipMalloc(&g->hub_list, max_hubs * sizeof(int32_t))) != hipSuccess)
-    return fail(e, "hub list");
-  if ((e = hipMemsetAsync(noniso_dev, 0, 8, s)) != hipSuccess) return fail(e, "memset");
-  hipLaunchKernelGGL(k_find_hubs, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr,
-                     n, g->hub_list, noniso_dev);
-  unsigned long long nh = 0;
-  if ((e = hipMemcpyAsync(&nh, noniso_dev, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
-    return fail(e, "copy");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
-  g->num_hubs = (int64_t)nh;
-  std::vector<uint64_t> off(nh + 1, 0);
-  if ((e = hipMalloc(&g->hub_off, (nh + 1) * sizeof(uint64_t))) != hipSuccess)
-    return fail(e, "hub offsets");
-  if (nh) {
-    hipLaunchKernelGGL(k_hub_chunks, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s,
-                       g->row_ptr, g->hub_list, (int64_t)nh, g->hub_off);
-    if ((e = hipMemcpyAsync(off.data() + 1, g->hub_off, nh * 8, hipMemcpyDeviceToHost, s)) !=
-        hipSuccess)
-      return fail(e, "copy");
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
-    for (size_t i = 1; i <= nh; ++i) off[i] += off[i - 1];
-  }
-  g->hub_chunks = (int64_t)off[nh];
-  if ((e = hipMemcpyAsync(g->hub_off, off.data(), (nh + 1) * 8, hipMemcpyHostToDevice, s)) !=
-      hipSuccess)
-    return fail(e, "copy");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   *out = g;
   return G5_OK;
 }
