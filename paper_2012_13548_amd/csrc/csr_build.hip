@@ -23,6 +23,8 @@
 //             bottom-up step tests a per-level bitmap of kHotMax bits (small
 //             enough to stay in L2) instead of a random word of the frontier
 #include <algorithm>
+#include <functional>
+#include <vector>
 
 #include "g5_internal.h"
 
@@ -247,6 +249,8 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
   // The tile (and the key before it) staged in LDS by coalesced loads: thread t
   // then takes its 16 consecutive keys from there (the compaction keeps key
   // order, so a thread's keys must be consecutive).  Past the end: sentinels.
+  // The same LDS then gathers the tile's kept entries, which the block writes
+  // out with coalesced stores.
   __shared__ uint64_t s_k[kCompactTile + 1];
   const uint64_t t0 = (uint64_t)blockIdx.x * kCompactTile;
   for (int x = threadIdx.x; x <= kCompactTile; x += kCompactBlock) {
@@ -255,33 +259,50 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
   }
   __syncthreads();
   const int x0 = threadIdx.x * kCompactItems + 1;  // s_k index of this thread's first key
-  uint64_t b = t0 + (uint64_t)threadIdx.x * kCompactItems;
+  const uint64_t b = t0 + (uint64_t)threadIdx.x * kCompactItems;
+  uint64_t kk[kCompactItems + 1];  // kk[0]: the key before this thread's first
+#pragma unroll
+  for (int j = 0; j <= kCompactItems; ++j) kk[j] = s_k[x0 - 1 + j];
   uint32_t c = 0;
+#pragma unroll
   for (int j = 0; j < kCompactItems; ++j) {
-    const uint64_t k = s_k[x0 + j];
-    if (b + j < nkeys && k != sent && (s_k[x0 + j - 1] >> wb) != (k >> wb)) ++c;
+    const uint64_t k = kk[j + 1];
+    if (b + j < nkeys && k != sent && (kk[j] >> wb) != (k >> wb)) ++c;
   }
   uint32_t tot;
-  uint64_t pos = boff[blockIdx.x] + block_excl_scan<kCompactBlock, uint32_t>(c, s, tot);
+  const uint32_t local0 = block_excl_scan<kCompactBlock, uint32_t>(c, s, tot);
+  __syncthreads();  // every thread holds its keys: s_k is reused for the output
+  int32_t *s_col = reinterpret_cast<int32_t *>(s_k);
+  uint8_t *s_wt = reinterpret_cast<uint8_t *>(s_col + kCompactTile);
+  uint64_t pos = boff[blockIdx.x] + local0;
+  uint32_t local = local0;
   const uint64_t vmask = (1ull << sb) - 1;
+#pragma unroll
   for (int j = 0; j < kCompactItems; ++j) {
-    uint64_t i = b + j;
+    const uint64_t i = b + j;
     if (i >= nkeys) break;
-    uint64_t k = s_k[x0 + j];
-    uint64_t prev = s_k[x0 + j - 1];  // the sentinel before key 0
-    int64_t up = i ? (int64_t)(prev >> (sb + wb)) : -1;
+    const uint64_t k = kk[j + 1];
+    const uint64_t prev = kk[j];  // the sentinel before key 0
+    const int64_t up = i ? (int64_t)(prev >> (sb + wb)) : -1;
     if (k != sent) {
       if (i == 0 || (prev >> wb) != (k >> wb)) {
-        col_idx[pos] = (int32_t)((k >> wb) & vmask);
-        if (wt) wt[pos] = (uint8_t)(k & 0xffu);
-        int64_t u = std::min<int64_t>((int64_t)(k >> (sb + wb)), n - 1);
+        s_col[local] = (int32_t)((k >> wb) & vmask);
+        if (wt) s_wt[local] = (uint8_t)(k & 0xffu);
+        const int64_t u = std::min<int64_t>((int64_t)(k >> (sb + wb)), n - 1);
         for (int64_t r = up + 1; r <= u; ++r) row_ptr[r] = (int64_t)pos;
         ++pos;
+        ++local;
       }
     } else if (i == 0 || prev != sent) {
       // first sentinel: rows after the last stored key are empty
       for (int64_t r = up + 1; r <= n; ++r) row_ptr[r] = (int64_t)pos;
     }
+  }
+  __syncthreads();
+  const uint64_t base = boff[blockIdx.x];
+  for (uint32_t x = threadIdx.x; x < tot; x += kCompactBlock) {
+    col_idx[base + x] = s_col[x];
+    if (wt) wt[base + x] = s_wt[x];
   }
 }
 
@@ -339,13 +360,127 @@ __device__ __forceinline__ uint64_t hint_key(const int64_t *rp, const uint16_t *
   return (d << 32) | (uint64_t)(0x7fffffffu - (uint32_t)u);
 }
 
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) x |= __shfl_xor(x, d, kWave);
+  return x;
+}
+
+// Hint candidates: the kHintCand vertices of largest key (degree, then smaller
+// id), in key order, held by every workgroup in an LDS hash table (id -> rank).
+// Any candidate's key exceeds that of every other vertex, so when a row holds
+// a candidate its best key is that of its smallest-rank candidate; only rows
+// without one need the degrees of their entries (about 1 % of the entries of
+// the Kronecker graphs).
+constexpr int kHintCand = 2048;
+constexpr int kCandSlots = 8192;  // load factor 1/4
+constexpr uint64_t kNone = ~0ull;
+
+struct CandSet {
+  int32_t *id;     // kCandSlots, -1 = empty
+  uint16_t *rank;  // kCandSlots
+  __device__ __forceinline__ static uint32_t slot(int32_t u) {
+    return ((uint32_t)u * 0x9E3779B1u) >> (32 - 13);
+  }
+  // every thread of the block takes part
+  __device__ void fill(const int32_t *__restrict__ cand, int kc) {
+    for (int x = threadIdx.x; x < kCandSlots; x += blockDim.x) id[x] = -1;
+    __syncthreads();
+    for (int r = threadIdx.x; r < kc; r += blockDim.x) {
+      const int32_t u = cand[r];
+      uint32_t x = slot(u);
+      while (atomicCAS(&id[x], -1, u) != -1) x = (x + 1) & (kCandSlots - 1);
+      rank[x] = (uint16_t)r;
+    }
+    __syncthreads();
+  }
+  __device__ __forceinline__ uint64_t rank_of(int32_t u) const {
+    uint32_t x = slot(u);
+    while (true) {
+      const int32_t y = id[x];
+      if (y == u) return rank[x];
+      if (y < 0) return kNone;
+      x = (x + 1) & (kCandSlots - 1);
+    }
+  }
+};
+
+// Rows of a wavefront's 64 lanes (len entries from 32-bit offset b32 each)
+// laid end to end, one entry per lane per 64-entry window; f(u) maps each
+// entry to a value and the values of a row are combined by `comb` (a
+// segmented scan over the lanes of each window).  Returns the lane's own
+// row's value (ident for an empty row).
+template <class F, class C>
+__device__ uint64_t packed_rows(uint32_t len, uint32_t b32, uint64_t ident, const int32_t *ci,
+                                F f, C comb, uint32_t *s_base, int32_t *s_row, uint64_t *s_acc) {
+  const int lane = __lane_id();
+  const int wb = (threadIdx.x / kWave) * kWave;
+  const uint64_t upto_mask = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+  const uint32_t incl = wave_incl_scan(len);
+  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  const uint32_t pre = incl - len;
+  // row entry j of the window sits at s_base[r] + j: b - pre + j lies in
+  // [0, nnz) < 2^32, so 32-bit wrap-around arithmetic gives it exactly
+  s_base[wb + lane] = b32 - pre;
+  s_acc[wb + lane] = ident;
+  int carry = 0;
+  for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
+    const bool starts = len > 0 && pre >= j0 && pre < j0 + kWave;
+    if (starts) s_row[wb + (int)(pre - j0)] = lane;
+    const uint64_t S = wave_or(starts ? (1ull << (pre - j0)) : 0ull);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint64_t upto = S & upto_mask;
+    const int r = upto ? s_row[wb + (kWave - 1 - __clzll((long long)upto))] : carry;
+    const uint32_t j = j0 + lane;
+    uint64_t val = ident;
+    if (j < total) val = f(ci[(uint32_t)(s_base[wb + r] + j)]);
+#pragma unroll
+    for (int dd = 1; dd < kWave; dd <<= 1) {
+      const uint64_t o = __shfl_up(val, dd, kWave);
+      const int orow = __shfl_up(r, dd, kWave);
+      if (lane >= dd && orow == r) val = comb(val, o);
+    }
+    const int nrow = __shfl_down(r, 1, kWave);
+    if (j < total && (lane == kWave - 1 || j + 1 == total || nrow != r))
+      s_acc[wb + r] = comb(s_acc[wb + r], val);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    carry = __shfl(r, kWave - 1, kWave);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const uint64_t out = s_acc[wb + lane];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  return out;
+}
+
+struct MinOp {
+  __device__ __forceinline__ uint64_t operator()(uint64_t a, uint64_t b) const {
+    return a < b ? a : b;
+  }
+};
+struct MaxOp {
+  __device__ __forceinline__ uint64_t operator()(uint64_t a, uint64_t b) const {
+    return a > b ? a : b;
+  }
+};
+
 // hint_id[v] = the target (or -1); hint[v] = the same with kHintOnly set when
 // it is v's only neighbour (only used while n <= 2^30, so ids leave bit 30 free).
+// A wavefront takes 64 consecutive vertices (hub rows aside, see k_hint_hubs):
+// first the candidate ranks of their entries (LDS lookups), then, for rows
+// without a candidate, the keys of their entries.
 __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
                                               const uint16_t *__restrict__ d16,
                                               const int32_t *__restrict__ ci, int64_t n,
-                                              int64_t words, int32_t *__restrict__ hint,
+                                              int64_t words, const int32_t *__restrict__ cand,
+                                              int kc, int32_t *__restrict__ hint,
                                               int32_t *__restrict__ hint_id) {
+  __shared__ uint32_t s_base[256];
+  __shared__ int32_t s_row[256];
+  __shared__ uint64_t s_acc[256];
+  __shared__ int32_t s_cid[kCandSlots];
+  __shared__ uint16_t s_crank[kCandSlots];
+  CandSet cs{s_cid, s_crank};
+  cs.fill(cand, kc);
   const int lane = __lane_id();
   const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -356,40 +491,43 @@ __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
       b = rp[v];
       e = rp[v + 1];
     }
-    uint64_t best = 0;
-    if (e - b <= kWave)
-      for (int64_t k = b; k < e; ++k) best = std::max(best, hint_key(rp, d16, ci[k]));
-    // rows of up to kHubDeg entries: the wavefront, 64 entries per step; hub
-    // rows are left to k_hint_hubs
-    uint64_t rem = __ballot(e - b > kWave && e - b <= kHubDeg);
-    while (rem) {
-      const int L = __ffsll((unsigned long long)rem) - 1;
-      rem &= rem - 1;
-      const int64_t kb = __shfl(b, L, kWave);
-      const int64_t ke = __shfl(e, L, kWave);
-      uint64_t m = 0;
-      for (int64_t k = kb + lane; k < ke; k += kWave) m = std::max(m, hint_key(rp, d16, ci[k]));
-#pragma unroll
-      for (int d = kWave / 2; d >= 1; d >>= 1) m = std::max(m, (uint64_t)__shfl_xor(m, d, kWave));
-      if (lane == L) best = m;
-    }
-    if (v < n && e - b <= kHubDeg) {
-      const int32_t t = best ? (int32_t)(0x7fffffffu - (uint32_t)(best & 0xffffffffu)) : -1;
+    const int64_t d = e - b;
+    const uint32_t len = d <= kHubDeg ? (uint32_t)d : 0u;
+    uint64_t rank = kNone;
+    if (kc > 0)
+      rank = packed_rows(len, (uint32_t)b, kNone, ci, [&](int32_t u) { return cs.rank_of(u); },
+                         MinOp(), s_base, s_row, s_acc);
+    const uint64_t best =
+        packed_rows(rank == kNone ? len : 0u, (uint32_t)b, 0ull, ci,
+                    [&](int32_t u) { return hint_key(rp, d16, u); }, MaxOp(), s_base, s_row, s_acc);
+    if (v < n && d <= kHubDeg) {
+      const int32_t t = rank != kNone ? cand[rank]
+                                      : (best ? (int32_t)(0x7fffffffu - (uint32_t)(best & 0xffffffffu))
+                                              : -1);
       hint_id[v] = t;
-      hint[v] = (t >= 0 && e - b == 1 && n <= (1ll << 30)) ? (t | kHintOnly) : t;
+      hint[v] = (t >= 0 && d == 1 && n <= (1ll << 30)) ? (t | kHintOnly) : t;
     }
   }
 }
 
 // Hub rows (longer than kHubDeg) in kHubChunk-edge pieces, one wavefront per
-// piece: the piece's best key goes to best[h] by a 64-bit atomic maximum.
+// piece.  RANKED: the piece's smallest candidate rank goes to best[h] by an
+// atomic minimum; otherwise (hubs left without a candidate, best[h] = kNone)
+// the piece's best key goes to key[h] by an atomic maximum.
 // off[h] = the first piece of hub h (off[nh] = pieces in all).
+template <bool RANKED>
 __global__ __launch_bounds__(256) void k_hint_hubs(const int64_t *__restrict__ rp,
                                                    const uint16_t *__restrict__ d16,
                                                    const int32_t *__restrict__ ci,
                                                    const int32_t *__restrict__ hubs,
                                                    const uint64_t *__restrict__ off, int64_t nh,
-                                                   unsigned long long *__restrict__ best) {
+                                                   const int32_t *__restrict__ cand, int kc,
+                                                   unsigned long long *__restrict__ best,
+                                                   unsigned long long *__restrict__ key) {
+  __shared__ int32_t s_cid[RANKED ? kCandSlots : 1];
+  __shared__ uint16_t s_crank[RANKED ? kCandSlots : 1];
+  CandSet cs{s_cid, s_crank};
+  if (RANKED) cs.fill(cand, kc);
   const int lane = __lane_id();
   const int64_t pieces = (int64_t)off[nh];
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -400,26 +538,52 @@ __global__ __launch_bounds__(256) void k_hint_hubs(const int64_t *__restrict__ r
       const int64_t mid = (lo + hi) >> 1;
       if ((int64_t)off[mid] <= c) lo = mid; else hi = mid;
     }
+    if (!RANKED && best[lo] != kNone) continue;  // wave-uniform
     const int32_t v = hubs[lo];
     const int64_t kb = rp[v] + (c - (int64_t)off[lo]) * kHubChunk;
     const int64_t ke = std::min<int64_t>(kb + kHubChunk, rp[v + 1]);
-    uint64_t m = 0;
-    for (int64_t k = kb + lane; k < ke; k += kWave) m = std::max(m, hint_key(rp, d16, ci[k]));
+    uint64_t m = RANKED ? kNone : 0;
+    for (int64_t k = kb + lane; k < ke; k += kWave) {
+      const int32_t u = ci[k];
+      if (RANKED)
+        m = std::min(m, cs.rank_of(u));
+      else
+        m = std::max(m, hint_key(rp, d16, u));
+    }
 #pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) m = std::max(m, (uint64_t)__shfl_xor(m, d, kWave));
-    if (lane == 0 && m) atomicMax(best + lo, (unsigned long long)m);
+    for (int dd = kWave / 2; dd >= 1; dd >>= 1) {
+      const uint64_t o = __shfl_xor(m, dd, kWave);
+      m = RANKED ? std::min(m, o) : std::max(m, o);
+    }
+    if (lane == 0) {
+      if (RANKED && m != kNone) atomicMin(best + lo, (unsigned long long)m);
+      if (!RANKED && m) atomicMax(key + lo, (unsigned long long)m);
+    }
   }
 }
 
-// The hubs' hints from their best keys (a hub has more than one neighbour, so
-// never kHintOnly).
+// key[h] = hint_key of hub h (degree, then smaller id).
+__global__ void k_hub_keys(const int64_t *__restrict__ rp, const int32_t *__restrict__ hubs,
+                           int64_t nh, uint64_t *__restrict__ key) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < nh) {
+    const int32_t u = hubs[h];
+    key[h] = ((uint64_t)(rp[u + 1] - rp[u]) << 32) | (uint64_t)(0x7fffffffu - (uint32_t)u);
+  }
+}
+
+// The hubs' hints from their best candidate ranks, or else their best keys (a
+// hub has more than one neighbour, so never kHintOnly).
 __global__ void k_hint_hubs_write(const int32_t *__restrict__ hubs, int64_t nh,
                                   const unsigned long long *__restrict__ best,
+                                  const unsigned long long *__restrict__ key,
+                                  const int32_t *__restrict__ cand,
                                   int32_t *__restrict__ hint, int32_t *__restrict__ hint_id) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (h < nh) {
-    const uint64_t b = best[h];
-    const int32_t t = b ? (int32_t)(0x7fffffffu - (uint32_t)(b & 0xffffffffu)) : -1;
+    const uint64_t r = best[h], b = key[h];
+    const int32_t t = r != kNone ? cand[r]
+                                 : (b ? (int32_t)(0x7fffffffu - (uint32_t)(b & 0xffffffffu)) : -1);
     hint_id[hubs[h]] = t;
     hint[hubs[h]] = t;
   }
@@ -704,28 +868,58 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
   if ((e = hipMalloc(&g->hint, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
   if ((e = hipMalloc(&g->hint_id, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
   {
-    DevBuf d16;
+    DevBuf d16, cand, hkeys, best, key;
     if ((e = d16.alloc(n * sizeof(uint16_t))) != hipSuccess) return fail(e, "degrees");
     hipLaunchKernelGGL(k_deg16, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr, n,
                        (uint16_t *)d16.p);
-    hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
-                       (const uint16_t *)d16.p, g->col_idx, n, g->words, g->hint, g->hint_id);
-    if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
-    if (g->num_hubs > 0) {
-      DevBuf best;
-      const int64_t nh = g->num_hubs;
-      if ((e = best.alloc(nh * sizeof(unsigned long long))) != hipSuccess) return fail(e, "hints");
-      if ((e = hipMemsetAsync(best.p, 0, nh * sizeof(unsigned long long), s)) != hipSuccess)
-        return fail(e, "memset");
-      hipLaunchKernelGGL(k_hint_hubs, dim3(grid_cap(g->hub_chunks, 4, ncu * 16)), dim3(256), 0, s,
-                         g->row_ptr, (const uint16_t *)d16.p, g->col_idx, g->hub_list,
-                         (const uint64_t *)g->hub_off, nh, (unsigned long long *)best.p);
-      hipLaunchKernelGGL(k_hint_hubs_write, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s,
-                         g->hub_list, nh, (const unsigned long long *)best.p, g->hint, g->hint_id);
-      if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+    // hint candidates: the hubs of largest key (every hub outranks every other
+    // vertex), ordered on the host
+    const int64_t nh = g->num_hubs;
+    const int kc = (int)std::min<int64_t>(nh, kHintCand);
+    if (nh > 0) {
+      if ((e = hkeys.alloc(nh * sizeof(uint64_t))) != hipSuccess ||
+          (e = cand.alloc(kc * sizeof(int32_t))) != hipSuccess ||
+          (e = best.alloc(nh * sizeof(uint64_t))) != hipSuccess ||
+          (e = key.alloc(nh * sizeof(uint64_t))) != hipSuccess)
+        return fail(e, "hints");
+      hipLaunchKernelGGL(k_hub_keys, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s,
+                         g->row_ptr, g->hub_list, nh, (uint64_t *)hkeys.p);
+      std::vector<uint64_t> hk(nh);
+      if ((e = hipMemcpyAsync(hk.data(), hkeys.p, nh * 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return fail(e, "copy");
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+      std::partial_sort(hk.begin(), hk.begin() + kc, hk.end(), std::greater<uint64_t>());
+      std::vector<int32_t> ids(kc);
+      for (int r = 0; r < kc; ++r) ids[r] = (int32_t)(0x7fffffffu - (uint32_t)(hk[r] & 0xffffffffu));
+      if ((e = hipMemcpyAsync(cand.p, ids.data(), kc * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+          (e = hipMemsetAsync(best.p, 0xff, nh * 8, s)) != hipSuccess ||
+          (e = hipMemsetAsync(key.p, 0, nh * 8, s)) != hipSuccess)
+        return fail(e, "copy");
+      // ids is read by the copy: keep it until the stream has taken it
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
     }
-    // d16 is freed on return from this scope: the stream must be done with it
+    hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+                       (const uint16_t *)d16.p, g->col_idx, n, g->words,
+                       (const int32_t *)cand.p, kc, g->hint, g->hint_id);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+    if (nh > 0) {
+      const dim3 grid(grid_cap(g->hub_chunks, 4, ncu * 16));
+      hipLaunchKernelGGL(k_hint_hubs<true>, grid, dim3(256), 0, s, g->row_ptr,
+                         (const uint16_t *)d16.p, g->col_idx, g->hub_list,
+                         (const uint64_t *)g->hub_off, nh, (const int32_t *)cand.p, kc,
+                         (unsigned long long *)best.p, (unsigned long long *)key.p);
+      hipLaunchKernelGGL(k_hint_hubs<false>, grid, dim3(256), 0, s, g->row_ptr,
+                         (const uint16_t *)d16.p, g->col_idx, g->hub_list,
+                         (const uint64_t *)g->hub_off, nh, (const int32_t *)cand.p, kc,
+                         (unsigned long long *)best.p, (unsigned long long *)key.p);
+      hipLaunchKernelGGL(k_hint_hubs_write, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s,
+                         g->hub_list, nh, (const unsigned long long *)best.p,
+                         (const unsigned long long *)key.p, (const int32_t *)cand.p, g->hint,
+                         g->hint_id);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
+    }
+    // the buffers of this scope are freed on return from it: the stream must
+    // be done with them
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   }
   {
