@@ -303,23 +303,26 @@ def gather_calibration(fr, sr, copy_split):
     it): the copy probe gives the bytes one request moves on a stream; the
     gather's requests beyond those of its index stream, per random pick, show
     whether scattered 8-byte reads cost one such request each."""
+    # the probe's gather is the run's first indexing dispatch (the probes run
+    # before the workload)
     is_take = lambda name: "index_elementwise_kernel" in name
     req = _per_dispatch_map(sr, "TCC_EA0_RDREQ_sum", is_take)
     fetch = _per_dispatch_map(fr, "FETCH_SIZE", is_take)
     copy_req = copy_split.get("TCC_EA0_RDREQ_sum")
     if not req or not copy_req:
         return None
-    r = max(req.values())
+    r = req[min(req)]
     per_req = COPY_PROBE_BYTES / copy_req
     index_req = GATHER_PICKS * 8 / per_req
     return {"picks": GATHER_PICKS, "read_requests": int(r),
             "stream_bytes_per_request": round(per_req, 2),
             "index_requests": int(index_req),
             "requests_per_pick": round((r - index_req) / GATHER_PICKS, 4),
-            "fetch_size_kib": round(max(fetch.values()), 1) if fetch else None}
+            "fetch_size_kib": round(fetch[min(fetch)], 1) if fetch else None}
 
 
-def summarize_trace(db, command, bench_json=None):
+def summarize_trace(db, command, bench_json=None,
+                    title="Kernel trace: scale-26 single-root BFS benchmark"):
     """Markdown summary of a rocprofv3 kernel trace (its SQLite database): the
     busiest kernels, and each step kernel's average over working launches,
     which is what the bench's avg_launch_ms measures with HIP events."""
@@ -338,7 +341,7 @@ def summarize_trace(db, command, bench_json=None):
         a[0] += 1
         a[1] += (t1 - t0) / 1e3
     total = sum(a[1] for a in agg.values())
-    out = ["# Kernel trace: scale-26 single-root BFS benchmark", "",
+    out = [f"# {title}", "",
            "Command (from the repository root):", "", "```", command, "```", "",
            "Durations are rocprofv3 kernel-trace dispatch times (microseconds), over the",
            "whole command (graph generation and CSR build, accounting pass, warm-up and",
@@ -353,6 +356,8 @@ def summarize_trace(db, command, bench_json=None):
         bench = json.loads(line)
     for kernel in ("k_bu_step", "k_bu_step_lds"):
         d = [(t1 - t0) / 1e3 for name, t0, t1 in rows if step_kernel_of(name) == kernel]
+        if not d:
+            continue
         work = [x for x in d if x > NOOP_US]
         out += ["", f"## {kernel} (timed variant, without byte counting)", "",
                 f"* dispatches: {len(d)}, of which {len(d) - len(work)} are steps queued ahead "
@@ -369,7 +374,36 @@ def summarize_trace(db, command, bench_json=None):
                 out.append(f"* the same run's bench line: {a['launches']} instrumented launches, "
                            f"{a['ms']} ms in all, avg {a['ms'] / max(a['launches'], 1):.4f} ms "
                            f"(HIP events)")
+    out += csr_build_section(rows, short)
     print("\n".join(out))
+
+
+def csr_build_section(rows, short):
+    """The CSR build of the largest graph in a kernel trace: its kernels from
+    the longest packing dispatch up to the first traversal after it."""
+    packs = [(t1 - t0, t0) for name, t0, t1 in rows if short(name) == "k_pack"]
+    if not packs:
+        return []
+    start = max(packs)[1]
+    after = [t0 for name, t0, t1 in rows if short(name) == "k_bfs_init" and t0 > start]
+    stop = min(after) if after else float("inf")
+    agg, last = {}, start
+    for name, t0, t1 in rows:
+        if start <= t0 < stop and short(name).startswith("k_"):
+            a = agg.setdefault(short(name), [0, 0.0])
+            a[0] += 1
+            a[1] += (t1 - t0) / 1e3
+            last = max(last, t1)
+    total = sum(a[1] for a in agg.values())
+    out = ["", "## CSR build of the scale-26 graph", "",
+           f"Kernel time {total / 1e3:.1f} ms; first kernel start to last kernel end "
+           f"{(last - start) / 1e6:.1f} ms (the build's own kernels; its copies and fills "
+           "and the host's reads of counts lie in between).", "",
+           "| kernel | calls | total ms | % |", "|---|---:|---:|---:|"]
+    for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        if t >= 10.0:
+            out.append(f"| `{k}` | {n} | {t / 1e3:.2f} | {100 * t / total:.1f} |")
+    return out
 
 
 def run_gpu(args):
@@ -823,6 +857,7 @@ def main():
     ap.add_argument("--summarize-trace", nargs="+", metavar=("DB", "BENCH_JSON"),
                     help="print a markdown summary of a rocprofv3 kernel-trace database")
     ap.add_argument("--trace-command", default="", help="command recorded with --summarize-trace")
+    ap.add_argument("--trace-title", default="", help="heading of the --summarize-trace summary")
     ap.add_argument("--alg3-curve", action="store_true",
                     help="time the host experiment (the paper's parallel level-synchronous BFS "
                          "with OpenMP) over thread counts, print one JSON line and exit")
@@ -834,7 +869,8 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace[0], args.trace_command,
-                        args.summarize_trace[1] if len(args.summarize_trace) > 1 else None)
+                        args.summarize_trace[1] if len(args.summarize_trace) > 1 else None,
+                        **({"title": args.trace_title} if args.trace_title else {}))
         return
     if args.reduce_pmc:
         reduce_pmc(args.reduce_pmc[0], args.reduce_pmc[1],
