@@ -374,6 +374,16 @@ def summarize_trace(db, command, bench_json=None,
                 out.append(f"* the same run's bench line: {a['launches']} instrumented launches, "
                            f"{a['ms']} ms in all, avg {a['ms'] / max(a['launches'], 1):.4f} ms "
                            f"(HIP events)")
+    d = [(t1 - t0) / 1e3 for name, t0, t1 in rows if short(name) == "k_sssp_step"]
+    if d:
+        work = [x for x in d if x > NOOP_US]
+        out += ["", "## k_sssp_step", "",
+                f"* dispatches: {len(d)}, of which {len(d) - len(work)} are steps queued past "
+                f"the end or steps with little work (< {NOOP_US:.0f} us)",
+                f"* the others: {len(work)}, average {sum(work) / max(len(work), 1):.2f} us, "
+                f"longest {max(work, default=0.0):.1f} us, {sum(work) / 1e3:.1f} ms in all"]
+        if bench and bench.get("sssp"):
+            out.append(f"* the same run's bench line: {bench['sssp']}")
     out += csr_build_section(rows, short)
     print("\n".join(out))
 
@@ -384,18 +394,23 @@ def csr_build_section(rows, short):
     packs = [(t1 - t0, t0) for name, t0, t1 in rows if short(name) == "k_pack"]
     if not packs:
         return []
+    build = ("k_pack", "k_radix_", "k_scan_u32", "k_set_u64", "k_heads_count", "k_compact",
+             "k_iso", "k_rp32", "k_find_hubs", "k_hub_", "k_deg16", "k_hint", "k_hot_")
+    is_build = lambda k: k.startswith(build)
     start = max(packs)[1]
-    after = [t0 for name, t0, t1 in rows if short(name) == "k_bfs_init" and t0 > start]
+    # up to the first other kernel of the library after the packing
+    after = [t0 for name, t0, t1 in rows
+             if t0 > start and short(name).startswith("k_") and not is_build(short(name))]
     stop = min(after) if after else float("inf")
     agg, last = {}, start
     for name, t0, t1 in rows:
-        if start <= t0 < stop and short(name).startswith("k_"):
+        if start <= t0 < stop and is_build(short(name)):
             a = agg.setdefault(short(name), [0, 0.0])
             a[0] += 1
             a[1] += (t1 - t0) / 1e3
             last = max(last, t1)
     total = sum(a[1] for a in agg.values())
-    out = ["", "## CSR build of the scale-26 graph", "",
+    out = ["", "## CSR build of the largest graph of the run", "",
            f"Kernel time {total / 1e3:.1f} ms; first kernel start to last kernel end "
            f"{(last - start) / 1e6:.1f} ms (the build's own kernels; its copies and fills "
            "and the host's reads of counts lie in between).", "",
@@ -483,6 +498,9 @@ def run_gpu(args):
     # the library's stream.  It is kept out of the timed steps because timed
     # dispatches slow the whole traversal by ~6 %.
     stats = [g5.bfs(csr, r, parent, level, time_steps=True)[2] for r in roots]
+    # the run's last traversal is a plain one from the first root: counter
+    # runs of this command read its levels in dispatch order
+    g5.bfs(csr, roots[0], parent, level)
     torch.cuda.synchronize()
     steps = step_table(stats, acct, work, n)
     log(f"instrumented pass done: {len(steps)} step kernels timed")
