@@ -71,6 +71,16 @@ enum Ctr : int {
   C_NCTR = 21
 };
 
+// Every access to the counters is a device-scope atomic: they are written by
+// one workgroup and read by the workgroups of the next kernel, which may run on
+// another XCD whose L2 holds an older copy of the line.
+__device__ __forceinline__ unsigned long long ctr_ld(const unsigned long long *ctr, int i) {
+  return __hip_atomic_load(ctr + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ctr_st(unsigned long long *ctr, int i, unsigned long long v) {
+  __hip_atomic_store(ctr + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Copies the counters to host memory.  Each 8-byte slot carries the low 16
 // bits of the sequence number above a 48-bit value, so every slot is complete
 // by itself and no release fence (a write-back of L2) is needed; the host waits
@@ -138,18 +148,19 @@ __device__ void td_decide(unsigned long long *ctr, int qs, int32_t lvl, bool fro
        ((double)mf > (double)mu / rule.alpha ||
         (rule.gamma > 0 && (double)mf > rule.gamma * (double)unv)));
   const bool go = qlen > 0 && !to_bu;
-  ctr[C_HEAVY] = (go && growing && rule.dirmode == G5_DIR_AUTO && rule.heavy_edges > 0 &&
-                  mf > rule.heavy_edges)
-                     ? 1ull
-                     : 0ull;
-  ctr[C_MU] = (unsigned long long)mu;
-  ctr[C_UNV] = (unsigned long long)unv;
-  ctr[C_MF] = mf;
-  ctr[C_GO] = go ? 1ull : 0ull;
-  ctr[C_ENDL] = qlen == 0 ? (unsigned long long)(lvl + 1) : 0ull;
-  if (go) ctr[C_LASTNF] = (unsigned long long)qlen;
-  ctr[C_QLEN0 + qs] = (unsigned long long)qlen;
-  ctr[C_QP0 + (qs ^ 1)] = 0;
+  ctr_st(ctr, C_HEAVY,
+         (go && growing && rule.dirmode == G5_DIR_AUTO && rule.heavy_edges > 0 &&
+          mf > rule.heavy_edges)
+             ? 1ull
+             : 0ull);
+  ctr_st(ctr, C_MU, (unsigned long long)mu);
+  ctr_st(ctr, C_UNV, (unsigned long long)unv);
+  ctr_st(ctr, C_MF, mf);
+  ctr_st(ctr, C_GO, go ? 1ull : 0ull);
+  ctr_st(ctr, C_ENDL, qlen == 0 ? (unsigned long long)(lvl + 1) : 0ull);
+  if (go) ctr_st(ctr, C_LASTNF, (unsigned long long)qlen);
+  ctr_st(ctr, C_QLEN0 + qs, (unsigned long long)qlen);
+  ctr_st(ctr, C_QP0 + (qs ^ 1), 0ull);
   publish(ctr, host, seq);
 }
 
@@ -199,15 +210,15 @@ __global__ void k_bfs_init(int64_t root, uint8_t *__restrict__ lev8,
     vis[i] = i == rw ? x | (1ull << (root & 63)) : x;
   }
   if (t == 0) {
-    for (int i = 0; i < C_NCTR; ++i) ctr[i] = 0;
+    for (int i = 0; i < C_NCTR; ++i) ctr_st(ctr, i, 0ull);
     const int64_t rdeg = rp[root + 1] - rp[root];  // 64-bit offsets
     q0[0] = (int32_t)root;
     qo0[0] = 0;
-    ctr[C_QLEN0] = 1;
-    ctr[C_QP0] = (1ull << 32) | (unsigned long long)rdeg;
-    ctr[C_RDEG] = (unsigned long long)rdeg;
-    ctr[C_MU] = (unsigned long long)(nnz - rdeg);
-    ctr[C_UNV] = (unsigned long long)(nonisolated - (rdeg > 0 ? 1 : 0));
+    ctr_st(ctr, C_QLEN0, 1ull);
+    ctr_st(ctr, C_QP0, (1ull << 32) | (unsigned long long)rdeg);
+    ctr_st(ctr, C_RDEG, (unsigned long long)rdeg);
+    ctr_st(ctr, C_MU, (unsigned long long)(nnz - rdeg));
+    ctr_st(ctr, C_UNV, (unsigned long long)(nonisolated - (rdeg > 0 ? 1 : 0)));
     td_decide(ctr, 0, 0, false, rule, 1, (uint64_t)rdeg, host, seq);
   }
 }
@@ -350,8 +361,8 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
   __shared__ int64_t s_base[kTdTile];
   __shared__ unsigned long long s_scan[kBlock / kWave];
   __shared__ unsigned long long s_gbase;
-  if (!ctr[C_GO]) {
-    if (ctr[C_ENDL] == (unsigned long long)next_level) {
+  if (!ctr_ld(ctr, C_GO)) {
+    if (ctr_ld(ctr, C_ENDL) == (unsigned long long)next_level) {
       const int64_t stride = (int64_t)gridDim.x * kBlock;
       if (fix) unreached_words(vis, iso, words, parent, stride);
       if (lev8) expand_levels(lev8, level, n, vec, stride, vis, iso, root);
@@ -360,10 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_td_expand(
   }
   const int nxt = cur ^ 1;
   unsigned long long *qn_pack = ctr + C_QP0 + nxt;
-  const int64_t qlen = (int64_t)ctr[C_QLEN0 + cur];
-  const uint32_t total = (uint32_t)ctr[C_MF];
+  const int64_t qlen = (int64_t)ctr_ld(ctr, C_QLEN0 + cur);
+  const uint32_t total = (uint32_t)ctr_ld(ctr, C_MF);
   // heavy: winners read no row offsets and get no queue entry (only counted)
-  const bool heavy = ctr[C_HEAVY] != 0;
+  const bool heavy = ctr_ld(ctr, C_HEAVY) != 0;
   // only the blocks that own a tile take part (and take a ticket): same-address
   // atomics are serialised, so 1500 tickets cost ~20 us on a small level
   const uint64_t ntiles = ((uint64_t)total + kTdTile - 1) / kTdTile;
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_front_from_level(
     unsigned long long *__restrict__ ctr, int64_t nf, const int32_t *__restrict__ hot,
     int64_t num_hot, uint64_t *__restrict__ fh, const uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ iso, int64_t root) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_NFIN] = (unsigned long long)nf;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr_st(ctr, C_NFIN, (unsigned long long)nf);
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = __lane_id();
@@ -1088,18 +1099,18 @@ __device__ __forceinline__ void bu_flush(const BuCount &c, uint64_t *s,
     if (ACCT) __threadfence();
     // the counters without the ticket bits, as the host reads them
     const uint64_t nnew = (old & ((1ull << kTicketShift) - 1)) + tn;
-    const uint64_t nf_in = ctr[C_NFIN];
+    const uint64_t nf_in = ctr_ld(ctr, C_NFIN);
     const bool to_td = nx.dirmode == G5_DIR_TOPDOWN ||
                        (nx.dirmode == G5_DIR_AUTO && (double)nnew < (double)nx.n / nx.beta &&
                         nnew < nf_in);
-    ctr[C_BUGO] = (nnew > 0 && !to_td) ? 1ull : 0ull;
-    ctr[C_NFIN] = nnew;
-    ctr[C_UNV] = __hip_atomic_load(ctr + C_UNV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - nnew;
+    ctr_st(ctr, C_BUGO, (nnew > 0 && !to_td) ? 1ull : 0ull);
+    ctr_st(ctr, C_NFIN, nnew);
+    ctr_st(ctr, C_UNV, ctr_ld(ctr, C_UNV) - nnew);
     atomicExch(ctr + C_NNEW, nnew);
     publish(ctr, host, seq);
     atomicExch(ctr + C_NNEW, 0ull);
-    ctr[C_QP0] = 0;  // a switch back to top-down fills a queue from zero
-    ctr[C_QP1] = 0;
+    ctr_st(ctr, C_QP0, 0ull);  // a switch back to top-down fills a queue from zero
+    ctr_st(ctr, C_QP1, 0ull);
     if (ACCT) {
       atomicExch(ctr + C_SCAN, 0ull);
       atomicExch(ctr + C_UNVIS, 0ull);
@@ -1123,7 +1134,8 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
     int64_t words, int32_t next_level, unsigned long long *__restrict__ ctr, bool packed,
     unsigned long long *__restrict__ host, unsigned long long seq, bool check_go, BuNext bn) {
   extern __shared__ uint64_t s_fh[];
-  if (check_go && !ctr[C_BUGO]) return;  // queued ahead; the last step chose top-down
+  // queued ahead and the last step chose top-down: nothing to do
+  if (check_go && !ctr_ld(ctr, C_BUGO)) return;
   __shared__ uint64_t s[kBuBlock / kWave];
   __shared__ uint32_t s_base[kBuBlock];
   __shared__ int32_t s_row[kBuBlock];
@@ -1350,7 +1362,7 @@ __global__ __launch_bounds__(kBlock) void k_front_queue(const uint64_t *__restri
     if (atomicAdd(ctr + C_TICKET, 1ull) + 1 == gridDim.x) {
       const unsigned long long qp = atomicAdd(ctr + C_QP0 + cur, 0ull);
       atomicExch(ctr + C_TICKET, 0ull);
-      ctr[C_LASTNF] = (unsigned long long)last_nf;
+      ctr_st(ctr, C_LASTNF, (unsigned long long)last_nf);
       td_decide(ctr, cur, lvl, true, rule, (int64_t)(qp >> 32), qp & 0xffffffffull, host, seq);
     }
   }

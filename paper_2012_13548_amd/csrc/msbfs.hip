@@ -443,7 +443,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_level(MsArgs a, int l) {
   }
   const uint64_t mu =
       l == 0 ? ld_agent(&ctl->mu0) : ld_agent(&ctl->mu_lv[(l - 1) & 1]) - ld_agent(&cur->dec);
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->mu_lv[l & 1] = mu;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&ctl->mu_lv[l & 1], mu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   level_body<PAR>(a, l, choose_td(a, mf, mu), nf, s_red);
 }
 
@@ -465,13 +466,16 @@ __global__ __launch_bounds__(kBlock) void k_ms_level_g(MsCtl *ctl, int j) {
   }
   const uint64_t mu =
       l == 0 ? ld_agent(&ctl->mu0) : ld_agent(&ctl->mu_lv[(l - 1) & 1]) - ld_agent(&cur->dec);
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->mu_lv[l & 1] = mu;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&ctl->mu_lv[l & 1], mu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   level_body<PAR>(a, l, choose_td(a, mf, mu), nf, s_red);
 }
 
 // Moves the level base of graph replays on by the levels one replay runs.
 __global__ void k_ms_advance(MsCtl *ctl, int levels) {
-  if (threadIdx.x == 0) ctl->lbase += (unsigned long long)levels;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&ctl->lbase, ld_agent(&ctl->lbase) + (unsigned long long)levels,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_fill_i8(int8_t *__restrict__ p, int64_t len, bool vec) {
@@ -509,7 +513,7 @@ __global__ void k_ms_seed(Roots64 roots_v, int k, int64_t n, uint64_t *seen, uin
   int b = threadIdx.x;
   if (b == 0) {
     ctl->args = args;
-    ctl->lbase = 0;
+    __hip_atomic_store(&ctl->lbase, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (b >= k) return;
   int64_t v = roots[b];
@@ -535,7 +539,8 @@ __global__ void k_ms_seed(Roots64 roots_v, int k, int64_t n, uint64_t *seen, uin
         all = false;
         break;
       }
-    ctl->mu0 = (unsigned long long)(rp[n] - (all ? d : 0));
+    __hip_atomic_store(&ctl->mu0, (unsigned long long)(rp[n] - (all ? d : 0)), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
