@@ -736,13 +736,14 @@ def run_sssp(args):
     prev = torch.empty(n, dtype=torch.int32, device=dev)
     m_r, infos = [], []
     for r in roots:
-        _, _, info = g5.sssp(csr, r, dist, prev, delta=args.sssp_delta, stats=True)
+        _, _, info = g5.sssp(csr, r, dist, prev, delta=args.sssp_delta, stats=True,
+                             pull_div=args.sssp_pull_div)
         m_r.append(int(deg[dist != -1].sum().item()) // 2)
         infos.append(info)
     times = []
     for i, r in enumerate(roots):
         e0.record()
-        g5.sssp(csr, r, dist, prev, delta=args.sssp_delta)
+        g5.sssp(csr, r, dist, prev, delta=args.sssp_delta, pull_div=args.sssp_pull_div)
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1) / 1e3)
@@ -751,13 +752,14 @@ def run_sssp(args):
            "delta": infos[0]["delta"], "hmean_gteps": round(hmean(teps) / 1e9, 3),
            "mean_ms": round(1e3 * sum(times) / len(times), 3), "csr_build_ms": round(build_ms, 2),
            "mean_rounds": round(sum(i["rounds"] for i in infos) / len(infos), 1),
-           "mean_buckets": round(sum(i["buckets"] for i in infos) / len(infos), 1)}
+           "mean_buckets": round(sum(i["buckets"] for i in infos) / len(infos), 1),
+           "mean_pulls": round(sum(i["pulls"] for i in infos) / len(infos), 1)}
     if args.sssp_oracle:
         import oracle as O
         eh, wh = K.edges_host(scale, args.edgefactor), K.weights_host(scale, args.edgefactor)
         ocsr = O.build_csr_w(eh, wh, n)
         del eh, wh
-        g5.sssp(csr, roots[0], dist, prev, delta=args.sssp_delta)
+        g5.sssp(csr, roots[0], dist, prev, delta=args.sssp_delta, pull_div=args.sssp_pull_div)
         od, _, dt = O.sssp_timed(ocsr, roots[0])
         out["oracle_root0_s"] = round(dt, 3)
         out["oracle_root0_gteps"] = round(m_r[0] / dt / 1e9, 5)
@@ -861,6 +863,8 @@ def main():
     ap.add_argument("--sssp-scale", type=int, default=22)
     ap.add_argument("--sssp-roots", type=int, default=16)
     ap.add_argument("--sssp-delta", type=int, default=0)
+    ap.add_argument("--sssp-pull-div", type=int, default=0,
+                    help="SSSP rounds with at least nnz/this many edges pull (0: default, <0: never)")
     ap.add_argument("--sssp-oracle", action="store_true",
                     help="check the first SSSP root against the oracle's Dijkstra (slow)")
     ap.add_argument("--no-batch", action="store_true")

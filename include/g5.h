@@ -269,7 +269,8 @@ g5_status g5_bfs_batch_ex(const g5_csr *g, const int64_t *roots, int32_t k, int3
 /* Kernel 3 (Section 2.4): single-source shortest paths from `src` over a
  * graph built by g5_build_csr_w, by parallel delta-stepping (the direction
  * named in Section 4.1; buckets of width delta, relaxations by atomic
- * minimum, one queue per round).
+ * minimum, one queue per round; a round whose queue holds a large share of
+ * the edges pulls instead).
  *   dist  device, uint32 [n]: the shortest-path distance from src, or
  *         0xFFFFFFFF (infinity) where v is not in src's component.
  *   prev  device, int32 [n]: prev[src] = src; for another reached v, the
@@ -282,7 +283,11 @@ g5_status g5_sssp(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev, v
 typedef struct {
   uint32_t delta;   /* bucket width (0 = the default, 32) */
   int32_t flags;    /* G5_FLAG_TIME_STEPS: time the call on the device (ms) */
-  int32_t reserved[6];
+  int32_t pull_div; /* a round whose queue's rows hold at least nnz / pull_div
+                       edges pulls (each vertex takes the best relaxation from
+                       its neighbours in the queue) instead of pushing;
+                       0 = the default (4), negative = never pull */
+  int32_t reserved[5];
 } g5_sssp_params;
 
 typedef struct {
@@ -293,7 +298,8 @@ typedef struct {
   int64_t delta;    /* bucket width used */
   double ms;        /* device time of the call (G5_FLAG_TIME_STEPS) */
   int64_t edges;    /* edges relaxed (the rows of the relaxed queue entries) */
-  int64_t reserved[3];
+  int64_t pulls;    /* rounds done by pulling */
+  int64_t reserved[2];
 } g5_sssp_stats;
 
 /* g5_sssp with explicit parameters (NULL = defaults) and statistics (NULL =

@@ -117,14 +117,15 @@ lib.g5_csr_copy_weights.restype = ctypes.c_int
 
 class SsspParams(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_uint32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("pull_div", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class SsspStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("scans", ctypes.c_int64),
                 ("buckets", ctypes.c_int64), ("relaxed", ctypes.c_int64),
                 ("delta", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("edges", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+                ("edges", ctypes.c_int64), ("pulls", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 2)]
 
 
 lib.g5_sssp.argtypes = [_P, _I64, _P, _P, _P]
@@ -234,11 +235,14 @@ def build_csr_w(edges, weights, n):
     return Csr(out.value, edges.device)
 
 
-def sssp(csr, src, dist=None, prev=None, delta=None, stats=False, time_call=False):
+def sssp(csr, src, dist=None, prev=None, delta=None, stats=False, time_call=False,
+         pull_div=None):
     """Kernel 3: (dist uint32-as-int32 tensor, prev int32 tensor) from ``src``
     on a graph built by :func:`build_csr_w`.  dist holds uint32 values (0xFFFFFFFF
     = unreached) in an int32 tensor (torch has no uint32 arithmetic); view it
-    with ``.cpu().numpy().view(numpy.uint32)``."""
+    with ``.cpu().numpy().view(numpy.uint32)``.  ``pull_div``: rounds whose
+    queue holds at least nnz / pull_div edges pull (None: the default, a
+    negative value: never)."""
     import torch
     if dist is None:
         dist = torch.empty(csr.n, dtype=torch.int32, device=csr.device)
@@ -250,6 +254,7 @@ def sssp(csr, src, dist=None, prev=None, delta=None, stats=False, time_call=Fals
     p = SsspParams()
     p.delta = int(delta or 0)
     p.flags = FLAG_TIME_STEPS if time_call else 0
+    p.pull_div = int(pull_div or 0)
     st = SsspStats()
     want = stats or time_call
     _check(lib.g5_sssp_ex(csr.handle, int(src), dist.data_ptr(), prev.data_ptr(),
@@ -258,7 +263,7 @@ def sssp(csr, src, dist=None, prev=None, delta=None, stats=False, time_call=Fals
     if not want:
         return dist, prev
     info = {k: getattr(st, k) for k in ("rounds", "scans", "buckets", "relaxed", "edges", "delta",
-                                        "ms")}
+                                        "ms", "pulls")}
     return dist, prev, info
 
 

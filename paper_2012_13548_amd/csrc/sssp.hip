@@ -25,7 +25,11 @@
 // first edge in the queue's edge list (assigned when it was appended, from one
 // packed atomic per wavefront), and each workgroup takes 1,024-edge tiles of
 // that list in turn, so hub rows are split across workgroups and short rows
-// are packed together.
+// are packed together.  A round whose queue holds a large share of the
+// graph's edges pulls instead: every vertex takes the best relaxation over its
+// neighbours in the queue (known by their stamp) and keeps it if it beats its
+// own word, so the distances need no atomics (a hub's row is read in pieces
+// that combine by atomic minimum).
 #include <algorithm>
 
 #include "g5_internal.h"
@@ -41,6 +45,9 @@ constexpr uint32_t kInf = 0xffffffffu;
 // seeded graphs, with tens of edges per vertex (a sweep at scale 22 over
 // 4..2^20: 16 and 32 within 4 %, 8 and 64 10-20 % slower).
 constexpr uint32_t kDefaultDelta = 32;
+// A relaxation round pulls when its queue's rows hold at least nnz /
+// kDefaultPullDiv edges.
+constexpr int kDefaultPullDiv = 4;
 
 enum SCtr : int {
   S_QP0 = 0,    // queue 0: entries << 32 | edges (appended to by one atomic per wavefront)
@@ -56,6 +63,7 @@ enum SCtr : int {
   S_BUCKETS = 10, // thresholds used (statistics)
   S_EPOCH = 11,   // last queue stamp handed out (read back by the host)
   S_TICK0 = 12,   // step tickets, by step parity (S_TICK0 + (j & 1))
+  S_PULLS = 14,   // relaxation rounds done by pulling (statistics)
   S_ST0 = 16,     // step state, by step parity: S_ST0 + (j & 1) * kStSlots + ST_*
   S_N = 32
 };
@@ -64,6 +72,16 @@ enum SCtr : int {
 // write, so a workgroup of step j that starts late still sees its step's state.
 enum StSlot : int { ST_QP = 0, ST_CUR = 1, ST_T = 2, ST_EP = 3, ST_DONE = 4 };
 constexpr int kStSlots = 8;
+
+// The counters and step states are written by one workgroup and read by the
+// workgroups of later steps, which may run on another XCD whose L2 holds an
+// older copy of the line: every access is a device-scope atomic.
+__device__ __forceinline__ unsigned long long s_ld(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void s_st(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Appends v (one lane each) to a queue with its first-edge index: a wave
 // prefix sum of the degrees and one atomic on the queue's packed counter
@@ -102,6 +120,11 @@ struct RelaxArgs {
   int nxt;
   uint64_t T;
   uint32_t epoch;  // stamp of the next queue
+  int64_t n;
+  const int32_t *hubs;      // rows longer than kHubDeg (from Kernel 1) and the
+  const uint64_t *hub_off;  // first kHubChunk-edge piece of each
+  int64_t num_hubs, hub_chunks;
+  uint64_t pull_edges;  // a round whose queue has at least this many edges pulls (0: never)
 };
 
 // Relaxes edge (u, v) of weight w from distance du; returns true when v must
@@ -139,15 +162,15 @@ __global__ void k_sssp_init(unsigned long long *__restrict__ dp, int64_t n, int6
     dp[i] = i == src ? (unsigned long long)src : ((unsigned long long)kInf << 32) | 0xffffffffull;
   for (int64_t i = t; i < words; i += stride) pend[i] = 0;
   if (t == 0) {
-    for (int i = 0; i < S_N; ++i) ctr[i] = 0;
+    for (int i = 0; i < S_N; ++i) s_st(ctr + i, 0ull);
     unsigned long long *st = ctr + S_ST0;  // step 0's state: queue 0 = {src}
-    st[ST_QP] = (1ull << 32) | (unsigned long long)(rp[src + 1] - rp[src]);
-    st[ST_CUR] = 0;
-    st[ST_T] = delta;
-    st[ST_EP] = epoch + 1;
-    ctr[S_MIN] = kInf;
-    ctr[S_BUCKETS] = 1;
-    ctr[S_EPOCH] = epoch + 1;
+    s_st(st + ST_QP, (1ull << 32) | (unsigned long long)(rp[src + 1] - rp[src]));
+    s_st(st + ST_CUR, 0ull);
+    s_st(st + ST_T, delta);
+    s_st(st + ST_EP, (unsigned long long)epoch + 1);
+    s_st(ctr + S_MIN, kInf);
+    s_st(ctr + S_BUCKETS, 1ull);
+    s_st(ctr + S_EPOCH, (unsigned long long)epoch + 1);
     q0[0] = (int32_t)src;
     qo0[0] = 0;
     stamp[src] = epoch;
@@ -252,6 +275,144 @@ __device__ void relax_round(const int32_t *__restrict__ q, const uint32_t *__res
   }
 }
 
+// The packed relaxation (dist[u] + w) << 32 | u of row entry k (edge (u, v) of
+// weight w) if u lies in the current queue (stamp == cur), else ~0.
+__device__ __forceinline__ unsigned long long pull_entry(const RelaxArgs &a, int64_t k,
+                                                         uint32_t cur) {
+  const int32_t u = a.ci[k];
+  if (a.stamp[u] != cur) return ~0ull;
+  const uint64_t du = a.dp[u] >> 32;
+  const uint64_t nd = du + a.wt[k];
+  if (nd >= (uint64_t)kInf) {  // du < kInf: u is in the queue
+    atomicOr(a.ctr + S_ERR, 1ull);
+    return ~0ull;
+  }
+  return (nd << 32) | (uint32_t)u;
+}
+
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) x |= __shfl_xor(x, d, kWave);
+  return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const unsigned long long o = __shfl_xor(x, d, kWave);
+    x = o < x ? o : x;
+  }
+  return x;
+}
+
+// Keeps v's pulled word `best` if it beats `old` (v's word before): v joins
+// the next queue when its distance improved below T, else the far set.
+// Returns whether v is to be appended (the caller appends by wavefront).
+__device__ __forceinline__ bool pull_keep(const RelaxArgs &a, int64_t v,
+                                          unsigned long long best, unsigned long long old,
+                                          uint64_t &far) {
+  if ((best >> 32) >= (old >> 32)) return false;  // at most a smaller predecessor
+  if ((best >> 32) < a.T) return atomicExch(a.stamp + v, a.epoch) != a.epoch;
+  far |= 1ull << (v & 63);
+  return false;
+}
+
+// One relaxation round by pulling (queue stamp cur): rows of up to kPullLane
+// entries are read by their lane, longer rows up to kHubDeg by the whole
+// wavefront, hub rows in kHubChunk-edge pieces spread over the wavefronts.
+// The queue's vertices leave the far set first, as in relax_round.  Every
+// relaxation of the round is at least `lower` (the start of the current
+// bucket, weights being non-negative), so a vertex whose distance is below it
+// cannot change, not even its predecessor, and its row is not read.
+constexpr int kPullLane = 32;
+
+__device__ void pull_round(const int32_t *__restrict__ q, int64_t qlen, uint32_t active,
+                           const RelaxArgs &a, uint32_t cur, uint64_t lower) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < qlen;
+       i += (int64_t)active * kBlock) {
+    const int32_t u = q[i];
+    const uint64_t bit = 1ull << (u & 63);
+    if (a.pend[u >> 6] & bit) atomicAnd((unsigned long long *)(a.pend + (u >> 6)), ~bit);
+  }
+  const int lane = __lane_id();
+  const int64_t gw = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)active * kBlock) / kWave;
+  const int64_t W = (a.n + kWave - 1) / kWave;
+  unsigned long long *npack = a.ctr + S_QP0 + a.nxt;
+  for (int64_t w = gw; w < W; w += nw) {
+    const int64_t v = w * kWave + lane;
+    int64_t b = 0, e = 0;
+    unsigned long long mine = 0;
+    if (v < a.n) mine = a.dp[v];
+    if (v < a.n && (mine >> 32) >= lower) {
+      b = a.rp[v];
+      e = a.rp[v + 1];
+    }
+    const int64_t d = e - b;
+    unsigned long long best = ~0ull;
+    if (d <= kPullLane)
+      for (int64_t k = b; k < e; ++k) {
+        const unsigned long long c = pull_entry(a, k, cur);
+        best = c < best ? c : best;
+      }
+    uint64_t rem = __ballot(d > kPullLane && d <= kHubDeg);
+    while (rem) {
+      const int L = __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1;
+      const int64_t kb = __shfl(b, L, kWave), ke = __shfl(e, L, kWave);
+      unsigned long long m = ~0ull;
+      for (int64_t k = kb + lane; k < ke; k += kWave) {
+        const unsigned long long c = pull_entry(a, k, cur);
+        m = c < m ? c : m;
+      }
+      m = wave_min_u64(m);
+      if (lane == L) best = m;
+    }
+    bool want = false;
+    uint64_t far = 0;
+    if (v < a.n && d <= kHubDeg && best != ~0ull && best < mine) {
+      // v's word has no other writer in this round; the atomic keeps it so
+      const unsigned long long old = atomicMin(a.dp + v, best);
+      if (best < old) want = pull_keep(a, v, best, old, far);
+    }
+    // the far-set bits of the wavefront's vertices share one word
+    far = wave_or_u64(far);
+    if (far && lane == 0) atomicOr((unsigned long long *)(a.pend + w), far);
+    push_wave(want, (int32_t)v, a.rp, a.qn, a.qon, npack);
+  }
+  for (int64_t c = gw; c < a.hub_chunks; c += nw) {
+    int64_t lo = 0, hi = a.num_hubs;  // the hub of piece c: the last i with hub_off[i] <= c
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)a.hub_off[mid] <= c)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int32_t h = a.hubs[lo];
+    if ((a.dp[h] >> 32) < lower) continue;  // wave-uniform
+    const int64_t kb = a.rp[h] + (c - (int64_t)a.hub_off[lo]) * kHubChunk;
+    const int64_t ke = std::min<int64_t>(kb + kHubChunk, a.rp[h + 1]);
+    unsigned long long m = ~0ull;
+    for (int64_t k = kb + lane; k < ke; k += kWave) {
+      const unsigned long long cnd = pull_entry(a, k, cur);
+      m = cnd < m ? cnd : m;
+    }
+    m = wave_min_u64(m);
+    bool want = false;
+    uint64_t far = 0;
+    if (lane == 0 && m != ~0ull) {
+      const unsigned long long old = atomicMin(a.dp + h, m);
+      if (m < old) want = pull_keep(a, h, m, old, far);
+    }
+    if (far) atomicOr((unsigned long long *)(a.pend + (h >> 6)), far);
+    push_wave(want, h, a.rp, a.qn, a.qon, npack);
+  }
+  // every wavefront's appends have returned before thread 0 takes the
+  // workgroup's ticket (the last workgroup reads the next queue's counter)
+  __syncthreads();
+}
+
 // Pending vertices with dist < T leave the far set for queue nxt (stamp =
 // epoch); the rest are counted and their smallest distance taken.
 __device__ void scan_pending(const unsigned long long *__restrict__ dp,
@@ -291,12 +452,20 @@ __device__ void scan_pending(const unsigned long long *__restrict__ dp,
     if (take) pend[w] = m & ~take;
   }
   __shared__ unsigned long long s_red[kBlock / kWave];
+  __shared__ uint32_t s_min[kBlock / kWave];
   const unsigned long long tl = block_sum<kBlock, unsigned long long>(left, s_red);
   uint32_t bm = dmin;
 #pragma unroll
   for (int d = kWave / 2; d >= 1; d >>= 1) bm = std::min(bm, (uint32_t)__shfl_xor(bm, d, kWave));
-  if (threadIdx.x == 0 && tl) atomicAdd(ctr + S_PEND, tl);
-  if (__lane_id() == 0 && bm != kInf) atomicMin(ctr + S_MIN, (unsigned long long)bm);
+  if (__lane_id() == 0) s_min[threadIdx.x / kWave] = bm;
+  __syncthreads();
+  // thread 0 adds the block's counts, and has their results back before it
+  // takes the workgroup's ticket (the last workgroup reads them)
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kBlock / kWave; ++i) bm = std::min(bm, s_min[i]);
+    if (tl) s_red[0] = atomicAdd(ctr + S_PEND, tl);
+    if (bm != kInf) s_red[1] = atomicMin(ctr + S_MIN, (unsigned long long)bm);
+  }
 }
 
 // Step j of the traversal; the host queues steps in groups without waiting.
@@ -311,25 +480,30 @@ __global__ __launch_bounds__(kBlock) void k_sssp_step(RelaxArgs a, int64_t j, in
   __shared__ int s_last;
   unsigned long long *ctr = a.ctr;
   unsigned long long *st = ctr + S_ST0 + (int)(j & 1) * kStSlots;
-  if (st[ST_DONE]) return;
-  const unsigned long long qp = st[ST_QP];
-  const int cur = (int)st[ST_CUR];
+  if (s_ld(st + ST_DONE)) return;
+  const unsigned long long qp = s_ld(st + ST_QP);
+  const int cur = (int)s_ld(st + ST_CUR);
   const int nxt = cur ^ 1;
   const int64_t qlen = (int64_t)(qp >> 32);
   const uint32_t total = (uint32_t)qp;
-  a.T = st[ST_T];
-  a.epoch = (uint32_t)st[ST_EP];
+  a.T = s_ld(st + ST_T);
+  a.epoch = (uint32_t)s_ld(st + ST_EP);
   a.nxt = nxt;
   a.qn = nxt ? q1 : q0;
   a.qon = nxt ? qo1 : qo0;
   // workgroups with work take part (and a ticket): same-address atomics serialise
+  const bool pull = qlen > 0 && a.pull_edges > 0 && (uint64_t)total >= a.pull_edges;
   const uint64_t need =
-      qlen > 0 ? std::max<uint64_t>(((uint64_t)total + kTile - 1) / kTile,
-                                    ((uint64_t)qlen + kBlock - 1) / kBlock)
-               : ((uint64_t)words + kBlock - 1) / kBlock;
+      pull ? ((uint64_t)a.n + kBlock - 1) / kBlock
+      : qlen > 0 ? std::max<uint64_t>(((uint64_t)total + kTile - 1) / kTile,
+                                      ((uint64_t)qlen + kBlock - 1) / kBlock)
+                 : ((uint64_t)words + kBlock - 1) / kBlock;
   const uint32_t active = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(gridDim.x, need));
   if (blockIdx.x >= active) return;
-  if (qlen > 0)
+  if (pull)
+    pull_round(cur ? q1 : q0, qlen, active, a, a.epoch - 1,  // the queue's stamp
+               a.T > delta ? a.T - delta : 0);
+  else if (qlen > 0)
     relax_round(cur ? q1 : q0, cur ? qo1 : qo0, qlen, total, active, a);
   else
     scan_pending(a.dp, a.rp, a.pend, words, a.T, a.qn, a.qon, nxt, a.stamp, a.epoch, ctr,
@@ -343,11 +517,12 @@ __global__ __launch_bounds__(kBlock) void k_sssp_step(RelaxArgs a, int64_t j, in
   unsigned long long *ns = ctr + S_ST0 + (int)((j + 1) & 1) * kStSlots;
   unsigned long long T = a.T, done = 0;
   if (qlen > 0) {
-    ctr[S_ROUNDS] += 1;
-    ctr[S_RELAX] += (unsigned long long)qlen;
-    ctr[S_EDGES] += (unsigned long long)total;
+    s_st(ctr + S_ROUNDS, s_ld(ctr + S_ROUNDS) + 1);
+    s_st(ctr + S_RELAX, s_ld(ctr + S_RELAX) + (unsigned long long)qlen);
+    s_st(ctr + S_EDGES, s_ld(ctr + S_EDGES) + (unsigned long long)total);
+    if (pull) s_st(ctr + S_PULLS, s_ld(ctr + S_PULLS) + 1);
   } else {
-    ctr[S_SCANS] += 1;
+    s_st(ctr + S_SCANS, s_ld(ctr + S_SCANS) + 1);
     if ((np >> 32) == 0) {
       // nothing below T: done without pending vertices, else the next scan
       // uses the end of the bucket of the smallest pending distance
@@ -357,23 +532,23 @@ __global__ __launch_bounds__(kBlock) void k_sssp_step(RelaxArgs a, int64_t j, in
         done = 1;
       } else {
         T = (mn / delta + 1) * delta;
-        ctr[S_BUCKETS] += 1;
+        s_st(ctr + S_BUCKETS, s_ld(ctr + S_BUCKETS) + 1);
       }
     }
     atomicExch(ctr + S_PEND, 0ull);
     atomicExch(ctr + S_MIN, (unsigned long long)kInf);
   }
-  ns[ST_QP] = np;
-  ns[ST_CUR] = (unsigned long long)nxt;
-  ns[ST_T] = T;
-  ns[ST_EP] = (unsigned long long)a.epoch + 1;
-  ns[ST_DONE] = done;
-  ctr[S_EPOCH] = (unsigned long long)a.epoch + 1;
+  s_st(ns + ST_QP, np);
+  s_st(ns + ST_CUR, (unsigned long long)nxt);
+  s_st(ns + ST_T, T);
+  s_st(ns + ST_EP, (unsigned long long)a.epoch + 1);
+  s_st(ns + ST_DONE, done);
+  s_st(ctr + S_EPOCH, (unsigned long long)a.epoch + 1);
   if (done) {
     // both parities: every later step finds the end, whichever state it reads
     // (every workgroup of this step has passed its check of st already)
-    st[ST_DONE] = 1;
-    ctr[S_DONE] = 1;
+    s_st(st + ST_DONE, 1ull);
+    s_st(ctr + S_DONE, 1ull);
   }
   atomicExch(ctr + S_QP0 + cur, 0ull);  // the consumed queue is step j + 1's output
   atomicExch(tick, 0ull);
@@ -504,6 +679,14 @@ g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev,
   a.pend = w.pend;
   a.stamp = w.stamp;
   a.ctr = ctr;
+  a.n = n;
+  a.hubs = g->hub_list;
+  a.hub_off = g->hub_off;
+  a.num_hubs = g->num_hubs;
+  a.hub_chunks = g->hub_chunks;
+  // rounds whose queue holds at least nnz / pull_div edges pull
+  const int pull_div = p.pull_div != 0 ? p.pull_div : kDefaultPullDiv;
+  a.pull_edges = pull_div > 0 ? std::max<uint64_t>(1, (uint64_t)g->nnz / (uint64_t)pull_div) : 0;
   // steps are queued in groups; the host reads the counters once per group
   unsigned long long hc[S_N] = {};
   int64_t steps = 0;
@@ -534,6 +717,7 @@ g5_status sssp_impl(const g5_csr *g, int64_t src, uint32_t *dist, int32_t *prev,
     stats->buckets = (int64_t)hc[S_BUCKETS];
     stats->relaxed = (int64_t)hc[S_RELAX];
     stats->edges = (int64_t)hc[S_EDGES];
+    stats->pulls = (int64_t)hc[S_PULLS];
     stats->delta = (int64_t)delta;
     if (timed) {
       float ms = 0;

@@ -64,6 +64,17 @@ def test_kronecker_distances(kron, delta):
         c.check(r, delta=delta)
 
 
+@pytest.mark.parametrize("pull_div", [-1, 2, 1_000_000])
+def test_kronecker_pull(kron, pull_div):
+    # never pull; pull the rounds holding half the edges; pull every round
+    c, roots = kron
+    pulls = 0
+    for r in roots:
+        _, _, info = c.check(r, pull_div=pull_div)
+        pulls += info["pulls"]
+    assert (pulls == 0) if pull_div < 0 else (pull_div < 1000 or pulls > 0)
+
+
 def test_kronecker_scale20():
     scale = 20
     n = 1 << scale
@@ -94,6 +105,8 @@ def test_structured():
         for r in roots:
             for delta in (None, 4):
                 c.check(r, delta=delta)
+            # every round pulled: hub rows in pieces, rows by lane and by wavefront
+            c.check(r, pull_div=1_000_000)
 
 
 def test_repeated_tuples_and_loops():
