@@ -4,7 +4,8 @@ For each Kronecker scale, a coordinate search over
   single root: alpha, beta (direction switch), bottom-up lane-scan width,
                workgroups per compute unit, packed row scan, the LDS budget and
                density threshold of the staged frontier; objective =
-               harmonic-mean TEPS over sample roots (m_r / device time per call);
+               harmonic-mean TEPS over sample roots of the large component
+               (m_r / device time per call);
   batch:       alpha and workgroups per compute unit of its per-level launches;
                objective = device time of one 64-root batch with parents.
 Writes ``tuning.json`` (every trial) and ``tuned_table.inc`` (the defaults table
@@ -45,7 +46,7 @@ def tune_scale(scale, nroots, rounds):
     dev = torch.device("cuda:0")
     e = K.edges_device(scale, device=dev)
     csr = g5.build_csr(e, n)
-    roots = K.select_roots(K.nonisolated_device(e, n).cpu().numpy(), max(nroots, 64),
+    roots = K.select_roots(K.nonisolated_device(e, n).cpu().numpy(), max(2 * nroots, 64),
                            K.root_seed(scale) + 7)  # tuning roots differ from benchmark roots
     del e
     torch.cuda.empty_cache()
@@ -54,11 +55,19 @@ def tune_scale(scale, nroots, rounds):
     del rp
     parent = torch.empty(n, dtype=torch.int32, device=dev)
     level = torch.empty(n, dtype=torch.int32, device=dev)
-    sample = roots[:nroots]
-    m_r = []
-    for r in sample:
+    # Sample roots from the large component only: a root in a small component
+    # (a few edges, time ~ launch latency) would dominate the harmonic mean and
+    # the search would tune that root alone.
+    sample, m_r = [], []
+    half_nnz = int(deg.sum().item()) // 2
+    for r in roots:
         g5.bfs(csr, r, parent, level)
-        m_r.append(int(deg[level >= 0].sum().item()) // 2)
+        m = int(deg[level >= 0].sum().item()) // 2
+        if m * 100 >= half_nnz:
+            sample.append(r)
+            m_r.append(m)
+        if len(sample) == nroots:
+            break
     del deg
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
