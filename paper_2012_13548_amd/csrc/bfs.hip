@@ -642,7 +642,12 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
   if (packed) {
     // Unresolved rows laid end to end, one entry per lane per 64-entry window;
     // a row's first hit in a window is its smallest hitting lane (LDS atomic
-    // min); resolved rows stop probing.
+    // min); resolved rows stop probing, and after a window that resolves rows
+    // the next window starts at the next entry of a row still unresolved, so
+    // the entries resolved rows did not need cost no windows (without the
+    // jump a wavefront whose other rows resolve early steps over all their
+    // entries to reach its last unresolved row: a bottom-up level on a small
+    // frontier of hubs took 7 ms instead of 1.4).
     const uint32_t len = (pending && !found) ? (uint32_t)(e - k) : 0u;
     const uint32_t incl = wave_incl_scan(len);
     const uint32_t total = __shfl(incl, kWave - 1, kWave);
@@ -680,9 +685,18 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
           s_first[wb + lane] = kWave;
           if (ACCT) cnt.nscan += (uint64_t)(j0 + fl - pre + 1);
         }
-        done |= __ballot(fresh);
+        const uint64_t fm = __ballot(fresh);
+        done |= fm;
         carry = __shfl(r, kWave - 1, kWave);
         if (done == ~0ull) break;
+        if (fm) {
+          // the next window starts where the next unresolved entry is: inside
+          // a row that covers j0 + 64 (no jump), or at the start of a later
+          // row (a row start: its window needs no carry)
+          const uint32_t nj = j0 + kWave;
+          const bool live = !((done >> lane) & 1) && pre + len > nj;
+          j0 = wave_min<uint32_t>(live ? (pre > nj ? pre : nj) : 0xffffffffu) - kWave;
+        }
       }
       if (ACCT && len > 0 && !found) cnt.nscan += len;
     }

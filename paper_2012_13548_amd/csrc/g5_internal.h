@@ -172,6 +172,16 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const T o = __shfl_xor(v, d, kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
 // Exclusive prefix sum over a block of NT threads; `s` is LDS scratch of
 // NT/64 entries.  Returns the exclusive prefix; `total` gets the block sum.
 template <int NT, typename T>
