@@ -52,7 +52,8 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-BFS_SOURCES = ["paper_2012_13548_amd/csrc/bfs.hip", "paper_2012_13548_amd/csrc/g5_internal.h"]
+BFS_SOURCES = ["paper_2012_13548_amd/csrc/bfs.hip", "paper_2012_13548_amd/csrc/g5_internal.h",
+               "paper_2012_13548_amd/csrc/tuned_table.inc"]
 
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
