@@ -774,7 +774,7 @@ __device__ __forceinline__ int select_bit(uint64_t x, uint32_t r) {
 // without this nearly every round waited for the row reads of a few lanes.
 constexpr uint32_t kRing = 128;
 
-template <int LANE_SCAN, int R, bool ACCT, class Front, bool COMPACT = false>
+template <int LANE_SCAN, int R, bool ACCT, class Front, bool COMPACT = false, bool SPEC = false>
 __device__ __forceinline__ void bu_chunks(
     const Front &F, const uint64_t *fh, const uint32_t *__restrict__ rp,
     const int32_t *__restrict__ ci, const int32_t *__restrict__ hint,
@@ -944,12 +944,21 @@ __device__ __forceinline__ void bu_chunks(
         par[j] = -1;
         b[j] = e[j] = 0;
         h[j] = (act[j] && hint) ? hint[v[j]] : -1;
+        if (SPEC && act[j]) {
+          uint32_t be[2];
+          __builtin_memcpy(be, rp + v[j], 8);  // both row offsets in one 8-byte load
+          b[j] = be[0];
+          e[j] = be[1];
+        }
         if (ACCT && act[j]) cnt.nunvis += 1;
       }
       // The hint (highest-degree neighbour): a hot target's bit is in fh (LDS);
       // another target needs the frontier, whose word is loaded together with
       // the row offsets (taken unless the hint is already known to hit).
-      // A vertex whose hint is its only neighbour has no row to read.
+      // A vertex whose hint is its only neighbour has no row to read.  With
+      // SPEC (sparse frontiers, where most hints miss) the row offsets come with
+      // the hint and the first row entries with the hint's frontier word, one
+      // dependent load fewer per vertex; a hint hit discards them.
       int hp[R];
       bool only[R];
 #pragma unroll
@@ -966,14 +975,29 @@ __device__ __forceinline__ void bu_chunks(
         }
       }
       uint32_t hw[R];
+      // the first LANE_SCAN entries of the row in LANE_SCAN/4 16-byte loads (col_idx
+      // is padded past nnz, so reading beyond the row's end stays in bounds)
+      int32_t u[R][LANE_SCAN];
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         hw[j] = (hp[j] == 2) ? F.word(h[j]) : 0u;
-        if (act[j] && hp[j] != 1 && !only[j]) {
+        if (!SPEC && act[j] && hp[j] != 1 && !only[j]) {
           uint32_t be[2];
           __builtin_memcpy(be, rp + v[j], 8);  // both row offsets in one 8-byte load
           b[j] = be[0];
           e[j] = be[1];
+        }
+        if (SPEC) {
+          if (only[j] || hp[j] == 1) e[j] = b[j];  // no row to read
+          if (act[j] && b[j] < e[j]) {
+            __builtin_memcpy(u[j], ci + b[j], LANE_SCAN * sizeof(int32_t));
+#pragma unroll
+            for (int t = 0; t < LANE_SCAN; ++t)
+              if (b[j] + t >= e[j]) u[j][t] = -1;
+          } else {
+#pragma unroll
+            for (int t = 0; t < LANE_SCAN; ++t) u[j][t] = -1;
+          }
         }
       }
 #pragma unroll
@@ -985,12 +1009,14 @@ __device__ __forceinline__ void bu_chunks(
         if (ACCT && via[j]) cnt.nhint += 1;
         if (ACCT && act[j] && !found[j] && !only[j]) cnt.nrows += 1;
       }
-      // the first LANE_SCAN entries of the row in LANE_SCAN/4 16-byte loads (col_idx
-      // is padded past nnz, so reading beyond the row's end stays in bounds)
-      int32_t u[R][LANE_SCAN];
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        if (act[j] && !found[j] && k[j] < e[j]) {
+        if (SPEC) {
+          if (found[j]) {
+#pragma unroll
+            for (int t = 0; t < LANE_SCAN; ++t) u[j][t] = -1;
+          }
+        } else if (act[j] && !found[j] && k[j] < e[j]) {
           __builtin_memcpy(u[j], ci + k[j], LANE_SCAN * sizeof(int32_t));
 #pragma unroll
           for (int t = 0; t < LANE_SCAN; ++t)
@@ -1205,7 +1231,7 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
   BuCount c;
   // (compacting hint misses as k_bu_step does measured no faster here: on a
   // sparse frontier most hints miss, so its rounds are dense already)
-  bu_chunks<LANE_SCAN, R, ACCT>(
+  bu_chunks<LANE_SCAN, R, ACCT, FrontLds, false, true>(
       FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, vis, next, parent,
       level, lev8, words, next_level, packed, gw, nw, s_base, s_row, s_first, s_nx, c);
   bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq, bn);
