@@ -112,6 +112,41 @@ def test_deep_switch_to_bottom_up():
         assert np.array_equal(parent[300 + 4000:], np.arange(300, 300 + 4000)), m
 
 
+def comb(seed=3):
+    """Rows the packed bottom-up scan resolves a few entries in, beside long rows
+    it never resolves: vertex 100 is the root; even-numbered vertices from 1101
+    on hold 3 smaller-id leaves, the root, then 150 larger-id leaves; odd ones
+    hold 253 leaves and not the root, so a wavefront's layout interleaves both
+    and the scan must jump past the resolved rows' remaining entries."""
+    rng = np.random.default_rng(seed)
+    lo, root, hi, first = np.arange(0, 100), 100, np.arange(101, 1101), 1101
+    edges = []
+    for k in range(400):
+        v = first + k
+        nb = [rng.choice(lo, 3, replace=False)]
+        nb += [[root], rng.choice(hi, 150, replace=False)] if k % 2 == 0 else \
+              [rng.choice(hi, 250, replace=False)]
+        edges += [(v, int(u)) for u in np.concatenate(nb)]
+    return np.array(edges, dtype=np.int64), first + 400, root
+
+
+@pytest.mark.parametrize("m", [dict(direction=g5.DIR_BOTTOMUP, packed=True, hint=False, lane_scan=1),
+                               dict(direction=g5.DIR_BOTTOMUP, packed=True, hint=False, lane_scan=4),
+                               dict(direction=g5.DIR_BOTTOMUP, packed=True, lane_scan=2, lds=False),
+                               dict(direction=g5.DIR_BOTTOMUP, packed=True, lds_density=1.0),
+                               dict(direction=g5.DIR_BOTTOMUP, packed=True, vertices_per_lane=2),
+                               dict(direction=g5.DIR_AUTO, packed=True)],
+                         ids=["bu-1", "bu-4", "bu-nolds-2", "bu-lds", "bu-vpl2", "auto"])
+def test_packed_scan_resolved_rows(m):
+    import oracle as O
+    e, n, root = comb()
+    c = Case(e, n)
+    for r in (root, n - 1, 0):
+        c.check_root(r, **m)
+        parent, level = c.check_root(r, min_parent=True, **m)
+        assert np.array_equal(parent, O.min_parents(c.ocsr, r, level)), (r, m)
+
+
 @pytest.fixture(scope="module")
 def kron10():
     scale = 10
