@@ -1768,8 +1768,19 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   }
     if (lds) {  // never queued ahead
       // at most 4 entries per lane: at 8 waves per SIMD the spills grow with the
-      // scan width (32 bytes per lane at 4, 72 at 8), and 4 measured ~1 % faster
-      if (acct) {
+      // scan width (32 bytes per lane at 4, 72 at 8), and 4 measured ~1 % faster;
+      // but 8 by default on a frontier below 1/16 of the summary bits, whose rows
+      // run longer before a hit (scale 26: 6-7 % faster on 5-6 K-vertex hub
+      // frontiers, 1-2 % slower on 16-21 K ones)
+      const bool wide = p.bu_lane_scan <= 0 &&
+                        (double)nf_prev * (double)(1ll << std::min(lds_gs, 40)) * 16.0 < (double)n;
+      if (wide) {
+        if (acct) {
+          G5_BU_P(G5_BUL, 8, true);
+        } else {
+          G5_BU_P(G5_BUL, 8, false);
+        }
+      } else if (acct) {
         if (lane_scan >= 8) {
           G5_BU_P(G5_BUL, 4, true);
         } else {
