@@ -771,6 +771,18 @@ def run_sssp(args):
     return out
 
 
+def run_serve(args):
+    """Serving extra: BFS requests on graphs of scales 16, 18, 20, 22 and 23
+    resident at once, Poisson arrivals at 0.7 of the saturated rate; latency
+    is completion minus arrival per request."""
+    from paper_2012_13548_amd import serve as S
+    out = S.run_poisson(requests=args.serve_requests, log=lambda m: log(f"serve: {m}"))
+    keep = ("requests", "errors", "p50_ms", "p99_ms", "mean_ms", "throughput_rps",
+            "aggregate_gteps", "mean_batch", "rate_rps", "saturated_rps", "load", "scales",
+            "workers")
+    return {k: out[k] for k in keep}
+
+
 def host_threads():
     try:
         return len(os.sched_getaffinity(0))
@@ -869,6 +881,9 @@ def main():
     ap.add_argument("--sssp-oracle", action="store_true",
                     help="check the first SSSP root against the oracle's Dijkstra (slow)")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="Poisson requests of the serving extra (graphs of scales 16-23 resident)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run the counter-calibration copy kernel first")
     ap.add_argument("--gather-probe", action="store_true",
@@ -920,6 +935,9 @@ def main():
     sssp = None if args.no_sssp else run_sssp(args)
     if sssp:
         log(f"sssp: {sssp}")
+    serve = None if args.no_serve else run_serve(args)
+    if serve:
+        log(f"serve: {serve}")
     cpu = None
     if not args.no_cpu:
         def gpu_level_of(r):
@@ -954,6 +972,7 @@ def main():
         "csr_build_ms": round(gpu["build_ms"], 2),
         "batch": batch,
         "sssp": sssp,
+        "serve": serve,
         "step_kernels": gpu["steps"],
         "per_level_root0": gpu["per_level_root0"],
     }

@@ -318,26 +318,19 @@ def poisson_run(server, graphs, roots_of, rate, count, seed=3000, t_limit=None):
     return reqs
 
 
-def main():
-    ap = argparse.ArgumentParser(description="Poisson serving run over resident Kronecker graphs")
-    ap.add_argument("--scales", type=int, nargs="+", default=[16, 18, 20, 22, 23])
-    ap.add_argument("--requests", type=int, default=10000)
-    ap.add_argument("--workers", type=int, default=4)
-    ap.add_argument("--load", type=float, default=0.7, help="arrival rate / saturated rate")
-    ap.add_argument("--budget-gb", type=float, default=0.0, help="HBM budget (0: 80%% of free)")
-    args = ap.parse_args()
-    import sys
+def run_poisson(scales=(16, 18, 20, 22, 23), requests=10000, workers=4, load=0.7,
+                budget_gb=0.0, log=None):
+    """Graphs of the given scales resident at once; a calibration run (2,000
+    requests queued at once) gives the saturated rate, then `requests` Poisson
+    arrivals at `load` times that rate.  Returns the summary with the run's
+    settings."""
     import torch
     import kronecker as K
     import paper_2012_13548_amd as g5
-
-    def log(msg):
-        sys.stderr.write(f"[serve] {msg}\n")
-        sys.stderr.flush()
-
+    log = log or (lambda msg: None)
     dev = torch.device("cuda:0")
     csrs, roots_of = {}, {}
-    for s in args.scales:
+    for s in scales:
         e = K.edges_device(s, device=dev)
         name = f"s{s}"
         csrs[name] = g5.build_csr(e, 1 << s)
@@ -348,14 +341,14 @@ def main():
         log(f"graph {name}: nnz {csrs[name].nnz}")
     names = list(csrs)
     free, _ = torch.cuda.mem_get_info()
-    budget = int(args.budget_gb * 2**30) if args.budget_gb > 0 else int(0.8 * free)
-    ex = GpuExecutor(csrs, args.workers)
+    budget = int(budget_gb * 2**30) if budget_gb > 0 else int(0.8 * free)
+    ex = GpuExecutor(csrs, workers)
     # warm-up: every graph once
     for gname in names:
         ex.run(gname, list(roots_of[gname][:2]), 0)
     # calibration: saturated throughput with everything queued at once
-    cal = Server(ex, budget, workers=args.workers, keep_results=False).start()
-    ncal = min(2000, args.requests)
+    cal = Server(ex, budget, workers=workers, keep_results=False).start()
+    ncal = min(2000, requests)
     rng = np.random.default_rng(1)
     t0 = time.monotonic()
     for i in range(ncal):
@@ -364,17 +357,37 @@ def main():
     cal.wait_all(ncal)
     sat = ncal / (time.monotonic() - t0)
     cal.stop()
-    rate = args.load * sat
+    rate = load * sat
     log(f"saturated {sat:.1f} req/s -> Poisson rate {rate:.1f} req/s")
-    srv = Server(ex, budget, workers=args.workers, keep_results=False).start()
+    srv = Server(ex, budget, workers=workers, keep_results=False).start()
     t_start = time.monotonic()
-    reqs = poisson_run(srv, names, roots_of, rate, args.requests)
+    reqs = poisson_run(srv, names, roots_of, rate, requests)
     srv.wait_all(len(reqs))
     srv.stop()
     out = srv.summary(t_first=t_start)
-    out.update({"scales": args.scales, "workers": args.workers, "rate_rps": round(rate, 1),
-                "saturated_rps": round(sat, 1), "load": args.load,
+    out.update({"scales": list(scales), "workers": workers, "rate_rps": round(rate, 1),
+                "saturated_rps": round(sat, 1), "load": load,
                 "budget_gb": round(budget / 2**30, 2)})
+    del ex, csrs
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description="Poisson serving run over resident Kronecker graphs")
+    ap.add_argument("--scales", type=int, nargs="+", default=[16, 18, 20, 22, 23])
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--load", type=float, default=0.7, help="arrival rate / saturated rate")
+    ap.add_argument("--budget-gb", type=float, default=0.0, help="HBM budget (0: 80%% of free)")
+    args = ap.parse_args()
+    import sys
+
+    def log(msg):
+        sys.stderr.write(f"[serve] {msg}\n")
+        sys.stderr.flush()
+
+    out = run_poisson(args.scales, args.requests, args.workers, args.load, args.budget_gb, log)
     print(json.dumps(out), flush=True)
 
 
