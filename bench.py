@@ -777,7 +777,7 @@ def run_serve(args):
     is completion minus arrival per request."""
     from paper_2012_13548_amd import serve as S
     out = S.run_poisson(requests=args.serve_requests, log=lambda m: log(f"serve: {m}"))
-    keep = ("requests", "errors", "p50_ms", "p99_ms", "mean_ms", "throughput_rps",
+    keep = ("requests", "errors", "error_kinds", "p50_ms", "p99_ms", "mean_ms", "throughput_rps",
             "aggregate_gteps", "mean_batch", "rate_rps", "saturated_rps", "load", "scales",
             "workers")
     return {k: out[k] for k in keep}

@@ -28,7 +28,6 @@
 #include <chrono>
 #include <cstring>
 
-#include <hip/hip_ext.h>
 
 #include "g5_internal.h"
 
@@ -1603,22 +1602,37 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   unsigned long long *ctr = (unsigned long long *)w.ctr;
   unsigned long long *hpub = (unsigned long long *)w.host_pub_dev;
   int64_t hc[C_NPUB] = {};  // the counters last published
-  if (timed && w.ev.empty()) {
-    w.ev.resize(2 * G5_MAX_STAT_LEVELS);
-    for (auto &e : w.ev) G5_HIP(hipEventCreate(&e));
-  }
-  auto ev_at = [&](int lv, int k) -> hipEvent_t {
-    return (timed && lv < G5_MAX_STAT_LEVELS) ? w.ev[2 * lv + k] : nullptr;
+  // Timed steps: every step launch is bracketed by two events of its own,
+  // recorded on the stream before and after it, and a level's time is that of
+  // its last step launch (a step queued ahead that its level did not use is
+  // followed by the one it did).  No event is recorded twice in a call: an
+  // event is bound to one launch at a time, never to two pending ones.  The
+  // events are created as needed and kept with the workspace, whose calls end
+  // with the stream synchronised.  (The markers between kernels slow a timed
+  // traversal by ~6 %; the benchmark's timed steps carry none.)
+  int ev_used = 0;
+  int lv_ev[G5_MAX_STAT_LEVELS];
+  for (int &x : lv_ev) x = -1;
+  auto ev_take = [&](int lv) -> int {
+    if (!timed || lv >= G5_MAX_STAT_LEVELS) return -1;
+    if (2 * (size_t)ev_used + 2 > w.ev.size()) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess) return -1;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return -1;
+      }
+      w.ev.push_back(a);
+      w.ev.push_back(b);
+    }
+    lv_ev[lv] = ev_used;
+    return ev_used++;
   };
-  // A timed level's step kernel carries the level's start and stop events in
-  // its own dispatch (no marker packets between kernels: recorded separately,
-  // two events per level made the traversal ~6 % slower).
-#define G5_KLAUNCH(E0, E1, K, G, B, SH, S, ...)                       \
-  do {                                                                \
-    if (E0)                                                           \
-      hipExtLaunchKernelGGL(K, G, B, SH, S, E0, E1, 0, __VA_ARGS__);   \
-    else                                                              \
-      hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                 \
+#define G5_KLAUNCH(E, K, G, B, SH, S, ...)                    \
+  do {                                                        \
+    if ((E) >= 0) G5_HIP(hipEventRecord(w.ev[2 * (E)], S));   \
+    hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);          \
+    if ((E) >= 0) G5_HIP(hipEventRecord(w.ev[2 * (E) + 1], S)); \
   } while (0)
 
   // With hints and claims by OR, parent starts as every vertex's hint target:
@@ -1701,9 +1715,9 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   auto launch_td = [&](int32_t lv, int c, unsigned long long sq) -> g5_status {
     const int nx = c ^ 1;
     uint8_t *l8 = sink(lv);
-    hipEvent_t t0 = ev_at(lv, 0), t1 = ev_at(lv, 1);
+    const int te = ev_take(lv);
 #define G5_TD(C)                                                                                 \
-  G5_KLAUNCH(t0, t1, k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, c, \
+  G5_KLAUNCH(te, k_td_expand<C>, dim3(td_grid), dim3(kBlock), 0, s, w.q[c], w.qoff[c], ctr, c, \
              g->rp32, g->col_idx, w.vis, parent, level, l8, w.q[nx], w.qoff[nx], lv + 1,          \
              rule_for(lv + 1), hpub, sq, (const uint64_t *)g->iso, W, prefill, n, lvec, root)
     if (min_parent)
@@ -1730,7 +1744,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     if (fh_words && !fh_ready)
       hipLaunchKernelGGL(k_fh_build, dim3(grid_for(g->num_hot, kBlock, ncu * 8)), dim3(kBlock),
                          0, s, f, g->hot, g->num_hot, w.fh);
-    hipEvent_t t0 = ev_at(lv, 0), t1 = ev_at(lv, 1);
+    const int te = ev_take(lv);
 #define G5_BUL(K, P, A)                                                                     \
   do {                                                                                      \
     const void *fn_ = (const void *)&k_bu_step_lds<K, P, A>;                                 \
@@ -1738,7 +1752,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     g5_status st_ = lds_ready(fn_, (int64_t)dyn_);                                          \
     if (st_ != G5_OK) return st_;                                                           \
     const int per_cu_ = resident_per_cu(fn_, kLdsBlock, dyn_);                              \
-    G5_KLAUNCH(t0, t1, (k_bu_step_lds<K, P, A>), dim3(ncu * per_cu_), dim3(kLdsBlock), dyn_, s, \
+    G5_KLAUNCH(te, (k_bu_step_lds<K, P, A>), dim3(ncu * per_cu_), dim3(kLdsBlock), dyn_, s, \
                g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words, w.vis, f, nfp, parent, level, \
                l8, W, lv + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub, sq, bn);          \
   } while (0)
@@ -1749,7 +1763,7 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     g5_status st_ = lds_ready(fn_, (int64_t)dyn_);                                          \
     if (st_ != G5_OK) return st_;                                                           \
     const int per_cu_ = resident_per_cu(fn_, kBuBlock, dyn_);                               \
-    G5_KLAUNCH(t0, t1, (k_bu_step<K, P, A>), dim3(ncu * std::min(bu_bpc, per_cu_)),         \
+    G5_KLAUNCH(te, (k_bu_step<K, P, A>), dim3(ncu * std::min(bu_bpc, per_cu_)),         \
                dim3(kBuBlock), dyn_, s, g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words,   \
                w.vis, f, nfp, parent, level, l8, W, lv + 1, ctr, packed, hpub, sq, check, bn); \
   } while (0)
@@ -1984,7 +1998,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     if (timed)
       for (int i = 0; i < std::min<int>(lvl, G5_MAX_STAT_LEVELS); ++i) {
         float a = 0;
-        G5_HIP(hipEventElapsedTime(&a, w.ev[2 * i], w.ev[2 * i + 1]));
+        if (lv_ev[i] >= 0)
+          G5_HIP(hipEventElapsedTime(&a, w.ev[2 * lv_ev[i]], w.ev[2 * lv_ev[i] + 1]));
         stats->step_ms[i] = a;
       }
   }

@@ -66,7 +66,7 @@ struct BfsWork {
   uint64_t *host_pub = nullptr;   // pinned, mapped: counters published by kernels + seq
   uint64_t *host_pub_dev = nullptr;  // its device address
   uint64_t seq = 0;           // last sequence number published
-  std::vector<hipEvent_t> ev; // step timing: 2 per level
+  std::vector<hipEvent_t> ev; // step timing: 2 per timed step launch of a call
   ~BfsWork();
 };
 

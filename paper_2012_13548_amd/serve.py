@@ -225,7 +225,12 @@ class Server:
         t1 = max(r.t_done for r in self.done) if t_last is None else t_last
         edges = sum(r.m_r for r in ok if r.m_r is not None)
         sizes = [k for _, k in self.launches]
+        kinds = {}
+        for r in self.done:
+            if r.error is not None:
+                kinds[r.error] = kinds.get(r.error, 0) + 1
         return {"requests": len(self.done), "errors": len(self.done) - len(ok),
+                "error_kinds": dict(sorted(kinds.items(), key=lambda kv: -kv[1])[:3]),
                 "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
                 "mean_ms": round(float(lat.mean()), 3),
