@@ -116,6 +116,8 @@ void g5_csr_free(g5_csr *g) {
   if (g->hint) (void)hipFree(g->hint);
   if (g->hot) (void)hipFree(g->hot);
   if (g->hint_id) (void)hipFree(g->hint_id);
+  if (g->hint_c) (void)hipFree(g->hint_c);
+  if (g->chunk_ni) (void)hipFree(g->chunk_ni);
   if (g->rp32) (void)hipFree(g->rp32);
   if (g->hub_list) (void)hipFree(g->hub_list);
   if (g->hub_off) (void)hipFree(g->hub_off);

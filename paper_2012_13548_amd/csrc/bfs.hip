@@ -773,11 +773,45 @@ __device__ __forceinline__ int select_bit(uint64_t x, uint32_t r) {
 // without this nearly every round waited for the row reads of a few lanes.
 constexpr uint32_t kRing = 128;
 
+// Hints by rank (the one-vertex-per-lane step): stored for the vertices of
+// degree >= 1 only, which an unvisited vertex of a bottom-up step always is,
+// at their rank: the chunk's base from cbase plus the count of such vertices
+// before it in the chunk, from the isolated bitmap's words (one coalesced load
+// per lane and chunk).  Half the vertices of a scale-26 graph are isolated, so
+// the hint lines the step reads hold twice as many useful entries.  The other
+// steps (latency-bound on sparse frontiers) read hints by vertex.
+template <bool RANK>
+struct HintRank {
+  const int32_t *hint;
+  uint64_t base = 0;  // vertices of degree >= 1 before this chunk
+  uint64_t ni = 0;    // this lane's word: bit set = degree >= 1
+  uint32_t pre = 0;   // such vertices in the chunk's earlier words
+  __device__ __forceinline__ HintRank(const int32_t *h, const uint64_t *cbase, const uint64_t *iso,
+                                      int64_t c, int64_t w, int64_t words)
+      : hint(h) {
+    if (RANK && hint) {  // uniform: every lane takes part in the scan
+      ni = w < words ? ~iso[w] : 0ull;
+      const uint32_t q = (uint32_t)__popcll(ni);
+      pre = wave_incl_scan<uint32_t>(q) - q;
+      base = cbase[c];
+    }
+  }
+  // hint of the vertex at bit `bit` of the chunk's word `pos` (-1 when inactive
+  // or without hints); every lane calls it (the shuffles read other lanes)
+  __device__ __forceinline__ int32_t at(bool act, int pos, int bit) const {
+    const uint64_t x = __shfl(ni, pos, kWave);
+    const uint32_t p = __shfl(pre, pos, kWave);
+    if (!act || !hint) return -1;
+    return hint[base + p + (uint32_t)__popcll(x & ((1ull << bit) - 1))];
+  }
+};
+
 template <int LANE_SCAN, int R, bool ACCT, class Front, bool COMPACT = false, bool SPEC = false>
 __device__ __forceinline__ void bu_chunks(
     const Front &F, const uint64_t *fh, const uint32_t *__restrict__ rp,
     const int32_t *__restrict__ ci, const int32_t *__restrict__ hint,
-    const int32_t *__restrict__ hint_id, uint64_t *__restrict__ vis,
+    const int32_t *__restrict__ hint_id, const uint64_t *__restrict__ cbase,
+    const uint64_t *__restrict__ iso, uint64_t *__restrict__ vis,
     uint64_t *__restrict__ next, int32_t *__restrict__ parent, int32_t *__restrict__ level,
     uint8_t *__restrict__ lev8, int64_t words, int32_t next_level, bool packed, int64_t gw,
     int64_t nw, uint32_t *s_base,
@@ -799,6 +833,7 @@ __device__ __forceinline__ void bu_chunks(
       const uint32_t total = __shfl(incl, kWave - 1, kWave);
       const uint32_t excl = incl - cl;
       nx[lane] = 0ull;
+      HintRank<true> hr_(hint, cbase, iso, c, w, words);
       uint32_t head = 0, queued = 0;  // wavefront-uniform ring state
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // a round over `take` (<= 64) queued vertices, one per lane: row offsets,
@@ -873,7 +908,7 @@ __device__ __forceinline__ void bu_chunks(
         const uint64_t word = __shfl(un, pos, kWave);
         const int bit = act ? select_bit(word, r) : 0;
         const int32_t v = (int32_t)((c * kWave + pos) * kWave + bit);
-        int32_t h = (act && hint) ? hint[v] : -1;
+        int32_t h = hr_.at(act, pos, bit);
         if (ACCT && act) cnt.nunvis += 1;
         int hp = 0;
         int32_t par = -1;
@@ -1167,6 +1202,7 @@ template <int LANE_SCAN, int R, bool ACCT>
 __global__ __launch_bounds__(kBuBlock) void k_bu_step(
     const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const int32_t *__restrict__ hint, const int32_t *__restrict__ hint_id,
+    const uint64_t *__restrict__ cbase, const uint64_t *__restrict__ iso,
     const uint64_t *__restrict__ fh, int64_t fh_words, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
     int32_t *__restrict__ parent, int32_t *__restrict__ level, uint8_t *__restrict__ lev8,
@@ -1187,7 +1223,8 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
   const int64_t nw = ((int64_t)gridDim.x * kBuBlock) / kWave;
   BuCount c;
   bu_chunks<LANE_SCAN, R, ACCT, FrontGlobal, R == 1>(
-      FrontGlobal{(const uint32_t *)front}, s_fh, rp, ci, hint, hint_id, vis, next, parent, level,
+      FrontGlobal{(const uint32_t *)front}, s_fh, rp, ci, hint, hint_id, cbase, iso, vis, next,
+      parent, level,
       lev8, words, next_level, packed, gw, nw, s_base, s_row, s_first, s_nx, c, s_ring);
   bu_flush<kBuBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
@@ -1208,6 +1245,7 @@ template <int LANE_SCAN, int R, bool ACCT>
 __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_bu_step_lds(
     const uint32_t *__restrict__ rp, const int32_t *__restrict__ ci,
     const int32_t *__restrict__ hint, const int32_t *__restrict__ hint_id,
+    const uint64_t *__restrict__ cbase, const uint64_t *__restrict__ iso,
     const uint64_t *__restrict__ fh, int64_t fh_words, uint64_t *__restrict__ vis,
     const uint64_t *__restrict__ front, uint64_t *__restrict__ next,
     int32_t *__restrict__ parent, int32_t *__restrict__ level, uint8_t *__restrict__ lev8,
@@ -1231,7 +1269,8 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
   // (compacting hint misses as k_bu_step does measured no faster here: on a
   // sparse frontier most hints miss, so its rounds are dense already)
   bu_chunks<LANE_SCAN, R, ACCT, FrontLds, false, true>(
-      FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, vis, next, parent,
+      FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, cbase, iso, vis,
+      next, parent,
       level, lev8, words, next_level, packed, gw, nw, s_base, s_row, s_first, s_nx, c);
   bu_flush<kLdsBlock, ACCT>(c, s, ctr, host, seq, bn);
 }
@@ -1691,7 +1730,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
   bool heavy_lv[G5_MAX_STAT_LEVELS] = {};  // heavy top-down levels (statistics)
   auto slot = [&]() -> int { return (stats && lvl < G5_MAX_STAT_LEVELS) ? lvl : -1; };
   const BuNext bn{p.direction, beta, n};
-  const int32_t *hint = use_hint ? g->hint : nullptr;
+  const int32_t *hint = use_hint ? g->hint : nullptr;      // by vertex
+  const int32_t *hint_r = use_hint ? g->hint_c : nullptr;  // by rank: the one-vertex-per-lane step
   const int32_t *hint_id = prefill ? nullptr : g->hint_id;
   const int64_t fh_words = use_hint ? (g->num_hot + 63) / 64 : 0;
   // expansion grid: the workgroups that fit at once, at most kTdBlocksPerCu per
@@ -1753,7 +1793,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     if (st_ != G5_OK) return st_;                                                           \
     const int per_cu_ = resident_per_cu(fn_, kLdsBlock, dyn_);                              \
     G5_KLAUNCH(te, (k_bu_step_lds<K, P, A>), dim3(ncu * per_cu_), dim3(kLdsBlock), dyn_, s, \
-               g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words, w.vis, f, nfp, parent, level, \
+               g->rp32, g->col_idx, hint, hint_id, g->chunk_ni, g->iso, w.fh, fh_words, w.vis, f,  \
+               nfp, parent, level,                                                          \
                l8, W, lv + 1, ctr, packed, w.sum, lds_words, lds_gs, hpub, sq, bn);          \
   } while (0)
 #define G5_BU(K, P, A)                                                                      \
@@ -1764,7 +1805,8 @@ g5_status bfs_impl(const g5_csr *g, int64_t root, int32_t *parent, int32_t *leve
     if (st_ != G5_OK) return st_;                                                           \
     const int per_cu_ = resident_per_cu(fn_, kBuBlock, dyn_);                               \
     G5_KLAUNCH(te, (k_bu_step<K, P, A>), dim3(ncu * std::min(bu_bpc, per_cu_)),         \
-               dim3(kBuBlock), dyn_, s, g->rp32, g->col_idx, hint, hint_id, w.fh, fh_words,   \
+               dim3(kBuBlock), dyn_, s, g->rp32, g->col_idx, (P) == 1 ? hint_r : hint, hint_id, \
+               g->chunk_ni, g->iso, w.fh, fh_words,                                         \
                w.vis, f, nfp, parent, level, l8, W, lv + 1, ctr, packed, hpub, sq, check, bn); \
   } while (0)
 #define G5_BU_P(M, K, A)          \

@@ -673,6 +673,44 @@ __global__ void k_hint_encode(int32_t *__restrict__ hint, int64_t n,
   }
 }
 
+// Vertices of degree >= 1 in each chunk of 64 bitmap words (one wavefront per
+// chunk; the isolated bitmap has its padding bits past n set).
+__global__ __launch_bounds__(256) void k_chunk_count(const uint64_t *__restrict__ iso,
+                                                     int64_t words, int64_t chunks,
+                                                     uint32_t *__restrict__ cnt) {
+  const int lane = __lane_id();
+  const int64_t stride = (int64_t)gridDim.x * (256 / kWave);
+  for (int64_t c = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kWave; c < chunks; c += stride) {
+    const int64_t w = c * kWave + lane;
+    const uint32_t q = w < words ? (uint32_t)__popcll(~iso[w]) : 0u;
+    const uint32_t t = wave_sum<uint32_t>(q);
+    if (lane == 0) cnt[c] = t;
+  }
+}
+
+// hint_c[rank] = hint[v] for the rank-th vertex v of degree >= 1: lane l of the
+// chunk's wavefront takes bitmap word l and writes its vertices' hints in order
+// from its exclusive prefix of the chunk's counts.
+__global__ __launch_bounds__(256) void k_hint_compact(const int32_t *__restrict__ hint,
+                                                      const uint64_t *__restrict__ iso,
+                                                      int64_t words, int64_t chunks,
+                                                      const uint64_t *__restrict__ cbase,
+                                                      int32_t *__restrict__ hint_c) {
+  const int lane = __lane_id();
+  const int64_t stride = (int64_t)gridDim.x * (256 / kWave);
+  for (int64_t c = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kWave; c < chunks; c += stride) {
+    const int64_t w = c * kWave + lane;
+    uint64_t x = w < words ? ~iso[w] : 0ull;
+    const uint32_t q = (uint32_t)__popcll(x);
+    uint64_t r = cbase[c] + (wave_incl_scan<uint32_t>(q) - q);
+    while (x) {
+      const int b = __ffsll((unsigned long long)x) - 1;
+      x &= x - 1;
+      hint_c[r++] = hint[w * 64 + b];
+    }
+  }
+}
+
 __global__ void k_rp32(const int64_t *__restrict__ rp, int64_t len, uint32_t *__restrict__ out) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
@@ -966,6 +1004,27 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
       if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
       g->num_hot = (int64_t)above;
     }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
+  }
+  {
+    // hints of the vertices of degree >= 1 only, by rank: the dense-frontier
+    // bottom-up step then reads lines that hold no isolated vertex (half of
+    // them at scale 26)
+    const int64_t chunks = (g->words + kWave - 1) / kWave;
+    DevBuf cnt;
+    if ((e = cnt.alloc(chunks * 4)) != hipSuccess ||
+        (e = hipMalloc(&g->chunk_ni, chunks * 8)) != hipSuccess ||
+        (e = hipMalloc(&g->hint_c, std::max<int64_t>(1, g->nonisolated) * sizeof(int32_t))) !=
+            hipSuccess)
+      return fail(e, "compact hints");
+    const int cgrid = grid_cap(chunks, 256 / kWave, ncu * 16);
+    hipLaunchKernelGGL(k_chunk_count, dim3(cgrid), dim3(256), 0, s, g->iso, g->words, chunks,
+                       (uint32_t *)cnt.p);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(kScanBlock), 0, s, (const uint32_t *)cnt.p,
+                       g->chunk_ni, chunks, (uint64_t *)nullptr);
+    hipLaunchKernelGGL(k_hint_compact, dim3(cgrid), dim3(256), 0, s, g->hint, g->iso, g->words,
+                       chunks, (const uint64_t *)g->chunk_ni, g->hint_c);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   }
 

@@ -130,6 +130,10 @@ struct g5_csr {
                                // INT32_MIN | i when that neighbour is hot[i]; | kHintOnly
                                // when it is the only neighbour
   int32_t *hint_id = nullptr;  // device [n]: highest-degree neighbour id, -1 if none
+  int32_t *hint_c = nullptr;   // device [nonisolated]: hint of the vertices of degree >= 1,
+                               // in vertex order (the dense-frontier bottom-up step reads these)
+  uint64_t *chunk_ni = nullptr;  // device [(words + 63) / 64]: vertices of degree >= 1 before
+                                 // each chunk of 64 bitmap words (4,096 vertices)
   int32_t *hot = nullptr;      // device [num_hot]: hint targets with a compact frontier bit
   int64_t num_hot = 0;         // at most kHotMax
   g5::Tuning tune{};           // defaults for this graph's scale
