@@ -632,21 +632,25 @@ struct BuCount {
 // either packed end to end (one entry per lane per 64-entry window) or one row
 // per 64-lane step.  With ACCT it counts the row entries read up to the first
 // hit.
-template <class Front, bool ACCT>
+template <class Front, bool ACCT, int NW>
 __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__restrict__ ci,
                                             bool packed, bool pending, int64_t k, int64_t e,
                                             bool &found, int32_t &par, uint32_t *s_base,
                                             int32_t *s_row, int32_t *s_first, BuCount &cnt) {
   const int lane = __lane_id();
   if (packed) {
-    // Unresolved rows laid end to end, one entry per lane per 64-entry window;
-    // a row's first hit in a window is its smallest hitting lane (LDS atomic
-    // min); resolved rows stop probing, and after a window that resolves rows
-    // the next window starts at the next entry of a row still unresolved, so
-    // the entries resolved rows did not need cost no windows (without the
-    // jump a wavefront whose other rows resolve early steps over all their
-    // entries to reach its last unresolved row: a bottom-up level on a small
-    // frontier of hubs took 7 ms instead of 1.4).
+    // Unresolved rows laid end to end, one entry per lane per 64-entry window,
+    // NW windows per step whose entry loads and then frontier-word loads are
+    // in flight together; a row's first hit in a step is its smallest hitting
+    // position (LDS atomic min over window * 64 + lane); resolved rows stop
+    // probing, and after a step that resolves rows the next step starts at the
+    // next entry of a row still unresolved, so the entries resolved rows did
+    // not need cost no windows (without the jump a wavefront whose other rows
+    // resolve early steps over all their entries to reach its last unresolved
+    // row: a bottom-up level on a small frontier of hubs took 7 ms instead of
+    // 1.4).  A row resolved in one window of a step may read a few entries of
+    // the next for nothing.
+    constexpr int kNone = kWave * NW;
     const uint32_t len = (pending && !found) ? (uint32_t)(e - k) : 0u;
     const uint32_t incl = wave_incl_scan(len);
     const uint32_t total = __shfl(incl, kWave - 1, kWave);
@@ -656,45 +660,66 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
       // row entry j of the window sits at s_base + j: k - pre + j lies in
       // [0, nnz) < 2^32, so 32-bit wrap-around arithmetic gives it exactly
       s_base[wb + lane] = (uint32_t)k - pre;
-      s_first[wb + lane] = kWave;
+      s_first[wb + lane] = kNone;
       uint64_t done = __ballot(len == 0);
       int carry = 0;
-      for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
-        const bool starts = len > 0 && pre >= j0 && pre < j0 + kWave;
-        if (starts) s_row[wb + (int)(pre - j0)] = lane;
-        const uint64_t S = wave_or_u64(starts ? (1ull << (pre - j0)) : 0ull);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const uint64_t upto = S & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
-        const int r = upto ? s_row[wb + (kWave - 1 - __clzll((long long)upto))] : carry;
-        const uint32_t j = j0 + lane;
-        int32_t u = -1;
-        bool hit = false;
-        if (j < total && !((done >> r) & 1)) {
-          u = ci[(uint32_t)(s_base[wb + r] + j)];
-          hit = F.test(u);
+      for (uint32_t j0 = 0; j0 < total; j0 += kNone) {
+        int32_t u[NW];
+        int r[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t jw = j0 + (uint32_t)(w * kWave);
+          const bool starts = len > 0 && pre >= jw && pre < jw + kWave;
+          if (starts) s_row[wb + (int)(pre - jw)] = lane;
+          const uint64_t S = wave_or_u64(starts ? (1ull << (pre - jw)) : 0ull);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const uint64_t upto = S & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
+          r[w] = upto ? s_row[wb + (kWave - 1 - __clzll((long long)upto))] : carry;
+          carry = __shfl(r[w], kWave - 1, kWave);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const uint32_t j = jw + lane;
+          u[w] = -1;
+          if (j < total && !((done >> r[w]) & 1)) u[w] = ci[(uint32_t)(s_base[wb + r[w]] + j)];
         }
-        if (hit) atomicMin(&s_first[wb + r], lane);
+        int p[NW];
+        uint32_t wd[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          p[w] = F.pre(u[w] < 0 ? 0 : u[w]);  // unconditional: no branch per entry
+          if (u[w] < 0) p[w] = 0;
+        }
+#pragma unroll
+        for (int w = 0; w < NW; ++w) wd[w] = (p[w] == 2) ? F.word(u[w]) : 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const bool hit = p[w] == 1 || (p[w] == 2 && ((wd[w] >> (u[w] & 31)) & 1));
+          if (hit) atomicMin(&s_first[wb + r[w]], w * kWave + lane);
+        }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const int fl = s_first[wb + lane];
-        const bool fresh = fl < kWave;
-        const int32_t gv = __shfl(u, fresh ? fl : lane, kWave);
+        const bool fresh = fl < kNone;
+        int32_t gv = __shfl(u[0], fresh ? (fl & (kWave - 1)) : lane, kWave);
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+          const int32_t g = __shfl(u[w], fresh ? (fl & (kWave - 1)) : lane, kWave);
+          if (fl / kWave == w) gv = g;
+        }
         if (fresh) {
           found = true;
           par = gv;
-          s_first[wb + lane] = kWave;
+          s_first[wb + lane] = kNone;
           if (ACCT) cnt.nscan += (uint64_t)(j0 + fl - pre + 1);
         }
         const uint64_t fm = __ballot(fresh);
         done |= fm;
-        carry = __shfl(r, kWave - 1, kWave);
         if (done == ~0ull) break;
         if (fm) {
-          // the next window starts where the next unresolved entry is: inside
-          // a row that covers j0 + 64 (no jump), or at the start of a later
+          // the next step starts where the next unresolved entry is: inside a
+          // row that covers j0 + NW * 64 (no jump), or at the start of a later
           // row (a row start: its window needs no carry)
-          const uint32_t nj = j0 + kWave;
+          const uint32_t nj = j0 + kNone;
           const bool live = !((done >> lane) & 1) && pre + len > nj;
-          j0 = wave_min<uint32_t>(live ? (pre > nj ? pre : nj) : 0xffffffffu) - kWave;
+          j0 = wave_min<uint32_t>(live ? (pre > nj ? pre : nj) : 0xffffffffu) - kNone;
         }
       }
       if (ACCT && len > 0 && !found) cnt.nscan += len;
@@ -806,7 +831,8 @@ struct HintRank {
   }
 };
 
-template <int LANE_SCAN, int R, bool ACCT, class Front, bool COMPACT = false, bool SPEC = false>
+template <int LANE_SCAN, int R, bool ACCT, class Front, bool COMPACT = false, bool SPEC = false,
+          int NW = 1>
 __device__ __forceinline__ void bu_chunks(
     const Front &F, const uint64_t *fh, const uint32_t *__restrict__ rp,
     const int32_t *__restrict__ ci, const int32_t *__restrict__ hint,
@@ -889,7 +915,7 @@ __device__ __forceinline__ void bu_chunks(
           k = std::min<uint32_t>(b + LANE_SCAN, e);
           if (ACCT) cnt.nscan += (uint64_t)(k - b);
         }
-        bu_row_rest<Front, ACCT>(F, ci, packed, a, (int64_t)k, (int64_t)e, found, par, s_base,
+        bu_row_rest<Front, ACCT, NW>(F, ci, packed, a, (int64_t)k, (int64_t)e, found, par, s_base,
                                  s_row, s_first, cnt);
         if (found) {
           parent[vv] = par;
@@ -1104,7 +1130,7 @@ __device__ __forceinline__ void bu_chunks(
       }
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        bu_row_rest<Front, ACCT>(F, ci, packed, act[j], (int64_t)k[j], (int64_t)e[j], found[j],
+        bu_row_rest<Front, ACCT, NW>(F, ci, packed, act[j], (int64_t)k[j], (int64_t)e[j], found[j],
                                  par[j], s_base, s_row, s_first, cnt);
         if (found[j]) {
           if (!via[j])
@@ -1234,6 +1260,8 @@ __global__ __launch_bounds__(kBuBlock) void k_bu_step(
 // hot-target words): probes of vertices whose summary bit is clear never leave
 // the compute unit.
 constexpr int kLdsBlock = 1024;
+// 64-entry windows per step of its packed row scan
+constexpr int kLdsWindows = 2;
 // k_bu_step_lds's own LDS arrays (about 20 KiB), with margin
 constexpr int64_t kBuStaticLds = 28 * 1024;
 
@@ -1268,7 +1296,7 @@ __global__ __launch_bounds__(kLdsBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
   BuCount c;
   // (compacting hint misses as k_bu_step does measured no faster here: on a
   // sparse frontier most hints miss, so its rounds are dense already)
-  bu_chunks<LANE_SCAN, R, ACCT, FrontLds, false, true>(
+  bu_chunks<LANE_SCAN, R, ACCT, FrontLds, false, true, kLdsWindows>(
       FrontLds{s_sum, (const uint32_t *)front, gs}, s_fh, rp, ci, hint, hint_id, cbase, iso, vis,
       next, parent,
       level, lev8, words, next_level, packed, gw, nw, s_base, s_row, s_first, s_nx, c);
