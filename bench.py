@@ -395,8 +395,9 @@ def csr_build_section(rows, short):
     packs = [(t1 - t0, t0) for name, t0, t1 in rows if short(name) == "k_pack"]
     if not packs:
         return []
-    build = ("k_pack", "k_radix_", "k_scan_u32", "k_set_u64", "k_heads_count", "k_compact",
-             "k_iso", "k_rp32", "k_find_hubs", "k_hub_", "k_deg16", "k_hint", "k_hot_")
+    build = ("k_pack", "k_hist_reduce", "k_digit_starts", "k_onesweep", "k_scan_u32",
+             "k_set_u64", "k_heads_count", "k_compact", "k_iso", "k_rp32", "k_find_hubs",
+             "k_hub_", "k_deg16", "k_hint", "k_hot_", "k_chunk_count")
     is_build = lambda k: k.startswith(build)
     start = max(packs)[1]
     # up to the first other kernel of the library after the packing

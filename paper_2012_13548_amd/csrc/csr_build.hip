@@ -4,8 +4,11 @@
 //
 //   pack      each non-loop tuple (u, v) -> keys (u << sb | v) and (v << sb | u);
 //             self-loops and out-of-range ids -> SENT (sorts last)
-//   sort      LSD radix sort of the 2*sb-bit keys, 8-bit digits, stable ranking
-//             by wavefront match (8 ballots per digit) and LDS counters
+//   sort      LSD radix sort of the 2*sb-bit keys, 8-bit digits: the digit
+//             histograms of every pass are counted while packing, then each
+//             pass is one sweep whose tiles rank their keys (wavefront match,
+//             8 ballots per digit, and LDS counters) and find where their digit
+//             runs go from the counts published by the tiles before them
 //   compact   keep the first of each run of equal keys -> col_idx; the source of
 //             each kept key opens rows (prev_source, source] -> row_ptr, so an
 //             empty row repeats the next index; rows after the last key get nnz
@@ -48,11 +51,18 @@ constexpr int kCompactTile = kCompactBlock * kCompactItems;  // 4096 keys
 // With weights (wb = 8) a key is (u << (sb + 8) | v << 8 | w): the sort then
 // orders each run of one (u, v) by weight, and the compaction keeps its first
 // key, i.e. the smallest weight of repeated tuples.  Without weights wb = 0.
+// Each block also counts the digits of its keys for every sort pass:
+// bh[block][pass][digit].
+constexpr int kMaxPasses = 8;
 __global__ __launch_bounds__(256) void k_pack(const int64_t *__restrict__ edges,
                                               const uint8_t *__restrict__ wts, int64_t m,
-                                              int64_t n, int sb, int wb, uint64_t sent,
+                                              int64_t n, int sb, int wb, uint64_t sent, int npass,
                                               uint64_t *__restrict__ keys,
+                                              uint32_t *__restrict__ bh,
                                               uint32_t *__restrict__ err) {
+  __shared__ uint32_t h[kMaxPasses][kRadix];
+  for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += blockDim.x) (&h[0][0])[i] = 0;
+  __syncthreads();
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool bad = false;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
@@ -69,34 +79,40 @@ __global__ __launch_bounds__(256) void k_pack(const int64_t *__restrict__ edges,
     o.x = k0;
     o.y = k1;
     reinterpret_cast<ulonglong2 *>(keys)[i] = o;
+#pragma unroll
+    for (int p = 0; p < kMaxPasses; ++p) {
+      if (p < npass) {
+        atomicAdd(&h[p][(uint32_t)(k0 >> (8 * p)) & 0xFF], 1u);
+        atomicAdd(&h[p][(uint32_t)(k1 >> (8 * p)) & 0xFF], 1u);
+      }
+    }
   }
   if (__ballot(bad) != 0 && __lane_id() == 0) atomicOr(err, 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < npass * kRadix; i += blockDim.x)
+    bh[(int64_t)blockIdx.x * npass * kRadix + i] = (&h[0][0])[i];
 }
 
-// Per-block digit histogram of the block's contiguous run of tiles.
-__global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(
-    const uint64_t *__restrict__ keys, uint64_t nkeys, int shift, int64_t tiles_per_block,
-    int nblocks, uint32_t *__restrict__ counts) {
-  __shared__ uint32_t hist[4][kRadix];
-  const int w = threadIdx.x / kWave;
-  for (int i = threadIdx.x; i < 4 * kRadix; i += kSortBlock) (&hist[0][0])[i] = 0;
-  __syncthreads();
-  uint64_t beg = (uint64_t)blockIdx.x * tiles_per_block * kSortTile;
-  uint64_t end = beg + (uint64_t)tiles_per_block * kSortTile;
-  if (end > nkeys) end = nkeys;
-  uint64_t i = beg + threadIdx.x;
-  for (; i + 3 * kSortBlock < end; i += 4 * kSortBlock) {
-    uint64_t a = keys[i], b = keys[i + kSortBlock], c = keys[i + 2 * kSortBlock],
-             d = keys[i + 3 * kSortBlock];
-    atomicAdd(&hist[w][(a >> shift) & 0xFF], 1u);
-    atomicAdd(&hist[w][(b >> shift) & 0xFF], 1u);
-    atomicAdd(&hist[w][(c >> shift) & 0xFF], 1u);
-    atomicAdd(&hist[w][(d >> shift) & 0xFF], 1u);
-  }
-  for (; i < end; i += kSortBlock) atomicAdd(&hist[w][(keys[i] >> shift) & 0xFF], 1u);
-  __syncthreads();
-  int d = threadIdx.x;  // kSortBlock == kRadix
-  counts[(int64_t)d * nblocks + blockIdx.x] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+// ghist[pass][digit] += the counts of blocks slice, slice + S, ... (S slices
+// per pass; ghist starts at zero).
+constexpr int kHistSlices = 32;
+__global__ __launch_bounds__(kRadix) void k_hist_reduce(const uint32_t *__restrict__ bh, int nbp,
+                                                        int npass,
+                                                        unsigned long long *__restrict__ ghist) {
+  const int p = blockIdx.x / kHistSlices, sl = blockIdx.x % kHistSlices;
+  uint64_t acc = 0;
+  for (int b = sl; b < nbp; b += kHistSlices)
+    acc += bh[((int64_t)b * npass + p) * kRadix + threadIdx.x];
+  if (acc) atomicAdd(ghist + p * kRadix + threadIdx.x, (unsigned long long)acc);
+}
+
+// dstart[pass][digit] = where the keys of that digit start in the pass's output.
+__global__ __launch_bounds__(kRadix) void k_digit_starts(const unsigned long long *__restrict__ ghist,
+                                                         uint64_t *__restrict__ dstart) {
+  __shared__ uint64_t s[kRadix / kWave];
+  const int i = blockIdx.x * kRadix + threadIdx.x;
+  uint64_t tot;
+  dstart[i] = block_excl_scan<kRadix, uint64_t>((uint64_t)ghist[i], s, tot);
 }
 
 // Exclusive scan of a uint32 array into uint64 (single block); *total = sum.
@@ -119,42 +135,63 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_u32(const uint32_t *__restr
   if (threadIdx.x == 0 && total) *total = tot;
 }
 
-// Stable scatter of one 8-bit digit.  Wavefront w of a tile owns keys
-// [w*kWaveKeys, (w+1)*kWaveKeys) in kSortItems steps of 64; a key's rank
-// inside its wavefront is the count of equal digits in earlier steps (LDS
-// counter) plus earlier lanes of its step (match mask from 8 ballots).  The
+// Status of (tile, digit) in one pass: the count of that digit in the tile
+// (state kStAgg) or in the tile and every tile before it (kStIncl), tagged
+// with the pass so that the words of an earlier pass read as not ready.
+constexpr uint64_t kStCount = (1ull << 56) - 1;
+constexpr uint64_t kStTagMask = 63ull << 56;
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStIncl = 2ull << 62;
+// A look-back waits on a tile that a running workgroup holds; it gives up
+// (and raises bit 2 of err, which ends every other wait of the launch) after
+// this many polls, so the launch always ends.
+constexpr int kSpinLimit = 1 << 18;
+
+// One stable pass over one 8-bit digit.  Workgroups take tiles of kSortTile
+// keys in increasing order from a counter, one ahead of the tile they work on
+// (a tile only waits on tiles with smaller numbers; the smallest unfinished
+// tile is one that a running workgroup works on, so every wait ends).  In a
+// tile, wavefront w owns keys [w*kWaveKeys, (w+1)*kWaveKeys) in kSortItems
+// steps of 64; a key's rank inside its wavefront is the count of equal digits
+// in earlier steps (LDS counter) plus earlier lanes of its step (match mask
+// from 8 ballots).  Thread d then publishes the tile's count of digit d, adds
+// up the counts of the tiles before (walking back to the first that
+// published an inclusive count) and publishes its own inclusive count.  The
 // next tile's keys are loaded while the current one is ranked and written.
-__global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
+__global__ __launch_bounds__(kSortBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_onesweep(
     const uint64_t *__restrict__ kin, uint64_t *__restrict__ kout, uint64_t nkeys, int shift,
-    int64_t tiles_per_block, int nblocks, const uint64_t *__restrict__ offs) {
+    uint64_t tag, uint32_t ntiles, const uint64_t *__restrict__ dstart, uint64_t *status,
+    uint32_t *ctr, uint32_t *err) {
   __shared__ uint64_t base[kRadix];
   __shared__ uint32_t wh[4][kRadix];
-  __shared__ uint32_t ttot[kRadix];
   __shared__ uint32_t doff[kRadix];        // where each digit's run starts in the tile
   __shared__ uint64_t s_keys[kSortTile];   // the tile's keys in digit order
   __shared__ uint32_t s_scan[kSortBlock / kWave];
+  __shared__ uint32_t s_tile[2];  // the first tile; the next tile
   const int tid = threadIdx.x, w = tid / kWave, lane = __lane_id();
-  base[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
-  const uint64_t lt = lanemask_lt();
-  int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+  if (tid == 0) s_tile[0] = atomicAdd(ctr, 1u);
+  __syncthreads();
+  uint32_t cur = s_tile[0];
   uint64_t next[kSortItems];
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const uint64_t idx = (uint64_t)t0 * kSortTile + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
-    next[j] = idx < nkeys ? kin[idx] : 0;
+    const uint64_t idx = (uint64_t)cur * kSortTile + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
+    next[j] = (cur < ntiles && idx < nkeys) ? kin[idx] : 0;
   }
-  for (int64_t t = t0; t < t0 + tiles_per_block; ++t) {
-    uint64_t tbase = (uint64_t)t * kSortTile;
-    if (tbase >= nkeys) break;
+  while (cur < ntiles) {
+    const uint64_t tbase = (uint64_t)cur * kSortTile;
     for (int d = lane; d < kRadix; d += kWave) wh[w][d] = 0;
     uint64_t key[kSortItems];
     uint32_t rank[kSortItems];
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) key[j] = next[j];
-    if (t + 1 < t0 + tiles_per_block) {
+    if (tid == 0) s_tile[1] = atomicAdd(ctr, 1u);
+    __syncthreads();  // the previous tile's readers of s_tile[1] passed the barrier that ended it
+    const uint32_t nxt = s_tile[1];
+    if (nxt < ntiles) {
 #pragma unroll
       for (int j = 0; j < kSortItems; ++j) {
-        const uint64_t idx = tbase + kSortTile + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
+        const uint64_t idx = (uint64_t)nxt * kSortTile + (uint64_t)w * kWaveKeys + (uint64_t)j * kWave + lane;
         next[j] = idx < nkeys ? kin[idx] : 0;
       }
     }
@@ -174,22 +211,27 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
       uint32_t old = 0;
       if (valid && lane == leader) old = atomicAdd(&wh[w][d], (uint32_t)__popcll(peers));
       old = __shfl(old, leader, kWave);
-      rank[j] = old + (uint32_t)__popcll(peers & lt);
+      // old + the number of peers in lower lanes
+      rank[j] = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)peers, old));
     }
     __syncthreads();
+    uint32_t cnt = 0;  // kSortBlock == kRadix: thread tid owns digit tid
     {
-      uint32_t s = 0;
 #pragma unroll
       for (int ww = 0; ww < 4; ++ww) {
         uint32_t c = wh[ww][tid];
-        wh[ww][tid] = s;
-        s += c;
+        wh[ww][tid] = cnt;
+        cnt += c;
       }
-      ttot[tid] = s;
       uint32_t total;
-      doff[tid] = block_excl_scan<kSortBlock, uint32_t>(s, s_scan, total);
+      doff[tid] = block_excl_scan<kSortBlock, uint32_t>(cnt, s_scan, total);
     }
-    __syncthreads();  // doff, wh and ttot complete
+    // publish this tile's count of digit tid for the tiles after it
+    uint64_t *const st = status + (uint64_t)cur * kRadix + tid;
+    __hip_atomic_store(st, tag | (cur == 0 ? kStIncl : kStAgg) | cnt, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();  // doff and wh complete
     // Stage the tile in LDS in digit order (stable: within a digit, keys keep
     // their input order), then write each digit's run out contiguously, so a
     // wavefront's stores cover few lines instead of one line per lane.
@@ -202,7 +244,34 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         if (lp < (uint32_t)kSortTile) s_keys[lp] = key[j];
       }
     }
-    __syncthreads();
+    // decoupled look-back over the tiles before this one, for digit tid
+    uint64_t excl = 0;
+    if (cur != 0) {
+      uint64_t k = cur - 1;
+      int spins = 0;
+      while (true) {
+        const uint64_t v = __hip_atomic_load(status + k * kRadix + tid, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        if ((v & kStTagMask) != tag || (v & (3ull << 62)) == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr(err, 2u);
+            break;
+          }
+          if ((spins & 63) == 0 &&
+              (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2u) != 0)
+            break;
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += v & kStCount;
+        if ((v & kStIncl) != 0 || k == 0) break;
+        --k;
+      }
+      __hip_atomic_store(st, tag | kStIncl | (excl + cnt), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    base[tid] = dstart[tid] + excl;
+    __syncthreads();  // s_keys and base complete
     const uint32_t tile_n = (uint32_t)std::min<uint64_t>(kSortTile, nkeys - tbase);
     for (uint32_t i = tid; i < tile_n; i += kSortBlock) {
       const uint64_t k = s_keys[i];
@@ -211,8 +280,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
       if (pos < nkeys) kout[pos] = k;
     }
     __syncthreads();
-    base[tid] += ttot[tid];
-    __syncthreads();
+    cur = nxt;
   }
 }
 
@@ -592,11 +660,20 @@ __global__ void k_hint_hubs_write(const int32_t *__restrict__ hubs, int64_t nh,
 constexpr int kHotBins = 1024;
 constexpr int kHotTile = 4096;  // vertices per workgroup when numbering hot targets
 
-// cnt[t] = number of vertices whose hint is t.  Most vertices name one of a
-// few hubs, so the lanes of a wavefront that name the same target are counted
-// together (one atomic per distinct target per wavefront).
-__global__ void k_hint_count(const int32_t *__restrict__ hint, int64_t n,
-                             uint32_t *__restrict__ cnt) {
+// cnt[t] = number of vertices whose hint is t.  Most vertices name one of the
+// hint candidates (the hubs of largest degree): those are counted in LDS by
+// candidate rank and added to cnt once per workgroup, since a device-scope
+// atomic per wavefront on one hub's counter would serialise at that address.
+// The other targets take one atomic per distinct target per wavefront.
+__global__ __launch_bounds__(256) void k_hint_count(const int32_t *__restrict__ hint, int64_t n,
+                                                    const int32_t *__restrict__ cand, int kc,
+                                                    uint32_t *__restrict__ cnt) {
+  __shared__ int32_t s_cid[kCandSlots];
+  __shared__ uint16_t s_crank[kCandSlots];
+  __shared__ uint32_t s_cnt[kHintCand];
+  CandSet cs{s_cid, s_crank};
+  for (int i = threadIdx.x; i < kHintCand; i += blockDim.x) s_cnt[i] = 0;
+  cs.fill(cand, kc);
   const int lane = __lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;  // a multiple of kWave
   const int64_t span = ((n + kWave - 1) / kWave) * kWave;    // every lane runs each round
@@ -604,6 +681,13 @@ __global__ void k_hint_count(const int32_t *__restrict__ hint, int64_t n,
     const int32_t h = v < n ? hint[v] : -1;
     const int32_t t = h >= 0 ? (h & ~kHintOnly) : -1;
     bool todo = t >= 0;
+    if (todo && kc > 0) {
+      const uint64_t r = cs.rank_of(t);
+      if (r != kNone) {
+        atomicAdd(&s_cnt[r], 1u);
+        todo = false;
+      }
+    }
     uint64_t m;
     while ((m = __ballot(todo)) != 0) {
       const int L = __ffsll((unsigned long long)m) - 1;
@@ -614,6 +698,9 @@ __global__ void k_hint_count(const int32_t *__restrict__ hint, int64_t n,
       if (same) todo = false;
     }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kc; i += blockDim.x)
+    if (s_cnt[i]) atomicAdd(cnt + cand[i], s_cnt[i]);
 }
 
 // hist[c] = number of targets named by c vertices (c >= kHotBins - 1 share the last bin)
@@ -768,28 +855,42 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
   uint64_t *keys = (uint64_t *)ka.p, *alt = (uint64_t *)kb.p;
 
   if (m > 0) {
-    hipLaunchKernelGGL(k_pack, dim3(grid_cap(m, 256, ncu * 64)), dim3(256), 0, s, edges,
-                       weighted ? weights : nullptr,
-                       m, n, sb, wb, sent, keys, err);
+    const int nbp = grid_cap(m, 256, ncu * 16);
+    // radix sort: one sweep per pass over tiles taken in order by resident
+    // workgroups (the pass counters and the status words start at zero)
+    const int npass = (key_bits + 7) / 8;
+    const uint64_t ntiles = (nkeys + kSortTile - 1) / kSortTile;
+    if (ntiles >= (1ull << 32)) {
+      set_error("g5_build_csr: too many tuples for the sort");
+      return G5_ERANGE;
+    }
+    const size_t hist_bytes = (size_t)nbp * npass * kRadix * sizeof(uint32_t);
+    const size_t status_bytes = (size_t)ntiles * kRadix * sizeof(uint64_t);
+    G5_HIP(hipMalloc(&counts.p, hist_bytes + 2 * kMaxPasses * kRadix * sizeof(uint64_t) +
+                                    kMaxPasses * sizeof(uint32_t)));
+    G5_HIP(hipMalloc(&offs.p, status_bytes));
+    uint32_t *bh = (uint32_t *)counts.p;
+    unsigned long long *ghist = (unsigned long long *)((char *)counts.p + hist_bytes);
+    uint64_t *dstart = (uint64_t *)(ghist + kMaxPasses * kRadix);
+    uint32_t *ctr = (uint32_t *)(dstart + kMaxPasses * kRadix);
+    G5_HIP(hipMemsetAsync(ghist, 0, kMaxPasses * kRadix * sizeof(uint64_t), s));
+    G5_HIP(hipMemsetAsync(ctr, 0, kMaxPasses * sizeof(uint32_t), s));
+    G5_HIP(hipMemsetAsync(offs.p, 0, status_bytes, s));
+    hipLaunchKernelGGL(k_pack, dim3(nbp), dim3(256), 0, s, edges, weighted ? weights : nullptr,
+                       m, n, sb, wb, sent, npass, keys, bh, err);
+    hipLaunchKernelGGL(k_hist_reduce, dim3(npass * kHistSlices), dim3(kRadix), 0, s,
+                       (const uint32_t *)bh, nbp, npass, ghist);
+    hipLaunchKernelGGL(k_digit_starts, dim3(npass), dim3(kRadix), 0, s,
+                       (const unsigned long long *)ghist, dstart);
     G5_LAUNCH_CHECK();
-    // radix sort
-    // one resident wave of workgroups, each over a contiguous run of tiles
     int per_cu = 0;
-    G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_radix_downsweep, kSortBlock, 0));
-    const int64_t max_blocks = (int64_t)ncu * std::max(per_cu, 1);
-    int64_t tiles = (int64_t)((nkeys + kSortTile - 1) / kSortTile);
-    int64_t tpb = (tiles + max_blocks - 1) / max_blocks;
-    int nb = (int)((tiles + tpb - 1) / tpb);
-    G5_HIP(hipMalloc(&counts.p, (size_t)kRadix * nb * sizeof(uint32_t)));
-    G5_HIP(hipMalloc(&offs.p, (size_t)kRadix * nb * sizeof(uint64_t)));
-    for (int shift = 0; shift < key_bits; shift += 8) {
-      hipLaunchKernelGGL(k_radix_upsweep, dim3(nb), dim3(kSortBlock), 0, s, keys, nkeys, shift,
-                         tpb, nb, (uint32_t *)counts.p);
-      hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(kScanBlock), 0, s,
-                         (const uint32_t *)counts.p, (uint64_t *)offs.p,
-                         (int64_t)kRadix * nb, (uint64_t *)nullptr);
-      hipLaunchKernelGGL(k_radix_downsweep, dim3(nb), dim3(kSortBlock), 0, s, keys, alt, nkeys,
-                         shift, tpb, nb, (const uint64_t *)offs.p);
+    G5_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_onesweep, kSortBlock, 0));
+    const int nb = (int)std::min<uint64_t>(ntiles, (uint64_t)ncu * std::max(per_cu, 1));
+    for (int p = 0; p < npass; ++p) {
+      hipLaunchKernelGGL(k_onesweep, dim3(nb), dim3(kSortBlock), 0, s, keys, alt, nkeys, 8 * p,
+                         (uint64_t)(p + 1) << 56, (uint32_t)ntiles,
+                         (const uint64_t *)(dstart + p * kRadix), (uint64_t *)offs.p, ctr + p,
+                         err);
       G5_LAUNCH_CHECK();
       std::swap(keys, alt);
     }
@@ -811,9 +912,13 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
   G5_HIP(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
   G5_HIP(hipMemcpyAsync(hv, nnz_dev, 8, hipMemcpyDeviceToHost, s));
   G5_HIP(hipStreamSynchronize(s));
-  if (herr) {
+  if (herr & 1u) {
     set_error("g5_build_csr: an edge names a vertex outside [0, n)");
     return G5_EINVAL;
+  }
+  if (herr & 2u) {
+    set_error("g5_build_csr: a radix sort pass did not see the counts of an earlier tile");
+    return G5_EDEVICE;
   }
   const uint64_t nnz = hv[0];
   if (nnz >= (1ull << 32)) {
@@ -905,15 +1010,17 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
   if ((e = hipMalloc(&g->hint, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
   if ((e = hipMalloc(&g->hint_id, n * sizeof(int32_t))) != hipSuccess) return fail(e, "hint");
+  DevBuf cand;  // the hint candidates (hubs of largest key), kept for the hot count
+  int kc = 0;
   {
-    DevBuf d16, cand, hkeys, best, key;
+    DevBuf d16, hkeys, best, key;
     if ((e = d16.alloc(n * sizeof(uint16_t))) != hipSuccess) return fail(e, "degrees");
     hipLaunchKernelGGL(k_deg16, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s, g->row_ptr, n,
                        (uint16_t *)d16.p);
     // hint candidates: the hubs of largest key (every hub outranks every other
     // vertex), ordered on the host
     const int64_t nh = g->num_hubs;
-    const int kc = (int)std::min<int64_t>(nh, kHintCand);
+    kc = (int)std::min<int64_t>(nh, kHintCand);
     if (nh > 0) {
       if ((e = hkeys.alloc(nh * sizeof(uint64_t))) != hipSuccess ||
           (e = cand.alloc(kc * sizeof(int32_t))) != hipSuccess ||
@@ -970,8 +1077,8 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
     if ((e = hipMemsetAsync(cnt.p, 0, n * 4, s)) != hipSuccess ||
         (e = hipMemsetAsync(hist.p, 0, kHotBins * 4, s)) != hipSuccess)
       return fail(e, "memset");
-    hipLaunchKernelGGL(k_hint_count, dim3(grid_cap(n, 256, ncu * 16)), dim3(256), 0, s, g->hint,
-                       n, (uint32_t *)cnt.p);
+    hipLaunchKernelGGL(k_hint_count, dim3(grid_cap(n, 256, ncu * 8)), dim3(256), 0, s, g->hint,
+                       n, (const int32_t *)cand.p, kc, (uint32_t *)cnt.p);
     hipLaunchKernelGGL(k_hint_hist, dim3(grid_cap(n, 256, ncu * 4)), dim3(256), 0, s,
                        (const uint32_t *)cnt.p, n, (uint32_t *)hist.p);
     if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
