@@ -327,12 +327,6 @@ __device__ int64_t block_search(const Off &off, int64_t len, uint32_t e) {
 // appends v to the next queue.
 enum Claim : int { CLAIM_OR = 0, CLAIM_CAS = 1, CLAIM_MIN = 2 };
 
-__device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) x |= __shfl_xor(x, d, kWave);
-  return x;
-}
-
 // Top-down expansion (runs only if the level's decision set ctr[C_GO]); a
 // block takes 1024-edge tiles of the frontier's edges (total ctr[C_MF]) in
 // turn.  A tile's claimed vertices go to the next queue together: their
@@ -661,6 +655,11 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
       // [0, nnz) < 2^32, so 32-bit wrap-around arithmetic gives it exactly
       s_base[wb + lane] = (uint32_t)k - pre;
       s_first[wb + lane] = kNone;
+      // s_row[p] = tag << 6 | lane when that lane's row starts at position p
+      // of the window with that tag (tags count windows from 1 in this call):
+      // a lane reads its own slot and one ballot gives the window's row starts
+      s_row[wb + lane] = 0;
+      uint32_t tag = 0;
       uint64_t done = __ballot(len == 0);
       int carry = 0;
       for (uint32_t j0 = 0; j0 < total; j0 += kNone) {
@@ -669,12 +668,14 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
           const uint32_t jw = j0 + (uint32_t)(w * kWave);
+          ++tag;
           const bool starts = len > 0 && pre >= jw && pre < jw + kWave;
-          if (starts) s_row[wb + (int)(pre - jw)] = lane;
-          const uint64_t S = wave_or_u64(starts ? (1ull << (pre - jw)) : 0ull);
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          if (starts) s_row[wb + (int)(pre - jw)] = (int32_t)((tag << 6) | (uint32_t)lane);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const uint64_t S = __ballot(((uint32_t)s_row[wb + lane] >> 6) == tag);
           const uint64_t upto = S & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
-          r[w] = upto ? s_row[wb + (kWave - 1 - __clzll((long long)upto))] : carry;
+          r[w] = upto ? (s_row[wb + (kWave - 1 - __clzll((long long)upto))] & (kWave - 1)) : carry;
           carry = __shfl(r[w], kWave - 1, kWave);
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           const uint32_t j = jw + lane;

@@ -428,12 +428,6 @@ __device__ __forceinline__ uint64_t hint_key(const int64_t *rp, const uint16_t *
   return (d << 32) | (uint64_t)(0x7fffffffu - (uint32_t)u);
 }
 
-__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
-#pragma unroll
-  for (int d = kWave / 2; d >= 1; d >>= 1) x |= __shfl_xor(x, d, kWave);
-  return x;
-}
-
 // Hint candidates: the kHintCand vertices of largest key (degree, then smaller
 // id), in key order, held by every workgroup in an LDS hash table (id -> rank).
 // Any candidate's key exceeds that of every other vertex, so when a row holds
@@ -491,14 +485,21 @@ __device__ uint64_t packed_rows(uint32_t len, uint32_t b32, uint64_t ident, cons
   // [0, nnz) < 2^32, so 32-bit wrap-around arithmetic gives it exactly
   s_base[wb + lane] = b32 - pre;
   s_acc[wb + lane] = ident;
+  // s_row[p] = tag << 6 | lane when that lane's row starts at position p of
+  // the window with that tag (tags count windows from 1 in this call): a lane
+  // reads its own slot and one ballot gives the window's row starts
+  s_row[wb + lane] = 0;
+  uint32_t tag = 0;
   int carry = 0;
   for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
+    ++tag;
     const bool starts = len > 0 && pre >= j0 && pre < j0 + kWave;
-    if (starts) s_row[wb + (int)(pre - j0)] = lane;
-    const uint64_t S = wave_or(starts ? (1ull << (pre - j0)) : 0ull);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (starts) s_row[wb + (int)(pre - j0)] = (int32_t)((tag << 6) | (uint32_t)lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint64_t S = __ballot(((uint32_t)s_row[wb + lane] >> 6) == tag);
     const uint64_t upto = S & upto_mask;
-    const int r = upto ? s_row[wb + (kWave - 1 - __clzll((long long)upto))] : carry;
+    const int r = upto ? (s_row[wb + (kWave - 1 - __clzll((long long)upto))] & (kWave - 1)) : carry;
     const uint32_t j = j0 + lane;
     uint64_t val = ident;
     if (j < total) val = f(ci[(uint32_t)(s_base[wb + r] + j)]);
