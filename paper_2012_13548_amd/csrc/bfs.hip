@@ -647,7 +647,7 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
     constexpr int kNone = kWave * NW;
     const uint32_t len = (pending && !found) ? (uint32_t)(e - k) : 0u;
     const uint32_t incl = wave_incl_scan(len);
-    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    const uint32_t total = lane_u32(incl, kWave - 1);
     if (total) {
       const uint32_t pre = incl - len;
       const int wb = (threadIdx.x / kWave) * kWave;
@@ -676,7 +676,7 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
           const uint64_t S = __ballot(((uint32_t)s_row[wb + lane] >> 6) == tag);
           const uint64_t upto = S & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
           r[w] = upto ? (s_row[wb + (kWave - 1 - __clzll((long long)upto))] & (kWave - 1)) : carry;
-          carry = __shfl(r[w], kWave - 1, kWave);
+          carry = (int)lane_u32((uint32_t)r[w], kWave - 1);
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           const uint32_t j = jw + lane;
           u[w] = -1;
@@ -717,10 +717,14 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
         if (fm) {
           // the next step starts where the next unresolved entry is: inside a
           // row that covers j0 + NW * 64 (no jump), or at the start of a later
-          // row (a row start: its window needs no carry)
+          // row (a row start: its window needs no carry).  max(pre, nj) does
+          // not decrease with the lane (pre is a prefix sum), so its minimum
+          // over the live lanes is that of the lowest live lane.
           const uint32_t nj = j0 + kNone;
           const bool live = !((done >> lane) & 1) && pre + len > nj;
-          j0 = wave_min<uint32_t>(live ? (pre > nj ? pre : nj) : 0xffffffffu) - kNone;
+          const uint64_t lv = __ballot(live);
+          j0 = (lv ? lane_u32(pre > nj ? pre : nj, __ffsll((unsigned long long)lv) - 1)
+                   : 0xffffffffu) - kNone;
         }
       }
       if (ACCT && len > 0 && !found) cnt.nscan += len;
@@ -731,7 +735,7 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
   while (rem) {
     const int L = __ffsll((unsigned long long)rem) - 1;
     rem &= rem - 1;
-    const int64_t kb = __shfl(k, L, kWave), ke = __shfl(e, L, kWave);
+    const int64_t kb = lane_i64(k, L), ke = lane_i64(e, L);
     int32_t got = -1;
     int64_t seen = ke - kb;
     for (int64_t c = kb; c < ke; c += kWave) {
@@ -745,7 +749,7 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
       const uint64_t hm = __ballot(hit);
       if (hm) {
         const int hl = __ffsll((unsigned long long)hm) - 1;
-        got = __shfl(u, hl, kWave);
+        got = (int32_t)lane_u32((uint32_t)u, hl);
         seen = c - kb + hl + 1;
         break;
       }
@@ -857,7 +861,7 @@ __device__ __forceinline__ void bu_chunks(
       const uint64_t un = ~vw;
       const uint32_t cl = (uint32_t)__popcll(un);
       const uint32_t incl = wave_incl_scan(cl);
-      const uint32_t total = __shfl(incl, kWave - 1, kWave);
+      const uint32_t total = lane_u32(incl, kWave - 1);
       const uint32_t excl = incl - cl;
       nx[lane] = 0ull;
       HintRank<true> hr_(hint, cbase, iso, c, w, words);
@@ -980,7 +984,7 @@ __device__ __forceinline__ void bu_chunks(
     const uint64_t un = ~vw;
     const uint32_t cl = (uint32_t)__popcll(un);
     const uint32_t incl = wave_incl_scan(cl);
-    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    const uint32_t total = lane_u32(incl, kWave - 1);
     const uint32_t excl = incl - cl;
     nx[lane] = 0ull;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

@@ -186,6 +186,17 @@ __device__ __forceinline__ T wave_min(T v) {
   return v;
 }
 
+// x of lane l, for a lane index that is the same in every lane (a constant or
+// derived from a ballot): a scalar read, not a cross-lane permute through LDS.
+__device__ __forceinline__ uint32_t lane_u32(uint32_t x, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+__device__ __forceinline__ int64_t lane_i64(int64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Exclusive prefix sum over a block of NT threads; `s` is LDS scratch of
 // NT/64 entries.  Returns the exclusive prefix; `total` gets the block sum.
 template <int NT, typename T>
