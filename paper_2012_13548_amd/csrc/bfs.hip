@@ -650,7 +650,8 @@ __device__ __forceinline__ void bu_row_rest(const Front &F, const int32_t *__res
     const uint32_t total = lane_u32(incl, kWave - 1);
     if (total) {
       const uint32_t pre = incl - len;
-      const int wb = (threadIdx.x / kWave) * kWave;
+      // the wavefront's slice of the per-lane LDS arrays, in a scalar register
+      const int wb = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) * kWave;
       // row entry j of the window sits at s_base + j: k - pre + j lies in
       // [0, nnz) < 2^32, so 32-bit wrap-around arithmetic gives it exactly
       s_base[wb + lane] = (uint32_t)k - pre;

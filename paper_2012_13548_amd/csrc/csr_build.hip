@@ -476,7 +476,7 @@ template <class F, class C>
 __device__ uint64_t packed_rows(uint32_t len, uint32_t b32, uint64_t ident, const int32_t *ci,
                                 F f, C comb, uint32_t *s_base, int32_t *s_row, uint64_t *s_acc) {
   const int lane = __lane_id();
-  const int wb = (threadIdx.x / kWave) * kWave;
+  const int wb = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) * kWave;  // scalar
   const uint64_t upto_mask = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
   const uint32_t incl = wave_incl_scan(len);
   const uint32_t total = __shfl(incl, kWave - 1, kWave);
