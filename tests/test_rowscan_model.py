@@ -2,7 +2,9 @@
 csrc/bfs.hip): 64 lanes lay their unresolved rows end to end, test one entry
 per lane per 64-entry window, take each row's first hit in row order by a
 minimum over the window, and after a window that resolves rows jump to the
-next entry of a row still unresolved.  Every entry index is asserted inside
+next entry of a row still unresolved.  Row starts come from tagged LDS slots
+and one ballot, checked against the OR over the lanes that defines them; the
+jump target is the lowest live lane's, checked against the minimum.  Every entry index is asserted inside
 its row, and hits and scan counts are compared with a sequential scan of each
 row; the window count is checked against the layout without jumps."""
 import random
@@ -24,20 +26,26 @@ def packed_scan(rows, front, ci, jump=True):
         return found, par, scanned, 0
     s_base = [(rows[l][2] - pre[l]) & 0xffffffff for l in range(W)]
     done = [length[l] == 0 for l in range(W)]
-    s_row, carry, j0, windows = [None] * W, 0, 0, 0
+    # s_row slot p holds tag << 6 | lane when that lane's row starts at
+    # position p of the window with that tag (tags count windows from 1;
+    # the slots are cleared when the scan starts)
+    s_row, carry, j0, windows, tag = [0] * W, 0, 0, 0, 0
     while j0 < total:
         windows += 1
+        tag += 1
         starts = [length[l] > 0 and j0 <= pre[l] < j0 + W for l in range(W)]
-        S = 0
+        S_or = 0  # the mask by definition: an OR over the lanes
         for l in range(W):
             if starts[l]:
-                s_row[pre[l] - j0] = l
-                S |= 1 << (pre[l] - j0)
+                s_row[pre[l] - j0] = (tag << 6) | l
+                S_or |= 1 << (pre[l] - j0)
+        S = sum(1 << p for p in range(W) if (s_row[p] >> 6) == tag)  # one ballot
+        assert S == S_or
         first = [W] * W
         u, r = [-1] * W, [0] * W
         for l in range(W):
             upto = S & ((2 << l) - 1)
-            r[l] = s_row[upto.bit_length() - 1] if upto else carry
+            r[l] = (s_row[upto.bit_length() - 1] & (W - 1)) if upto else carry
             j = j0 + l
             if j < total and not done[r[l]]:
                 idx = (s_base[r[l]] + j) & 0xffffffff
@@ -56,8 +64,13 @@ def packed_scan(rows, front, ci, jump=True):
             break
         nj = j0 + W
         if jump and fresh:
-            live = [max(pre[l], nj) for l in range(W) if not done[l] and pre[l] + length[l] > nj]
-            nj = min(live) if live else 1 << 32
+            lv = [l for l in range(W) if not done[l] and pre[l] + length[l] > nj]
+            live = [max(pre[l], nj) for l in lv]
+            # the kernel reads the lowest live lane: max(pre, nj) does not
+            # decrease with the lane, so that is the minimum over the live lanes
+            low = max(pre[lv[0]], nj) if lv else 1 << 32
+            assert low == (min(live) if live else 1 << 32)
+            nj = low
         j0 = nj
     for l in range(W):
         if length[l] and not found[l]:
