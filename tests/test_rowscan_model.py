@@ -4,8 +4,9 @@ per lane per 64-entry window, take each row's first hit in row order by a
 minimum over the window, and after a window that resolves rows jump to the
 next entry of a row still unresolved.  Row starts come from tagged LDS slots
 and one ballot, checked against the OR over the lanes that defines them; the
-jump target is the lowest live lane's, checked against the minimum.  Every entry index is asserted inside
-its row, and hits and scan counts are compared with a sequential scan of each
+jump target is the lowest live lane's, checked against the minimum.  Every
+entry index is asserted inside its row, and hits and scan counts are compared
+with a sequential scan of each
 row; the window count is checked against the layout without jumps."""
 import random
 
