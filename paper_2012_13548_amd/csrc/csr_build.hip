@@ -469,9 +469,9 @@ struct CandSet {
 
 // Rows of a wavefront's 64 lanes (len entries from 32-bit offset b32 each)
 // laid end to end, one entry per lane per 64-entry window; f(u) maps each
-// entry to a value and the values of a row are combined by `comb` (a
-// segmented scan over the lanes of each window).  Returns the lane's own
-// row's value (ident for an empty row).
+// entry to a value and the values of a row are combined by `comb` (a minimum
+// or maximum, taken by LDS atomics into the row's slot).  Returns the lane's
+// own row's value (ident for an empty row).
 template <class F, class C>
 __device__ uint64_t packed_rows(uint32_t len, uint32_t b32, uint64_t ident, const int32_t *ci,
                                 F f, C comb, uint32_t *s_base, int32_t *s_row, uint64_t *s_acc) {
@@ -503,17 +503,11 @@ __device__ uint64_t packed_rows(uint32_t len, uint32_t b32, uint64_t ident, cons
     const uint32_t j = j0 + lane;
     uint64_t val = ident;
     if (j < total) val = f(ci[(uint32_t)(s_base[wb + r] + j)]);
-#pragma unroll
-    for (int dd = 1; dd < kWave; dd <<= 1) {
-      const uint64_t o = __shfl_up(val, dd, kWave);
-      const int orow = __shfl_up(r, dd, kWave);
-      if (lane >= dd && orow == r) val = comb(val, o);
-    }
-    const int nrow = __shfl_down(r, 1, kWave);
-    if (j < total && (lane == kWave - 1 || j + 1 == total || nrow != r))
-      s_acc[wb + r] = comb(s_acc[wb + r], val);
+    // each entry with a value combines it into its row's slot by an LDS
+    // atomic (min and max do not depend on the order)
+    if (val != ident) comb.into(&s_acc[wb + r], val);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    carry = __shfl(r, kWave - 1, kWave);
+    carry = (int)__builtin_amdgcn_readlane(r, kWave - 1);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const uint64_t out = s_acc[wb + lane];
@@ -522,13 +516,13 @@ __device__ uint64_t packed_rows(uint32_t len, uint32_t b32, uint64_t ident, cons
 }
 
 struct MinOp {
-  __device__ __forceinline__ uint64_t operator()(uint64_t a, uint64_t b) const {
-    return a < b ? a : b;
+  __device__ __forceinline__ void into(uint64_t *slot, uint64_t v) const {
+    atomicMin((unsigned long long *)slot, (unsigned long long)v);
   }
 };
 struct MaxOp {
-  __device__ __forceinline__ uint64_t operator()(uint64_t a, uint64_t b) const {
-    return a > b ? a : b;
+  __device__ __forceinline__ void into(uint64_t *slot, uint64_t v) const {
+    atomicMax((unsigned long long *)slot, (unsigned long long)v);
   }
 };
 
@@ -537,15 +531,18 @@ struct MaxOp {
 // A wavefront takes 64 consecutive vertices (hub rows aside, see k_hint_hubs):
 // first the candidate ranks of their entries (LDS lookups), then, for rows
 // without a candidate, the keys of their entries.
-__global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
+// 1,024-thread workgroups: the 48 KB candidate table in LDS is shared by 16
+// wavefronts, and two workgroups fit a compute unit.
+constexpr int kHintBlock = 1024;
+__global__ __launch_bounds__(kHintBlock) void k_hint(const int64_t *__restrict__ rp,
                                               const uint16_t *__restrict__ d16,
                                               const int32_t *__restrict__ ci, int64_t n,
                                               int64_t words, const int32_t *__restrict__ cand,
                                               int kc, int32_t *__restrict__ hint,
                                               int32_t *__restrict__ hint_id) {
-  __shared__ uint32_t s_base[256];
-  __shared__ int32_t s_row[256];
-  __shared__ uint64_t s_acc[256];
+  __shared__ uint32_t s_base[kHintBlock];
+  __shared__ int32_t s_row[kHintBlock];
+  __shared__ uint64_t s_acc[kHintBlock];
   __shared__ int32_t s_cid[kCandSlots];
   __shared__ uint16_t s_crank[kCandSlots];
   CandSet cs{s_cid, s_crank};
@@ -585,7 +582,7 @@ __global__ __launch_bounds__(256) void k_hint(const int64_t *__restrict__ rp,
 // the piece's best key goes to key[h] by an atomic maximum.
 // off[h] = the first piece of hub h (off[nh] = pieces in all).
 template <bool RANKED>
-__global__ __launch_bounds__(256) void k_hint_hubs(const int64_t *__restrict__ rp,
+__global__ __launch_bounds__(kHintBlock) void k_hint_hubs(const int64_t *__restrict__ rp,
                                                    const uint16_t *__restrict__ d16,
                                                    const int32_t *__restrict__ ci,
                                                    const int32_t *__restrict__ hubs,
@@ -1044,17 +1041,18 @@ g5_status build_csr_impl(const int64_t *edges, const uint8_t *weights, bool weig
       // ids is read by the copy: keep it until the stream has taken it
       if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "sync");
     }
-    hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, 4, ncu * 16)), dim3(256), 0, s, g->row_ptr,
+    hipLaunchKernelGGL(k_hint, dim3(grid_cap(g->words, kHintBlock / kWave, ncu * 4)),
+                       dim3(kHintBlock), 0, s, g->row_ptr,
                        (const uint16_t *)d16.p, g->col_idx, n, g->words,
                        (const int32_t *)cand.p, kc, g->hint, g->hint_id);
     if ((e = hipGetLastError()) != hipSuccess) return fail(e, "launch");
     if (nh > 0) {
-      const dim3 grid(grid_cap(g->hub_chunks, 4, ncu * 16));
-      hipLaunchKernelGGL(k_hint_hubs<true>, grid, dim3(256), 0, s, g->row_ptr,
+      const dim3 grid(grid_cap(g->hub_chunks, kHintBlock / kWave, ncu * 4));
+      hipLaunchKernelGGL(k_hint_hubs<true>, grid, dim3(kHintBlock), 0, s, g->row_ptr,
                          (const uint16_t *)d16.p, g->col_idx, g->hub_list,
                          (const uint64_t *)g->hub_off, nh, (const int32_t *)cand.p, kc,
                          (unsigned long long *)best.p, (unsigned long long *)key.p);
-      hipLaunchKernelGGL(k_hint_hubs<false>, grid, dim3(256), 0, s, g->row_ptr,
+      hipLaunchKernelGGL(k_hint_hubs<false>, grid, dim3(kHintBlock), 0, s, g->row_ptr,
                          (const uint16_t *)d16.p, g->col_idx, g->hub_list,
                          (const uint64_t *)g->hub_off, nh, (const int32_t *)cand.p, kc,
                          (unsigned long long *)best.p, (unsigned long long *)key.p);
