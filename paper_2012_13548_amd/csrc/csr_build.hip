@@ -118,19 +118,37 @@ __global__ __launch_bounds__(kRadix) void k_digit_starts(const unsigned long lon
 }
 
 // Exclusive scan of a uint32 array into uint64 (single block); *total = sum.
+// Each thread takes a contiguous segment whose length is a multiple of 4, read
+// 16 bytes at a time (`in` comes from hipMalloc: 16-byte aligned), so that a
+// long array (a million tile counts) costs few dependent loads per thread.
 __global__ __launch_bounds__(kScanBlock) void k_scan_u32(const uint32_t *__restrict__ in,
                                                         uint64_t *__restrict__ out,
                                                         int64_t len,
                                                         uint64_t *__restrict__ total) {
   __shared__ uint64_t s[kScanBlock / kWave];
-  int64_t per = (len + kScanBlock - 1) / kScanBlock;
-  int64_t b = per * threadIdx.x, e = std::min<int64_t>(b + per, len);
+  const int64_t per = ((len + kScanBlock - 1) / kScanBlock + 3) & ~int64_t(3);
+  const int64_t b = std::min<int64_t>(per * threadIdx.x, len), e = std::min<int64_t>(b + per, len);
+  const int64_t e4 = b + ((e - b) & ~int64_t(3));  // whole groups of 4
   uint64_t sum = 0;
-  for (int64_t i = b; i < e; ++i) sum += in[i];
+#pragma unroll 4
+  for (int64_t i = b; i < e4; i += 4) {
+    const uint4 x = *reinterpret_cast<const uint4 *>(in + i);
+    sum += (uint64_t)x.x + x.y + x.z + x.w;
+  }
+  for (int64_t i = e4; i < e; ++i) sum += in[i];
   uint64_t tot;
   uint64_t run = block_excl_scan<kScanBlock, uint64_t>(sum, s, tot);
-  for (int64_t i = b; i < e; ++i) {
-    uint64_t x = in[i];
+#pragma unroll 4
+  for (int64_t i = b; i < e4; i += 4) {
+    const uint4 x = *reinterpret_cast<const uint4 *>(in + i);
+    out[i] = run;
+    out[i + 1] = run + x.x;
+    out[i + 2] = run + x.x + x.y;
+    out[i + 3] = run + x.x + x.y + x.z;
+    run += (uint64_t)x.x + x.y + x.z + x.w;
+  }
+  for (int64_t i = e4; i < e; ++i) {
+    const uint64_t x = in[i];
     out[i] = run;
     run += x;
   }
